@@ -1,0 +1,346 @@
+"""FP64 CPU oracle for Parareal with low-rank coarse solvers.
+
+TEST INFRASTRUCTURE ONLY.  This package is the independent reference that
+the GPU library is checked against.  Only the test suite, the smoke check and
+the CPU-baseline leg of the benchmark may import it; the product code never
+does, and it shares no code with the product.
+
+The arithmetic lives in ``lrpr_oracle.c`` (plain loops, FP64, compiled with
+``-ffp-contract=off``); this module marshals NumPy arrays into it and adds the
+Parareal recursion and the error bounds, written in the paper's notation:
+
+* Parareal iteration and its initialisation: Sec. 2, eq. (def_Parareal).
+* Affine fine solver F_n v = F_n' v + b_n with b_n = F_n 0: eq. (F_n_affine).
+* Low-rank coarse solver G_n: eq. (spectral_G); its linear part G_n'.
+* Randomized SVD: Sec. 2.1 steps 1-6 (in C).
+* a priori bound: Thm. 1, eq. (error_bound_eps_delta2);
+  a posteriori bound: Thm. 3, eqs. (apost_bound), (apost_bound_sup).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lrpr_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liblrpr_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle's C code into a shared library (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.ora_assemble.restype = ctypes.c_int
+        lib.ora_assemble.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+        lib.ora_band_lu.restype = ctypes.c_int
+        lib.ora_band_lu.argtypes = [ctypes.c_int, ctypes.c_int, _dp]
+        lib.ora_fine_steps.restype = None
+        lib.ora_fine_steps.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int,
+                                       _dp, ctypes.c_long, ctypes.c_int,
+                                       _dp, ctypes.c_long, _ip, _dp]
+        lib.ora_adjoint_steps.restype = None
+        lib.ora_adjoint_steps.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
+                                          _dp, ctypes.c_long, ctypes.c_int]
+        lib.ora_householder_qr.restype = ctypes.c_int
+        lib.ora_householder_qr.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _dp, _dp]
+        lib.ora_jacobi_svd.restype = ctypes.c_int
+        lib.ora_jacobi_svd.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
+        lib.ora_rsvd.restype = ctypes.c_int
+        lib.ora_rsvd.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int, _dp, ctypes.c_long, _dp, _dp, _dp]
+        lib.ora_lowrank_apply.restype = None
+        lib.ora_lowrank_apply.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int,
+                                          _dp, _dp]
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def _fortran(a):
+    return np.asfortranarray(np.asarray(a, dtype=np.float64))
+
+
+def _fortran_copy(a):
+    return np.array(a, dtype=np.float64, order="F", copy=True)
+
+
+# ---------------------------------------------------------------------------
+# operator, factor, fine propagator
+# ---------------------------------------------------------------------------
+class Operator:
+    """Implicit-Euler matrix M = I + dt*A of one slice and its band LU.
+
+    A is the finite-difference analogue (first-order upwind advection) of the
+    paper's parabolic operator; the fine solver is implicit Euler with m
+    steps of size dt per slice (Sec. 4, first paragraph, with finite
+    differences in place of finite elements).
+    """
+
+    def __init__(self, dim, nx, nu, beta, c, dt):
+        self.dim, self.nx, self.nu, self.c, self.dt = dim, nx, float(nu), float(c), float(dt)
+        self.beta = (float(beta[0]), float(beta[1]) if dim == 2 else 0.0)
+        self.n = nx if dim == 1 else nx * nx
+        self.bw = 1 if dim == 1 else nx
+        lib = _load()
+        self.band = np.zeros((self.n, 2 * self.bw + 1), dtype=np.float64)
+        lib.ora_assemble(dim, nx, self.nu, self.beta[0], self.beta[1], self.c, self.dt, _p(self.band))
+        self.lu = self.band.copy()
+        info = lib.ora_band_lu(self.n, self.bw, _p(self.lu))
+        if info != 0:
+            raise ArithmeticError("zero pivot at row %d" % (info - 1))
+
+    def dense(self):
+        """Dense M (for tiny test grids only)."""
+        n, b = self.n, self.bw
+        M = np.zeros((n, n))
+        for i in range(n):
+            for j in range(max(0, i - b), min(n, i + b + 1)):
+                M[i, j] = self.band[i, j - i + b]
+        return M
+
+    def dense_lu(self):
+        """Dense (L, U) of the band LU (tiny grids only)."""
+        n, b = self.n, self.bw
+        L, U = np.eye(n), np.zeros((n, n))
+        for i in range(n):
+            for j in range(max(0, i - b), min(n, i + b + 1)):
+                if j < i:
+                    L[i, j] = self.lu[i, j - i + b]
+                else:
+                    U[i, j] = self.lu[i, j - i + b]
+        return L, U
+
+    def fine(self, X, m, f=None, fcol=None, fscale=None):
+        """m implicit-Euler steps for every column of X (n x w), returns a new array.
+
+        Column c gets the source fscale[c, j] * f[:, fcol[c]] at step j (evaluated
+        at the step's end time); without f the map is T = M^{-m}.
+        """
+        X = _fortran_copy(X)
+        if X.ndim == 1:
+            X = X.reshape(-1, 1, order="F")
+        n, w = X.shape
+        assert n == self.n
+        fp = fc = fs = None
+        ldf = 0
+        if f is not None:
+            f = _fortran(f)
+            if f.ndim == 1:
+                f = f.reshape(-1, 1, order="F")
+            ldf = f.shape[0]
+            fcol = np.ascontiguousarray(np.zeros(w, np.int32) if fcol is None else fcol, dtype=np.int32)
+            fc = fcol.ctypes.data_as(_ip)
+            fp = _p(f)
+            if fscale is not None:
+                fscale = np.ascontiguousarray(np.broadcast_to(np.asarray(fscale, np.float64), (w, m)))
+                fs = _p(fscale)
+        _load().ora_fine_steps(self.n, self.bw, _p(self.lu), self.dt, m, _p(X), n, w, fp, ldf, fc, fs)
+        return X
+
+    def adjoint(self, X, m):
+        """X <- (M^T)^{-m} X, the adjoint of the source-free fine propagator."""
+        X = _fortran_copy(X)
+        if X.ndim == 1:
+            X = X.reshape(-1, 1, order="F")
+        n, w = X.shape
+        _load().ora_adjoint_steps(self.n, self.bw, _p(self.lu), m, _p(X), n, w)
+        return X
+
+
+def householder_qr(Y):
+    Y = _fortran(Y)
+    n, l = Y.shape
+    Q = np.zeros((n, l), order="F")
+    R = np.zeros((l, l), order="F")
+    _load().ora_householder_qr(n, l, _p(Y), n, _p(Q), _p(R))
+    return Q, R
+
+
+def jacobi_svd(M):
+    M = _fortran(M)
+    l = M.shape[0]
+    U = np.zeros((l, l), order="F")
+    V = np.zeros((l, l), order="F")
+    S = np.zeros(l)
+    sweeps = _load().ora_jacobi_svd(l, _p(M), _p(U), _p(S), _p(V))
+    if sweeps < 0:
+        raise ArithmeticError("Jacobi SVD did not converge")
+    return U, S, V
+
+
+def rsvd(op: Operator, m: int, k: int, p: int, Omega):
+    """Randomized SVD of T = M^{-m} (Sec. 2.1).  Returns (Uk, S_all, Vk)."""
+    Omega = _fortran(Omega)
+    n, l = Omega.shape
+    assert l == k + p and n == op.n
+    Uk = np.zeros((n, k), order="F")
+    Vk = np.zeros((n, k), order="F")
+    S = np.zeros(l)
+    sw = _load().ora_rsvd(n, op.bw, _p(op.lu), m, k, p, _p(Omega), n, _p(Uk), _p(S), _p(Vk))
+    if sw < 0:
+        raise ArithmeticError("Jacobi SVD did not converge")
+    return Uk, S, Vk
+
+
+def lowrank_apply(Uk, S, Vk, V):
+    """G_n' V = Uk (S .* (Vk^T V)) column by column."""
+    Uk, Vk, V = _fortran(Uk), _fortran(Vk), _fortran(V)
+    if V.ndim == 1:
+        V = V.reshape(-1, 1, order="F")
+    n, k = Uk.shape
+    w = V.shape[1]
+    S = np.ascontiguousarray(S[:k], dtype=np.float64)
+    out = np.zeros((n, w), order="F")
+    _load().ora_lowrank_apply(n, k, _p(Uk), _p(S), _p(Vk), w, _p(V), _p(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Parareal (Sec. 2) and bounds (Sec. 3)
+# ---------------------------------------------------------------------------
+class Slice:
+    """One Parareal interval [t_{n-1}, t_n]: its fine solver F_n (operator, m
+    steps, source f with per-step time factors) and, once built, the coarse
+    factors (Uk, S, Vk) and b_n = F_n 0."""
+
+    def __init__(self, op: Operator, m: int, f=None, fscale=None):
+        self.op, self.m, self.f, self.fscale = op, m, f, fscale
+        self.Uk = self.S = self.Vk = None
+        self.b = None
+
+    def F(self, v):
+        """Affine fine solver F_n v (eq. F_n_affine)."""
+        if self.f is None:
+            return self.op.fine(v, self.m)[:, 0]
+        return self.op.fine(v, self.m, self.f, None, self.fscale)[:, 0]
+
+    def Fp(self, v):
+        """Linear part F_n' = T_n."""
+        return self.op.fine(v, self.m)[:, 0]
+
+    def Gp(self, v):
+        """Linear part G_n' of the coarse solver."""
+        if self.Uk is None or self.Uk.shape[1] == 0:
+            return np.zeros(self.op.n)
+        return lowrank_apply(self.Uk, self.S, self.Vk, v)[:, 0]
+
+
+def build_coarse(slices, k, p, omegas):
+    """Set up all coarse solvers: rSVD of every F_n' and b_n = F_n 0."""
+    for s, om in zip(slices, omegas):
+        if k + p > 0:
+            s.Uk, s.S, s.Vk = rsvd(s.op, s.m, k, p, om)
+        else:
+            s.Uk = np.zeros((s.op.n, 0))
+            s.Vk = np.zeros((s.op.n, 0))
+            s.S = np.zeros(0)
+        s.b = s.F(np.zeros(s.op.n))
+
+
+def sequential(slices, u0):
+    """Reference trajectory u_n = F_n u_{n-1} (Sec. 2, first display)."""
+    u = [np.asarray(u0, np.float64).copy()]
+    for s in slices:
+        u.append(s.F(u[-1]))
+    return np.array(u)
+
+
+def parareal(slices, u0, tol, max_iter=None):
+    """Parareal with low-rank coarse solvers, eq. (def_Parareal).
+
+    u^k_0 = u0;  u^0_n = G_n u^0_{n-1} = G_n' u^0_{n-1} + b_n;
+    u^{k+1}_n = F_n u^k_{n-1} + G_n' u^{k+1}_{n-1} - G_n' u^k_{n-1}.
+    The b_n cancel in the correction (Remark on the affine part), so the
+    linear part G_n' is used there and G_n' u^k_{n-1} is kept from the
+    previous sweep.  Stops when max_n ||u^{k+1}_n - u^k_n||_2 < tol or after
+    N iterations (where the iteration is exact).
+
+    Returns dict: iterates (list of (N+1) x n arrays, u^0..u^K), incr (list),
+    iters (K).
+    """
+    N = len(slices)
+    if max_iter is None:
+        max_iter = N
+    u0 = np.asarray(u0, np.float64)
+    cur = [u0.copy()]
+    gold = [None]
+    for n in range(1, N + 1):
+        gp = slices[n - 1].Gp(cur[n - 1])
+        gold.append(gp)
+        cur.append(gp + slices[n - 1].b)
+    iterates = [np.array(cur)]
+    incrs = []
+    k = 0
+    while k < max_iter:
+        Fu = [None] + [slices[n - 1].F(cur[n - 1]) for n in range(1, N + 1)]
+        new = [u0.copy()]
+        gnew = [None]
+        for n in range(1, N + 1):
+            gp = slices[n - 1].Gp(new[n - 1])
+            gnew.append(gp)
+            new.append(Fu[n] + gp - gold[n])
+        incr = max(float(np.linalg.norm(new[n] - cur[n])) for n in range(1, N + 1))
+        incrs.append(incr)
+        cur, gold = new, gnew
+        iterates.append(np.array(cur))
+        k += 1
+        if incr < tol or k >= N:
+            break
+    return {"iterates": iterates, "incr": incrs, "iters": k}
+
+
+def bound_constants(slices, k):
+    """delta = max_n sigma_{n,1}, eps = max_n sigma_{n,k+1} (Thm. 1, eq.
+    bounds_delta_eps); sigma_{n,k+1} is taken from the oversampled values."""
+    delta = max(float(s.S[0]) for s in slices)
+    eps = max(float(s.S[k]) if len(s.S) > k else 0.0 for s in slices)
+    return delta, eps
+
+
+def apriori_bound(delta, eps, bnorms, k, n):
+    """Thm. 1, eq. (error_bound_eps_delta2):
+    ||e^k_n|| <= 2 eps^k sum_{m=0}^{n-k-1} C(n-m, k) delta^{n-m-k} ||b_m||,
+    with b_0 = u_0."""
+    s = 0.0
+    for m in range(0, n - k):
+        s += math.comb(n - m, k) * delta ** (n - m - k) * bnorms[m]
+    return 2.0 * eps ** k * s
+
+
+def apost_bound(delta, eps, incr_norms):
+    """Thm. 3, eq. (apost_bound): for n = 1..N,
+    ||e^k_n|| <= eps sum_{m=1}^{n-1} delta^{n-m-1} ||u^k_m - u^{k-1}_m||.
+    incr_norms[m-1] = ||u^k_m - u^{k-1}_m|| for m = 1..N.  Returns N values."""
+    N = len(incr_norms)
+    out = []
+    for n in range(1, N + 1):
+        s = 0.0
+        for m in range(1, n):
+            s += delta ** (n - m - 1) * incr_norms[m - 1]
+        out.append(eps * s)
+    return np.array(out)
