@@ -1,0 +1,233 @@
+/*
+ * lrpr.h -- C ABI of the MI355X (gfx950) library for Parareal with low-rank
+ * coarse solvers (Gander, Ohlberger, Rave, arXiv 2508.08873).
+ *
+ * The library builds, on one GPU:
+ *   - the fine propagator: implicit-Euler steps of a finite-difference
+ *     diffusion-advection-reaction operator through a banded LU, batched over
+ *     many right-hand sides (forward F_n and adjoint F_n'^*), Sec. 2 eq.
+ *     (F_n_affine) and Sec. 2.1 step 3;
+ *   - the randomized SVD of every slice's transfer operator F_n' (Sec. 2.1,
+ *     steps 1-6), giving the low-rank coarse solvers G_n (eq. spectral_G);
+ *   - the Parareal iteration with those coarse solvers (Sec. 2, eq.
+ *     def_Parareal) and its a posteriori bound (Sec. 3, eq. apost_bound).
+ *
+ * Conventions for every call:
+ *   - Matrices are column-major.  "device" pointers point to GPU memory of
+ *     the context's device; "host" pointers to ordinary CPU memory.
+ *   - The caller owns every array it passes.  Handles (lrpr_ctx,
+ *     lrpr_factor, lrpr_coarse) own the memory they allocate and free it in
+ *     their destroy call.
+ *   - Work is queued on the context's HIP stream.  Calls that return host
+ *     outputs synchronise that stream before returning; others are
+ *     asynchronous (device outputs are valid once the stream reaches them).
+ *   - Every call returns an lrpr_status.  On LRPR_ERR_ARG nothing is written.
+ *     lrpr_last_error() gives a message for the last failing call of a
+ *     context.  No exception crosses the ABI.
+ *   - One host thread per context at a time.
+ */
+#ifndef LRPR_H
+#define LRPR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lrpr_ctx_s *lrpr_ctx;
+typedef struct lrpr_factor_s *lrpr_fac;   /* factor handle (returned by lrpr_factor) */
+typedef struct lrpr_coarse_s *lrpr_coarse;
+
+/* Arithmetic precision of a fine solve: states, factors and accumulation. */
+typedef enum { LRPR_F64 = 0, LRPR_F32 = 1 } lrpr_prec;
+
+typedef enum {
+    LRPR_OK = 0,
+    LRPR_ERR_ARG = 1,          /* invalid argument; nothing was written        */
+    LRPR_ERR_NOMEM = 2,        /* device allocation failed                     */
+    LRPR_ERR_ZERO_PIVOT = 3,   /* band LU met a zero or non-finite pivot       */
+    LRPR_ERR_QR_BREAKDOWN = 4, /* orthonormalisation failed even in fallback   */
+    LRPR_ERR_NOCONV = 5,       /* Parareal did not reach tol within max_iter   */
+    LRPR_ERR_NONFINITE = 6,    /* NaN or Inf met in a result                   */
+    LRPR_ERR_HIP = 7           /* HIP runtime error                            */
+} lrpr_status;
+
+/* Operator of one time slice:  u_t = -A u + f  with A the finite-difference
+ * discretisation of  -nu*Laplace(u) + beta.grad(u) + c*u  on the unit
+ * interval (dim=1, n = nx interior points) or unit square (dim=2,
+ * n = nx*nx, index i + nx*j with x fastest), h = 1/(nx+1), first-order
+ * upwind advection, homogeneous Dirichlet boundary.  The fine step is
+ * implicit Euler with step dt: (I + dt*A) x_new = x_old + dt*f(t_new).
+ * Half-bandwidth b = 1 (dim=1) or nx (dim=2).  (The paper discretises with
+ * finite elements; Sec. 4, first paragraph.) */
+typedef struct {
+    int dim;       /* 1 or 2 */
+    int nx;        /* interior points per axis, >= 1 */
+    double nu;     /* diffusion, > 0 */
+    double beta1;  /* advection velocity, x component */
+    double beta2;  /* advection velocity, y component (ignored for dim=1) */
+    double c;      /* reaction, >= 0 */
+    double dt;     /* implicit-Euler step, > 0 */
+} lrpr_op_desc;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, queueing work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+lrpr_status lrpr_ctx_create(int device, void *hip_stream, lrpr_ctx *out);
+void lrpr_ctx_destroy(lrpr_ctx ctx);
+/* Replace the stream used by later calls. */
+lrpr_status lrpr_ctx_set_stream(lrpr_ctx ctx, void *hip_stream);
+/* Message of the last failing call on ctx (static storage owned by ctx). */
+const char *lrpr_last_error(lrpr_ctx ctx);
+
+/* ---- factor (a1, a2) ---------------------------------------------------- */
+
+/* Assemble M = I + dt*A on the device and factor it M = L U by banded
+ * Gaussian elimination without pivoting, in FP64 (the paper's fine solver
+ * factors the backward-Euler matrix once and reuses it for all right-hand
+ * sides, Sec. 4.4).  M is an M-matrix that is diagonally dominant by rows
+ * and columns, so no pivoting is needed.  The factorisation is always FP64;
+ * store_mask selects the copies kept for the solves: bit 0 (1) an FP64
+ * copy (needed for LRPR_F64 solves), bit 1 (2) an FP32 copy rounded from
+ * the FP64 factors (needed for LRPR_F32 solves); 0 means 1.  The FP64 band
+ * LU itself is kept only with bit 0.  Errors: LRPR_ERR_ARG (bad
+ * descriptor), LRPR_ERR_ZERO_PIVOT, LRPR_ERR_NOMEM.  Synchronises the
+ * stream. */
+lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lrpr_fac *out);
+void lrpr_factor_destroy(lrpr_fac f);
+/* n = unknowns, bw = half-bandwidth, dt = step. */
+lrpr_status lrpr_factor_info(lrpr_fac f, int64_t *n, int *bw, double *dt);
+/* Copy the FP64 band LU (kept when store_mask has bit 0) to host memory:
+ * lu_host is n x (2*bw+1) row-major,
+ * entry (i, j) of L (j < i, unit diagonal not stored) or U (j >= i) at
+ * lu_host[i*(2*bw+1) + j - i + bw].  Synchronises. */
+lrpr_status lrpr_factor_copy_lu(lrpr_ctx ctx, lrpr_fac f, double *lu_host);
+
+/* ---- batched fine propagator (a3, a4, a5) ------------------------------- */
+
+/* One panel: w right-hand sides that share the factor F.
+ *   X      device, n x w, leading dimension ldx >= n, element type by prec
+ *          (double for LRPR_F64, float for LRPR_F32); in: start states,
+ *          out: states after nsteps steps.
+ *   f      device, n x nf source vectors (same element type), ld ldf, or
+ *          NULL for no source.
+ *   fcol   device int[w]: source column used by RHS c, or -1 for none;
+ *          NULL means column 0 for every RHS (only read if f != NULL).
+ *   fscale device double[w*nsteps]: time factor of RHS c at step j at
+ *          fscale[c*nsteps + j] (the source is f(x)*phi(t) evaluated at the
+ *          step's end time); NULL means 1.  */
+typedef struct {
+    lrpr_fac F;
+    void *X;
+    int64_t ldx;
+    int w;
+    const void *f;
+    int64_t ldf;
+    const int *fcol;
+    const double *fscale;
+} lrpr_panel;
+
+/* Fine propagator F_n (Sec. 2, eq. F_n_affine): for every panel and every
+ * column, nsteps implicit-Euler steps
+ *     (I + dt*A) x_{j+1} = x_j + dt * fscale[c][j] * f[:, fcol[c]]
+ * through the panel's band LU (forward then back substitution).  Without a
+ * source this is the transfer operator T = M^{-nsteps} (= F_n').  All panels
+ * run in one launch; panels may use different factors and sizes.
+ * Errors: LRPR_ERR_ARG (null/mismatched arguments, missing FP32 factor). */
+lrpr_status lrpr_fine_step_batched(lrpr_ctx ctx, int npanels, const lrpr_panel *panels,
+                                   int nsteps, lrpr_prec prec);
+
+/* Adjoint propagator F_n'^* (Sec. 2.1 step 3): X <- (M^T)^{-nsteps} X for
+ * every panel (forward substitution with U^T, back substitution with L^T,
+ * the same factors read transposed).  The panels' f/fcol/fscale are
+ * ignored (the adjoint of the linear part has no source). */
+lrpr_status lrpr_adjoint_step_batched(lrpr_ctx ctx, int npanels, const lrpr_panel *panels,
+                                      int nsteps, lrpr_prec prec);
+
+/* ---- randomized SVD build (a6, a7) --------------------------------------- */
+
+/* One Parareal slice for the coarse-solver build: its factor, truncation
+ * rank k (R_n in the paper) and oversampling p, and its Gaussian test
+ * matrix Omega (device, n x (k+p), column-major, ld n, element type of
+ * range_prec).  k + p <= 128, k + p <= n. */
+typedef struct {
+    lrpr_fac F;
+    int k;
+    int p;
+    const void *Omega;
+} lrpr_slice_desc;
+
+/* Randomized SVD of every slice's transfer operator T = M^{-nsteps}
+ * (Sec. 2.1, steps 1-6), all slices together:
+ *   Y = T Omega (fine sweep, range_prec);  Y = Q R (CholeskyQR2 with FP64
+ *   Gram and Cholesky; Householder fallback on breakdown);  Z = T^T Q
+ *   (adjoint sweep);  Z = Qz Rz;  Mm = Rz^T = Uh diag(S) Vh^T (one-sided
+ *   Jacobi, FP64);  U_k = Q Uh[:, :k],  V_k = Qz Vh[:, :k]  (FP64).
+ * Each pair (U_k[:, r], V_k[:, r]) is signed so that the largest-magnitude
+ * entry of U_k[:, r] (lowest index on ties) is positive.
+ * *out receives a coarse handle holding, per slice, U_k, S (all k+p
+ * singular values) and V_k in device memory.
+ * sigma_host: host, NULL or sum over slices of (k+p) doubles: all singular
+ *   values, slice after slice.
+ * fallback_host: host, NULL or int[nslices]: 1 where the Householder
+ *   fallback orthonormalised Y or Z.
+ * Errors: LRPR_ERR_ARG, LRPR_ERR_NOMEM, LRPR_ERR_QR_BREAKDOWN,
+ * LRPR_ERR_NONFINITE.  Synchronises. */
+lrpr_status lrpr_rsvd_build(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
+                            int nsteps, lrpr_prec range_prec, lrpr_coarse *out,
+                            double *sigma_host, int *fallback_host);
+void lrpr_coarse_destroy(lrpr_coarse c);
+/* Device pointers (owned by the handle) of slice s: U (n x k), S (k+p
+ * values), V (n x k); k and n of that slice. */
+lrpr_status lrpr_coarse_get(lrpr_coarse c, int s, const double **U, const double **S,
+                            const double **V, int *k, int64_t *n);
+
+/* Linear part of the coarse solver, G_n' v = U_k (S_k .* (V_k^T v))
+ * (Sec. 2, eq. spectral_G without b_n; Sec. 2.2 last paragraph) for the w
+ * columns of Vin (device, n x w, ld n, FP64) into Out (device, same shape).
+ * Asynchronous. */
+lrpr_status lrpr_coarse_apply(lrpr_ctx ctx, lrpr_coarse c, int s, int w, const double *Vin,
+                              double *Out);
+
+/* ---- Parareal (a8, a9) --------------------------------------------------- */
+
+/* Parareal with the low-rank coarse solvers of c (Sec. 2, eq.
+ * def_Parareal) for nreq independent problems that share the slices'
+ * operators (different initial values and sources):
+ *   b_n = F_n 0 (fine sweep from zero with source);
+ *   u^0_0 = u0, u^0_n = G_n' u^0_{n-1} + b_n;
+ *   u^{k+1}_n = F_n u^k_{n-1} + G_n' u^{k+1}_{n-1} - G_n' u^k_{n-1}
+ * (the fine solves of an iteration run as one batched launch; the
+ * correction is a sequential sweep over n in FP64), stopping per problem
+ * when max_n ||u^{k+1}_n - u^k_n||_2 < tol or after N = nslices
+ * iterations.
+ *   F        host array of nslices factors (slice n uses F[n-1]); must
+ *            match the slices c was built from.
+ *   u0       device, n x nreq (FP64).
+ *   f        device, n x nreq sources (FP64; converted internally for FP32
+ *            fine solves) or NULL.
+ *   fscale   device, nslices*nsteps doubles: time factor at the end of step
+ *            j of slice n at fscale[(n-1)*nsteps + j], shared by all
+ *            problems; NULL means 1.
+ *   U        device, output, nreq blocks of n x (N+1) (FP64): the last
+ *            iterate u^K_0..u^K_N of each problem, block r at U + r*n*(N+1).
+ *   iters_host  host int[nreq]: iterations K done per problem.
+ *   incr_host   host double[nreq*max_iter] or NULL: increments per
+ *            iteration (row r at incr_host + r*max_iter).
+ *   apost_host  host double[nreq*N] or NULL: a posteriori bound (eq.
+ *            apost_bound) of the last iterate, per slice, with
+ *            delta = max_n sigma_{n,1}, eps = max_n sigma_{n,k+1}.
+ * Returns LRPR_ERR_NOCONV (with all outputs written) if some problem
+ * did not reach tol within max_iter iterations (max_iter < N).
+ * Synchronises. */
+lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, int nsteps,
+                                lrpr_prec fine_prec, int nreq, const double *u0, const double *f,
+                                const double *fscale, double tol, int max_iter, double *U,
+                                int *iters_host, double *incr_host, double *apost_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRPR_H */

@@ -1,0 +1,288 @@
+// Host side of the C ABI: contexts, factors, batched fine/adjoint sweeps.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "lrpr_internal.h"
+
+using namespace lrpr;
+
+namespace lrpr {
+
+lrpr_status fail(lrpr_ctx ctx, lrpr_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+static lrpr_status hipfail(lrpr_ctx ctx, hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, e == hipErrorOutOfMemory ? LRPR_ERR_NOMEM : LRPR_ERR_HIP, m);
+}
+
+}  // namespace lrpr
+
+#define HIPCHK(call, what)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return lrpr::hipfail(ctx, e_, what); \
+    } while (0)
+
+extern "C" {
+
+lrpr_status lrpr_ctx_create(int device, void *hip_stream, lrpr_ctx *out) {
+    if (!out) return LRPR_ERR_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return LRPR_ERR_ARG;
+    lrpr_ctx ctx = new (std::nothrow) lrpr_ctx_s();
+    if (!ctx) return LRPR_ERR_NOMEM;
+    ctx->dev = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return LRPR_ERR_HIP;
+    }
+    *out = ctx;
+    return LRPR_OK;
+}
+
+void lrpr_ctx_destroy(lrpr_ctx ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->dev);
+    if (ctx->d_items) {
+        hipStreamSynchronize(ctx->stream);
+        hipFree(ctx->d_items);
+    }
+    delete ctx;
+}
+
+lrpr_status lrpr_ctx_set_stream(lrpr_ctx ctx, void *hip_stream) {
+    if (!ctx) return LRPR_ERR_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return LRPR_OK;
+}
+
+const char *lrpr_last_error(lrpr_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+// ---------------------------------------------------------------------------
+static void free_tiles(TileSet &t) {
+    void *ps[6] = {t.Lb, t.Ub, t.DL, t.DU, t.DLT, t.DUT};
+    for (void *p : ps)
+        if (p) hipFree(p);
+    t = TileSet();
+}
+
+static hipError_t alloc_tiles(TileSet &t, int NT, int nb, size_t esz) {
+    const size_t band = (size_t)NT * nb * TILE_ELEMS * esz;
+    const size_t diag = (size_t)NT * TILE_ELEMS * esz;
+    hipError_t e;
+    if ((e = hipMalloc(&t.Lb, band ? band : esz)) != hipSuccess) return e;
+    if ((e = hipMalloc(&t.Ub, band ? band : esz)) != hipSuccess) return e;
+    if ((e = hipMalloc(&t.DL, diag)) != hipSuccess) return e;
+    if ((e = hipMalloc(&t.DU, diag)) != hipSuccess) return e;
+    if ((e = hipMalloc(&t.DLT, diag)) != hipSuccess) return e;
+    if ((e = hipMalloc(&t.DUT, diag)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+void lrpr_factor_destroy(lrpr_fac f) {
+    if (!f) return;
+    hipSetDevice(f->dev);
+    hipDeviceSynchronize();
+    if (f->lu) hipFree(f->lu);
+    free_tiles(f->t64);
+    free_tiles(f->t32);
+    delete f;
+}
+
+lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lrpr_fac *out) {
+    if (!ctx || !op || !out) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: null argument");
+    if ((op->dim != 1 && op->dim != 2) || op->nx < 1 || !(op->nu > 0) || !(op->dt > 0) ||
+        !(op->c >= 0) || !std::isfinite(op->beta1) || !std::isfinite(op->beta2))
+        return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: invalid operator descriptor");
+    if (store_mask == 0) store_mask = 1;
+    if (store_mask & ~3) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: store_mask must be 1, 2 or 3");
+    const int64_t n = op->dim == 1 ? op->nx : (int64_t)op->nx * op->nx;
+    const int bw = op->dim == 1 ? 1 : op->nx;
+    if (n >= (int64_t)1 << 31) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: n too large");
+    if (bw > 1023) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: half-bandwidth above 1023");
+    HIPCHK(hipSetDevice(ctx->dev), "hipSetDevice");
+    lrpr_fac f = new (std::nothrow) lrpr_factor_s();
+    if (!f) return fail(ctx, LRPR_ERR_NOMEM, "lrpr_factor: host allocation");
+    f->dev = ctx->dev;
+    f->op = *op;
+    f->n = n;
+    f->bw = bw;
+    f->NT = (int)((n + TILE - 1) / TILE);
+    f->nb = (bw + TILE - 1) / TILE;
+    f->mask = store_mask;
+    double *band = nullptr;
+    int *d_info = nullptr;
+    int info = 0;
+    hipError_t e;
+    auto cleanup = [&](lrpr_status st, const std::string &msg) {
+        if (band && band != f->lu) hipFree(band);
+        if (d_info) hipFree(d_info);
+        lrpr_factor_destroy(f);
+        return fail(ctx, st, msg);
+    };
+    if ((e = hipMalloc(&band, sizeof(double) * (size_t)n * (2 * bw + 1))) != hipSuccess)
+        return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: band allocation");
+    if ((e = hipMalloc(&d_info, sizeof(int))) != hipSuccess)
+        return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: info allocation");
+    if ((e = hipMemsetAsync(d_info, 0, sizeof(int), ctx->stream)) != hipSuccess)
+        return cleanup(LRPR_ERR_HIP, "lrpr_factor: memset");
+    if ((e = launch_assemble(*op, n, bw, band, ctx->stream)) != hipSuccess)
+        return cleanup(LRPR_ERR_HIP, std::string("assemble: ") + hipGetErrorString(e));
+    if ((e = launch_band_lu(n, bw, band, d_info, ctx->stream)) != hipSuccess)
+        return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
+    if ((e = hipMemcpyAsync(&info, d_info, sizeof(int), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+        return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
+    if (info != 0) {
+        char msg[128];
+        snprintf(msg, sizeof msg, "lrpr_factor: zero or non-finite pivot at row %d", info - 1);
+        return cleanup(LRPR_ERR_ZERO_PIVOT, msg);
+    }
+    if (store_mask & 1) {
+        if (alloc_tiles(f->t64, f->NT, f->nb, sizeof(double)) != hipSuccess)
+            return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP64 tile allocation");
+    }
+    if (store_mask & 2) {
+        if (alloc_tiles(f->t32, f->NT, f->nb, sizeof(float)) != hipSuccess)
+            return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP32 tile allocation");
+    }
+    if ((e = launch_pack_tiles(n, bw, f->NT, f->nb, band, (store_mask & 1) ? &f->t64 : nullptr,
+                               (store_mask & 2) ? &f->t32 : nullptr, ctx->stream)) != hipSuccess)
+        return cleanup(LRPR_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+        return cleanup(LRPR_ERR_HIP, std::string("factor: ") + hipGetErrorString(e));
+    hipFree(d_info);
+    d_info = nullptr;
+    if (store_mask & 1) {
+        f->lu = band;
+    } else {
+        hipFree(band);
+    }
+    band = nullptr;
+    *out = f;
+    return LRPR_OK;
+}
+
+lrpr_status lrpr_factor_info(lrpr_fac f, int64_t *n, int *bw, double *dt) {
+    if (!f) return LRPR_ERR_ARG;
+    if (n) *n = f->n;
+    if (bw) *bw = f->bw;
+    if (dt) *dt = f->op.dt;
+    return LRPR_OK;
+}
+
+lrpr_status lrpr_factor_copy_lu(lrpr_ctx ctx, lrpr_fac f, double *lu_host) {
+    if (!ctx || !f || !lu_host) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_copy_lu: null argument");
+    if (!f->lu) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_copy_lu: factor kept without FP64 band LU");
+    HIPCHK(hipSetDevice(ctx->dev), "hipSetDevice");
+    HIPCHK(hipMemcpyAsync(lu_host, f->lu, sizeof(double) * (size_t)f->n * (2 * f->bw + 1),
+                          hipMemcpyDeviceToHost, ctx->stream),
+           "copy LU");
+    HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+    return LRPR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched sweeps
+// ---------------------------------------------------------------------------
+namespace lrpr {
+
+FacView fac_view(lrpr_fac f, bool f32) {
+    const TileSet &t = f32 ? f->t32 : f->t64;
+    FacView v;
+    v.Lb = t.Lb; v.Ub = t.Ub; v.DL = t.DL; v.DU = t.DU; v.DLT = t.DLT; v.DUT = t.DUT;
+    v.n = (int)f->n;
+    v.NT = f->NT;
+    v.nb = f->nb;
+    v.dt = f->op.dt;
+    return v;
+}
+
+lrpr_status ensure_items(lrpr_ctx ctx, size_t count) {
+    if (count <= ctx->items_cap) return LRPR_OK;
+    if (ctx->d_items) {
+        hipStreamSynchronize(ctx->stream);
+        hipFree(ctx->d_items);
+        ctx->d_items = nullptr;
+        ctx->items_cap = 0;
+    }
+    size_t cap = 1024;
+    while (cap < count) cap *= 2;
+    hipError_t e = hipMalloc(&ctx->d_items, cap * sizeof(SweepItem));
+    if (e != hipSuccess) return hipfail(ctx, e, "sweep item buffer");
+    ctx->items_cap = cap;
+    return LRPR_OK;
+}
+
+// Validate panels and turn them into 16-column work items; launch one sweep.
+lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
+                      bool adjoint) {
+    if (!ctx) return LRPR_ERR_ARG;
+    if (npanels < 0 || (npanels > 0 && !panels) || nsteps < 0 || (prec != LRPR_F64 && prec != LRPR_F32))
+        return fail(ctx, LRPR_ERR_ARG, "sweep: invalid arguments");
+    const bool f32 = prec == LRPR_F32;
+    std::vector<SweepItem> items;
+    int max_nb = 1;
+    for (int p = 0; p < npanels; ++p) {
+        const lrpr_panel &P = panels[p];
+        if (!P.F || (P.w > 0 && !P.X) || P.w < 0 || P.ldx < P.F->n)
+            return fail(ctx, LRPR_ERR_ARG, "sweep: panel with null factor/X or ldx < n");
+        if (P.F->dev != ctx->dev) return fail(ctx, LRPR_ERR_ARG, "sweep: factor on another device");
+        if ((f32 && !(P.F->mask & 2)) || (!f32 && !(P.F->mask & 1)))
+            return fail(ctx, LRPR_ERR_ARG, "sweep: factor has no copy in the requested precision");
+        if (!adjoint && P.f && P.ldf < P.F->n) return fail(ctx, LRPR_ERR_ARG, "sweep: ldf < n");
+        if (P.F->nb > max_nb) max_nb = P.F->nb;
+        const size_t esz = f32 ? sizeof(float) : sizeof(double);
+        for (int c0 = 0; c0 < P.w; c0 += TILE) {
+            SweepItem it;
+            it.fac = fac_view(P.F, f32);
+            it.X = (char *)P.X + (size_t)c0 * P.ldx * esz;
+            it.ldx = P.ldx;
+            it.ncols = P.w - c0 < TILE ? P.w - c0 : TILE;
+            it.pad_ = 0;
+            it.f = adjoint ? nullptr : P.f;
+            it.ldf = P.ldf;
+            it.fcol = (!adjoint && P.f && P.fcol) ? P.fcol + c0 : nullptr;
+            it.fscale = (!adjoint && P.f && P.fscale) ? P.fscale + (size_t)c0 * nsteps : nullptr;
+            items.push_back(it);
+        }
+    }
+    if (items.empty() || nsteps == 0) return LRPR_OK;
+    if (max_nb > 64) return fail(ctx, LRPR_ERR_ARG, "sweep: half-bandwidth above 1023");
+    hipError_t e = hipSetDevice(ctx->dev);
+    if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+    lrpr_status st = ensure_items(ctx, items.size());
+    if (st != LRPR_OK) return st;
+    e = hipMemcpyAsync(ctx->d_items, items.data(), items.size() * sizeof(SweepItem),
+                       hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return hipfail(ctx, e, "sweep item upload");
+    e = launch_sweep(adjoint, f32, (int)items.size(), ctx->d_items, nsteps, max_nb, ctx->stream);
+    if (e != hipSuccess) return hipfail(ctx, e, "sweep launch");
+    return LRPR_OK;
+}
+
+}  // namespace lrpr
+
+extern "C" {
+
+lrpr_status lrpr_fine_step_batched(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps,
+                                   lrpr_prec prec) {
+    return run_sweep(ctx, npanels, panels, nsteps, prec, false);
+}
+
+lrpr_status lrpr_adjoint_step_batched(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps,
+                                      lrpr_prec prec) {
+    return run_sweep(ctx, npanels, panels, nsteps, prec, true);
+}
+
+}  // extern "C"

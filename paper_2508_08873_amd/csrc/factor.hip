@@ -1,0 +1,207 @@
+// Operator assembly, banded LU without pivoting, and packing of the factors
+// into the tiled layout read by the sweep kernels.
+#include "lrpr_internal.h"
+
+namespace lrpr {
+
+// ---------------------------------------------------------------------------
+// Assembly of M = I + dt*A into band storage n x (2b+1), row-major, entry
+// (i, j) at i*(2b+1) + j - i + b.  A: finite differences of
+// -nu*Laplace + beta.grad + c on the unit interval/square, h = 1/(nx+1),
+// first-order upwind (the upwind neighbour is the west/south one for a
+// positive velocity component), homogeneous Dirichlet boundary.  One thread
+// per band entry.
+// ---------------------------------------------------------------------------
+__global__ void k_assemble(lrpr_op_desc op, int64_t n, int bw, double *band) {
+    const int W = 2 * bw + 1;
+    const int64_t total = n * W;
+    const double h = 1.0 / (double)(op.nx + 1);
+    const double dif = op.nu / (h * h);
+    const double b1 = op.beta1, b2 = op.dim == 2 ? op.beta2 : 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / W;
+        const int d = (int)(e - i * W);
+        const int64_t jcol = i - bw + d;
+        double v = 0.0;
+        if (jcol >= 0 && jcol < n) {
+            if (op.dim == 1) {
+                if (jcol == i) v = 1.0 + op.dt * (2.0 * dif + fabs(b1) / h + op.c);
+                else if (jcol == i - 1) v = op.dt * (-dif - fmax(b1, 0.0) / h);
+                else if (jcol == i + 1) v = op.dt * (-dif - fmax(-b1, 0.0) / h);
+            } else {
+                const int nx = op.nx;
+                const int64_t ix = i % nx;
+                if (jcol == i) v = 1.0 + op.dt * (4.0 * dif + (fabs(b1) + fabs(b2)) / h + op.c);
+                else if (jcol == i - 1 && ix > 0) v = op.dt * (-dif - fmax(b1, 0.0) / h);
+                else if (jcol == i + 1 && ix < nx - 1) v = op.dt * (-dif - fmax(-b1, 0.0) / h);
+                else if (jcol == i - nx) v = op.dt * (-dif - fmax(b2, 0.0) / h);
+                else if (jcol == i + nx) v = op.dt * (-dif - fmax(-b2, 0.0) / h);
+            }
+        }
+        band[e] = v;
+    }
+}
+
+hipError_t launch_assemble(const lrpr_op_desc &op, int64_t n, int bw, double *band, hipStream_t s) {
+    const int64_t total = n * (2 * bw + 1);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(256), 0, s, op, n, bw, band);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Banded LU without pivoting (Doolittle, right-looking): for each pivot q,
+// the multipliers L[q+1+i][q] = a[q+1+i][q] / a[q][q] and the rank-1 update
+// a[q+1+i][q+1+j] -= L[q+1+i][q] * a[q][q+1+j] of the (b x b) window.  One
+// workgroup per factor, the window is updated in place in global memory
+// (L2-resident for b <= 511).  *info = q+1 on a zero/non-finite pivot.
+// ---------------------------------------------------------------------------
+constexpr int LU_THREADS = 1024;
+constexpr int LU_TX = 64;
+
+__global__ __launch_bounds__(LU_THREADS) void k_band_lu(int64_t n, int bw, double *band, int *info) {
+    extern __shared__ double sm_lu[];
+    double *urow = sm_lu;          // [bw]
+    double *lcol = sm_lu + bw;     // [bw]
+    const int64_t W = 2 * bw + 1;
+    const int tid = threadIdx.x;
+    const int tx = tid % LU_TX, ty = tid / LU_TX;
+    constexpr int TY = LU_THREADS / LU_TX;
+    for (int64_t q = 0; q < n; ++q) {
+        const double piv = band[q * W + bw];
+        if (!(piv != 0.0) || !isfinite(piv)) {
+            if (tid == 0) *info = (int)(q + 1);
+            return;
+        }
+        const int ni = (int)((n - 1 - q) < bw ? (n - 1 - q) : bw);
+        for (int t = tid; t < ni; t += LU_THREADS) {
+            urow[t] = band[q * W + bw + 1 + t];
+            const int64_t pos = (q + 1 + t) * W + (bw - 1 - t);
+            const double l = band[pos] / piv;
+            band[pos] = l;
+            lcol[t] = l;
+        }
+        __syncthreads();
+        for (int i = ty; i < ni; i += TY) {
+            const double li = lcol[i];
+            double *rowp = band + (q + 1 + i) * W + bw - i;   // entry (q+1+i, q+1+j) at rowp[j]
+            for (int j = tx; j < ni; j += LU_TX) rowp[j] -= li * urow[j];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_band_lu(int64_t n, int bw, double *band, int *info, hipStream_t s) {
+    const size_t lds = sizeof(double) * 2 * (size_t)bw;
+    hipLaunchKernelGGL(k_band_lu, dim3(1), dim3(LU_THREADS), lds, s, n, bw, band, info);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Packing.  Band tiles in the 4x4 sub-block layout; diagonal tiles inverted
+// (FP64) and stored as MFMA A operands in "chunk kc of lane l at kc*64 + l"
+// order.  For the f64 MFMA the contraction index of (lane l, chunk kc) is
+// 4*kc + l/16; for f32 it is 4*(l/16) + kc, matching how the accumulator
+// registers of the previous product are consumed as B operands.
+// ---------------------------------------------------------------------------
+__device__ inline double lu_at(const double *lu, int64_t n, int bw, int64_t i, int64_t j) {
+    if (i < 0 || j < 0 || i >= n || j >= n) return 0.0;
+    const int64_t d = j - i;
+    if (d < -bw || d > bw) return 0.0;
+    return lu[i * (2 * bw + 1) + d + bw];
+}
+
+__global__ void k_pack_band(int64_t n, int bw, int NT, int nb, const double *lu, double *L64,
+                            double *U64, float *L32, float *U32) {
+    const int64_t total = (int64_t)NT * nb * TILE_ELEMS;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t tileidx = e / TILE_ELEMS;
+        const int o = (int)(e % TILE_ELEMS);
+        const int64_t I = tileidx / nb;
+        const int j = (int)(tileidx % nb);
+        const int sb = o >> 4, wi = o & 15;
+        const int r = (sb & 3) * 4 + (wi >> 2);
+        const int cc = (sb >> 2) * 4 + (wi & 3);
+        const int64_t i = I * TILE + r;
+        // L(I, I-nb+j): strictly lower part only
+        const int64_t ql = (I - nb + j) * TILE + cc;
+        double lv = (ql < i) ? lu_at(lu, n, bw, i, ql) : 0.0;
+        // U(I, I+1+j)
+        const int64_t qu = (I + 1 + j) * TILE + cc;
+        double uv = (qu > i) ? lu_at(lu, n, bw, i, qu) : 0.0;
+        if (L64) { L64[e] = lv; U64[e] = uv; }
+        if (L32) { L32[e] = (float)lv; U32[e] = (float)uv; }
+    }
+}
+
+// slot of element (row m, contraction k) of a diagonal A-operand tile
+__device__ inline int dslot(bool f32, int m, int k) {
+    if (!f32) return (k >> 2) * 64 + m + 16 * (k & 3);   // k = 4kc + g
+    return (k & 3) * 64 + m + 16 * (k >> 2);             // k = 4g + kc
+}
+
+// One thread per (tile row, column of the inverse): 16 threads per tile row.
+__global__ void k_pack_diag(int64_t n, int bw, int NT, const double *lu, double *DL64, double *DU64,
+                            double *DLT64, double *DUT64, float *DL32, float *DU32, float *DLT32,
+                            float *DUT32) {
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (tid >= (int64_t)NT * TILE) return;
+    const int64_t I = tid / TILE;
+    const int col = (int)(tid % TILE);
+    const int64_t base = I * TILE;
+    double xl[TILE], xu[TILE];
+    // column `col` of L_II^{-1}: forward substitution on e_col (unit diagonal)
+    for (int r = 0; r < TILE; ++r) {
+        double v = (r == col) ? 1.0 : 0.0;
+        for (int q = 0; q < r; ++q) v -= lu_at(lu, n, bw, base + r, base + q) * xl[q];
+        xl[r] = v;
+    }
+    // column `col` of U_II^{-1}: back substitution; padded rows are identity
+    for (int r = TILE - 1; r >= 0; --r) {
+        double v = (r == col) ? 1.0 : 0.0;
+        for (int q = r + 1; q < TILE; ++q) v -= lu_at(lu, n, bw, base + r, base + q) * xu[q];
+        const double d = (base + r < n) ? lu_at(lu, n, bw, base + r, base + r) : 1.0;
+        xu[r] = v / d;
+    }
+    const int64_t off = I * TILE_ELEMS;
+    for (int r = 0; r < TILE; ++r) {
+        // D[r][col] and its transpose DT[col][r]
+        if (DL64) {
+            DL64[off + dslot(false, r, col)] = xl[r];
+            DU64[off + dslot(false, r, col)] = xu[r];
+            DLT64[off + dslot(false, col, r)] = xl[r];
+            DUT64[off + dslot(false, col, r)] = xu[r];
+        }
+        if (DL32) {
+            DL32[off + dslot(true, r, col)] = (float)xl[r];
+            DU32[off + dslot(true, r, col)] = (float)xu[r];
+            DLT32[off + dslot(true, col, r)] = (float)xl[r];
+            DUT32[off + dslot(true, col, r)] = (float)xu[r];
+        }
+    }
+}
+
+hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu, const TileSet *t64,
+                             const TileSet *t32, hipStream_t s) {
+    const int64_t total = (int64_t)NT * nb * TILE_ELEMS;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_pack_band, dim3((unsigned)blocks), dim3(256), 0, s, n, bw, NT, nb, lu,
+                       t64 ? (double *)t64->Lb : nullptr, t64 ? (double *)t64->Ub : nullptr,
+                       t32 ? (float *)t32->Lb : nullptr, t32 ? (float *)t32->Ub : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t th = (int64_t)NT * TILE;
+    hipLaunchKernelGGL(k_pack_diag, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, n, bw, NT, lu,
+                       t64 ? (double *)t64->DL : nullptr, t64 ? (double *)t64->DU : nullptr,
+                       t64 ? (double *)t64->DLT : nullptr, t64 ? (double *)t64->DUT : nullptr,
+                       t32 ? (float *)t32->DL : nullptr, t32 ? (float *)t32->DU : nullptr,
+                       t32 ? (float *)t32->DLT : nullptr, t32 ? (float *)t32->DUT : nullptr);
+    return hipGetLastError();
+}
+
+}  // namespace lrpr

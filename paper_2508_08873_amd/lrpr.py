@@ -1,0 +1,254 @@
+"""Thin ctypes binding of the lrpr C ABI (include/lrpr.h).
+
+Argument marshalling only: torch tensors supply device memory and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels.  Loading fails loudly if ``liblrpr.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblrpr.so")
+
+LRPR_F64, LRPR_F32 = 0, 1
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_ZERO_PIVOT", 4: "ERR_QR_BREAKDOWN",
+          5: "ERR_NOCONV", 6: "ERR_NONFINITE", 7: "ERR_HIP"}
+EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_last_error",
+           "lrpr_factor", "lrpr_factor_destroy", "lrpr_factor_info", "lrpr_factor_copy_lu",
+           "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build",
+           "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_parareal_solve"]
+
+
+class LrprError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class OpDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("nu", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("c", ctypes.c_double),
+                ("dt", ctypes.c_double)]
+
+
+class Panel(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_void_p), ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64),
+                ("w", ctypes.c_int), ("f", ctypes.c_void_p), ("ldf", ctypes.c_int64),
+                ("fcol", ctypes.c_void_p), ("fscale", ctypes.c_void_p)]
+
+
+class SliceDesc(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_void_p), ("k", ctypes.c_int), ("p", ctypes.c_int),
+                ("Omega", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load liblrpr.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblrpr.so not built: run `python -m paper_2508_08873_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    lib.lrpr_ctx_create.argtypes = [i32, vp, P(vp)]
+    lib.lrpr_ctx_destroy.argtypes = [vp]
+    lib.lrpr_ctx_destroy.restype = None
+    lib.lrpr_ctx_set_stream.argtypes = [vp, vp]
+    lib.lrpr_last_error.argtypes = [vp]
+    lib.lrpr_last_error.restype = ctypes.c_char_p
+    lib.lrpr_factor.argtypes = [vp, P(OpDesc), i32, P(vp)]
+    lib.lrpr_factor_destroy.argtypes = [vp]
+    lib.lrpr_factor_destroy.restype = None
+    lib.lrpr_factor_info.argtypes = [vp, P(i64), P(i32), P(dbl)]
+    lib.lrpr_factor_copy_lu.argtypes = [vp, vp, vp]
+    lib.lrpr_fine_step_batched.argtypes = [vp, i32, P(Panel), i32, i32]
+    lib.lrpr_adjoint_step_batched.argtypes = [vp, i32, P(Panel), i32, i32]
+    lib.lrpr_rsvd_build.argtypes = [vp, i32, P(SliceDesc), i32, i32, P(vp), vp, vp]
+    lib.lrpr_coarse_destroy.argtypes = [vp]
+    lib.lrpr_coarse_destroy.restype = None
+    lib.lrpr_coarse_get.argtypes = [vp, i32, P(vp), P(vp), P(vp), P(i32), P(i64)]
+    lib.lrpr_coarse_apply.argtypes = [vp, vp, i32, i32, vp, vp]
+    lib.lrpr_parareal_solve.argtypes = [vp, vp, P(vp), i32, i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
+    for name in EXPORTS:
+        if name not in ("lrpr_ctx_destroy", "lrpr_factor_destroy", "lrpr_coarse_destroy", "lrpr_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """lrpr_ctx bound to a torch device; uses torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.device = device
+        h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(device).cuda_stream
+        self._check(self.lib.lrpr_ctx_create(device, ctypes.c_void_p(stream), ctypes.byref(h)), ctx=None)
+        self.h = h
+
+    def _check(self, st, ctx="self"):
+        if st != 0:
+            msg = ""
+            if ctx == "self":
+                msg = self.lib.lrpr_last_error(self.h).decode()
+            raise LrprError(st, msg)
+
+    def sync_stream(self):
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.lib.lrpr_ctx_set_stream(self.h, ctypes.c_void_p(stream))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lrpr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- factor -----------------------------------------------------------
+    def factor(self, dim, nx, nu, beta, c, dt, store_mask=1):
+        d = OpDesc(dim, nx, float(nu), float(beta[0]), float(beta[1]) if dim == 2 else 0.0, float(c), float(dt))
+        h = ctypes.c_void_p()
+        self.sync_stream()
+        self._check(self.lib.lrpr_factor(self.h, ctypes.byref(d), int(store_mask), ctypes.byref(h)))
+        return Factor(self, h)
+
+    # -- sweeps -----------------------------------------------------------
+    def _panels(self, specs):
+        arr = (Panel * len(specs))()
+        for i, s in enumerate(specs):
+            X = s["X"]
+            f = s.get("f")
+            arr[i] = Panel(s["F"].h, X.data_ptr(), X.stride(1) if X.dim() == 2 and X.shape[1] > 1 else X.shape[0],
+                           X.shape[1] if X.dim() == 2 else 1,
+                           f.data_ptr() if f is not None else None,
+                           (f.stride(1) if f.dim() == 2 and f.shape[1] > 1 else f.shape[0]) if f is not None else 0,
+                           s["fcol"].data_ptr() if s.get("fcol") is not None else None,
+                           s["fscale"].data_ptr() if s.get("fscale") is not None else None)
+        return arr
+
+    def fine_step_batched(self, specs, nsteps, prec=LRPR_F64):
+        """specs: list of dicts {F, X (n x w, column-major = t().contiguous().t()), f, fcol, fscale}."""
+        arr = self._panels(specs)
+        self.sync_stream()
+        self._check(self.lib.lrpr_fine_step_batched(self.h, len(specs), arr, int(nsteps), int(prec)))
+
+    def adjoint_step_batched(self, specs, nsteps, prec=LRPR_F64):
+        arr = self._panels(specs)
+        self.sync_stream()
+        self._check(self.lib.lrpr_adjoint_step_batched(self.h, len(specs), arr, int(nsteps), int(prec)))
+
+    # -- rSVD -------------------------------------------------------------
+    def rsvd_build(self, slices, nsteps, range_prec=LRPR_F64):
+        """slices: list of (Factor, k, p, Omega tensor n x (k+p) column-major)."""
+        arr = (SliceDesc * len(slices))()
+        tot = 0
+        for i, (F, k, p, Om) in enumerate(slices):
+            arr[i] = SliceDesc(F.h, int(k), int(p), Om.data_ptr() if Om is not None else None)
+            tot += k + p
+        sig = (ctypes.c_double * max(tot, 1))()
+        fb = (ctypes.c_int * max(len(slices), 1))()
+        h = ctypes.c_void_p()
+        self.sync_stream()
+        self._check(self.lib.lrpr_rsvd_build(self.h, len(slices), arr, int(nsteps), int(range_prec),
+                                             ctypes.byref(h), sig, fb))
+        return Coarse(self, h, [F for (F, _, _, _) in slices], list(sig)[:tot], list(fb)[:len(slices)])
+
+    # -- Parareal ---------------------------------------------------------
+    def parareal_solve(self, coarse, factors, nsteps, u0, f=None, fscale=None, tol=1e-10, max_iter=None,
+                       fine_prec=LRPR_F64):
+        """u0: (n, nreq) float64 cuda column-major; f: (n, nreq) or None; fscale: (N*nsteps,) float64."""
+        N = len(factors)
+        if max_iter is None:
+            max_iter = N
+        n, nreq = u0.shape
+        U = torch.zeros((nreq, N + 1, n), dtype=torch.float64, device=u0.device)
+        fa = (ctypes.c_void_p * N)(*[F.h.value for F in factors])
+        iters = (ctypes.c_int * nreq)()
+        incr = (ctypes.c_double * (nreq * max_iter))()
+        apost = (ctypes.c_double * (nreq * N))()
+        self.sync_stream()
+        st = self.lib.lrpr_parareal_solve(self.h, coarse.h, fa, int(nsteps), int(fine_prec), int(nreq),
+                                          _ptr(u0), _ptr(f), _ptr(fscale), float(tol), int(max_iter),
+                                          _ptr(U), iters, incr, apost)
+        if st not in (0, 5):
+            self._check(st)
+        return {"U": U, "iters": list(iters), "incr": [list(incr[r * max_iter:(r + 1) * max_iter]) for r in range(nreq)],
+                "apost": [list(apost[r * N:(r + 1) * N]) for r in range(nreq)], "status": st}
+
+
+class Factor:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+        n, bw, dt = ctypes.c_int64(), ctypes.c_int(), ctypes.c_double()
+        ctx.lib.lrpr_factor_info(h, ctypes.byref(n), ctypes.byref(bw), ctypes.byref(dt))
+        self.n, self.bw, self.dt = n.value, bw.value, dt.value
+
+    def lu_host(self):
+        import numpy as np
+        out = np.zeros((self.n, 2 * self.bw + 1), dtype=np.float64)
+        self.ctx._check(self.ctx.lib.lrpr_factor_copy_lu(self.ctx.h, self.h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.lrpr_factor_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Coarse:
+    def __init__(self, ctx, h, factors, sigma, fallback):
+        self.ctx, self.h, self.factors, self.sigma, self.fallback = ctx, h, factors, sigma, fallback
+
+    def get(self, s):
+        """(U, S, V) of slice s copied into new torch tensors (n x k, k+p, n x k)."""
+        U, S, V = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        k, n = ctypes.c_int(), ctypes.c_int64()
+        self.ctx._check(self.ctx.lib.lrpr_coarse_get(self.h, s, ctypes.byref(U), ctypes.byref(S), ctypes.byref(V),
+                                                     ctypes.byref(k), ctypes.byref(n)))
+        return k.value, n.value, U.value, S.value, V.value
+
+    def apply(self, s, Vin):
+        out = torch.empty_like(Vin)
+        self.ctx.sync_stream()
+        self.ctx._check(self.ctx.lib.lrpr_coarse_apply(self.ctx.h, self.h, s, Vin.shape[1], _ptr(Vin), _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.lrpr_coarse_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def colmajor(t):
+    """Column-major (Fortran-order) copy of a 2-D tensor: element (i, c) at i + c*n."""
+    return t.t().contiguous().t()
