@@ -51,10 +51,10 @@ lrpr_status lrpr_ctx_create(int device, void *hip_stream, lrpr_ctx *out) {
 void lrpr_ctx_destroy(lrpr_ctx ctx) {
     if (!ctx) return;
     hipSetDevice(ctx->dev);
-    if (ctx->d_items) {
-        hipStreamSynchronize(ctx->stream);
-        hipFree(ctx->d_items);
-    }
+    hipStreamSynchronize(ctx->stream);
+    if (ctx->d_items) hipFree(ctx->d_items);
+    for (auto &kv : ctx->ws)
+        if (kv.second.first) hipFree(kv.second.first);
     delete ctx;
 }
 

@@ -1,8 +1,575 @@
+// Host side of the C ABI: randomized-SVD build of the coarse solvers and
+// the Parareal solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+
+#include "dense.h"
 #include "lrpr_internal.h"
-extern "C" {
-lrpr_status lrpr_rsvd_build(lrpr_ctx ctx, int, const lrpr_slice_desc *, int, lrpr_prec, lrpr_coarse *, double *, int *) { return lrpr::fail(ctx, LRPR_ERR_ARG, "not built"); }
-void lrpr_coarse_destroy(lrpr_coarse) {}
-lrpr_status lrpr_coarse_get(lrpr_coarse, int, const double **, const double **, const double **, int *, int64_t *) { return LRPR_ERR_ARG; }
-lrpr_status lrpr_coarse_apply(lrpr_ctx ctx, lrpr_coarse, int, int, const double *, double *) { return lrpr::fail(ctx, LRPR_ERR_ARG, "not built"); }
-lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse, const lrpr_fac *, int, lrpr_prec, int, const double *, const double *, const double *, double, int, double *, int *, double *, double *) { return lrpr::fail(ctx, LRPR_ERR_ARG, "not built"); }
+
+namespace lrpr {
+FacView fac_view(lrpr_fac f, bool f32);
+lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
+                      bool adjoint);
+
+// Workspace cached per context and purpose; grows on demand.
+void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err);
+}  // namespace lrpr
+
+using namespace lrpr;
+
+namespace {
+
+struct Scoped {   // device allocations freed at scope exit (after a stream sync)
+    hipStream_t s;
+    std::vector<void *> ptrs;
+    explicit Scoped(hipStream_t st) : s(st) {}
+    ~Scoped() {
+        if (!ptrs.empty()) hipStreamSynchronize(s);
+        for (void *p : ptrs) hipFree(p);
+    }
+    template <typename T>
+    hipError_t alloc(T **p, size_t count) {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 16);
+        if (e == hipSuccess) ptrs.push_back(q);
+        *p = (T *)q;
+        return e;
+    }
+};
+
+lrpr_status herr(lrpr_ctx ctx, hipError_t e, const char *what) {
+    return fail(ctx, e == hipErrorOutOfMemory ? LRPR_ERR_NOMEM : LRPR_ERR_HIP,
+                std::string(what) + ": " + hipGetErrorString(e));
 }
+
+#define CK(call, what)                                  \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return herr(ctx, e_, what); \
+    } while (0)
+
+template <typename T>
+hipError_t upload(T *dst, const std::vector<T> &src, hipStream_t s) {
+    if (src.empty()) return hipSuccess;
+    return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+// Low-rank apply over w columns, split so that k*w fits the kernel's LDS.
+hipError_t lowrank_cols(LrArgs a, double *part, double *incpart, hipStream_t s) {
+    const int maxw = std::max(1, 12288 / std::max(a.k, 1));
+    const int w = a.w;
+    for (int c0 = 0; c0 < w; c0 += maxw) {
+        LrArgs b = a;
+        const int64_t off = (int64_t)c0 * a.n;
+        b.w = std::min(maxw, w - c0);
+        b.x = a.x ? a.x + off : nullptr;
+        b.out = a.out + off;
+        b.gold = a.gold ? a.gold + off : nullptr;
+        b.bvec = a.bvec ? a.bvec + off : nullptr;
+        b.fu64 = a.fu64 ? a.fu64 + off : nullptr;
+        b.fu32 = a.fu32 ? a.fu32 + off : nullptr;
+        b.active = a.active ? a.active + c0 : nullptr;
+        b.part = part;
+        b.incpart = incpart ? incpart + (int64_t)c0 : nullptr;   // layout [chunk][w] with stride w below
+        if (incpart && b.w != w) return hipErrorInvalidValue;    // increments need all columns in one pass
+        hipError_t e = launch_lowrank(b, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+namespace lrpr {
+void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err);
+}
+
+// ---------------------------------------------------------------------------
+// rSVD build
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void lrpr_coarse_destroy(lrpr_coarse c) {
+    if (!c) return;
+    hipSetDevice(c->dev);
+    hipDeviceSynchronize();
+    for (size_t s = 0; s < c->U.size(); ++s) {
+        if (c->U[s]) hipFree(c->U[s]);
+        if (c->V[s]) hipFree(c->V[s]);
+        if (c->S[s]) hipFree(c->S[s]);
+    }
+    delete c;
+}
+
+lrpr_status lrpr_coarse_get(lrpr_coarse c, int s, const double **U, const double **S, const double **V, int *k,
+                            int64_t *n) {
+    if (!c || s < 0 || s >= c->nslices) return LRPR_ERR_ARG;
+    if (U) *U = c->U[s];
+    if (S) *S = c->S[s];
+    if (V) *V = c->V[s];
+    if (k) *k = c->k[s];
+    if (n) *n = c->n[s];
+    return LRPR_OK;
+}
+
+lrpr_status lrpr_rsvd_build(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices, int nsteps,
+                            lrpr_prec range_prec, lrpr_coarse *out, double *sigma_host, int *fallback_host) {
+    if (!ctx) return LRPR_ERR_ARG;
+    if (nslices <= 0 || !slices || !out || nsteps < 0 || (range_prec != LRPR_F64 && range_prec != LRPR_F32))
+        return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: invalid arguments");
+    const bool f32 = range_prec == LRPR_F32;
+    const size_t esz = f32 ? sizeof(float) : sizeof(double);
+    int lmax = 1, kmax = 1;
+    int64_t nmax = 1;
+    for (int s = 0; s < nslices; ++s) {
+        const lrpr_slice_desc &d = slices[s];
+        const int l = d.k + d.p;
+        if (!d.F || !d.Omega || d.k < 0 || d.p < 0 || l < 1 || l > LMAX || l > d.F->n)
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: slice needs factor, Omega, 1 <= k+p <= min(96, n)");
+        if (!(d.F->mask & 1) || (f32 && !(d.F->mask & 2)))
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: factor lacks the FP64 (and, for FP32, FP32) copy");
+        if (d.F->dev != ctx->dev) return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: factor on another device");
+        lmax = std::max(lmax, l);
+        kmax = std::max(kmax, d.k);
+        nmax = std::max(nmax, d.F->n);
+    }
+    CK(hipSetDevice(ctx->dev), "hipSetDevice");
+    hipStream_t st = ctx->stream;
+    Scoped mem(st);
+    // offsets of every slice's n x l block in the tall arenas
+    std::vector<int64_t> off(nslices + 1, 0);
+    std::vector<int> ls(nslices);
+    for (int s = 0; s < nslices; ++s) {
+        ls[s] = slices[s].k + slices[s].p;
+        off[s + 1] = off[s] + slices[s].F->n * ls[s];
+    }
+    const int64_t tot = off[nslices];
+    void *Y = nullptr, *Z = nullptr;
+    double *Q = nullptr, *QZ = nullptr, *T2 = nullptr;
+    CK(hipMalloc(&Y, tot * esz), "rsvd Y");
+    mem.ptrs.push_back(Y);
+    CK(hipMalloc(&Z, tot * esz), "rsvd Z");
+    mem.ptrs.push_back(Z);
+    CK(mem.alloc(&Q, tot), "rsvd Q");
+    CK(mem.alloc(&QZ, tot), "rsvd Qz");
+    CK(mem.alloc(&T2, tot), "rsvd tmp");
+    const size_t SM = (size_t)LMAX * LMAX;
+    double *G, *R1, *I1, *R2, *I2, *RY, *RZ, *Mm, *Uh, *Vh, *Sd, *part;
+    int *d_ls, *stat1, *stat2, *sweeps;
+    const int nchunks = gram_chunks(nmax);
+    CK(mem.alloc(&G, SM * nslices), "G");
+    CK(mem.alloc(&R1, SM * nslices), "R1");
+    CK(mem.alloc(&I1, SM * nslices), "I1");
+    CK(mem.alloc(&R2, SM * nslices), "R2");
+    CK(mem.alloc(&I2, SM * nslices), "I2");
+    CK(mem.alloc(&RY, SM * nslices), "RY");
+    CK(mem.alloc(&RZ, SM * nslices), "RZ");
+    CK(mem.alloc(&Mm, SM * nslices), "Mm");
+    CK(mem.alloc(&Uh, SM * nslices), "Uh");
+    CK(mem.alloc(&Vh, SM * nslices), "Vh");
+    CK(mem.alloc(&Sd, (size_t)LMAX * nslices), "S");
+    CK(mem.alloc(&part, SM * nslices * nchunks), "gram partials");
+    CK(mem.alloc(&d_ls, nslices), "ls");
+    CK(mem.alloc(&stat1, nslices), "stat1");
+    CK(mem.alloc(&stat2, nslices), "stat2");
+    CK(mem.alloc(&sweeps, nslices), "sweeps");
+    CK(upload(d_ls, ls, st), "upload ls");
+
+    // --- step 1: Y = T Omega (fine sweep without source) ------------------
+    for (int s = 0; s < nslices; ++s)
+        CK(hipMemcpyAsync((char *)Y + off[s] * esz, slices[s].Omega, (size_t)(off[s + 1] - off[s]) * esz,
+                          hipMemcpyDeviceToDevice, st),
+           "copy Omega");
+    // consecutive slices with the same factor form one panel (contiguous blocks)
+    auto make_panels = [&](void *base) {
+        std::vector<lrpr_panel> P;
+        for (int s = 0; s < nslices; ++s) {
+            if (!P.empty() && P.back().F == slices[s].F) {
+                P.back().w += ls[s];
+                continue;
+            }
+            lrpr_panel p{};
+            p.F = slices[s].F;
+            p.X = (char *)base + off[s] * esz;
+            p.ldx = slices[s].F->n;
+            p.w = ls[s];
+            P.push_back(p);
+        }
+        return P;
+    };
+    {
+        std::vector<lrpr_panel> P = make_panels(Y);
+        lrpr_status r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, false);
+        if (r != LRPR_OK) return r;
+    }
+
+    // --- CholeskyQR2 with Householder fallback ---------------------------
+    std::vector<GramJob> gj(nslices);
+    std::vector<RowMatJob> rj(nslices);
+    GramJob *d_gj;
+    RowMatJob *d_rj;
+    HouseJob *d_hj;
+    SignJob *d_sj;
+    CK(mem.alloc(&d_gj, nslices), "jobs");
+    CK(mem.alloc(&d_rj, nslices), "jobs");
+    CK(mem.alloc(&d_hj, nslices), "jobs");
+    CK(mem.alloc(&d_sj, nslices), "jobs");
+    std::vector<int> fallback(nslices, 0);
+
+    // orthonormalise A (T or FP64 arena) into Qout (FP64); R into Rout
+    auto cholqr2 = [&](const void *A, bool a32, double *Qout, double *Rout) -> lrpr_status {
+        for (int s = 0; s < nslices; ++s)
+            gj[s] = GramJob{(const char *)A + off[s] * (a32 ? 4 : 8), slices[s].F->n, ls[s], 0};
+        CK(upload(d_gj, gj, st), "upload");
+        CK(launch_gram(a32, d_gj, nslices, nchunks, part, G, st), "gram 1");
+        CK(launch_chol(d_ls, nslices, G, R1, I1, stat1, 2e-8, st), "chol 1");
+        for (int s = 0; s < nslices; ++s)
+            rj[s] = RowMatJob{(const char *)A + off[s] * (a32 ? 4 : 8), slices[s].F->n, I1 + SM * s,
+                              T2 + off[s], slices[s].F->n, slices[s].F->n, ls[s], ls[s], 1, 0};
+        CK(upload(d_rj, rj, st), "upload");
+        CK(launch_rowmat(a32 ? 1 : 0, 0, d_rj, nslices, nmax, st), "Y Rinv");
+        for (int s = 0; s < nslices; ++s) gj[s] = GramJob{T2 + off[s], slices[s].F->n, ls[s], 0};
+        CK(upload(d_gj, gj, st), "upload");
+        CK(launch_gram(false, d_gj, nslices, nchunks, part, G, st), "gram 2");
+        CK(launch_chol(d_ls, nslices, G, R2, I2, stat2, 0.1, st), "chol 2");
+        for (int s = 0; s < nslices; ++s)
+            rj[s] = RowMatJob{T2 + off[s], slices[s].F->n, I2 + SM * s, Qout + off[s], slices[s].F->n,
+                              slices[s].F->n, ls[s], ls[s], 1, 0};
+        CK(upload(d_rj, rj, st), "upload");
+        CK(launch_rowmat(0, 0, d_rj, nslices, nmax, st), "Q1 Rinv");
+        CK(launch_trmm_upper(d_ls, nslices, R2, R1, Rout, st), "R2 R1");
+        std::vector<int> h1(nslices), h2(nslices);
+        CK(hipMemcpyAsync(h1.data(), stat1, sizeof(int) * nslices, hipMemcpyDeviceToHost, st), "stat");
+        CK(hipMemcpyAsync(h2.data(), stat2, sizeof(int) * nslices, hipMemcpyDeviceToHost, st), "stat");
+        CK(hipStreamSynchronize(st), "sync");
+        std::vector<HouseJob> hj;
+        for (int s = 0; s < nslices; ++s) {
+            if (!h1[s] && !h2[s]) continue;
+            fallback[s] = 1;
+            // FP64 working copy of the panel in T2, Q into Qout, R into Rout
+            const int64_t cnt = off[s + 1] - off[s];
+            CK(launch_convert(a32 ? 1 : 0, 0, (const char *)A + off[s] * (a32 ? 4 : 8), T2 + off[s], cnt, st),
+               "fallback copy");
+            hj.push_back(HouseJob{T2 + off[s], Qout + off[s], Rout + SM * s, slices[s].F->n, ls[s], 0});
+        }
+        if (!hj.empty()) {
+            CK(upload(d_hj, hj, st), "upload");
+            CK(launch_householder(d_hj, (int)hj.size(), st), "householder");
+        }
+        return LRPR_OK;
+    };
+
+    lrpr_status r = cholqr2(Y, f32, Q, RY);            // step 2
+    if (r != LRPR_OK) return r;
+    // --- step 3: Z = T^T Q (adjoint sweep) ---------------------------------
+    CK(launch_convert(0, f32 ? 1 : 0, Q, Z, tot, st), "Q -> Z");
+    {
+        std::vector<lrpr_panel> P = make_panels(Z);
+        r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, true);
+        if (r != LRPR_OK) return r;
+    }
+    r = cholqr2(Z, f32, QZ, RZ);                       // step 4
+    if (r != LRPR_OK) return r;
+    // --- step 5: Mm = Rz^T, small SVD --------------------------------------
+    CK(launch_transpose_small(d_ls, nslices, RZ, Mm, st), "Rz^T");
+    CK(launch_jacobi(d_ls, nslices, lmax, Mm, Uh, Sd, Vh, sweeps, st), "jacobi");
+    // --- step 6: U_k = Q Uh[:, :k], V_k = Qz Vh[:, :k] ---------------------
+    lrpr_coarse c = new (std::nothrow) lrpr_coarse_s();
+    if (!c) return fail(ctx, LRPR_ERR_NOMEM, "coarse handle");
+    c->dev = ctx->dev;
+    c->nslices = nslices;
+    c->n.resize(nslices);
+    c->k.resize(nslices);
+    c->l.resize(nslices);
+    c->U.assign(nslices, nullptr);
+    c->V.assign(nslices, nullptr);
+    c->S.assign(nslices, nullptr);
+    c->F.resize(nslices);
+    auto bail = [&](lrpr_status stt, const char *msg) {
+        lrpr_coarse_destroy(c);
+        return fail(ctx, stt, msg);
+    };
+    for (int s = 0; s < nslices; ++s) {
+        c->n[s] = slices[s].F->n;
+        c->k[s] = slices[s].k;
+        c->l[s] = ls[s];
+        c->F[s] = slices[s].F;
+        const size_t nk = (size_t)c->n[s] * std::max(slices[s].k, 1);
+        if (hipMalloc(&c->U[s], nk * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->V[s], nk * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->S[s], LMAX * sizeof(double)) != hipSuccess)
+            return bail(LRPR_ERR_NOMEM, "coarse factors");
+        if (hipMemcpyAsync(c->S[s], Sd + (size_t)LMAX * s, LMAX * sizeof(double), hipMemcpyDeviceToDevice, st) !=
+            hipSuccess)
+            return bail(LRPR_ERR_HIP, "copy S");
+    }
+    for (int s = 0; s < nslices; ++s)
+        rj[s] = RowMatJob{Q + off[s], c->n[s], Uh + SM * s, c->U[s], c->n[s], c->n[s], ls[s], slices[s].k, 0, 0};
+    if (upload(d_rj, rj, st) != hipSuccess || launch_rowmat(0, 0, d_rj, nslices, nmax, st) != hipSuccess)
+        return bail(LRPR_ERR_HIP, "U_k = Q Uh");
+    for (int s = 0; s < nslices; ++s)
+        rj[s] = RowMatJob{QZ + off[s], c->n[s], Vh + SM * s, c->V[s], c->n[s], c->n[s], ls[s], slices[s].k, 0, 0};
+    if (upload(d_rj, rj, st) != hipSuccess || launch_rowmat(0, 0, d_rj, nslices, nmax, st) != hipSuccess)
+        return bail(LRPR_ERR_HIP, "V_k = Qz Vh");
+    std::vector<SignJob> sj(nslices);
+    for (int s = 0; s < nslices; ++s) sj[s] = SignJob{c->U[s], c->V[s], c->n[s], slices[s].k, 0};
+    if (upload(d_sj, sj, st) != hipSuccess || launch_signfix(d_sj, nslices, kmax, st) != hipSuccess)
+        return bail(LRPR_ERR_HIP, "sign normalisation");
+    std::vector<double> hs((size_t)LMAX * nslices);
+    std::vector<int> hsw(nslices);
+    if (hipMemcpyAsync(hs.data(), Sd, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(hsw.data(), sweeps, nslices * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return bail(LRPR_ERR_HIP, "rsvd readback");
+    int pos = 0;
+    for (int s = 0; s < nslices; ++s) {
+        for (int j = 0; j < ls[s]; ++j) {
+            const double v = hs[(size_t)LMAX * s + j];
+            if (!std::isfinite(v)) return bail(LRPR_ERR_NONFINITE, "non-finite singular value");
+            c->sigma.push_back(v);
+            if (sigma_host) sigma_host[pos] = v;
+            ++pos;
+        }
+        if (hsw[s] < 0) return bail(LRPR_ERR_NONFINITE, "Jacobi SVD did not converge");
+    }
+    if (fallback_host)
+        for (int s = 0; s < nslices; ++s) fallback_host[s] = fallback[s];
+    *out = c;
+    return LRPR_OK;
+}
+
+lrpr_status lrpr_coarse_apply(lrpr_ctx ctx, lrpr_coarse c, int s, int w, const double *Vin, double *Out) {
+    if (!ctx) return LRPR_ERR_ARG;
+    if (!c || s < 0 || s >= c->nslices || w < 0 || (w > 0 && (!Vin || !Out)))
+        return fail(ctx, LRPR_ERR_ARG, "lrpr_coarse_apply: invalid arguments");
+    if (w == 0) return LRPR_OK;
+    CK(hipSetDevice(ctx->dev), "hipSetDevice");
+    hipError_t e;
+    const int64_t nch = lr_chunks(c->n[s]);
+    const int k = c->k[s];
+    double *part = (double *)ws_get(ctx, "lr_part", sizeof(double) * (size_t)nch * std::max(k, 1) *
+                                                         std::min(w, std::max(1, 12288 / std::max(k, 1))), &e);
+    if (!part) return herr(ctx, e, "workspace");
+    LrArgs a{};
+    a.U = c->U[s]; a.S = c->S[s]; a.V = c->V[s];
+    a.x = Vin; a.out = Out;
+    a.n = c->n[s]; a.k = k; a.w = w; a.mode = 0;
+    CK(lowrank_cols(a, part, nullptr, ctx->stream), "low-rank apply");
+    return LRPR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Parareal
+// ---------------------------------------------------------------------------
+lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, int nsteps, lrpr_prec fine_prec,
+                                int nreq, const double *u0, const double *f, const double *fscale, double tol,
+                                int max_iter, double *U, int *iters_host, double *incr_host, double *apost_host) {
+    if (!ctx) return LRPR_ERR_ARG;
+    if (!c || !F || nsteps < 1 || nreq < 1 || !u0 || !U || !iters_host || max_iter < 1 ||
+        (fine_prec != LRPR_F64 && fine_prec != LRPR_F32) || !(tol >= 0))
+        return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: invalid arguments");
+    const int N = c->nslices;
+    const int64_t n = c->n[0];
+    const bool f32 = fine_prec == LRPR_F32;
+    int kmax = 0;
+    for (int s = 0; s < N; ++s) {
+        if (!F[s] || F[s]->n != n || c->n[s] != n)
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: slices must share one size n");
+        if ((f32 && !(F[s]->mask & 2)) || (!f32 && !(F[s]->mask & 1)))
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: factor lacks the requested precision");
+        kmax = std::max(kmax, c->k[s]);
+    }
+    if (max_iter > N) max_iter = N;
+    CK(hipSetDevice(ctx->dev), "hipSetDevice");
+    hipStream_t st = ctx->stream;
+    const size_t blk = (size_t)n * nreq;           // one slice's n x nreq block
+    const size_t esz = f32 ? 4 : 8;
+    hipError_t e = hipSuccess;
+    auto W = [&](const char *key, size_t bytes) { return ws_get(ctx, key, bytes, &e); };
+    double *Ucur = (double *)W("pr_u", sizeof(double) * blk * (N + 1));
+    double *Gold = (double *)W("pr_gold", sizeof(double) * blk * N);
+    double *Bv = (double *)W("pr_b", sizeof(double) * blk * N);
+    void *X = W("pr_x", esz * blk * N);
+    void *fsrc = f ? W("pr_f", esz * blk) : nullptr;
+    int *fcol = (int *)W("pr_fcol", sizeof(int) * (size_t)N * nreq);
+    double *fsc = (double *)W("pr_fsc", sizeof(double) * (size_t)N * nreq * nsteps);
+    const int64_t nch = lr_chunks(n);
+    double *part = (double *)W("pr_part", sizeof(double) * (size_t)nch * std::max(kmax, 1) * nreq);
+    double *incpart = (double *)W("pr_incpart", sizeof(double) * (size_t)nch * nreq);
+    double *inc2 = (double *)W("pr_inc2", sizeof(double) * (size_t)N * nreq);
+    int *active = (int *)W("pr_active", sizeof(int) * nreq);
+    if (e != hipSuccess || !Ucur || !Gold || !Bv || !X || !fcol || !fsc || !part || !incpart || !inc2 || !active)
+        return herr(ctx, e == hipSuccess ? hipErrorOutOfMemory : e, "parareal workspace");
+    if ((size_t)kmax * nreq > 12288) return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: k * nreq above 12288");
+
+    // per-column source index and time factors: column (slice s, request r)
+    std::vector<int> hfcol((size_t)N * nreq);
+    std::vector<double> hfsc((size_t)N * nreq * nsteps, 1.0);
+    std::vector<double> hphi;
+    if (fscale) {
+        hphi.resize((size_t)N * nsteps);
+        CK(hipMemcpyAsync(hphi.data(), fscale, sizeof(double) * hphi.size(), hipMemcpyDeviceToHost, st), "fscale");
+        CK(hipStreamSynchronize(st), "sync");
+    }
+    for (int s = 0; s < N; ++s)
+        for (int q = 0; q < nreq; ++q) {
+            hfcol[(size_t)s * nreq + q] = q;
+            if (fscale)
+                for (int j = 0; j < nsteps; ++j) hfsc[((size_t)s * nreq + q) * nsteps + j] = hphi[(size_t)s * nsteps + j];
+        }
+    CK(upload(fcol, hfcol, st), "fcol");
+    CK(upload(fsc, hfsc, st), "fscale");
+    if (f) CK(launch_convert(0, f32 ? 1 : 0, f, fsrc, (int64_t)blk, st), "source copy");
+    std::vector<int> hact(nreq, 1);
+    CK(upload(active, hact, st), "active");
+    // panels: consecutive slices with the same factor share one panel
+    std::vector<lrpr_panel> P;
+    for (int s = 0; s < N; ++s) {
+        if (!P.empty() && P.back().F == F[s]) {
+            P.back().w += nreq;
+            continue;
+        }
+        lrpr_panel p{};
+        p.F = F[s];
+        p.X = (char *)X + (size_t)s * blk * esz;
+        p.ldx = n;
+        p.w = nreq;
+        p.f = fsrc;
+        p.ldf = n;
+        p.fcol = fsrc ? fcol + (size_t)s * nreq : nullptr;
+        p.fscale = fsrc ? fsc + (size_t)s * nreq * nsteps : nullptr;
+        P.push_back(p);
+    }
+    // b_n = F_n 0
+    if (f32) CK(launch_fillf((float *)X, (int64_t)blk * N, 0.0f, st), "zero");
+    else CK(launch_fill((double *)X, (int64_t)blk * N, 0.0, st), "zero");
+    lrpr_status r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, fine_prec, false);
+    if (r != LRPR_OK) return r;
+    CK(launch_convert(f32 ? 1 : 0, 0, X, Bv, (int64_t)blk * N, st), "b_n");
+    // u^0: u^0_0 = u0, u^0_n = G_n' u^0_{n-1} + b_n
+    CK(hipMemcpyAsync(Ucur, u0, sizeof(double) * blk, hipMemcpyDeviceToDevice, st), "u0");
+    for (int s = 0; s < N; ++s) {
+        LrArgs a{};
+        a.U = c->U[s]; a.S = c->S[s]; a.V = c->V[s];
+        a.x = Ucur + (size_t)s * blk;
+        a.out = Ucur + (size_t)(s + 1) * blk;
+        a.gold = Gold + (size_t)s * blk;
+        a.bvec = Bv + (size_t)s * blk;
+        a.active = active;
+        a.n = n; a.k = c->k[s]; a.w = nreq; a.mode = 1;
+        CK(lowrank_cols(a, part, nullptr, st), "coarse init");
+    }
+    std::vector<int> iters(nreq, 0);
+    std::vector<double> incr((size_t)nreq * max_iter, 0.0);
+    std::vector<double> last_inc((size_t)N * nreq, 0.0), hinc((size_t)N * nreq);
+    std::vector<int> conv(nreq, 0);
+    int nactive = nreq;
+    for (int k = 0; k < max_iter && nactive > 0; ++k) {
+        // fine solves of all slices from u^k_{n-1}, one batched launch
+        CK(launch_convert(0, f32 ? 1 : 0, Ucur, X, (int64_t)blk * N, st), "u -> X");
+        r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, fine_prec, false);
+        if (r != LRPR_OK) return r;
+        // sequential correction sweep
+        for (int s = 0; s < N; ++s) {
+            LrArgs a{};
+            a.U = c->U[s]; a.S = c->S[s]; a.V = c->V[s];
+            a.x = Ucur + (size_t)s * blk;
+            a.out = Ucur + (size_t)(s + 1) * blk;
+            a.gold = Gold + (size_t)s * blk;
+            if (f32) a.fu32 = (const float *)X + (size_t)s * blk;
+            else a.fu64 = (const double *)X + (size_t)s * blk;
+            a.active = active;
+            a.n = n; a.k = c->k[s]; a.w = nreq; a.mode = 2;
+            CK(lowrank_cols(a, part, incpart, st), "correction");
+            CK(launch_inc_reduce(incpart, nch, nreq, inc2 + (size_t)s * nreq, st), "increment");
+        }
+        CK(hipMemcpyAsync(hinc.data(), inc2, sizeof(double) * hinc.size(), hipMemcpyDeviceToHost, st), "inc");
+        CK(hipStreamSynchronize(st), "sync");
+        bool changed = false;
+        for (int q = 0; q < nreq; ++q) {
+            if (!hact[q]) continue;
+            double mx = 0.0;
+            for (int s = 0; s < N; ++s) {
+                const double v = hinc[(size_t)s * nreq + q];
+                last_inc[(size_t)s * nreq + q] = std::sqrt(v);
+                mx = std::max(mx, v);
+            }
+            const double inc = std::sqrt(mx);
+            if (!std::isfinite(inc)) return fail(ctx, LRPR_ERR_NONFINITE, "non-finite Parareal increment");
+            incr[(size_t)q * max_iter + k] = inc;
+            iters[q] = k + 1;
+            if (inc < tol || k + 1 >= N) {
+                conv[q] = 1;
+                hact[q] = 0;
+                --nactive;
+                changed = true;
+            }
+        }
+        if (changed && nactive > 0) {
+            CK(upload(active, hact, st), "active");
+        }
+    }
+    // output layout: request q -> n x (N+1) block
+    for (int q = 0; q < nreq; ++q)
+        CK(hipMemcpy2DAsync(U + (size_t)q * n * (N + 1), sizeof(double) * n, Ucur + (size_t)q * n,
+                            sizeof(double) * blk, sizeof(double) * n, N + 1, hipMemcpyDeviceToDevice, st),
+           "output");
+    // a posteriori bound (eq. apost_bound) with delta = max sigma_1, eps = max sigma_{k+1}
+    double delta = 0.0, eps = 0.0;
+    bool have_eps = true;
+    {
+        size_t pos = 0;
+        for (int s = 0; s < N; ++s) {
+            delta = std::max(delta, c->sigma[pos]);
+            if (c->l[s] > c->k[s]) eps = std::max(eps, c->sigma[pos + c->k[s]]);
+            else have_eps = false;
+            pos += c->l[s];
+        }
+    }
+    for (int q = 0; q < nreq; ++q) {
+        iters_host[q] = iters[q];
+        if (incr_host)
+            for (int k = 0; k < max_iter; ++k) incr_host[(size_t)q * max_iter + k] = incr[(size_t)q * max_iter + k];
+        if (apost_host) {
+            for (int nn = 1; nn <= N; ++nn) {
+                double sum = 0.0;
+                for (int m = 1; m < nn; ++m) sum += std::pow(delta, nn - m - 1) * last_inc[(size_t)(m - 1) * nreq + q];
+                apost_host[(size_t)q * N + nn - 1] = have_eps ? eps * sum : NAN;
+            }
+        }
+    }
+    CK(hipStreamSynchronize(st), "sync");
+    for (int q = 0; q < nreq; ++q)
+        if (!conv[q]) return fail(ctx, LRPR_ERR_NOCONV, "Parareal did not reach tol within max_iter");
+    return LRPR_OK;
+}
+
+}  // extern "C"
+
+namespace lrpr {
+
+void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err) {
+    auto &slot = ctx->ws[key];
+    if (slot.second >= bytes && slot.first) return slot.first;
+    if (slot.first) {
+        hipStreamSynchronize(ctx->stream);
+        hipFree(slot.first);
+        slot = {nullptr, 0};
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        if (err) *err = e;
+        return nullptr;
+    }
+    slot = {p, bytes};
+    return p;
+}
+
+}  // namespace lrpr

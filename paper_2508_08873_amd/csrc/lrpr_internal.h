@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "lrpr.h"
@@ -90,6 +92,8 @@ struct lrpr_ctx_s {
     // scratch for sweep work-item arrays
     lrpr::SweepItem *d_items = nullptr;
     size_t items_cap = 0;
+    // device workspaces cached by purpose (grown on demand, freed on destroy)
+    std::map<std::string, std::pair<void *, size_t>> ws;
 };
 
 namespace lrpr {

@@ -249,6 +249,22 @@ class Coarse:
             pass
 
 
+class _DevArray:
+    """Exposes a library-owned device array through __cuda_array_interface__."""
+
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr), False),
+                                         "version": 2, "strides": None}
+
+
+def device_view(ptr, n, k, dtype=torch.float64):
+    """Column-major n x k device array at ptr (library-owned), as a torch
+    tensor view (no copy; valid while the owning handle lives)."""
+    ts = {torch.float64: "<f8", torch.float32: "<f4"}[dtype]
+    t = torch.as_tensor(_DevArray(ptr, (k, n), ts), device="cuda")
+    return t.t()
+
+
 def colmajor(t):
     """Column-major (Fortran-order) copy of a 2-D tensor: element (i, c) at i + c*n."""
     return t.t().contiguous().t()
