@@ -82,6 +82,19 @@ lrpr_status lrpr_ctx_set_stream(lrpr_ctx ctx, void *hip_stream);
 /* Message of the last failing call on ctx (static storage owned by ctx). */
 const char *lrpr_last_error(lrpr_ctx ctx);
 
+/* Sweep timing.  While enabled, every fine/adjoint sweep launch queued by
+ * this context is bracketed by HIP events on the context's stream, and its
+ * algorithmic work is recorded: 4*n*b flops per right-hand-side step, and
+ * 2*n*s bytes per right-hand-side step (state in and out) plus n*(2b+1)*s
+ * bytes per step for each factor read (s = 8 or 4 bytes per value). */
+lrpr_status lrpr_profile_enable(lrpr_ctx ctx, int enable);
+/* Synchronises the stream and returns, for the launches recorded since the
+ * last read: total kernel time in ms, number of launches, algorithmic flops
+ * and bytes, and right-hand-side steps; then clears the record.  Any output
+ * pointer may be NULL. */
+lrpr_status lrpr_profile_read(lrpr_ctx ctx, double *ms, int64_t *launches, double *flops, double *bytes,
+                              double *rhs_steps);
+
 /* ---- factor (a1, a2) ---------------------------------------------------- */
 
 /* Assemble M = I + dt*A on the device and factor it M = L U by banded

@@ -68,22 +68,30 @@ const char *lrpr_last_error(lrpr_ctx ctx) { return ctx ? ctx->err.c_str() : "nul
 
 // ---------------------------------------------------------------------------
 static void free_tiles(TileSet &t) {
-    void *ps[6] = {t.Lb, t.Ub, t.DL, t.DU, t.DLT, t.DUT};
-    for (void *p : ps)
+    for (void *p : t.alloc)
         if (p) hipFree(p);
+    if (t.zt) hipFree(t.zt);
+    if (t.sink) hipFree(t.sink);
     t = TileSet();
 }
 
+// Tile arrays with guard_rows(nb) zero tile rows on both sides; the TileSet
+// pointers address tile row 0.
 static hipError_t alloc_tiles(TileSet &t, int NT, int nb, size_t esz) {
-    const size_t band = (size_t)NT * nb * TILE_ELEMS * esz;
-    const size_t diag = (size_t)NT * TILE_ELEMS * esz;
+    const size_t G = (size_t)guard_rows(nb);
+    const size_t rows = (size_t)NT + 2 * G;
+    const size_t per_row[10] = {(size_t)nb, (size_t)nb, 1, 1, 1, 1, 1, 1, 1, 1};
+    void **dst[10] = {&t.Lb, &t.Ub, &t.DL, &t.DU, &t.DLT, &t.DUT, &t.EL, &t.EU, &t.ELT, &t.EUT};
     hipError_t e;
-    if ((e = hipMalloc(&t.Lb, band ? band : esz)) != hipSuccess) return e;
-    if ((e = hipMalloc(&t.Ub, band ? band : esz)) != hipSuccess) return e;
-    if ((e = hipMalloc(&t.DL, diag)) != hipSuccess) return e;
-    if ((e = hipMalloc(&t.DU, diag)) != hipSuccess) return e;
-    if ((e = hipMalloc(&t.DLT, diag)) != hipSuccess) return e;
-    if ((e = hipMalloc(&t.DUT, diag)) != hipSuccess) return e;
+    for (int a = 0; a < 10; ++a) {
+        const size_t bytes = rows * per_row[a] * TILE_ELEMS * esz;
+        if ((e = hipMalloc(&t.alloc[a], bytes)) != hipSuccess) return e;
+        if ((e = hipMemset(t.alloc[a], 0, bytes)) != hipSuccess) return e;
+        *dst[a] = (char *)t.alloc[a] + G * per_row[a] * TILE_ELEMS * esz;
+    }
+    if ((e = hipMalloc(&t.zt, TILE_ELEMS * esz)) != hipSuccess) return e;
+    if ((e = hipMemset(t.zt, 0, TILE_ELEMS * esz)) != hipSuccess) return e;
+    if ((e = hipMalloc(&t.sink, TILE_ELEMS * esz)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -154,11 +162,17 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
         if (alloc_tiles(f->t32, f->NT, f->nb, sizeof(float)) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP32 tile allocation");
     }
+    double *inv_scratch = nullptr;
+    if ((e = hipMalloc(&inv_scratch, sizeof(double) * 2 * (size_t)f->NT * TILE_ELEMS)) != hipSuccess)
+        return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: scratch allocation");
     if ((e = launch_pack_tiles(n, bw, f->NT, f->nb, band, (store_mask & 1) ? &f->t64 : nullptr,
-                               (store_mask & 2) ? &f->t32 : nullptr, ctx->stream)) != hipSuccess)
+                               (store_mask & 2) ? &f->t32 : nullptr, inv_scratch, ctx->stream)) != hipSuccess) {
+        hipFree(inv_scratch);
         return cleanup(LRPR_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
-    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
-        return cleanup(LRPR_ERR_HIP, std::string("factor: ") + hipGetErrorString(e));
+    }
+    e = hipStreamSynchronize(ctx->stream);
+    hipFree(inv_scratch);
+    if (e != hipSuccess) return cleanup(LRPR_ERR_HIP, std::string("factor: ") + hipGetErrorString(e));
     hipFree(d_info);
     d_info = nullptr;
     if (store_mask & 1) {
@@ -200,7 +214,8 @@ namespace lrpr {
 FacView fac_view(lrpr_fac f, bool f32) {
     const TileSet &t = f32 ? f->t32 : f->t64;
     FacView v;
-    v.Lb = t.Lb; v.Ub = t.Ub; v.DL = t.DL; v.DU = t.DU; v.DLT = t.DLT; v.DUT = t.DUT;
+    v.Lb = t.Lb; v.Ub = t.Ub; v.DL = t.DL; v.DU = t.DU; v.DLT = t.DLT; v.DUT = t.DUT; v.zt = t.zt; v.sink = t.sink;
+    v.EL = t.EL; v.EU = t.EU; v.ELT = t.ELT; v.EUT = t.EUT;
     v.n = (int)f->n;
     v.NT = f->NT;
     v.nb = f->nb;
@@ -266,8 +281,35 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
     e = hipMemcpyAsync(ctx->d_items, items.data(), items.size() * sizeof(SweepItem),
                        hipMemcpyHostToDevice, ctx->stream);
     if (e != hipSuccess) return hipfail(ctx, e, "sweep item upload");
+    lrpr_ctx_s::ProfRec rec{};
+    if (ctx->prof) {
+        // algorithmic work: 4 n b flops and 2 n s bytes per RHS step, plus one
+        // read of each distinct factor per step
+        const double s = f32 ? 4.0 : 8.0;
+        std::vector<lrpr_fac> seen;
+        for (int p = 0; p < npanels; ++p) {
+            const lrpr_panel &P = panels[p];
+            const double n = (double)P.F->n, b = (double)P.F->bw;
+            rec.flops += 4.0 * n * b * P.w * nsteps;
+            rec.bytes += 2.0 * n * s * P.w * nsteps;
+            rec.rhs_steps += (double)P.w * nsteps;
+            bool dup = false;
+            for (lrpr_fac q : seen) dup = dup || q == P.F;
+            if (!dup) {
+                seen.push_back(P.F);
+                rec.bytes += n * (2.0 * b + 1.0) * s * nsteps;
+            }
+        }
+        if ((e = hipEventCreate(&rec.a)) != hipSuccess || (e = hipEventCreate(&rec.b)) != hipSuccess ||
+            (e = hipEventRecord(rec.a, ctx->stream)) != hipSuccess)
+            return hipfail(ctx, e, "profile event");
+    }
     e = launch_sweep(adjoint, f32, (int)items.size(), ctx->d_items, nsteps, max_nb, ctx->stream);
     if (e != hipSuccess) return hipfail(ctx, e, "sweep launch");
+    if (ctx->prof) {
+        if ((e = hipEventRecord(rec.b, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "profile event");
+        ctx->prof_recs.push_back(rec);
+    }
     return LRPR_OK;
 }
 
@@ -278,6 +320,36 @@ extern "C" {
 lrpr_status lrpr_fine_step_batched(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps,
                                    lrpr_prec prec) {
     return run_sweep(ctx, npanels, panels, nsteps, prec, false);
+}
+
+lrpr_status lrpr_profile_enable(lrpr_ctx ctx, int enable) {
+    if (!ctx) return LRPR_ERR_ARG;
+    ctx->prof = enable != 0;
+    return LRPR_OK;
+}
+
+lrpr_status lrpr_profile_read(lrpr_ctx ctx, double *ms, int64_t *launches, double *flops, double *bytes,
+                              double *rhs_steps) {
+    if (!ctx) return LRPR_ERR_ARG;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hipfail(ctx, e, "profile sync");
+    double tms = 0, fl = 0, by = 0, rs = 0;
+    for (auto &r : ctx->prof_recs) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) tms += t;
+        fl += r.flops;
+        by += r.bytes;
+        rs += r.rhs_steps;
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    if (ms) *ms = tms;
+    if (launches) *launches = (int64_t)ctx->prof_recs.size();
+    if (flops) *flops = fl;
+    if (bytes) *bytes = by;
+    if (rhs_steps) *rhs_steps = rs;
+    ctx->prof_recs.clear();
+    return LRPR_OK;
 }
 
 lrpr_status lrpr_adjoint_step_batched(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps,

@@ -143,10 +143,9 @@ __device__ inline int dslot(bool f32, int m, int k) {
     return (k & 3) * 64 + m + 16 * (k >> 2);             // k = 4g + kc
 }
 
-// One thread per (tile row, column of the inverse): 16 threads per tile row.
-__global__ void k_pack_diag(int64_t n, int bw, int NT, const double *lu, double *DL64, double *DU64,
-                            double *DLT64, double *DUT64, float *DL32, float *DU32, float *DLT32,
-                            float *DUT32) {
+// Phase 1: FP64 inverses of the diagonal tiles, natural row-major 16x16 per
+// tile row (scratch).  One thread per (tile row, column of the inverse).
+__global__ void k_diag_inv(int64_t n, int bw, int NT, const double *lu, double *Linv, double *Uinv) {
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (tid >= (int64_t)NT * TILE) return;
     const int64_t I = tid / TILE;
@@ -166,26 +165,72 @@ __global__ void k_pack_diag(int64_t n, int bw, int NT, const double *lu, double 
         const double d = (base + r < n) ? lu_at(lu, n, bw, base + r, base + r) : 1.0;
         xu[r] = v / d;
     }
+    for (int r = 0; r < TILE; ++r) {
+        Linv[I * TILE_ELEMS + r * TILE + col] = xl[r];
+        Uinv[I * TILE_ELEMS + r * TILE + col] = xu[r];
+    }
+}
+
+// Phase 2: diagonal inverses D and the "newest-tile" products E of every
+// tile row, stored as MFMA A operands (dslot layout), FP64 and/or FP32.
+//   forward L pass (ascending):  D = L_II^{-1},      E[I] = L(I,I-1) L_{I-1,I-1}^{-1}
+//   forward U pass (descending): D = U_II^{-1},      E[I] = U(I,I+1) U_{I+1,I+1}^{-1}
+//   adjoint U^T pass (asc.):     D = U_II^{-T},      E[I] = U(I-1,I)^T U_{I-1,I-1}^{-T}
+//   adjoint L^T pass (desc.):    D = L_II^{-T},      E[I] = L(I+1,I)^T L_{I+1,I+1}^{-T}
+// so that the newest band tile's contribution to row I is E[I] applied to
+// the pre-inverse residual s of the neighbouring row (y = D s).
+// One thread per (tile row, column).
+struct DiagOut {
+    void *D[4];   // DL, DU, DLT, DUT
+    void *E[4];   // EL, EU, ELT, EUT
+};
+
+__global__ void k_pack_diag(int64_t n, int bw, int NT, const double *lu, const double *Linv,
+                            const double *Uinv, DiagOut o64, DiagOut o32) {
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (tid >= (int64_t)NT * TILE) return;
+    const int64_t I = tid / TILE;
+    const int col = (int)(tid % TILE);
+    const int64_t base = I * TILE;
+    const double *Li = Linv + I * TILE_ELEMS, *Ui = Uinv + I * TILE_ELEMS;
+    double e[4][TILE];
+    for (int r = 0; r < TILE; ++r) {
+        double el = 0, eu = 0, eut = 0, elt = 0;
+        for (int k = 0; k < TILE; ++k) {
+            if (I >= 1) {
+                // L(I, I-1)[r][k] * Linv_{I-1}[k][col]
+                el += lu_at(lu, n, bw, base + r, base - TILE + k) * Linv[(I - 1) * TILE_ELEMS + k * TILE + col];
+                // U(I-1, I)[k][r] * Uinv_{I-1}[col][k]
+                eut += lu_at(lu, n, bw, base - TILE + k, base + r) * Uinv[(I - 1) * TILE_ELEMS + col * TILE + k];
+            }
+            if (I + 1 < NT) {
+                // U(I, I+1)[r][k] * Uinv_{I+1}[k][col]
+                eu += lu_at(lu, n, bw, base + r, base + TILE + k) * Uinv[(I + 1) * TILE_ELEMS + k * TILE + col];
+                // L(I+1, I)[k][r] * Linv_{I+1}[col][k]
+                elt += lu_at(lu, n, bw, base + TILE + k, base + r) * Linv[(I + 1) * TILE_ELEMS + col * TILE + k];
+            }
+        }
+        e[0][r] = el; e[1][r] = eu; e[2][r] = elt; e[3][r] = eut;
+    }
     const int64_t off = I * TILE_ELEMS;
     for (int r = 0; r < TILE; ++r) {
-        // D[r][col] and its transpose DT[col][r]
-        if (DL64) {
-            DL64[off + dslot(false, r, col)] = xl[r];
-            DU64[off + dslot(false, r, col)] = xu[r];
-            DLT64[off + dslot(false, col, r)] = xl[r];
-            DUT64[off + dslot(false, col, r)] = xu[r];
-        }
-        if (DL32) {
-            DL32[off + dslot(true, r, col)] = (float)xl[r];
-            DU32[off + dslot(true, r, col)] = (float)xu[r];
-            DLT32[off + dslot(true, col, r)] = (float)xl[r];
-            DUT32[off + dslot(true, col, r)] = (float)xu[r];
+        // D entries (r, col) and transposes (col, r); E entries (r, col)
+        const double dv[4] = {Li[r * TILE + col], Ui[r * TILE + col], Li[col * TILE + r], Ui[col * TILE + r]};
+        for (int a = 0; a < 4; ++a) {
+            if (o64.D[a]) {
+                ((double *)o64.D[a])[off + dslot(false, r, col)] = dv[a];
+                ((double *)o64.E[a])[off + dslot(false, r, col)] = e[a][r];
+            }
+            if (o32.D[a]) {
+                ((float *)o32.D[a])[off + dslot(true, r, col)] = (float)dv[a];
+                ((float *)o32.E[a])[off + dslot(true, r, col)] = (float)e[a][r];
+            }
         }
     }
 }
 
 hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu, const TileSet *t64,
-                             const TileSet *t32, hipStream_t s) {
+                             const TileSet *t32, double *scratch, hipStream_t s) {
     const int64_t total = (int64_t)NT * nb * TILE_ELEMS;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
@@ -196,11 +241,20 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t th = (int64_t)NT * TILE;
-    hipLaunchKernelGGL(k_pack_diag, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, n, bw, NT, lu,
-                       t64 ? (double *)t64->DL : nullptr, t64 ? (double *)t64->DU : nullptr,
-                       t64 ? (double *)t64->DLT : nullptr, t64 ? (double *)t64->DUT : nullptr,
-                       t32 ? (float *)t32->DL : nullptr, t32 ? (float *)t32->DU : nullptr,
-                       t32 ? (float *)t32->DLT : nullptr, t32 ? (float *)t32->DUT : nullptr);
+    double *Linv = scratch, *Uinv = scratch + (size_t)NT * TILE_ELEMS;
+    hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, n, bw, NT, lu, Linv, Uinv);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    DiagOut o64{}, o32{};
+    if (t64) {
+        o64.D[0] = t64->DL; o64.D[1] = t64->DU; o64.D[2] = t64->DLT; o64.D[3] = t64->DUT;
+        o64.E[0] = t64->EL; o64.E[1] = t64->EU; o64.E[2] = t64->ELT; o64.E[3] = t64->EUT;
+    }
+    if (t32) {
+        o32.D[0] = t32->DL; o32.D[1] = t32->DU; o32.D[2] = t32->DLT; o32.D[3] = t32->DUT;
+        o32.E[0] = t32->EL; o32.E[1] = t32->EU; o32.E[2] = t32->ELT; o32.E[3] = t32->EUT;
+    }
+    hipLaunchKernelGGL(k_pack_diag, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, n, bw, NT, lu, Linv,
+                       Uinv, o64, o32);
     return hipGetLastError();
 }
 

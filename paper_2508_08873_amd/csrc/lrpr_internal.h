@@ -36,15 +36,23 @@ namespace lrpr {
 // ---------------------------------------------------------------------------
 constexpr int TILE = 16;
 constexpr int TILE_ELEMS = 256;
+// zero tile rows kept before and after every tile array (beyond the band and
+// the sweep's prefetch window, reads land on zeros)
+inline int guard_rows(int nb) { return nb + 8; }
 
-struct TileSet {            // device arrays of one precision
+struct TileSet {            // device arrays of one precision (pointers to tile row 0)
     void *Lb = nullptr, *Ub = nullptr;
     void *DL = nullptr, *DU = nullptr, *DLT = nullptr, *DUT = nullptr;
+    void *EL = nullptr, *EU = nullptr, *ELT = nullptr, *EUT = nullptr;
+    void *zt = nullptr;    // one all-zero tile: target of loads outside the band
+    void *sink = nullptr;  // one scratch tile: target of masked-off stores
+    void *alloc[10] = {};  // allocations behind Lb..EUT (they start guard rows earlier)
 };
 
 // Device-side view of one factor, passed by value to the sweep kernels.
 struct FacView {
-    const void *Lb, *Ub, *DL, *DU, *DLT, *DUT;
+    const void *Lb, *Ub, *DL, *DU, *DLT, *DUT, *EL, *EU, *ELT, *EUT, *zt;
+    void *sink;
     int n, NT, nb;
     double dt;
 };
@@ -92,6 +100,13 @@ struct lrpr_ctx_s {
     // scratch for sweep work-item arrays
     lrpr::SweepItem *d_items = nullptr;
     size_t items_cap = 0;
+    // sweep timing records (lrpr_profile_enable)
+    struct ProfRec {
+        hipEvent_t a, b;
+        double flops, bytes, rhs_steps;
+    };
+    bool prof = false;
+    std::vector<ProfRec> prof_recs;
     // device workspaces cached by purpose (grown on demand, freed on destroy)
     std::map<std::string, std::pair<void *, size_t>> ws;
 };
@@ -105,7 +120,7 @@ lrpr_status fail(lrpr_ctx ctx, lrpr_status st, const std::string &msg);
 hipError_t launch_assemble(const lrpr_op_desc &op, int64_t n, int bw, double *band, hipStream_t s);
 hipError_t launch_band_lu(int64_t n, int bw, double *band, int *info, hipStream_t s);
 hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu, const TileSet *t64,
-                             const TileSet *t32, hipStream_t s);
+                             const TileSet *t32, double *scratch, hipStream_t s);
 hipError_t launch_sweep(bool adjoint, bool f32, int nitems, const SweepItem *d_items, int nsteps,
                         int max_nb, hipStream_t s);
 

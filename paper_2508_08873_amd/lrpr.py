@@ -20,7 +20,8 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_ZERO_PIVOT", 4: "ERR_QR
 EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_last_error",
            "lrpr_factor", "lrpr_factor_destroy", "lrpr_factor_info", "lrpr_factor_copy_lu",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build",
-           "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_parareal_solve"]
+           "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_parareal_solve",
+           "lrpr_profile_enable", "lrpr_profile_read"]
 
 
 class LrprError(RuntimeError):
@@ -78,6 +79,8 @@ def load():
     lib.lrpr_coarse_get.argtypes = [vp, i32, P(vp), P(vp), P(vp), P(i32), P(i64)]
     lib.lrpr_coarse_apply.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.lrpr_parareal_solve.argtypes = [vp, vp, P(vp), i32, i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
+    lib.lrpr_profile_enable.argtypes = [vp, i32]
+    lib.lrpr_profile_read.argtypes = [vp, P(dbl), P(i64), P(dbl), P(dbl), P(dbl)]
     for name in EXPORTS:
         if name not in ("lrpr_ctx_destroy", "lrpr_factor_destroy", "lrpr_coarse_destroy", "lrpr_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -121,6 +124,17 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    # -- sweep timing -----------------------------------------------------
+    def profile(self, enable=True):
+        self._check(self.lib.lrpr_profile_enable(self.h, int(enable)))
+
+    def profile_read(self):
+        ms, fl, by, rs = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        nl = ctypes.c_int64()
+        self._check(self.lib.lrpr_profile_read(self.h, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(fl),
+                                               ctypes.byref(by), ctypes.byref(rs)))
+        return {"ms": ms.value, "launches": nl.value, "flops": fl.value, "bytes": by.value, "rhs_steps": rs.value}
 
     # -- factor -----------------------------------------------------------
     def factor(self, dim, nx, nu, beta, c, dt, store_mask=1):
