@@ -42,7 +42,22 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-cols", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calib(mib):
+    """Plain copy kernel of known size: reading FETCH_SIZE / WRITE_SIZE for it
+    gives the factor between the counters and the bytes actually moved."""
+    import torch
+    nel = mib * (1 << 20) // 8
+    src = torch.ones(nel, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calib_bytes_read": nel * 8, "copy_calib_bytes_written": nel * 8, "launches": 5}))
 
 
 def cpu_baseline_and_parity(ctx, lrpr, P, prec, ncols, nsteps, seed):
@@ -63,7 +78,7 @@ def cpu_baseline_and_parity(ctx, lrpr, P, prec, ncols, nsteps, seed):
     ref = op.fine(X0, nsteps, f, None, fsc)
     t1 = time.perf_counter()
     dt = torch.float64 if prec == "f64" else torch.float32
-    F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=1 if prec == "f64" else 3)
+    F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=(1 if prec == "f64" else 3) | 4)
     X = lrpr.colmajor(torch.from_numpy(X0).to("cuda", dt))
     spec = {"F": F, "X": X, "f": lrpr.colmajor(torch.from_numpy(f.reshape(-1, 1)).to("cuda", dt)),
             "fscale": torch.from_numpy(np.ascontiguousarray(fsc)).to("cuda")}
@@ -84,6 +99,9 @@ def main():
         print("bench.py measures one GPU only: the hot path runs on a single MI355X "
               "(multi-GPU sharding is described, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calib:
+        copy_calib(args.copy_calib)
+        return
     import torch
     from paper_2508_08873_amd import inputs, lrpr
 
@@ -104,7 +122,7 @@ def main():
 
     def one_step(times):
         ta = time.perf_counter()
-        F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=1 if prec == "f64" else 3)
+        F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=(1 if prec == "f64" else 3) | 4)
         tb = time.perf_counter()
         coarse = ctx.rsvd_build([(F, P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, fp)
         tc = time.perf_counter()

@@ -95,30 +95,38 @@ lrpr_status lrpr_profile_enable(lrpr_ctx ctx, int enable);
 lrpr_status lrpr_profile_read(lrpr_ctx ctx, double *ms, int64_t *launches, double *flops, double *bytes,
                               double *rhs_steps);
 
-/* ---- factor (a1, a2) ---------------------------------------------------- */
+/* ---- operator assembly and band LU (Sec. 4.4) --------------------------- */
+
+enum { LRPR_STORE_F64 = 1, LRPR_STORE_F32 = 2, LRPR_STORE_MIRROR = 4 };
 
 /* Assemble M = I + dt*A on the device and factor it M = L U by banded
  * Gaussian elimination without pivoting, in FP64 (the paper's fine solver
  * factors the backward-Euler matrix once and reuses it for all right-hand
  * sides, Sec. 4.4).  M is an M-matrix that is diagonally dominant by rows
  * and columns, so no pivoting is needed.  The factorisation is always FP64;
- * store_mask selects the copies kept for the solves: bit 0 (1) an FP64
- * copy (needed for LRPR_F64 solves), bit 1 (2) an FP32 copy rounded from
- * the FP64 factors (needed for LRPR_F32 solves); 0 means 1.  The FP64 band
- * LU itself is kept only with bit 0.  Errors: LRPR_ERR_ARG (bad
- * descriptor), LRPR_ERR_ZERO_PIVOT, LRPR_ERR_NOMEM.  Synchronises the
- * stream. */
+ * store_mask selects the copies kept for the solves (an OR of):
+ *   LRPR_STORE_F64 (1)    FP64 tiles (needed for LRPR_F64 solves) and the
+ *                         FP64 band LU;
+ *   LRPR_STORE_F32 (2)    FP32 tiles rounded from the FP64 factors (needed
+ *                         for LRPR_F32 solves);
+ *   LRPR_STORE_MIRROR (4) for each precision kept, also the band tiles of
+ *                         U^T and L^T, so adjoint sweeps read contiguous
+ *                         tiles (faster; doubles the band-tile memory,
+ *                         about 2 n (2b+1) bytes per byte of precision).
+ * 0 means LRPR_STORE_F64; at least one of F64/F32 must be set.  Errors:
+ * LRPR_ERR_ARG (bad descriptor or mask), LRPR_ERR_ZERO_PIVOT,
+ * LRPR_ERR_NOMEM.  Synchronises the stream. */
 lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lrpr_fac *out);
 void lrpr_factor_destroy(lrpr_fac f);
 /* n = unknowns, bw = half-bandwidth, dt = step. */
 lrpr_status lrpr_factor_info(lrpr_fac f, int64_t *n, int *bw, double *dt);
-/* Copy the FP64 band LU (kept when store_mask has bit 0) to host memory:
+/* Copy the FP64 band LU (kept with LRPR_STORE_F64) to host memory:
  * lu_host is n x (2*bw+1) row-major,
  * entry (i, j) of L (j < i, unit diagonal not stored) or U (j >= i) at
  * lu_host[i*(2*bw+1) + j - i + bw].  Synchronises. */
 lrpr_status lrpr_factor_copy_lu(lrpr_ctx ctx, lrpr_fac f, double *lu_host);
 
-/* ---- batched fine propagator (a3, a4, a5) ------------------------------- */
+/* ---- batched fine propagator and its adjoint (Sec. 2, Sec. 2.1) --------- */
 
 /* One panel: w right-hand sides that share the factor F.
  *   X      device, n x w, leading dimension ldx >= n, element type by prec
@@ -159,7 +167,7 @@ lrpr_status lrpr_fine_step_batched(lrpr_ctx ctx, int npanels, const lrpr_panel *
 lrpr_status lrpr_adjoint_step_batched(lrpr_ctx ctx, int npanels, const lrpr_panel *panels,
                                       int nsteps, lrpr_prec prec);
 
-/* ---- randomized SVD build (a6, a7) --------------------------------------- */
+/* ---- randomized SVD build (Sec. 2.1) ------------------------------------- */
 
 /* One Parareal slice for the coarse-solver build: its factor, truncation
  * rank k (R_n in the paper) and oversampling p, and its Gaussian test
@@ -204,7 +212,7 @@ lrpr_status lrpr_coarse_get(lrpr_coarse c, int s, const double **U, const double
 lrpr_status lrpr_coarse_apply(lrpr_ctx ctx, lrpr_coarse c, int s, int w, const double *Vin,
                               double *Out);
 
-/* ---- Parareal (a8, a9) --------------------------------------------------- */
+/* ---- Parareal with the low-rank coarse propagator (Sec. 2) -------------- */
 
 /* Parareal with the low-rank coarse solvers of c (Sec. 2, eq.
  * def_Parareal) for nreq independent problems that share the slices'

@@ -76,18 +76,19 @@ static void free_tiles(TileSet &t) {
 }
 
 // Tile arrays with guard_rows(nb) zero tile rows on both sides; the TileSet
-// pointers address tile row 0.
-static hipError_t alloc_tiles(TileSet &t, int NT, int nb, size_t esz) {
+// pointers address tile row 0.  The mirrored band arrays only with `mirror`.
+static hipError_t alloc_tiles(TileSet &t, int NT, int nb, size_t esz, bool mirror) {
     const size_t G = (size_t)guard_rows(nb);
     const size_t rows = (size_t)NT + 2 * G;
-    const size_t per_row[10] = {(size_t)nb, (size_t)nb, 1, 1, 1, 1, 1, 1, 1, 1};
-    void **dst[10] = {&t.Lb, &t.Ub, &t.DL, &t.DU, &t.DLT, &t.DUT, &t.EL, &t.EU, &t.ELT, &t.EUT};
     hipError_t e;
-    for (int a = 0; a < 10; ++a) {
-        const size_t bytes = rows * per_row[a] * TILE_ELEMS * esz;
+    for (int a = 0; a < TS_COUNT; ++a) {
+        const bool band = a == TS_LB || a == TS_UB || a == TS_UTB || a == TS_LTB;
+        if (!mirror && (a == TS_UTB || a == TS_LTB)) continue;
+        const size_t per_row = band ? (size_t)nb : 1;
+        const size_t bytes = rows * per_row * TILE_ELEMS * esz;
         if ((e = hipMalloc(&t.alloc[a], bytes)) != hipSuccess) return e;
         if ((e = hipMemset(t.alloc[a], 0, bytes)) != hipSuccess) return e;
-        *dst[a] = (char *)t.alloc[a] + G * per_row[a] * TILE_ELEMS * esz;
+        t.a[a] = (char *)t.alloc[a] + G * per_row * TILE_ELEMS * esz;
     }
     if ((e = hipMalloc(&t.zt, TILE_ELEMS * esz)) != hipSuccess) return e;
     if ((e = hipMemset(t.zt, 0, TILE_ELEMS * esz)) != hipSuccess) return e;
@@ -110,8 +111,11 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
     if ((op->dim != 1 && op->dim != 2) || op->nx < 1 || !(op->nu > 0) || !(op->dt > 0) ||
         !(op->c >= 0) || !std::isfinite(op->beta1) || !std::isfinite(op->beta2))
         return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: invalid operator descriptor");
-    if (store_mask == 0) store_mask = 1;
-    if (store_mask & ~3) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: store_mask must be 1, 2 or 3");
+    if (store_mask == 0) store_mask = LRPR_STORE_F64;
+    if ((store_mask & ~(LRPR_STORE_F64 | LRPR_STORE_F32 | LRPR_STORE_MIRROR)) ||
+        !(store_mask & (LRPR_STORE_F64 | LRPR_STORE_F32)))
+        return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: store_mask must hold F64 and/or F32 (and optionally MIRROR)");
+    const bool mirror = (store_mask & LRPR_STORE_MIRROR) != 0;
     const int64_t n = op->dim == 1 ? op->nx : (int64_t)op->nx * op->nx;
     const int bw = op->dim == 1 ? 1 : op->nx;
     if (n >= (int64_t)1 << 31) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: n too large");
@@ -154,19 +158,20 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
         snprintf(msg, sizeof msg, "lrpr_factor: zero or non-finite pivot at row %d", info - 1);
         return cleanup(LRPR_ERR_ZERO_PIVOT, msg);
     }
-    if (store_mask & 1) {
-        if (alloc_tiles(f->t64, f->NT, f->nb, sizeof(double)) != hipSuccess)
+    if (store_mask & LRPR_STORE_F64) {
+        if (alloc_tiles(f->t64, f->NT, f->nb, sizeof(double), mirror) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP64 tile allocation");
     }
-    if (store_mask & 2) {
-        if (alloc_tiles(f->t32, f->NT, f->nb, sizeof(float)) != hipSuccess)
+    if (store_mask & LRPR_STORE_F32) {
+        if (alloc_tiles(f->t32, f->NT, f->nb, sizeof(float), mirror) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP32 tile allocation");
     }
     double *inv_scratch = nullptr;
     if ((e = hipMalloc(&inv_scratch, sizeof(double) * 2 * (size_t)f->NT * TILE_ELEMS)) != hipSuccess)
         return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: scratch allocation");
-    if ((e = launch_pack_tiles(n, bw, f->NT, f->nb, band, (store_mask & 1) ? &f->t64 : nullptr,
-                               (store_mask & 2) ? &f->t32 : nullptr, inv_scratch, ctx->stream)) != hipSuccess) {
+    if ((e = launch_pack_tiles(n, bw, f->NT, f->nb, band, (store_mask & LRPR_STORE_F64) ? &f->t64 : nullptr,
+                               (store_mask & LRPR_STORE_F32) ? &f->t32 : nullptr, inv_scratch, ctx->stream)) !=
+        hipSuccess) {
         hipFree(inv_scratch);
         return cleanup(LRPR_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
     }
@@ -175,7 +180,7 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
     if (e != hipSuccess) return cleanup(LRPR_ERR_HIP, std::string("factor: ") + hipGetErrorString(e));
     hipFree(d_info);
     d_info = nullptr;
-    if (store_mask & 1) {
+    if (store_mask & LRPR_STORE_F64) {
         f->lu = band;
     } else {
         hipFree(band);
@@ -214,8 +219,9 @@ namespace lrpr {
 FacView fac_view(lrpr_fac f, bool f32) {
     const TileSet &t = f32 ? f->t32 : f->t64;
     FacView v;
-    v.Lb = t.Lb; v.Ub = t.Ub; v.DL = t.DL; v.DU = t.DU; v.DLT = t.DLT; v.DUT = t.DUT; v.zt = t.zt; v.sink = t.sink;
-    v.EL = t.EL; v.EU = t.EU; v.ELT = t.ELT; v.EUT = t.EUT;
+    for (int a = 0; a < TS_COUNT; ++a) v.a[a] = t.a[a];
+    v.zt = t.zt;
+    v.sink = t.sink;
     v.n = (int)f->n;
     v.NT = f->NT;
     v.nb = f->nb;
@@ -248,15 +254,17 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
     const bool f32 = prec == LRPR_F32;
     std::vector<SweepItem> items;
     int max_nb = 1;
+    bool strided = false;   // adjoint: some factor has no mirrored set
     for (int p = 0; p < npanels; ++p) {
         const lrpr_panel &P = panels[p];
         if (!P.F || (P.w > 0 && !P.X) || P.w < 0 || P.ldx < P.F->n)
             return fail(ctx, LRPR_ERR_ARG, "sweep: panel with null factor/X or ldx < n");
         if (P.F->dev != ctx->dev) return fail(ctx, LRPR_ERR_ARG, "sweep: factor on another device");
-        if ((f32 && !(P.F->mask & 2)) || (!f32 && !(P.F->mask & 1)))
+        if ((f32 && !(P.F->mask & LRPR_STORE_F32)) || (!f32 && !(P.F->mask & LRPR_STORE_F64)))
             return fail(ctx, LRPR_ERR_ARG, "sweep: factor has no copy in the requested precision");
         if (!adjoint && P.f && P.ldf < P.F->n) return fail(ctx, LRPR_ERR_ARG, "sweep: ldf < n");
         if (P.F->nb > max_nb) max_nb = P.F->nb;
+        if (P.w > 0 && !(P.F->mask & LRPR_STORE_MIRROR)) strided = true;
         const size_t esz = f32 ? sizeof(float) : sizeof(double);
         for (int c0 = 0; c0 < P.w; c0 += TILE) {
             SweepItem it;
@@ -304,7 +312,7 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
             (e = hipEventRecord(rec.a, ctx->stream)) != hipSuccess)
             return hipfail(ctx, e, "profile event");
     }
-    e = launch_sweep(adjoint, f32, (int)items.size(), ctx->d_items, nsteps, max_nb, ctx->stream);
+    e = launch_sweep(adjoint, strided, f32, (int)items.size(), ctx->d_items, nsteps, max_nb, ctx->stream);
     if (e != hipSuccess) return hipfail(ctx, e, "sweep launch");
     if (ctx->prof) {
         if ((e = hipEventRecord(rec.b, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "profile event");

@@ -132,7 +132,7 @@ lrpr_status lrpr_rsvd_build(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *sl
         const int l = d.k + d.p;
         if (!d.F || !d.Omega || d.k < 0 || d.p < 0 || l < 1 || l > LMAX || l > d.F->n)
             return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: slice needs factor, Omega, 1 <= k+p <= min(96, n)");
-        if (!(d.F->mask & 1) || (f32 && !(d.F->mask & 2)))
+        if (!(d.F->mask & LRPR_STORE_F64) || (f32 && !(d.F->mask & LRPR_STORE_F32)))
             return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: factor lacks the FP64 (and, for FP32, FP32) copy");
         if (d.F->dev != ctx->dev) return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: factor on another device");
         lmax = std::max(lmax, l);
@@ -381,7 +381,7 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
     for (int s = 0; s < N; ++s) {
         if (!F[s] || F[s]->n != n || c->n[s] != n)
             return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: slices must share one size n");
-        if ((f32 && !(F[s]->mask & 2)) || (!f32 && !(F[s]->mask & 1)))
+        if ((f32 && !(F[s]->mask & LRPR_STORE_F32)) || (!f32 && !(F[s]->mask & LRPR_STORE_F64)))
             return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: factor lacks the requested precision");
         kmax = std::max(kmax, c->k[s]);
     }

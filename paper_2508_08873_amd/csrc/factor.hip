@@ -100,11 +100,12 @@ hipError_t launch_band_lu(int64_t n, int bw, double *band, int *info, hipStream_
 }
 
 // ---------------------------------------------------------------------------
-// Packing.  Band tiles in the 4x4 sub-block layout; diagonal tiles inverted
-// (FP64) and stored as MFMA A operands in "chunk kc of lane l at kc*64 + l"
-// order.  For the f64 MFMA the contraction index of (lane l, chunk kc) is
-// 4*kc + l/16; for f32 it is 4*(l/16) + kc, matching how the accumulator
-// registers of the previous product are consumed as B operands.
+// Packing into the lane-major MFMA A-operand layout of every tile: the value
+// lane l feeds as chunk kc is T[m][k] with m = l%16 and the contraction index
+// k = 4 kc + l/16 (FP64) or 4 (l/16) + kc (FP32), the row that register kc
+// of an accumulator holds.  Position of (l, kc): FP32 4 l + kc (one 16-byte
+// load per lane), FP64 128 (kc/2) + 2 l + kc%2 (two 16-byte loads, each a
+// contiguous 1 KiB across the wave).
 // ---------------------------------------------------------------------------
 __device__ inline double lu_at(const double *lu, int64_t n, int bw, int64_t i, int64_t j) {
     if (i < 0 || j < 0 || i >= n || j >= n) return 0.0;
@@ -113,8 +114,23 @@ __device__ inline double lu_at(const double *lu, int64_t n, int bw, int64_t i, i
     return lu[i * (2 * bw + 1) + d + bw];
 }
 
-__global__ void k_pack_band(int64_t n, int bw, int NT, int nb, const double *lu, double *L64,
-                            double *U64, float *L32, float *U32) {
+// position of element (row m, contraction k) of an A-operand tile
+__device__ inline int aslot(bool f32, int m, int k) {
+    if (f32) return 4 * (16 * (k >> 2) + m) + (k & 3);                 // g = k/4, kc = k%4
+    const int kc = k >> 2, l = 16 * (k & 3) + m;                       // g = k%4, kc = k/4
+    return 128 * (kc >> 1) + 2 * l + (kc & 1);
+}
+
+// One thread per element (tile row I, band index j, row r, column q) of the
+// band tiles; writes the FP64 and/or FP32 copies of
+//   Lb[I][j] = L(I, I-nb+j), Ub[I][j] = U(I, I+1+j)
+// and, when requested, the mirrored set
+//   UTb[I][j] = U(I-nb+j, I)^T, LTb[I][j] = L(I+1+j, I)^T.
+struct BandOut {
+    void *b[4];   // Lb, Ub, UTb, LTb (null: not stored)
+};
+
+__global__ void k_pack_band(int64_t n, int bw, int NT, int nb, const double *lu, BandOut o64, BandOut o32) {
     const int64_t total = (int64_t)NT * nb * TILE_ELEMS;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -122,25 +138,21 @@ __global__ void k_pack_band(int64_t n, int bw, int NT, int nb, const double *lu,
         const int o = (int)(e % TILE_ELEMS);
         const int64_t I = tileidx / nb;
         const int j = (int)(tileidx % nb);
-        const int sb = o >> 4, wi = o & 15;
-        const int r = (sb & 3) * 4 + (wi >> 2);
-        const int cc = (sb >> 2) * 4 + (wi & 3);
+        const int r = o >> 4, q = o & 15;
         const int64_t i = I * TILE + r;
-        // L(I, I-nb+j): strictly lower part only
-        const int64_t ql = (I - nb + j) * TILE + cc;
-        double lv = (ql < i) ? lu_at(lu, n, bw, i, ql) : 0.0;
-        // U(I, I+1+j)
-        const int64_t qu = (I + 1 + j) * TILE + cc;
-        double uv = (qu > i) ? lu_at(lu, n, bw, i, qu) : 0.0;
-        if (L64) { L64[e] = lv; U64[e] = uv; }
-        if (L32) { L32[e] = (float)lv; U32[e] = (float)uv; }
+        const int64_t jl = (I - nb + j) * TILE + q;   // column in tile row I-nb+j
+        const int64_t ju = (I + 1 + j) * TILE + q;    // column in tile row I+1+j
+        double v[4];
+        v[0] = (jl < i) ? lu_at(lu, n, bw, i, jl) : 0.0;   // L strictly lower
+        v[1] = (ju > i) ? lu_at(lu, n, bw, i, ju) : 0.0;   // U strictly upper
+        v[2] = (jl < i) ? lu_at(lu, n, bw, jl, i) : 0.0;   // U^T strictly lower
+        v[3] = (ju > i) ? lu_at(lu, n, bw, ju, i) : 0.0;   // L^T strictly upper
+        const int64_t base = tileidx * TILE_ELEMS;
+        for (int a = 0; a < 4; ++a) {
+            if (o64.b[a]) ((double *)o64.b[a])[base + aslot(false, r, q)] = v[a];
+            if (o32.b[a]) ((float *)o32.b[a])[base + aslot(true, r, q)] = (float)v[a];
+        }
     }
-}
-
-// slot of element (row m, contraction k) of a diagonal A-operand tile
-__device__ inline int dslot(bool f32, int m, int k) {
-    if (!f32) return (k >> 2) * 64 + m + 16 * (k & 3);   // k = 4kc + g
-    return (k & 3) * 64 + m + 16 * (k >> 2);             // k = 4g + kc
 }
 
 // Phase 1: FP64 inverses of the diagonal tiles, natural row-major 16x16 per
@@ -172,7 +184,7 @@ __global__ void k_diag_inv(int64_t n, int bw, int NT, const double *lu, double *
 }
 
 // Phase 2: diagonal inverses D and the "newest-tile" products E of every
-// tile row, stored as MFMA A operands (dslot layout), FP64 and/or FP32.
+// tile row, stored as MFMA A operands (aslot layout), FP64 and/or FP32.
 //   forward L pass (ascending):  D = L_II^{-1},      E[I] = L(I,I-1) L_{I-1,I-1}^{-1}
 //   forward U pass (descending): D = U_II^{-1},      E[I] = U(I,I+1) U_{I+1,I+1}^{-1}
 //   adjoint U^T pass (asc.):     D = U_II^{-T},      E[I] = U(I-1,I)^T U_{I-1,I-1}^{-T}
@@ -218,12 +230,12 @@ __global__ void k_pack_diag(int64_t n, int bw, int NT, const double *lu, const d
         const double dv[4] = {Li[r * TILE + col], Ui[r * TILE + col], Li[col * TILE + r], Ui[col * TILE + r]};
         for (int a = 0; a < 4; ++a) {
             if (o64.D[a]) {
-                ((double *)o64.D[a])[off + dslot(false, r, col)] = dv[a];
-                ((double *)o64.E[a])[off + dslot(false, r, col)] = e[a][r];
+                ((double *)o64.D[a])[off + aslot(false, r, col)] = dv[a];
+                ((double *)o64.E[a])[off + aslot(false, r, col)] = e[a][r];
             }
             if (o32.D[a]) {
-                ((float *)o32.D[a])[off + dslot(true, r, col)] = (float)dv[a];
-                ((float *)o32.E[a])[off + dslot(true, r, col)] = (float)e[a][r];
+                ((float *)o32.D[a])[off + aslot(true, r, col)] = (float)dv[a];
+                ((float *)o32.E[a])[off + aslot(true, r, col)] = (float)e[a][r];
             }
         }
     }
@@ -235,9 +247,13 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_pack_band, dim3((unsigned)blocks), dim3(256), 0, s, n, bw, NT, nb, lu,
-                       t64 ? (double *)t64->Lb : nullptr, t64 ? (double *)t64->Ub : nullptr,
-                       t32 ? (float *)t32->Lb : nullptr, t32 ? (float *)t32->Ub : nullptr);
+    BandOut b64{}, b32{};
+    const int bidx[4] = {TS_LB, TS_UB, TS_UTB, TS_LTB};
+    for (int a = 0; a < 4; ++a) {
+        b64.b[a] = t64 ? t64->a[bidx[a]] : nullptr;
+        b32.b[a] = t32 ? t32->a[bidx[a]] : nullptr;
+    }
+    hipLaunchKernelGGL(k_pack_band, dim3((unsigned)blocks), dim3(256), 0, s, n, bw, NT, nb, lu, b64, b32);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t th = (int64_t)NT * TILE;
@@ -245,13 +261,12 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
     hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, n, bw, NT, lu, Linv, Uinv);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     DiagOut o64{}, o32{};
-    if (t64) {
-        o64.D[0] = t64->DL; o64.D[1] = t64->DU; o64.D[2] = t64->DLT; o64.D[3] = t64->DUT;
-        o64.E[0] = t64->EL; o64.E[1] = t64->EU; o64.E[2] = t64->ELT; o64.E[3] = t64->EUT;
-    }
-    if (t32) {
-        o32.D[0] = t32->DL; o32.D[1] = t32->DU; o32.D[2] = t32->DLT; o32.D[3] = t32->DUT;
-        o32.E[0] = t32->EL; o32.E[1] = t32->EU; o32.E[2] = t32->ELT; o32.E[3] = t32->EUT;
+    const int didx[4] = {TS_DL, TS_DU, TS_DLT, TS_DUT}, eidx[4] = {TS_EL, TS_EU, TS_ELT, TS_EUT};
+    for (int a = 0; a < 4; ++a) {
+        o64.D[a] = t64 ? t64->a[didx[a]] : nullptr;
+        o64.E[a] = t64 ? t64->a[eidx[a]] : nullptr;
+        o32.D[a] = t32 ? t32->a[didx[a]] : nullptr;
+        o32.E[a] = t32 ? t32->a[eidx[a]] : nullptr;
     }
     hipLaunchKernelGGL(k_pack_diag, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, n, bw, NT, lu, Linv,
                        Uinv, o64, o32);

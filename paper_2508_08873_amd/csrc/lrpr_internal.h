@@ -20,19 +20,23 @@ namespace lrpr {
 // half-width b spans nb = ceil(b/16) tiles on each side of the diagonal.
 //   Lb[I][j]  = L(I, I-nb+j),  j = 0..nb-1   (strictly-left band tiles of L)
 //   Ub[I][j]  = U(I, I+1+j),   j = 0..nb-1   (strictly-right band tiles of U)
-//   DL[I]     = inverse of the unit lower triangular diagonal tile L(I,I)
-//   DU[I]     = inverse of the upper triangular diagonal tile U(I,I)
-//   DLT[I], DUT[I] = transposes of DL[I], DU[I] (adjoint sweeps)
+//   UTb[I][j] = U^T(I, I-nb+j)               (mirrored set, optional)
+//   LTb[I][j] = L^T(I, I+1+j)                (mirrored set, optional)
+//   DL[I], DU[I]   = inverses of the diagonal tiles L(I,I), U(I,I)
+//   DLT[I], DUT[I] = their transposes (adjoint sweeps)
+//   EL[I] = L(I,I-1) DL[I-1],   EU[I] = U(I,I+1) DU[I+1]
+//   EUT[I] = U(I-1,I)^T DUT[I-1], ELT[I] = L(I+1,I)^T DLT[I+1]
 // Tiles outside the matrix are zero; the diagonal tiles of the padded rows
 // beyond n are the identity.  Each tile has 256 elements.
 //
-// Band tiles use a 4x4 sub-block layout: element (r, c) at
-//   ((c/4)*4 + r/4)*16 + (r%4)*4 + c%4,
-// so that both the tile and its transpose load as MFMA A operands with
-// whole 4x4 sub-blocks per cache line.
-// Diagonal (D*) tiles are stored pre-arranged as MFMA A operands: chunk kc of
-// lane l at [kc*64 + l] (the k index of that slot depends on the precision,
-// see tiles.hip).
+// Every tile is stored as MFMA A operands, lane-major: the four values lane l
+// feeds to the four 16x16x4 products of a 16x16x16 contraction sit together
+// (one 16-byte load in FP32, two in FP64).  With g = l/16, m = l%16 and kc the
+// chunk, the value is T[m][kappa(g, kc)], where the contraction index
+// kappa(g, kc) = 4 kc + g (FP64) or 4 g + kc (FP32) is the row that register
+// kc of an MFMA accumulator holds, so accumulators feed the next product as B
+// operands directly.  Position of (l, kc) in the tile:
+//   FP32: 4 l + kc;     FP64: 128 (kc/2) + 2 l + kc%2.
 // ---------------------------------------------------------------------------
 constexpr int TILE = 16;
 constexpr int TILE_ELEMS = 256;
@@ -40,18 +44,19 @@ constexpr int TILE_ELEMS = 256;
 // the sweep's prefetch window, reads land on zeros)
 inline int guard_rows(int nb) { return nb + 8; }
 
+enum { TS_LB, TS_UB, TS_UTB, TS_LTB, TS_DL, TS_DU, TS_DLT, TS_DUT, TS_EL, TS_EU, TS_ELT, TS_EUT, TS_COUNT };
+
 struct TileSet {            // device arrays of one precision (pointers to tile row 0)
-    void *Lb = nullptr, *Ub = nullptr;
-    void *DL = nullptr, *DU = nullptr, *DLT = nullptr, *DUT = nullptr;
-    void *EL = nullptr, *EU = nullptr, *ELT = nullptr, *EUT = nullptr;
-    void *zt = nullptr;    // one all-zero tile: target of loads outside the band
-    void *sink = nullptr;  // one scratch tile: target of masked-off stores
-    void *alloc[10] = {};  // allocations behind Lb..EUT (they start guard rows earlier)
+    void *a[TS_COUNT] = {};      // indexed by TS_*; UTb/LTb null without the mirrored set
+    void *zt = nullptr;          // one all-zero tile: target of loads outside the band
+    void *sink = nullptr;        // one scratch tile: target of masked-off stores
+    void *alloc[TS_COUNT] = {};  // allocations behind a[] (they start guard rows earlier)
 };
 
 // Device-side view of one factor, passed by value to the sweep kernels.
 struct FacView {
-    const void *Lb, *Ub, *DL, *DU, *DLT, *DUT, *EL, *EU, *ELT, *EUT, *zt;
+    const void *a[TS_COUNT];
+    const void *zt;
     void *sink;
     int n, NT, nb;
     double dt;
@@ -78,8 +83,8 @@ struct lrpr_factor_s {
     int64_t n = 0;
     int bw = 0;
     int NT = 0, nb = 0;
-    int mask = 0;
-    double *lu = nullptr;          // FP64 band LU, n x (2bw+1) row-major (kept with mask bit 0)
+    int mask = 0;                  // LRPR_STORE_* bits
+    double *lu = nullptr;          // FP64 band LU, n x (2bw+1) row-major (kept with LRPR_STORE_F64)
     lrpr::TileSet t64, t32;
 };
 
@@ -121,7 +126,9 @@ hipError_t launch_assemble(const lrpr_op_desc &op, int64_t n, int bw, double *ba
 hipError_t launch_band_lu(int64_t n, int bw, double *band, int *info, hipStream_t s);
 hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu, const TileSet *t64,
                              const TileSet *t32, double *scratch, hipStream_t s);
-hipError_t launch_sweep(bool adjoint, bool f32, int nitems, const SweepItem *d_items, int nsteps,
+// adjoint sweeps read the mirrored set unless `strided` (then the forward
+// tiles are read transposed)
+hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const SweepItem *d_items, int nsteps,
                         int max_nb, hipStream_t s);
 
 }  // namespace lrpr

@@ -1,21 +1,32 @@
 // Batched implicit-Euler sweeps through a banded LU on gfx950 (CDNA4).
 //
 // One implicit-Euler step of the fine propagator solves (I + dt A) x_new =
-// x_old + dt f(t_new) with M = L U: a forward substitution with L then a
+// x_old + dt f(t_new) with M = L U: a forward substitution with L, then a
 // back substitution with U (Sec. 2, eq. F_n_affine; the paper's solver reuses
 // one factorisation for all right-hand sides of a step, Sec. 4.4).  The
-// adjoint (Sec. 2.1 step 3) solves M^T z = x: forward with U^T, back with L^T.
+// adjoint (Sec. 2.1, step 3) solves M^T z = x with M^T = U^T L^T: forward
+// with U^T, back with L^T.  Both are the same two-pass sweep over band tiles:
+// the forward set holds L and U, the mirrored set U^T and L^T of the same LU.
+// Without a mirrored set the adjoint reads the forward tiles transposed.
 //
-// Blocking.  Rows are cut into tile rows of 16.  For tile row I the solve is
-//     y_I = D_I (r_I - sum_J B_IJ y_J)
-// where the B_IJ are the nb band tiles on the already-solved side and D_I the
-// inverse of the diagonal tile.  Both products are 16x16x16 contractions on
-// the matrix cores (v_mfma_*_16x16x4), one wave per 16 right-hand sides.
-// The last nb solved tiles of the group live in an LDS ring; the band tiles
-// stream from L2/HBM straight into VGPRs.  KW waves split the nb band tiles
-// of a tile row, their partial sums meet in LDS, and wave 0 finishes the row
-// (source term, diagonal inverse, store).  The state stays column-major in
-// HBM and is read/written once per substitution pass.
+// Blocking.  Rows are cut into tile rows of 16.  For tile row I of a pass
+//     y_I = D_I s_I,   s_I = r_I - sum_{bulk J} B_IJ y_J - E_I s_{I-1}
+// where the B_IJ are the nb-1 older band tiles, D_I is the inverse of the
+// diagonal tile and E_I = B_{I,I-1} D_{I-1} is the newest band tile times the
+// neighbour's inverse, so the row-to-row recurrence only runs through s.
+// Every product is a 16x16x16 contraction on the matrix cores
+// (v_mfma_*_16x16x4), 16 right-hand sides per workgroup.
+//
+// Waves of a workgroup (KW = 8):
+//   wave 0        finisher: s, t = E s, y = D s, ring and HBM store;
+//   waves 1..5    bulk: partial sums over the older band tiles, operands
+//                 prefetched PD-1 tile rows ahead into registers;
+//   wave 6        factor helper: prefetches D and E of coming rows;
+//   wave 7        state helper: prefetches the right-hand side rows.
+// The last nb solved tiles live in an LDS ring; helpers hand their operands
+// to the finisher through a triple-buffered LDS area.  One barrier per tile
+// row orders LDS traffic only, so prefetches stay in flight across it.
+// Narrow bands (nb <= 4) run one wave that does everything.
 #include "lrpr_internal.h"
 
 namespace lrpr {
@@ -28,6 +39,9 @@ template <typename T> using gptr_mut = __attribute__((address_space(1))) T *;
 template <typename T> __device__ __forceinline__ T gld(const T *p) { return *(gptr<T>)p; }
 template <typename T> __device__ __forceinline__ void gst(T *p, T v) { *(gptr_mut<T>)p = v; }
 
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 template <typename T> struct Mf;
 
 // f64 16x16x4: A[m][k] in lane m+16k, B[k][n] in lane n+16k,
@@ -37,7 +51,16 @@ template <> struct Mf<double> {
     __device__ static inline v4 mma(double a, double b, v4 c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    // row held by register i of lane group g
     __device__ static inline int row(int g, int i) { return 4 * i + g; }
+    // position of (lane l, chunk kc) in a lane-major tile
+    __device__ static inline int slot(int l, int kc) { return 128 * (kc >> 1) + 2 * l + (kc & 1); }
+    // (lane group, chunk) whose contraction index is k
+    __device__ static inline void gk(int k, int &g, int &kc) { g = k & 3; kc = k >> 2; }
+    __device__ static inline void ld4(const double *tile, int l, double (&v)[4]) {
+        const d2v a = *(gptr<d2v>)(tile + 2 * l), b = *(gptr<d2v>)(tile + 128 + 2 * l);
+        v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
+    }
 };
 
 // f32 16x16x4: A and B as above, D[m][n] in lane n+16(m/4), register m%4.
@@ -47,41 +70,11 @@ template <> struct Mf<float> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     __device__ static inline int row(int g, int i) { return 4 * g + i; }
-};
-
-// One substitution pass over all tile rows of one 16-column group.
-//   ASC   : ascending tile rows (forward substitution) or descending.
-//   TRANS : band tiles are read transposed from the other triangle's
-//           storage (adjoint).
-// Per tile row I the nb band tiles split into the "newest" one (J = I-1 when
-// ascending, I+1 when descending), whose right-hand factor y_J wave 0 still
-// holds in registers, and nb-1 "bulk" tiles (J further away) that all KW
-// waves share, reading y_J from the LDS ring.  Operands of the next PD tile
-// rows are prefetched into registers, so global-memory latency overlaps the
-// matrix-core work.  One barrier per tile row: before it the waves post their
-// bulk partial sums (double-buffered), after it wave 0 finishes the row
-// (source term, newest tile, diagonal inverse, ring and HBM store).
-template <typename T> struct NewestOff;
-// f64: the accumulator register kc holds rows 4kc + lane/16, i.e. the B
-// operand of chunk kc in the standard k order, same A offsets as bulk tiles.
-template <> struct NewestOff<double> {
-    __device__ static inline void get(bool trans, int c, int g, int off_fwd, int off_adj, int &off, int &stride) {
-        off = trans ? off_adj : off_fwd;
-        stride = trans ? 16 : 64;
-    }
-};
-// f32: register kc holds rows 4*(lane/16) + kc, so chunk kc contracts over
-// k = 4*(lane/16) + kc; in the sub-block layout a lane's four chunks are
-// adjacent (forward) or 4 apart (transposed).
-template <> struct NewestOff<float> {
-    __device__ static inline void get(bool trans, int c, int g, int, int, int &off, int &stride) {
-        if (!trans) {
-            off = (g * 4 + (c >> 2)) * 16 + (c & 3) * 4;
-            stride = 1;
-        } else {
-            off = ((c >> 2) * 4 + g) * 16 + (c & 3);
-            stride = 4;
-        }
+    __device__ static inline int slot(int l, int kc) { return 4 * l + kc; }
+    __device__ static inline void gk(int k, int &g, int &kc) { g = k >> 2; kc = k & 3; }
+    __device__ static inline void ld4(const float *tile, int l, float (&v)[4]) {
+        const f4v a = *(gptr<f4v>)(tile + 4 * l);
+        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
     }
 };
 
@@ -93,35 +86,27 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Roles of the waves of a workgroup (KW > 1):
-//   wave 0          finisher: newest tile, source term, diagonal inverse,
-//                   ring and HBM store of each tile row; no global loads;
-//   waves 1..NBW    bulk: partial sums over the nb-1 older band tiles;
-//   wave NBW+1      factor helper: prefetches the newest band tile and the
-//                   diagonal inverse of coming rows, hands them to wave 0
-//                   through LDS;
-//   wave NBW+2      state helper: prefetches the right-hand side rows (state
-//                   and source) the same way.
-// With KW == 1 (narrow bands) the single wave does everything.
-template <typename T, int KW, int TPW, int PD, bool ASC, bool TRANS>
+// One pass (ascending or descending tile rows) over one 16-column group.
+//   band  : band tiles of the pass, nb per tile row (row I, index j)
+//   dtile : diagonal inverses; etile: newest-tile products (one per row)
+//   STRIDED: the band tiles are the forward set's, read transposed: tile
+//            (row J, index nb-1-j), each lane gathering its four values.
+// Registers and LDS hold 16x16 blocks in accumulator order: value i of lane
+// l is row Mf::row(l/16, i), column l%16 — the B operand of chunk i.
+template <typename T, int KW, int TPW, int PD, bool ASC, bool STRIDED>
 struct Pass {
     typedef typename Mf<T>::v4 v4;
     static constexpr int NBW = KW > 1 ? KW - 3 : 1;   // bulk waves
-    const SweepItem &it;
     const T *__restrict__ band;
     const T *__restrict__ dtile;
     const T *__restrict__ etile;
     const T *__restrict__ zt;
     T *ring;
-    T *red;   // [2][NBW][256]
-    T *hand;  // [3][4][256]: newest, D, x, f
     int lane, w, g, c, n, NT, nb, RS, nbulk;
-    int boff, bstr, noff, nstr;
+    int soff[4];   // STRIDED: position of this lane's chunk values in a forward tile
 
-    __device__ Pass(const SweepItem &it_, const T *band_, const T *dtile_, const T *etile_, T *ring_, T *red_,
-                    T *hand_)
-        : it(it_), band(band_), dtile(dtile_), etile(etile_), zt((const T *)it_.fac.zt), ring(ring_), red(red_),
-          hand(hand_) {
+    __device__ Pass(const SweepItem &it, const T *band_, const T *dtile_, const T *etile_, T *ring_)
+        : band(band_), dtile(dtile_), etile(etile_), zt((const T *)it.fac.zt), ring(ring_) {
         lane = threadIdx.x & 63;
         w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar)
         g = lane >> 4;
@@ -131,21 +116,24 @@ struct Pass {
         nb = it.fac.nb;
         RS = nb + 1;
         nbulk = nb - 1;
-        const int off_fwd = ((c >> 2) * 16) + ((c & 3) * 4) + g;   // + 64*kc; lane's row = c
-        const int off_adj = ((c >> 2) * 64) + (g * 4) + (c & 3);   // + 16*kc
-        boff = TRANS ? off_adj : off_fwd;
-        bstr = TRANS ? 16 : 64;
-        NewestOff<T>::get(TRANS, c, g, off_fwd, off_adj, noff, nstr);
+        // transposed: A'[c][k] = T[k][c] with k = row(g, kc); element (k, c) of
+        // the forward tile is held by lane 16 g' + k, chunk kc' where the
+        // contraction index of (g', kc') is c
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            int gp, kcp;
+            Mf<T>::gk(c, gp, kcp);
+            soff[kc] = Mf<T>::slot(16 * gp + Mf<T>::row(g, kc), kcp);
+        }
     }
     __device__ __forceinline__ int row_of(int q) const { return ASC ? q : NT - 1 - q; }
     __device__ __forceinline__ const T *tile_ptr(int I, int j, int J) const {
-        if (TRANS) return band + ((int64_t)J * nb + (nb - 1 - j)) * TILE_ELEMS;
+        if (STRIDED) return band + ((int64_t)J * nb + (nb - 1 - j)) * TILE_ELEMS;
         return band + ((int64_t)I * nb + j) * TILE_ELEMS;
     }
-    // bulk tile t of this wave (wb = index among the bulk waves).  Tile rows
-    // outside [0, NT) are zero guard rows of the tile arrays, so every address
-    // within the prefetch window is valid; only surplus slots (idx >= nb-1)
-    // read the zero tile.
+    // bulk tile t of bulk wave wb.  Tile rows outside [0, NT) are zero guard
+    // rows of the tile arrays, so every address within the prefetch window is
+    // valid; surplus slots (idx >= nb-1) read the zero tile.
     __device__ __forceinline__ bool bulk(int q, int wb, int t, int &j, int &J) const {
         const int I = row_of(q);
         const int idx = wb + NBW * t;
@@ -153,15 +141,21 @@ struct Pass {
         J = ASC ? I - nb + j : I + 1 + j;
         return idx < nbulk;
     }
+    __device__ __forceinline__ void ld_tile(const T *tp, T (&v)[4]) const {
+        if (STRIDED) {
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) v[kc] = gld(tp + soff[kc]);
+        } else {
+            Mf<T>::ld4(tp, lane, v);
+        }
+    }
     template <int NTP>
     __device__ __forceinline__ void load_bulk(int q, int wb, T (&ab)[NTP][4]) const {
         const int I = row_of(q);
 #pragma unroll
         for (int t = 0; t < NTP; ++t) {
             int j, J;
-            const T *tp = bulk(q, wb, t, j, J) ? tile_ptr(I, j, J) : zt;
-#pragma unroll
-            for (int kc = 0; kc < 4; ++kc) ab[t][kc] = gld(tp + boff + bstr * kc);
+            ld_tile(bulk(q, wb, t, j, J) ? tile_ptr(I, j, J) : zt, ab[t]);
         }
     }
     // ring slot of tile row J given sI = slot of the current row I (J within
@@ -195,57 +189,41 @@ struct Pass {
     __device__ __forceinline__ int next_slot(int sI) const {
         return ASC ? (sI + 1 == RS ? 0 : sI + 1) : (sI == 0 ? RS - 1 : sI - 1);
     }
-    // operands of the finisher for row q: newest band tile and diagonal inverse
-    __device__ __forceinline__ void load_fac(int q, T (&nbv)[4], T (&dbv)[4]) const {
-        const int I = row_of(q);
-        const int jn = ASC ? nb - 1 : 0;
-        const int Jn = ASC ? I - 1 : I + 1;
-        const T *tn = tile_ptr(I, jn, Jn);           // guard rows are zero
-        const T *D = dtile + (int64_t)I * TILE_ELEMS;
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-            nbv[kc] = gld(tn + noff + nstr * kc);
-            dbv[kc] = gld(D + kc * 64 + lane);
-        }
-    }
-    // finisher operands staged for row q: diagonal inverse of row q and the
-    // newest-tile product E of row q+1 (applied to the residual s of row q)
+    // diagonal inverse of row q and newest-tile product of row q+1 (guard
+    // rows are zero)
     __device__ __forceinline__ void load_de(int q, T (&dbv)[4], T (&ebv)[4]) const {
-        const T *D = dtile + (int64_t)row_of(q) * TILE_ELEMS;
-        const T *E = etile + (int64_t)row_of(q + 1) * TILE_ELEMS;
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-            dbv[kc] = gld(D + kc * 64 + lane);
-            ebv[kc] = gld(E + kc * 64 + lane);
-        }
+        Mf<T>::ld4(dtile + (int64_t)row_of(q) * TILE_ELEMS, lane, dbv);
+        Mf<T>::ld4(etile + (int64_t)row_of(q + 1) * TILE_ELEMS, lane, ebv);
     }
-    // right-hand side rows of row q: state x and source f (D-layout rows)
-    __device__ __forceinline__ void load_state(int q, const T *X, int64_t ldx, bool colok, const T *fsrc,
+    // right-hand side rows of row q (accumulator order), clamped into the
+    // arrays: rows >= n, columns >= ncols and rows of q >= NT are never stored
+    // and meet only zero band entries, so any finite value serves
+    __device__ __forceinline__ void load_state(int q, const T *X, int64_t ldx, int col, const T *fsrc,
                                                int64_t fstride, T (&xbv)[4], T (&fbv)[4]) const {
         const int I = row_of(q);
-        const bool okq = q < NT;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int row = I * TILE + Mf<T>::row(g, i);
-            const bool okr = okq && colok && row < n;
-            xbv[i] = gld(okr ? X + row + (int64_t)c * ldx : zt);
-            fbv[i] = gld(okr ? fsrc + row * fstride : zt);
+            int row = I * TILE + Mf<T>::row(g, i);
+            row = row < 0 ? 0 : (row >= n ? n - 1 : row);
+            xbv[i] = gld(X + row + (int64_t)col * ldx);
+            fbv[i] = gld(fsrc + row * fstride);
         }
     }
 };
 
-template <typename T, int KW, int TPW, int PD, bool ASC, bool TRANS>
+template <typename T, int KW, int TPW, int PD, bool ASC, bool STRIDED>
 __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restrict__ band,
                                            const T *__restrict__ dtile, const T *__restrict__ etile, T *ring,
                                            T *red, T *hand, bool with_src, int step, int nsteps) {
     typedef typename Mf<T>::v4 v4;
-    typedef Pass<T, KW, TPW, PD, ASC, TRANS> PS;
-    PS P(it, band, dtile, etile, ring, red, hand);
+    typedef Pass<T, KW, TPW, PD, ASC, STRIDED> PS;
+    PS P(it, band, dtile, etile, ring);
     const int NT = P.NT, lane = P.lane, g = P.g, c = P.c, n = P.n;
     const int NTp = (NT + PD - 1) / PD * PD;   // rows beyond NT are zero work
     T *X = (T *)it.X;
     const int64_t ldx = it.ldx;
     const bool colok = c < it.ncols;
+    const int col = colok ? c : 0;
     // source of this lane's column: f(x) * dt * phi(t_step), or the zero tile
     const T *fsrc = P.zt;
     int64_t fstride = 0;
@@ -261,17 +239,26 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
     }
     T *sink = (T *)it.fac.sink;
     const int w = P.w;
+    // y of tile row Irow: into ring slot ri (accumulator order) and into X
+    auto store_y = [&](const v4 &y, T *ri, int Irow, bool ok) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ri[i * 64 + lane] = y[i];
+            const int row = Irow * TILE + Mf<T>::row(g, i);
+            gst((ok && colok && row < n) ? X + row + (int64_t)c * ldx : sink + lane, y[i]);
+        }
+    };
     if (KW == 1) {
         // ---- single wave: everything, prefetching PD-1 rows ahead
         T abuf[PD][TPW][4];
-        T nbuf[PD][4], dbuf[PD][4], xbuf[PD][4], fbuf[PD][4];
+        T dbuf[PD][4], ebuf[PD][4], xbuf[PD][4], fbuf[PD][4];
 #pragma unroll
         for (int u = 0; u < PD - 1; ++u) {
             P.load_bulk(u, 0, abuf[u]);
-            P.load_fac(u, nbuf[u], dbuf[u]);
-            P.load_state(u, X, ldx, colok, fsrc, fstride, xbuf[u], fbuf[u]);
+            P.load_de(u, dbuf[u], ebuf[u]);
+            P.load_state(u, X, ldx, col, fsrc, fstride, xbuf[u], fbuf[u]);
         }
-        v4 yprev = {0, 0, 0, 0};
+        v4 tnext = {0, 0, 0, 0};
         int sI = P.row_of(0) % P.RS;
         for (int q0 = 0; q0 < NTp; q0 += PD) {
 #pragma unroll
@@ -279,29 +266,23 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
                 const int q = q0 + u;
                 const int un = (u + PD - 1) % PD;
                 P.load_bulk(q + PD - 1, 0, abuf[un]);
-                P.load_fac(q + PD - 1, nbuf[un], dbuf[un]);
-                P.load_state(q + PD - 1, X, ldx, colok, fsrc, fstride, xbuf[un], fbuf[un]);
+                P.load_de(q + PD - 1, dbuf[un], ebuf[un]);
+                P.load_state(q + PD - 1, X, ldx, col, fsrc, fstride, xbuf[un], fbuf[un]);
                 __builtin_amdgcn_sched_barrier(0);
                 const bool okq = q < NT;
                 const int I = P.row_of(q);
-                v4 a = P.bulk_mma(q, 0, sI, abuf[u]);
-#pragma unroll
-                for (int kc = 0; kc < 4; ++kc) a = Mf<T>::mma(nbuf[u][kc], yprev[kc], a);
+                const v4 a = P.bulk_mma(q, 0, sI, abuf[u]);
                 v4 sv;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) sv[i] = (xbuf[u][i] + fs * fbuf[u][i]) - a[i];
-                v4 y = {0, 0, 0, 0};
+                for (int i = 0; i < 4; ++i) sv[i] = (xbuf[u][i] + fs * fbuf[u][i]) - (a[i] + tnext[i]);
+                v4 y = {0, 0, 0, 0}, tn = {0, 0, 0, 0};
 #pragma unroll
-                for (int kc = 0; kc < 4; ++kc) y = Mf<T>::mma(dbuf[u][kc], sv[kc], y);
-                T *ri = ring + (okq ? sI : P.RS) * TILE_ELEMS;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int rr = Mf<T>::row(g, i);
-                    ri[rr * TILE + c] = y[i];
-                    const int row = I * TILE + rr;
-                    gst((okq && colok && row < n) ? X + row + (int64_t)c * ldx : sink + lane, y[i]);
+                for (int kc = 0; kc < 4; ++kc) {
+                    y = Mf<T>::mma(dbuf[u][kc], sv[kc], y);
+                    tn = Mf<T>::mma(ebuf[u][kc], sv[kc], tn);
                 }
-                yprev = y;
+                tnext = tn;
+                store_y(y, ring + (okq ? sI : P.RS) * TILE_ELEMS, I, okq);
                 sI = P.next_slot(sI);
                 lds_barrier();
             }
@@ -322,19 +303,11 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
             const bool okq = q < NT;
             const int I = P.row_of(q);
             const T *h = hand + (q % 3) * 4 * TILE_ELEMS;
-            // y_{q-1} = D_{q-1} s_{q-1}: ring and HBM
             {
                 v4 y = {0, 0, 0, 0};
 #pragma unroll
                 for (int kc = 0; kc < 4; ++kc) y = Mf<T>::mma(dprev[kc], sprev[kc], y);
-                T *ri = ring + sprev_slot * TILE_ELEMS;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int rr = Mf<T>::row(g, i);
-                    ri[rr * TILE + c] = y[i];
-                    const int row = Iprev * TILE + rr;
-                    gst((okprev && colok && row < n) ? X + row + (int64_t)c * ldx : sink + lane, y[i]);
-                }
+                store_y(y, ring + sprev_slot * TILE_ELEMS, Iprev, okprev);
             }
             T dcur[4], ecur[4], rcur[4];
 #pragma unroll
@@ -365,19 +338,11 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
             okprev = okq;
             sI = P.next_slot(sI);
         }
-        // last row's solution
         {
             v4 y = {0, 0, 0, 0};
 #pragma unroll
             for (int kc = 0; kc < 4; ++kc) y = Mf<T>::mma(dprev[kc], sprev[kc], y);
-            T *ri = ring + sprev_slot * TILE_ELEMS;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int rr = Mf<T>::row(g, i);
-                ri[rr * TILE + c] = y[i];
-                const int row = Iprev * TILE + rr;
-                gst((okprev && colok && row < n) ? X + row + (int64_t)c * ldx : sink + lane, y[i]);
-            }
+            store_y(y, ring + sprev_slot * TILE_ELEMS, Iprev, okprev);
         }
     } else if (w <= PS::NBW) {
         // ---- bulk waves
@@ -394,7 +359,7 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
                 const int un = (u + PD - 1) % PD;
                 P.load_bulk(q + PD - 1, wb, abuf[un]);
                 __builtin_amdgcn_sched_barrier(0);
-                v4 acc = P.bulk_mma(q, wb, sI, abuf[u]);
+                const v4 acc = P.bulk_mma(q, wb, sI, abuf[u]);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) red[((q & 1) * PS::NBW + wb) * TILE_ELEMS + i * 64 + lane] = acc[i];
                 sI = P.next_slot(sI);
@@ -405,8 +370,10 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
         // ---- helpers: stage the finisher's operands of row q+1 in hand[(q+1)%3]
         //      (D and E from the factor helper, r = x + dt phi f from the state helper)
         constexpr int PDH = 4;
-        if (w == PS::NBW + 1) {
-            T b0[PDH][4], b1[PDH][4];
+        T b0[PDH][4], b1[PDH][4];
+        const bool facw = (w == PS::NBW + 1);
+        const int NTh = (NTp + PDH - 1) / PDH * PDH;
+        if (facw) {
             auto post = [&](int q, const T (&v0)[4], const T (&v1)[4]) {
                 T *h = hand + (q % 3) * 4 * TILE_ELEMS;
 #pragma unroll
@@ -419,7 +386,6 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
             for (int u = 0; u < PDH - 1; ++u) P.load_de(u, b0[u], b1[u]);
             post(0, b0[0], b1[0]);
             lds_barrier();
-            const int NTh = (NTp + PDH - 1) / PDH * PDH;
             for (int q0 = 0; q0 < NTh; q0 += PDH) {
 #pragma unroll
                 for (int u = 0; u < PDH; ++u) {
@@ -433,22 +399,20 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
                 }
             }
         } else {
-            T b0[PDH][4], b1[PDH][4];
             auto post = [&](int q, const T (&x)[4], const T (&fv)[4]) {
                 T *h = hand + (q % 3) * 4 * TILE_ELEMS + 2 * TILE_ELEMS;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) h[i * 64 + lane] = x[i] + fs * fv[i];
             };
 #pragma unroll
-            for (int u = 0; u < PDH - 1; ++u) P.load_state(u, X, ldx, colok, fsrc, fstride, b0[u], b1[u]);
+            for (int u = 0; u < PDH - 1; ++u) P.load_state(u, X, ldx, col, fsrc, fstride, b0[u], b1[u]);
             post(0, b0[0], b1[0]);
             lds_barrier();
-            const int NTh = (NTp + PDH - 1) / PDH * PDH;
             for (int q0 = 0; q0 < NTh; q0 += PDH) {
 #pragma unroll
                 for (int u = 0; u < PDH; ++u) {
                     const int q = q0 + u;
-                    P.load_state(q + PDH - 1, X, ldx, colok, fsrc, fstride, b0[(u + PDH - 1) % PDH],
+                    P.load_state(q + PDH - 1, X, ldx, col, fsrc, fstride, b0[(u + PDH - 1) % PDH],
                                  b1[(u + PDH - 1) % PDH]);
                     __builtin_amdgcn_sched_barrier(0);
                     if (q < NTp) {
@@ -463,7 +427,9 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
     __syncthreads();
 }
 
-template <typename T, int KW, int TPW, int PD, bool ADJ>
+// ADJ: adjoint sweep, on the mirrored set or (STRIDED) the transposed
+// forward tiles.
+template <typename T, int KW, int TPW, int PD, bool ADJ, bool STRIDED>
 __global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__ items, int nitems,
                                                    int nsteps) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -473,36 +439,46 @@ __global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__
         // the ring must hold finite values only: zero tiles multiply stale slots
         for (int e = threadIdx.x; e < (it.fac.nb + 2) * TILE_ELEMS; e += blockDim.x) ring[e] = (T)0;
         __syncthreads();
-        T *red = ring + (it.fac.nb + 2) * TILE_ELEMS;   // [2][KW-3][256]
-        T *hand = red + 2 * (KW > 1 ? KW - 3 : 1) * TILE_ELEMS;   // [3][4][256]
-        const T *Lb = (const T *)it.fac.Lb, *Ub = (const T *)it.fac.Ub;
+        T *red = ring + (it.fac.nb + 2) * TILE_ELEMS;              // [2][KW-3][256]
+        T *hand = red + 2 * (KW > 1 ? KW - 3 : 1) * TILE_ELEMS;     // [3][4][256]
+        const void *const *a = it.fac.a;
         for (int step = 0; step < nsteps; ++step) {
             if (!ADJ) {
-                sweep_pass<T, KW, TPW, PD, true, false>(it, Lb, (const T *)it.fac.DL, (const T *)it.fac.EL, ring, red, hand,
-                                                    it.f != nullptr, step, nsteps);
-                sweep_pass<T, KW, TPW, PD, false, false>(it, Ub, (const T *)it.fac.DU, (const T *)it.fac.EU, ring, red, hand, false,
-                                                     step, nsteps);
+                sweep_pass<T, KW, TPW, PD, true, false>(it, (const T *)a[TS_LB], (const T *)a[TS_DL],
+                                                        (const T *)a[TS_EL], ring, red, hand, it.f != nullptr,
+                                                        step, nsteps);
+                sweep_pass<T, KW, TPW, PD, false, false>(it, (const T *)a[TS_UB], (const T *)a[TS_DU],
+                                                         (const T *)a[TS_EU], ring, red, hand, false, step, nsteps);
+            } else if (!STRIDED) {
+                sweep_pass<T, KW, TPW, PD, true, false>(it, (const T *)a[TS_UTB], (const T *)a[TS_DUT],
+                                                        (const T *)a[TS_EUT], ring, red, hand, false, step, nsteps);
+                sweep_pass<T, KW, TPW, PD, false, false>(it, (const T *)a[TS_LTB], (const T *)a[TS_DLT],
+                                                         (const T *)a[TS_ELT], ring, red, hand, false, step, nsteps);
             } else {
-                sweep_pass<T, KW, TPW, PD, true, true>(it, Ub, (const T *)it.fac.DUT, (const T *)it.fac.EUT, ring, red, hand, false,
-                                                   step, nsteps);
-                sweep_pass<T, KW, TPW, PD, false, true>(it, Lb, (const T *)it.fac.DLT, (const T *)it.fac.ELT, ring, red, hand, false,
-                                                    step, nsteps);
+                sweep_pass<T, KW, TPW, PD, true, true>(it, (const T *)a[TS_UB], (const T *)a[TS_DUT],
+                                                       (const T *)a[TS_EUT], ring, red, hand, false, step, nsteps);
+                sweep_pass<T, KW, TPW, PD, false, true>(it, (const T *)a[TS_LB], (const T *)a[TS_DLT],
+                                                        (const T *)a[TS_ELT], ring, red, hand, false, step, nsteps);
             }
         }
     }
 }
 
 template <typename T, int KW, int TPW, int PD>
-static hipError_t launch_t(bool adjoint, int nitems, const SweepItem *d_items, int nsteps, int max_nb,
-                           hipStream_t s) {
-    // LDS: ring of nb+1 solved tiles + double-buffered partial sums of KW-1 waves
+static hipError_t launch_t(bool adjoint, bool strided, int nitems, const SweepItem *d_items, int nsteps,
+                           int max_nb, hipStream_t s) {
+    // LDS: ring of nb+1 solved tiles (+1 dummy slot), double-buffered partial
+    // sums of the bulk waves, triple-buffered hand-off (D, E, r)
     const size_t lds = (size_t)(max_nb + 2 + 2 * (KW > 1 ? KW - 3 : 1) + 12) * TILE_ELEMS * sizeof(T);
     const int grid = nitems < 65536 ? nitems : 65536;
-    if (adjoint)
-        hipLaunchKernelGGL((k_sweep<T, KW, TPW, PD, true>), dim3(grid), dim3(64 * KW), lds, s, d_items,
+    if (!adjoint)
+        hipLaunchKernelGGL((k_sweep<T, KW, TPW, PD, false, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
+                           nitems, nsteps);
+    else if (!strided)
+        hipLaunchKernelGGL((k_sweep<T, KW, TPW, PD, true, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
                            nitems, nsteps);
     else
-        hipLaunchKernelGGL((k_sweep<T, KW, TPW, PD, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
+        hipLaunchKernelGGL((k_sweep<T, KW, TPW, PD, true, true>), dim3(grid), dim3(64 * KW), lds, s, d_items,
                            nitems, nsteps);
     return hipGetLastError();
 }
@@ -511,22 +487,24 @@ static hipError_t launch_t(bool adjoint, int nitems, const SweepItem *d_items, i
 // band tiles (TPW = ceil((nb-1)/(KW-3)) each), two helper waves prefetch the
 // finisher's operands.  Narrow bands run on one wave.
 template <typename T>
-static hipError_t launch_prec(bool adjoint, int nitems, const SweepItem *d_items, int nsteps,
+static hipError_t launch_prec(bool adjoint, bool strided, int nitems, const SweepItem *d_items, int nsteps,
                               int max_nb, hipStream_t s) {
-    if (max_nb <= 1) return launch_t<T, 1, 1, 3>(adjoint, nitems, d_items, nsteps, max_nb, s);
-    if (max_nb <= 4) return launch_t<T, 1, 3, 3>(adjoint, nitems, d_items, nsteps, max_nb, s);
-    if (max_nb <= 8) return launch_t<T, 8, 2, sizeof(T) == 8 ? 4 : 6>(adjoint, nitems, d_items, nsteps, max_nb, s);
-    if (max_nb <= 16) return launch_t<T, 8, 3, sizeof(T) == 8 ? 4 : 5>(adjoint, nitems, d_items, nsteps, max_nb, s);
-    if (max_nb <= 32) return launch_t<T, 8, 7, 3>(adjoint, nitems, d_items, nsteps, max_nb, s);
-    if (max_nb <= 64) return launch_t<T, 8, 13, 2>(adjoint, nitems, d_items, nsteps, max_nb, s);
+    if (max_nb <= 1) return launch_t<T, 1, 1, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    if (max_nb <= 4) return launch_t<T, 1, 3, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    if (max_nb <= 8)
+        return launch_t<T, 8, 2, sizeof(T) == 8 ? 4 : 6>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    if (max_nb <= 16)
+        return launch_t<T, 8, 3, sizeof(T) == 8 ? 4 : 5>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    if (max_nb <= 32) return launch_t<T, 8, 7, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    if (max_nb <= 64) return launch_t<T, 8, 13, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep(bool adjoint, bool f32, int nitems, const SweepItem *d_items, int nsteps,
+hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const SweepItem *d_items, int nsteps,
                         int max_nb, hipStream_t s) {
     if (nitems <= 0 || nsteps <= 0) return hipSuccess;
-    if (f32) return launch_prec<float>(adjoint, nitems, d_items, nsteps, max_nb, s);
-    return launch_prec<double>(adjoint, nitems, d_items, nsteps, max_nb, s);
+    if (f32) return launch_prec<float>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    return launch_prec<double>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
 }
 
 }  // namespace lrpr

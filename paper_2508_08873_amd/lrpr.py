@@ -24,6 +24,10 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
            "lrpr_profile_enable", "lrpr_profile_read"]
 
 
+# lrpr_factor store_mask bits (include/lrpr.h)
+STORE_F64, STORE_F32, STORE_MIRROR = 1, 2, 4
+
+
 class LrprError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (STATUS.get(status, status), msg))

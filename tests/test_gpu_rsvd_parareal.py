@@ -50,7 +50,7 @@ def _prod_err(Ug, Sg, Vg, Uo, So, Vo, k, seed=7):
     return np.linalg.norm(Pg - Po) / np.linalg.norm(Po)
 
 
-def _build(ctx, ora, P, nslices, prec=0, shared=True):
+def _build(ctx, ora, P, nslices, prec=0, shared=True, mask=7):
     ops, facs = [], []
     for s in range(1, nslices + 1):
         if shared and s > 1:
@@ -59,7 +59,7 @@ def _build(ctx, ora, P, nslices, prec=0, shared=True):
             continue
         ops.append(ora.Operator(**P.op_params(s)))
         pp = P.op_params(s)
-        facs.append(ctx.factor(pp["dim"], pp["nx"], pp["nu"], pp["beta"], pp["c"], pp["dt"], store_mask=3))
+        facs.append(ctx.factor(pp["dim"], pp["nx"], pp["nu"], pp["beta"], pp["c"], pp["dt"], store_mask=mask))
     oms = [P.omega(s) for s in range(1, nslices + 1)]
     dt = torch.float64 if prec == 0 else torch.float32
     dev_oms = [_dev(o, dt) for o in oms]
@@ -104,9 +104,11 @@ def test_rsvd_2d(ctx, ora, prec, nx, k, p):
 
 
 def test_rsvd_per_slice_factors(ctx, ora):
-    """Time-dependent nu_n: every slice has its own factor (one launch)."""
+    """Time-dependent nu_n: every slice has its own factor (one launch); the
+    factors are kept without the mirrored set, so the adjoint reads them
+    transposed."""
     P = inputs.tiny2d(nx=23, N=4, m=3, k=8, p=2, nu_of_t=True)
-    ops, facs, oms, coarse = _build(ctx, ora, P, P.N, 0, shared=False)
+    ops, facs, oms, coarse = _build(ctx, ora, P, P.N, 0, shared=False, mask=3)
     l = P.k + P.p
     for s in range(P.N):
         Uo, So, Vo = ora.rsvd(ops[s], P.m, P.k, P.p, oms[s])
@@ -178,7 +180,6 @@ def test_parareal_2d_multi_request(ctx, ora):
         b = mix["U"][r].cpu().numpy()
         assert alone["iters"][0] == mix["iters"][r]
         assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
-        Pr = inputs.tiny2d(nx=31, N=6, m=4, k=8, p=3)
         f = srcs[r]
         sl = [ora.Slice(ops[s], P.m, f, P.fscale(s + 1)) for s in range(P.N)]
         ora.build_coarse(sl, P.k, P.p, oms)
