@@ -131,31 +131,36 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
     f->nb = (bw + TILE - 1) / TILE;
     f->mask = store_mask;
     double *band = nullptr;
-    int *d_info = nullptr;
-    int info = 0;
+    void *scratch = nullptr;
     hipError_t e;
     auto cleanup = [&](lrpr_status st, const std::string &msg) {
         if (band && band != f->lu) hipFree(band);
-        if (d_info) hipFree(d_info);
+        if (scratch) hipFree(scratch);
         lrpr_factor_destroy(f);
         return fail(ctx, st, msg);
     };
+    // scratch: tile-LU panels and flags, later the diagonal-tile inverses
+    size_t sbytes = tile_lu_scratch_bytes(f->NT, f->nb);
+    const size_t inv_bytes = sizeof(double) * 2 * (size_t)f->NT * TILE_ELEMS;
+    if (inv_bytes > sbytes) sbytes = inv_bytes;
     if ((e = hipMalloc(&band, sizeof(double) * (size_t)n * (2 * bw + 1))) != hipSuccess)
         return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: band allocation");
-    if ((e = hipMalloc(&d_info, sizeof(int))) != hipSuccess)
-        return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: info allocation");
-    if ((e = hipMemsetAsync(d_info, 0, sizeof(int), ctx->stream)) != hipSuccess)
-        return cleanup(LRPR_ERR_HIP, "lrpr_factor: memset");
+    if ((e = hipMalloc(&scratch, sbytes)) != hipSuccess)
+        return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: scratch allocation");
     if ((e = launch_assemble(*op, n, bw, band, ctx->stream)) != hipSuccess)
         return cleanup(LRPR_ERR_HIP, std::string("assemble: ") + hipGetErrorString(e));
-    if ((e = launch_band_lu(n, bw, band, d_info, ctx->stream)) != hipSuccess)
+    int *d_info = nullptr, *d_err = nullptr;
+    if ((e = launch_tile_lu(n, bw, f->NT, f->nb, band, scratch, &d_info, &d_err, ctx->stream)) != hipSuccess)
         return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
-    if ((e = hipMemcpyAsync(&info, d_info, sizeof(int), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess ||
+    int flags[2] = {0, 0};
+    if ((e = hipMemcpyAsync(&flags[0], d_info, sizeof(int), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(&flags[1], d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
         return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
-    if (info != 0) {
+    if (flags[1] != 0) return cleanup(LRPR_ERR_HIP, "band LU: a panel wait timed out");
+    if (flags[0] != 0x7f7f7f7f) {
         char msg[128];
-        snprintf(msg, sizeof msg, "lrpr_factor: zero or non-finite pivot at row %d", info - 1);
+        snprintf(msg, sizeof msg, "lrpr_factor: zero or non-finite pivot at row %d", flags[0] - 1);
         return cleanup(LRPR_ERR_ZERO_PIVOT, msg);
     }
     if (store_mask & LRPR_STORE_F64) {
@@ -166,20 +171,14 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
         if (alloc_tiles(f->t32, f->NT, f->nb, sizeof(float), mirror) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP32 tile allocation");
     }
-    double *inv_scratch = nullptr;
-    if ((e = hipMalloc(&inv_scratch, sizeof(double) * 2 * (size_t)f->NT * TILE_ELEMS)) != hipSuccess)
-        return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: scratch allocation");
     if ((e = launch_pack_tiles(n, bw, f->NT, f->nb, band, (store_mask & LRPR_STORE_F64) ? &f->t64 : nullptr,
-                               (store_mask & LRPR_STORE_F32) ? &f->t32 : nullptr, inv_scratch, ctx->stream)) !=
-        hipSuccess) {
-        hipFree(inv_scratch);
+                               (store_mask & LRPR_STORE_F32) ? &f->t32 : nullptr, (double *)scratch,
+                               ctx->stream)) != hipSuccess)
         return cleanup(LRPR_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
-    }
-    e = hipStreamSynchronize(ctx->stream);
-    hipFree(inv_scratch);
-    if (e != hipSuccess) return cleanup(LRPR_ERR_HIP, std::string("factor: ") + hipGetErrorString(e));
-    hipFree(d_info);
-    d_info = nullptr;
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+        return cleanup(LRPR_ERR_HIP, std::string("factor: ") + hipGetErrorString(e));
+    hipFree(scratch);
+    scratch = nullptr;
     if (store_mask & LRPR_STORE_F64) {
         f->lu = band;
     } else {

@@ -1,5 +1,5 @@
-// Operator assembly, banded LU without pivoting, and packing of the factors
-// into the tiled layout read by the sweep kernels.
+// Operator assembly and packing of the LU factors into the tiled layout read
+// by the sweep kernels (the LU itself is in lu.hip).
 #include "lrpr_internal.h"
 
 namespace lrpr {
@@ -48,54 +48,6 @@ hipError_t launch_assemble(const lrpr_op_desc &op, int64_t n, int bw, double *ba
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(256), 0, s, op, n, bw, band);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Banded LU without pivoting (Doolittle, right-looking): for each pivot q,
-// the multipliers L[q+1+i][q] = a[q+1+i][q] / a[q][q] and the rank-1 update
-// a[q+1+i][q+1+j] -= L[q+1+i][q] * a[q][q+1+j] of the (b x b) window.  One
-// workgroup per factor, the window is updated in place in global memory
-// (L2-resident for b <= 511).  *info = q+1 on a zero/non-finite pivot.
-// ---------------------------------------------------------------------------
-constexpr int LU_THREADS = 1024;
-constexpr int LU_TX = 64;
-
-__global__ __launch_bounds__(LU_THREADS) void k_band_lu(int64_t n, int bw, double *band, int *info) {
-    extern __shared__ double sm_lu[];
-    double *urow = sm_lu;          // [bw]
-    double *lcol = sm_lu + bw;     // [bw]
-    const int64_t W = 2 * bw + 1;
-    const int tid = threadIdx.x;
-    const int tx = tid % LU_TX, ty = tid / LU_TX;
-    constexpr int TY = LU_THREADS / LU_TX;
-    for (int64_t q = 0; q < n; ++q) {
-        const double piv = band[q * W + bw];
-        if (!(piv != 0.0) || !isfinite(piv)) {
-            if (tid == 0) *info = (int)(q + 1);
-            return;
-        }
-        const int ni = (int)((n - 1 - q) < bw ? (n - 1 - q) : bw);
-        for (int t = tid; t < ni; t += LU_THREADS) {
-            urow[t] = band[q * W + bw + 1 + t];
-            const int64_t pos = (q + 1 + t) * W + (bw - 1 - t);
-            const double l = band[pos] / piv;
-            band[pos] = l;
-            lcol[t] = l;
-        }
-        __syncthreads();
-        for (int i = ty; i < ni; i += TY) {
-            const double li = lcol[i];
-            double *rowp = band + (q + 1 + i) * W + bw - i;   // entry (q+1+i, q+1+j) at rowp[j]
-            for (int j = tx; j < ni; j += LU_TX) rowp[j] -= li * urow[j];
-        }
-        __syncthreads();
-    }
-}
-
-hipError_t launch_band_lu(int64_t n, int bw, double *band, int *info, hipStream_t s) {
-    const size_t lds = sizeof(double) * 2 * (size_t)bw;
-    hipLaunchKernelGGL(k_band_lu, dim3(1), dim3(LU_THREADS), lds, s, n, bw, band, info);
     return hipGetLastError();
 }
 

@@ -1,0 +1,282 @@
+// Banded LU without pivoting, M = L U, as a pipelined tile factorisation on
+// the matrix cores (FP64).  The paper's fine solver factors the implicit-Euler
+// matrix once and reuses it for every right-hand side (Sec. 4.4); M is a
+// row- and column-diagonally dominant M-matrix, so elimination without
+// pivoting is stable.
+//
+// Tiles of 16x16: tile column J holds tile rows I = J-nb..J+nb (nb =
+// ceil(b/16)).  Right-looking elimination in tile form:
+//   for K < J (K >= J-nb):  U(K,J) = L(K,K)^{-1} A(K,J)
+//                           A(I,J) -= L(I,K) U(K,J),   K < I <= K+nb
+//   then                    A(J,J) = L(J,J) U(J,J)     (unblocked, in LDS)
+//                           L(I,J) = A(I,J) U(J,J)^{-1},  J < I <= J+nb
+// Entries outside the band stay exactly zero (each of their update terms has
+// a zero factor), so only in-band entries are stored back.
+//
+// Workgroup p owns tile columns J = p, p+P, p+2P, ... and keeps the 2nb+1
+// tiles of its current column in registers (accumulator layout, tiles dealt
+// round-robin to the waves).  When column J is done it publishes L(J,J)^{-1}
+// and the L(I,J) tiles (MFMA A-operand layout) and raises flag[J]; the owner
+// of a later column waits for flag[K] before applying panel K.  Every wait
+// is bounded: on time-out it raises *err and the kernel runs to its end.
+// All P workgroups are resident together (P is a few dozen), and every wait
+// is for a lower column, so the pipeline always drains.
+#include "lrpr_internal.h"
+
+namespace lrpr {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// MFMA A-operand tiles, lane-major: chunk kc of lane l at 128 (kc/2) + 2 l +
+// kc%2; lane l = 16 g + m holds row m, contraction index k = 4 kc + g.
+__device__ __forceinline__ int apos(int m, int k) { return 128 * ((k >> 2) >> 1) + 2 * (16 * (k & 3) + m) + ((k >> 2) & 1); }
+typedef __attribute__((address_space(1))) const d2v *gd2p;
+__device__ __forceinline__ void ld_a(const double *tile, int lane, double (&v)[4]) {
+    const d2v x = *(gd2p)(tile + 2 * lane), y = *(gd2p)(tile + 128 + 2 * lane);
+    v[0] = x[0]; v[1] = x[1]; v[2] = y[0]; v[3] = y[1];
+}
+
+struct LuArgs {
+    int64_t n;
+    int bw, NT, nb;
+    double *band;   // n x (2bw+1) row-major: in M, out L (strict lower) and U
+    double *Lt;     // [NT][nb] tiles: L(K+1+d, K), A-operand layout
+    double *Li;     // [NT] tiles: L(K,K)^{-1}, A-operand layout
+    int *flag;      // [NT], zero on entry
+    int *info;      // min over bad pivots of (row + 1); 0x7f7f7f7f if none
+    int *err;       // nonzero after a wait timed out
+    int spin_limit;
+};
+
+// wait until column K is published (thread 0 polls, the workgroup follows)
+__device__ __forceinline__ void wait_col(const LuArgs &a, int K) {
+    if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_load(a.flag + K, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+            if (++spins > a.spin_limit) {
+                __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <int NW, int TPW>
+__global__ __launch_bounds__(64 * NW) void k_tile_lu(LuArgs a) {
+    __shared__ double ubuf[2][256];   // U(K,J), accumulator order
+    __shared__ double sd[256];        // diagonal tile, row-major
+    __shared__ double sli[256];       // L(J,J)^{-1}, row-major
+    __shared__ double sui[256];       // U(J,J)^{-1}, row-major
+    __shared__ double st[NW][256];    // per-wave transposition buffer
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, c = lane & 15;
+    const int nb = a.nb, NT = a.NT, bw = a.bw;
+    const int64_t n = a.n, W = 2 * bw + 1;
+    double *band = a.band;
+
+    for (int J = blockIdx.x; J < NT; J += gridDim.x) {
+        // ---- load tile column J (tile t = I - J + nb, owned by wave t % NW)
+        v4d acc[TPW];
+#pragma unroll
+        for (int s = 0; s < TPW; ++s) {
+            const int t = w + NW * s;
+            const int I = J - nb + t;
+            const bool ex = t <= 2 * nb && I >= 0 && I < NT;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t row = (int64_t)I * TILE + 4 * i + g, col = (int64_t)J * TILE + c;
+                double v = 0.0;
+                if (ex) {
+                    if (row >= n || col >= n) v = (row == col) ? 1.0 : 0.0;   // padding: identity
+                    else if (col - row <= bw && row - col <= bw) v = band[row * W + (col - row) + bw];
+                }
+                acc[s][i] = v;
+            }
+        }
+        // ---- apply panels K = J-nb .. J-1
+        const int K0 = J - nb > 0 ? J - nb : 0;
+        for (int K = K0; K < J; ++K) {
+            wait_col(a, K);
+            const int tK = K - J + nb;
+            double *ub = ubuf[K & 1];
+            if (w == tK % NW) {
+                double li[4];
+                ld_a(a.Li + (int64_t)K * TILE_ELEMS, lane, li);
+#pragma unroll
+                for (int s = 0; s < TPW; ++s) {
+                    if (s == tK / NW) {
+                        v4d u = {0, 0, 0, 0};
+#pragma unroll
+                        for (int kc = 0; kc < 4; ++kc) u = mfma64(li[kc], acc[s][kc], u);
+                        acc[s] = u;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) ub[i * 64 + lane] = u[i];
+                    }
+                }
+            }
+            __syncthreads();
+            double ubv[4];
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) ubv[kc] = ub[kc * 64 + lane];
+#pragma unroll
+            for (int s = 0; s < TPW; ++s) {
+                const int t = w + NW * s;
+                const int I = J - nb + t;
+                if (t <= 2 * nb && I > K && I <= K + nb && I < NT) {
+                    double l[4];
+                    ld_a(a.Lt + ((int64_t)K * nb + (I - K - 1)) * TILE_ELEMS, lane, l);
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) acc[s] = mfma64(-l[kc], ubv[kc], acc[s]);
+                }
+            }
+        }
+        // ---- diagonal tile: unblocked LU in LDS
+        if (w == nb % NW) {
+#pragma unroll
+            for (int s = 0; s < TPW; ++s)
+                if (s == nb / NW) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) sd[(4 * i + g) * TILE + c] = acc[s][i];
+                }
+        }
+        __syncthreads();
+        const int r = (tid >> 4) & 15, q = tid & 15;
+        for (int p = 0; p < TILE; ++p) {
+            const double piv = sd[p * TILE + p];
+            if (tid == 0 && (int64_t)J * TILE + p < n && !(piv != 0.0 && isfinite(piv)))
+                atomicMin(a.info, J * TILE + p + 1);
+            if (tid < 256 && r > p && q == p) sd[r * TILE + p] /= piv;
+            __syncthreads();
+            if (tid < 256 && r > p && q > p) sd[r * TILE + q] -= sd[r * TILE + p] * sd[p * TILE + q];
+            __syncthreads();
+        }
+        // inverses of the unit-lower L(J,J) (threads 0..15, one column each)
+        // and of the upper U(J,J) (threads 16..31)
+        if (tid < TILE) {
+            double x[TILE];
+#pragma unroll
+            for (int rr = 0; rr < TILE; ++rr) {
+                double v = (rr == tid) ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = 0; k < rr; ++k) v -= sd[rr * TILE + k] * x[k];
+                x[rr] = v;
+                sli[rr * TILE + tid] = v;
+            }
+        } else if (tid < 2 * TILE) {
+            const int cc = tid - TILE;
+            double x[TILE];
+#pragma unroll
+            for (int rr = TILE - 1; rr >= 0; --rr) {
+                double v = (rr == cc) ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = rr + 1; k < TILE; ++k) v -= sd[rr * TILE + k] * x[k];
+                x[rr] = v / sd[rr * TILE + rr];
+                sui[rr * TILE + cc] = x[rr];
+            }
+        }
+        __syncthreads();
+        if (tid < 256) a.Li[(int64_t)J * TILE_ELEMS + apos(r, q)] = sli[r * TILE + q];
+        // ---- L(I,J) = A(I,J) U(J,J)^{-1}: A(I,J) as A operand via the wave's
+        //      transposition buffer, U^{-1} as B operand
+        double uiv[4];
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) uiv[kc] = sui[(4 * kc + g) * TILE + c];
+        double *stw = st[w];
+#pragma unroll
+        for (int s = 0; s < TPW; ++s) {
+            const int t = w + NW * s;
+            const int I = J - nb + t;
+            if (t > nb && t <= 2 * nb && I < NT) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) stw[(4 * i + g) * TILE + c] = acc[s][i];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                v4d l = {0, 0, 0, 0};
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) l = mfma64(stw[c * TILE + 4 * kc + g], uiv[kc], l);
+                acc[s] = l;
+                double *dst = a.Lt + ((int64_t)J * nb + (t - nb - 1)) * TILE_ELEMS;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dst[apos(4 * i + g, c)] = l[i];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        // ---- publish panel J
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(a.flag + J, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // ---- store the column's factors into the band (in-band entries)
+#pragma unroll
+        for (int s = 0; s < TPW; ++s) {
+            const int t = w + NW * s;
+            const int I = J - nb + t;
+            if (t <= 2 * nb && t != nb && I >= 0 && I < NT) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t row = (int64_t)I * TILE + 4 * i + g, col = (int64_t)J * TILE + c;
+                    if (row < n && col < n && col - row <= bw && row - col <= bw)
+                        band[row * W + (col - row) + bw] = acc[s][i];
+                }
+            }
+        }
+        if (tid < 256) {
+            const int64_t row = (int64_t)J * TILE + r, col = (int64_t)J * TILE + q;
+            if (row < n && col < n && col - row <= bw && row - col <= bw) band[row * W + (col - row) + bw] = sd[r * TILE + q];
+        }
+        __syncthreads();   // sd, sli, sui, ubuf are reused by the next column
+    }
+}
+
+size_t tile_lu_scratch_bytes(int NT, int nb) {
+    return sizeof(double) * ((size_t)NT * nb + NT) * TILE_ELEMS + sizeof(int) * ((size_t)NT + 2);
+}
+
+hipError_t launch_tile_lu(int64_t n, int bw, int NT, int nb, double *band, void *scratch, int **info_dev,
+                          int **err_dev, hipStream_t s) {
+    LuArgs a;
+    a.n = n;
+    a.bw = bw;
+    a.NT = NT;
+    a.nb = nb;
+    a.band = band;
+    a.Lt = (double *)scratch;
+    a.Li = a.Lt + (size_t)NT * nb * TILE_ELEMS;
+    a.flag = (int *)(a.Li + (size_t)NT * TILE_ELEMS);
+    a.info = a.flag + NT;
+    a.err = a.info + 1;
+    a.spin_limit = 1 << 22;
+    *info_dev = a.info;
+    *err_dev = a.err;
+    hipError_t e;
+    if ((e = hipMemsetAsync(a.flag, 0, sizeof(int) * (size_t)NT, s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(a.info, 0x7f, sizeof(int), s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(a.err, 0, sizeof(int), s)) != hipSuccess) return e;
+    int P = nb + 9;
+    if (P > NT) P = NT;
+    if (nb <= 4)
+        hipLaunchKernelGGL((k_tile_lu<4, 3>), dim3(P), dim3(256), 0, s, a);
+    else if (nb <= 16)
+        hipLaunchKernelGGL((k_tile_lu<4, 9>), dim3(P), dim3(256), 0, s, a);
+    else if (nb <= 32)
+        hipLaunchKernelGGL((k_tile_lu<4, 17>), dim3(P), dim3(256), 0, s, a);
+    else if (nb <= 64)
+        hipLaunchKernelGGL((k_tile_lu<8, 17>), dim3(P), dim3(512), 0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace lrpr
