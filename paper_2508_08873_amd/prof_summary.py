@@ -1,0 +1,117 @@
+"""Summaries of rocprofv3 output for the sweep kernel, written to profiles/.
+
+    python -m paper_2508_08873_amd.prof_summary --name NAME --command CMD \\
+        --stats DIR/kt_kernel_stats.csv \\
+        [--fetch DIR/..._counter_collection.csv --write DIR/..._counter_collection.csv \\
+         --calib-fetch DIR/... --calib-write DIR/... --calib-bytes B] [--bench bench.json]
+
+Writes profiles/NAME.md (human-readable: per-kernel time table, HBM bytes per
+sweep launch, the calibration factors) and profiles/NAME.json (the figures
+bench.py reads for ``roofline.traffic``), both stamped with a hash of the
+sweep kernel's sources: bench.py reports the traffic only while the sources
+still hash to the same value.
+
+HBM bytes: FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled
+by (bytes a plain device copy of known size moves) / (what the same counter
+reads for that copy).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import statistics
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+SWEEP_SOURCES = ["csrc/sweep.hip", "csrc/lrpr_internal.h", "csrc/factor.hip"]
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha1()
+    for rel in SWEEP_SOURCES:
+        with open(os.path.join(PKG, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _counter(path, match):
+    vals = []
+    for r in csv.DictReader(open(path)):
+        if match in r["Kernel_Name"]:
+            vals.append(float(r["Counter_Value"]) * 1024.0)
+    return vals
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--name", required=True)
+    ap.add_argument("--command", required=True, help="the full command the figures come from")
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--calib-fetch")
+    ap.add_argument("--calib-write")
+    ap.add_argument("--calib-bytes", type=float, default=0.0)
+    ap.add_argument("--calib-kernel", default="copyBuffer")
+    ap.add_argument("--kernel", default="k_sweep")
+    ap.add_argument("--bench")
+    args = ap.parse_args()
+
+    rows = list(csv.DictReader(open(args.stats)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = ["# rocprofv3 summary: %s" % args.name, "", "Command:", "", "    " + args.command, "",
+             "Kernel time (`--kernel-trace --stats`):", "",
+             "| kernel | calls | total ms | avg ms | % |", "|---|---|---|---|---|"]
+    for r in rows[:14]:
+        name = r["Name"]
+        if len(name) > 70:
+            name = name[:67] + "..."
+        lines.append("| `%s` | %s | %.2f | %.4f | %.1f |" % (name.replace("|", "/"), r["Calls"],
+                                                           float(r["TotalDurationNs"]) / 1e6,
+                                                           float(r["AverageNs"]) / 1e6,
+                                                           100.0 * float(r["TotalDurationNs"]) / total))
+    sweep = [r for r in rows if args.kernel in r["Name"]]
+    calls = sum(int(r["Calls"]) for r in sweep)
+    avg_ms = sum(float(r["TotalDurationNs"]) for r in sweep) / max(calls, 1) / 1e6
+    out = {"name": args.name, "command": args.command, "kernel": args.kernel, "source_sha1": sweep_source_hash(),
+           "sweep_launches": calls, "sweep_avg_launch_ms": avg_ms}
+    lines += ["", "Sweep kernel (`%s`, all instantiations): %d launches, average %.3f ms per launch." %
+              (args.kernel, calls, avg_ms)]
+    if args.fetch and args.write and args.calib_fetch and args.calib_write and args.calib_bytes > 0:
+        cf = _counter(args.calib_fetch, args.calib_kernel)
+        cw = _counter(args.calib_write, args.calib_kernel)
+        kf = args.calib_bytes / statistics.mean(cf)
+        kw = args.calib_bytes / statistics.mean(cw)
+        f = _counter(args.fetch, args.kernel)
+        w = _counter(args.write, args.kernel)
+        fb = statistics.mean(f) * kf
+        wb = statistics.mean(w) * kw
+        out.update({"calib_factor_fetch": kf, "calib_factor_write": kw, "fetch_bytes_per_launch": fb,
+                    "write_bytes_per_launch": wb, "traffic_bytes_per_launch": fb + wb,
+                    "fetch_bytes_each": [x * kf for x in f], "write_bytes_each": [x * kw for x in w]})
+        lines += ["", "HBM traffic (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`, separate runs of the same command):",
+                  "",
+                  "- copy calibration: a %.0f-byte device copy reads FETCH_SIZE x %.3f and WRITE_SIZE x %.3f of "
+                  "the bytes it moves; the factors below undo that" % (args.calib_bytes, 1 / kf, 1 / kw),
+                  "- factors: fetch x %.3f, write x %.3f" % (kf, kw),
+                  "- per sweep launch (mean over %d launches): fetch %.2f GB, write %.2f GB, total %.2f GB" %
+                  (len(f), fb / 1e9, wb / 1e9, (fb + wb) / 1e9),
+                  "- per launch: " + ", ".join("%.2f+%.2f GB" % (a * kf / 1e9, b * kw / 1e9) for a, b in zip(f, w))]
+    if args.bench:
+        b = json.loads(open(args.bench).read().strip().splitlines()[-1])
+        lines += ["", "Bench line of the same build:", "", "    " + json.dumps(b)]
+    lines += ["", "Sweep sources hash (sha1 of %s): `%s`" % (", ".join(SWEEP_SOURCES), out["source_sha1"])]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", args.name + ".md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(os.path.join(ROOT, "profiles", args.name + ".json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("wrote profiles/%s.md and .json" % args.name)
+
+
+if __name__ == "__main__":
+    main()
