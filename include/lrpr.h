@@ -248,6 +248,61 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
                                 const double *fscale, double tol, int max_iter, double *U,
                                 int *iters_host, double *incr_host, double *apost_host);
 
+
+/* ---- serving: continuous batching of Parareal solves (Sec. 2) ----------- */
+
+/* The coarse propagators depend on the source only through b_n = F_n 0
+ * (eq. F_n_affine, eq. spectral_G), so the device-resident U_k, S_k, V_k of
+ * an operator serve every request that brings a new initial value and
+ * source.  The server runs the iteration of eq. def_Parareal per request
+ * (FP64 fine steps) and batches all requests of an operator into one fine
+ * sweep and one coarse sweep per step; requests that arrive while a step is
+ * on the GPU join the operator's next step.  Operators step independently
+ * on their own streams.  A request's result does not depend on which other
+ * requests share its steps.
+ *
+ * Threading: one host thread per server.  Calls that overlap on one server
+ * are not supported. */
+typedef struct lrpr_server_s *lrpr_server;
+
+typedef struct {
+    lrpr_coarse C;          /* coarse propagators of the operator's N slices */
+    const lrpr_fac *F;      /* host array of N factor handles (may alias one;
+                               must keep FP64 tiles); read at create time */
+    int nsteps;             /* implicit-Euler steps per slice */
+    const double *fscale;   /* device, N*nsteps source time factors (as in
+                               lrpr_parareal_solve) or NULL (= 1); copied */
+} lrpr_serve_op;
+
+/* budget_bytes bounds the server's per-request device state (2*N*n doubles
+ * per admitted request); requests wait in a FIFO per operator until their
+ * state fits.  max_active_per_op caps the requests per step of one operator
+ * (0: as many as the coarse kernel takes, 12288/k).  The handles in ops must
+ * outlive the server.  Errors: LRPR_ERR_ARG, LRPR_ERR_NOMEM, LRPR_ERR_HIP. */
+lrpr_status lrpr_server_create(lrpr_ctx ctx, int nops, const lrpr_serve_op *ops, double tol,
+                               size_t budget_bytes, int max_active_per_op, lrpr_server *out);
+/* Synchronises the server's streams and frees everything it owns. */
+void lrpr_server_destroy(lrpr_server s);
+/* Queue a request for operator op: u0 and f device vectors (n, FP64), U the
+ * device output (n x (N+1), FP64, column s = u_s).  All three are caller
+ * memory that must stay valid until the request is reported done; U holds
+ * the last iterate then.  No GPU work is done here.  *id is the request's
+ * handle in lrpr_server_progress.  Errors: LRPR_ERR_ARG, LRPR_ERR_NOMEM
+ * (the request alone exceeds the budget). */
+lrpr_status lrpr_server_submit(lrpr_server s, int op, const double *u0, const double *f, double *U,
+                               int64_t *id);
+/* Advance the server: finish steps that completed, admit queued requests,
+ * launch the next step of every idle operator with work.  wait != 0 blocks
+ * until at least one step completes (if any is in flight).  Returns up to
+ * max_done completed requests (ids and iteration counts; -1 for a request
+ * whose increments became non-finite); the others are returned by later
+ * calls. */
+lrpr_status lrpr_server_progress(lrpr_server s, int wait, int max_done, int64_t *done_ids, int *done_iters,
+                                 int *ndone);
+/* Requests queued / in the current steps, and the budgeted bytes in use. */
+lrpr_status lrpr_server_stats(lrpr_server s, int *queued, int *active, int64_t *bytes_in_use);
+const char *lrpr_server_last_error(lrpr_server s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,15 @@ struct LrArgs {            // low-rank apply / Parareal correction on w columns
     int k, w;
     int mode;
     int pad_;
+    // Column tables (used when cu != null, modes 1 and 2 per column): column
+    // c works on slice s of its own request, x = cu[c] + coff, out = cu[c] +
+    // coff + n, gold = cgold[c] + coff, bvec = Fu = cfu[c] + coff (FP64),
+    // mode = cmode[c] (0 = leave the column untouched).
+    double *const *cu;
+    double *const *cgold;
+    const double *const *cfu;
+    const int *cmode;
+    int64_t coff;
 };
 
 int gram_chunks(int64_t nmax);

@@ -479,7 +479,9 @@ __global__ __launch_bounds__(LR_THREADS) void k_lr_dots(LrArgs a) {
 #pragma unroll
                 for (int q = 0; q < LR_RB; ++q) vv[q] = (rb + q < a.k) ? a.V[i + (int64_t)(rb + q) * a.n] : 0.0;
 #pragma unroll
-                for (int q = 0; q < LR_CB; ++q) xx[q] = (cb + q < a.w) ? a.x[i + (int64_t)(cb + q) * a.n] : 0.0;
+                for (int q = 0; q < LR_CB; ++q)
+                    xx[q] = (cb + q >= a.w) ? 0.0
+                            : a.cu ? a.cu[cb + q][a.coff + i] : a.x[i + (int64_t)(cb + q) * a.n];
 #pragma unroll
                 for (int p = 0; p < LR_RB; ++p)
 #pragma unroll
@@ -511,7 +513,9 @@ __global__ __launch_bounds__(LR_THREADS) void k_lr_dots(LrArgs a) {
 // g = U coef for the block's rows; mode 0: out = g; mode 1 (Parareal
 // initialisation): gold = g, out = g + bvec; mode 2 (correction):
 // u_new = Fu + g - gold, incpart += ||u_new - out||^2, out = u_new, gold = g.
-// Columns with active[c] == 0 are left untouched (modes 1, 2).
+// Columns with active[c] == 0 are left untouched (modes 1, 2).  With column
+// tables the mode is per column (and 0 means untouched); increments are
+// written for every column (zero unless mode 2).
 __global__ __launch_bounds__(LR_THREADS) void k_lr_combine(LrArgs a) {
     extern __shared__ double coef[];   // [k*w]
     __shared__ double red[LR_THREADS / 64][LR_CB];
@@ -526,10 +530,34 @@ __global__ __launch_bounds__(LR_THREADS) void k_lr_combine(LrArgs a) {
     const int64_t r0 = (int64_t)blockIdx.x * LR_CHUNK;
     const int64_t r1 = (r0 + LR_CHUNK < a.n) ? r0 + LR_CHUNK : a.n;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool incs = a.mode == 2 || a.cu;
     for (int cb = 0; cb < a.w; cb += LR_CB) {
         double inc[LR_CB];
+        // per-column operands: u (x) and out, gold, bvec / Fu, mode
+        double *outp[LR_CB], *goldp[LR_CB];
+        const double *bp[LR_CB];
+        const float *fp32[LR_CB];
+        int md[LR_CB];
 #pragma unroll
-        for (int q = 0; q < LR_CB; ++q) inc[q] = 0.0;
+        for (int q = 0; q < LR_CB; ++q) {
+            inc[q] = 0.0;
+            const int cc = cb + q < a.w ? cb + q : a.w - 1;
+            if (a.cu) {
+                outp[q] = a.cu[cc] + a.coff + a.n;
+                goldp[q] = a.cgold[cc] + a.coff;
+                bp[q] = a.cfu[cc] + a.coff;
+                fp32[q] = nullptr;
+                md[q] = cb + q < a.w ? a.cmode[cc] : 0;
+            } else {
+                const int64_t o = (int64_t)cc * a.n;
+                outp[q] = a.out + o;
+                goldp[q] = a.gold ? a.gold + o : nullptr;
+                bp[q] = a.mode == 1 ? (a.bvec ? a.bvec + o : nullptr) : (a.fu64 ? a.fu64 + o : nullptr);
+                fp32[q] = a.fu32 ? a.fu32 + o : nullptr;
+                md[q] = cb + q >= a.w ? -1 : (a.mode != 0 && a.active && !a.active[cc]) ? -1 : a.mode;
+                if (a.mode == 0 && cb + q < a.w) md[q] = 0;
+            }
+        }
         for (int64_t i = r0 + threadIdx.x; i < r1; i += LR_THREADS) {
             double gs[LR_CB];
 #pragma unroll
@@ -542,28 +570,24 @@ __global__ __launch_bounds__(LR_THREADS) void k_lr_combine(LrArgs a) {
             }
 #pragma unroll
             for (int q = 0; q < LR_CB; ++q) {
-                const int cc = cb + q;
-                if (cc >= a.w) continue;
-                const int64_t o = i + (int64_t)cc * a.n;
-                const bool active = !a.active || a.active[cc];
-                if (a.mode == 0) {
-                    a.out[o] = gs[q];
-                } else if (!active) {
-                    continue;
-                } else if (a.mode == 1) {
-                    a.gold[o] = gs[q];
-                    a.out[o] = gs[q] + (a.bvec ? a.bvec[o] : 0.0);
+                const int m = md[q];
+                if (a.cu ? m == 0 : m < 0) continue;
+                if (!a.cu && m == 0) {
+                    outp[q][i] = gs[q];
+                } else if (m == 1) {
+                    goldp[q][i] = gs[q];
+                    outp[q][i] = gs[q] + (bp[q] ? bp[q][i] : 0.0);
                 } else {
-                    const double fu = a.fu32 ? (double)a.fu32[o] : a.fu64[o];
-                    const double un = fu + gs[q] - a.gold[o];
-                    const double d = un - a.out[o];
+                    const double fu = fp32[q] ? (double)fp32[q][i] : bp[q][i];
+                    const double un = fu + gs[q] - goldp[q][i];
+                    const double d = un - outp[q][i];
                     inc[q] += d * d;
-                    a.out[o] = un;
-                    a.gold[o] = gs[q];
+                    outp[q][i] = un;
+                    goldp[q][i] = gs[q];
                 }
             }
         }
-        if (a.mode == 2) {
+        if (incs) {
 #pragma unroll
             for (int q = 0; q < LR_CB; ++q) {
                 double v = inc[q];

@@ -21,7 +21,9 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
            "lrpr_factor", "lrpr_factor_destroy", "lrpr_factor_info", "lrpr_factor_copy_lu",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build",
            "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_parareal_solve",
-           "lrpr_profile_enable", "lrpr_profile_read"]
+           "lrpr_profile_enable", "lrpr_profile_read",
+           "lrpr_server_create", "lrpr_server_destroy", "lrpr_server_submit", "lrpr_server_progress",
+           "lrpr_server_stats", "lrpr_server_last_error"]
 
 
 # lrpr_factor store_mask bits (include/lrpr.h)
@@ -44,6 +46,11 @@ class Panel(ctypes.Structure):
     _fields_ = [("F", ctypes.c_void_p), ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64),
                 ("w", ctypes.c_int), ("f", ctypes.c_void_p), ("ldf", ctypes.c_int64),
                 ("fcol", ctypes.c_void_p), ("fscale", ctypes.c_void_p)]
+
+
+class ServeOp(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_void_p), ("F", ctypes.POINTER(ctypes.c_void_p)), ("nsteps", ctypes.c_int),
+                ("fscale", ctypes.c_void_p)]
 
 
 class SliceDesc(ctypes.Structure):
@@ -85,8 +92,17 @@ def load():
     lib.lrpr_parareal_solve.argtypes = [vp, vp, P(vp), i32, i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
     lib.lrpr_profile_enable.argtypes = [vp, i32]
     lib.lrpr_profile_read.argtypes = [vp, P(dbl), P(i64), P(dbl), P(dbl), P(dbl)]
+    lib.lrpr_server_create.argtypes = [vp, i32, P(ServeOp), dbl, ctypes.c_size_t, i32, P(vp)]
+    lib.lrpr_server_destroy.argtypes = [vp]
+    lib.lrpr_server_destroy.restype = None
+    lib.lrpr_server_submit.argtypes = [vp, i32, vp, vp, vp, P(i64)]
+    lib.lrpr_server_progress.argtypes = [vp, i32, i32, P(i64), P(i32), P(i32)]
+    lib.lrpr_server_stats.argtypes = [vp, P(i32), P(i32), P(i64)]
+    lib.lrpr_server_last_error.argtypes = [vp]
+    lib.lrpr_server_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("lrpr_ctx_destroy", "lrpr_factor_destroy", "lrpr_coarse_destroy", "lrpr_last_error"):
+        if name not in ("lrpr_ctx_destroy", "lrpr_factor_destroy", "lrpr_coarse_destroy", "lrpr_last_error",
+                        "lrpr_server_destroy", "lrpr_server_last_error"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -258,6 +274,76 @@ class Coarse:
     def close(self):
         if getattr(self, "h", None):
             self.ctx.lib.lrpr_coarse_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """lrpr_server: continuous batching of Parareal solves over device-resident
+    coarse propagators.  ops: list of (coarse, factors (list of N), nsteps,
+    fscale tensor (N*nsteps doubles) or None)."""
+
+    def __init__(self, ctx, ops, tol, budget_bytes, max_active=0):
+        self.ctx, self.lib = ctx, ctx.lib
+        self._keep = []
+        arr = (ServeOp * len(ops))()
+        self.n, self.N = [], []
+        for i, (coarse, facs, nsteps, fsc) in enumerate(ops):
+            fa = (ctypes.c_void_p * len(facs))(*[f.h.value for f in facs])
+            self._keep += [coarse, facs, fa, fsc]
+            arr[i] = ServeOp(coarse.h, ctypes.cast(fa, ctypes.POINTER(ctypes.c_void_p)), int(nsteps),
+                             fsc.data_ptr() if fsc is not None else None)
+            self.n.append(facs[0].n)
+            self.N.append(len(facs))
+        h = ctypes.c_void_p()
+        ctx.sync_stream()
+        torch.cuda.current_stream(ctx.device).synchronize()
+        ctx._check(self.lib.lrpr_server_create(ctx.h, len(ops), arr, float(tol), int(budget_bytes), int(max_active),
+                                               ctypes.byref(h)))
+        self.h = h
+        self.pending = {}
+
+    def _check(self, st):
+        if st != 0:
+            raise LrprError(st, self.lib.lrpr_server_last_error(self.h).decode())
+
+    def submit(self, op, u0, f, sync=True):
+        """Queue a request; returns (id, U) with U the n x (N+1) output
+        (column-major, filled when the request is reported done)."""
+        if sync:
+            torch.cuda.current_stream(self.ctx.device).synchronize()
+        n, N = self.n[op], self.N[op]
+        U = torch.empty((N + 1, n), dtype=torch.float64, device=u0.device).t()
+        rid = ctypes.c_int64()
+        self._check(self.lib.lrpr_server_submit(self.h, int(op), _ptr(u0), _ptr(f), _ptr(U), ctypes.byref(rid)))
+        self.pending[rid.value] = (u0, f, U)
+        return rid.value, U
+
+    def progress(self, wait=True, max_done=4096):
+        """Advance the server; returns [(id, iterations)] of requests done."""
+        ids = (ctypes.c_int64 * max_done)()
+        its = (ctypes.c_int * max_done)()
+        nd = ctypes.c_int()
+        self._check(self.lib.lrpr_server_progress(self.h, 1 if wait else 0, max_done, ids, its, ctypes.byref(nd)))
+        out = []
+        for i in range(nd.value):
+            self.pending.pop(ids[i], None)
+            out.append((ids[i], its[i]))
+        return out
+
+    def stats(self):
+        q, a, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        self._check(self.lib.lrpr_server_stats(self.h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(b)))
+        return {"queued": q.value, "active": a.value, "bytes_in_use": b.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lrpr_server_destroy(self.h)
             self.h = None
 
     def __del__(self):
