@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-cols", type=int, default=384)
     ap.add_argument("--cpu-steps", type=int, default=32)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--serve-duration", type=float, default=15.0, help="arrival window (s)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -91,6 +94,94 @@ def cpu_baseline_and_parity(ctx, lrpr, P, prec, ncols, nsteps, seed):
     return {"value": rate, "unit": "RHS*steps/s", "cores": threads, "kind": "oracle",
             "sample": "%d RHS x %d implicit-Euler steps of the 255^2 operator with source (FP64 C oracle, "
                       "OpenMP over RHS columns), %.1f s" % (ncols, nsteps, t1 - t0)}, err
+
+
+def serve_bench(ctx, lrpr, inputs, seed, rate, duration):
+    """Serving workload: three operators (127^2, 255^2, 511^2; nu=1,
+    beta=(10,5), c=1, 64 slices x 32 steps, k=48, p=12) with device-resident
+    coarse propagators; requests (new u0 and f each, operator uniform) arrive
+    as a Poisson stream and are served by lrpr_server with continuous batching,
+    FP64 fine steps, tolerance 1e-8.  Latency = completion - arrival."""
+    import torch
+    probs = inputs.serve3(seed=seed)
+    ops = []
+    t_setup = time.perf_counter()
+    for P in probs:
+        F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=lrpr.STORE_F64 | lrpr.STORE_MIRROR)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed * 1000 + P.nx)
+        Om = torch.randn((P.N, P.l, P.n), generator=gen, device="cuda", dtype=torch.float64)
+        coarse = ctx.rsvd_build([(F, P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, 0)
+        del Om
+        fsc = torch.from_numpy(np.concatenate([P.fscale(s) for s in range(1, P.N + 1)])).to("cuda")
+        ops.append((coarse, [F] * P.N, P.m, fsc))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    arr = inputs.arrivals(seed=seed, rate=rate, duration=duration)
+    r = inputs.rng(seed, "request", 0)
+    which = r.integers(0, len(probs), size=len(arr))
+    reqs = []
+    for i, op in enumerate(which):
+        P = probs[op]
+        reqs.append((int(op), lrpr.colmajor(torch.from_numpy(P.u0(req=i + 1)).to("cuda").reshape(-1, 1)),
+                     lrpr.colmajor(torch.from_numpy(P.source(req=i + 1)).to("cuda").reshape(-1, 1))))
+    torch.cuda.synchronize()
+    srv = lrpr.Server(ctx, ops, tol=probs[0].tol, budget_bytes=64 << 30)
+    arrival, opof, lat, iters = {}, {}, {}, {}
+    nxt = 0
+    t0 = time.perf_counter()
+    while len(lat) < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and arr[nxt] <= now:
+            op, u0, f = reqs[nxt]
+            rid, _ = srv.submit(op, u0, f, sync=False)
+            arrival[rid], opof[rid] = arr[nxt], op
+            nxt += 1
+        fin = srv.progress(wait=False)
+        tnow = time.perf_counter() - t0
+        for rid, it in fin:
+            lat[rid] = tnow - arrival[rid]
+            iters[rid] = it
+        if not fin:
+            time.sleep(0.0005)
+    t_end = time.perf_counter() - t0
+    srv.close()
+    L = np.array([lat[k] for k in sorted(lat)])
+    per_op = {}
+    for o, P in enumerate(probs):
+        lo = np.array([lat[k] for k in lat if opof[k] == o])
+        if len(lo):
+            per_op[P.name] = {"requests": int(len(lo)), "p50_s": float(np.percentile(lo, 50)),
+                              "p99_s": float(np.percentile(lo, 99)),
+                              "mean_iters": float(np.mean([iters[k] for k in iters if opof[k] == o]))}
+    for c in ops:
+        c[0].close()
+        c[1][0].close()
+    return {"workload": "serve3: operators 127^2, 255^2, 511^2 (nu=1, beta=(10,5), c=1, 64 slices x 32 steps, "
+                        "k=48, p=12), Poisson arrivals %.1f/s for %.0f s, new u0 (8x8 sine modes) and f (1-6 "
+                        "bumps) per request, FP64 fine steps, tol 1e-8" % (rate, duration),
+            "requests": int(len(L)), "p50_s": float(np.percentile(L, 50)), "p99_s": float(np.percentile(L, 99)),
+            "solves_per_s": float(len(L) / t_end), "wall_s": t_end, "setup_s": t_setup,
+            "failed": int(sum(1 for v in iters.values() if v < 0)), "per_operator": per_op}
+
+
+def plain_per_rhs(ctx, lrpr, P):
+    """Plain per-RHS FP64 form: one right-hand side through the fine
+    propagator (m steps, with source) per call, timed with events."""
+    import torch
+    F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=lrpr.STORE_F64)
+    X = lrpr.colmajor(torch.zeros((P.n, 1), dtype=torch.float64, device="cuda"))
+    f = lrpr.colmajor(torch.from_numpy(P.source().reshape(-1, 1)).to("cuda"))
+    fsc = torch.from_numpy(P.fscale(1).reshape(1, -1).copy()).to("cuda")
+    spec = {"F": F, "X": X, "f": f, "fscale": fsc}
+    ctx.fine_step_batched([spec], P.m, 0)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.fine_step_batched([spec], P.m, 0)
+    p = ctx.profile_read()
+    ctx.profile(False)
+    F.close()
+    return P.m / (p["ms"] / 1000.0)
 
 
 def traffic_from_profile(prec):
@@ -206,6 +297,10 @@ def main():
         "range_finder_sweeps_rhs_steps_per_s": rr, "parareal_sweeps_rhs_steps_per_s": pr,
         "roofline": roofline,
     }
+    res["plain_per_rhs_fp64_rhs_steps_per_s"] = plain_per_rhs(ctx, lrpr, P)
+    res["batched_vs_plain_per_rhs"] = rr / res["plain_per_rhs_fp64_rhs_steps_per_s"]
+    if not args.no_serve:
+        res["serve"] = serve_bench(ctx, lrpr, inputs, args.seed, args.serve_rate, args.serve_duration)
     if not args.no_cpu:
         cb, err = cpu_baseline_and_parity(ctx, lrpr, P, prec, args.cpu_cols, args.cpu_steps, args.seed)
         res["cpu_baseline"] = cb
