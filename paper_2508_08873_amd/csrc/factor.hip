@@ -74,16 +74,22 @@ __device__ inline int aslot(bool f32, int m, int k) {
 }
 
 // One thread per element (tile row I, band index j, row r, column q) of the
-// band tiles; writes the FP64 and/or FP32 copies of
-//   Lb[I][j] = L(I, I-nb+j), Ub[I][j] = U(I, I+1+j)
+// band tiles; writes the FP64 and/or FP32 copies of the band tiles multiplied
+// from the left by their row's diagonal-tile inverse (Linv, Uinv: FP64,
+// row-major per tile row, from k_diag_inv):
+//   Lb[I][j]  = L(I,I)^{-1}   L(I, I-nb+j)
+//   Ub[I][j]  = U(I,I)^{-1}   U(I, I+1+j)
 // and, when requested, the mirrored set
-//   UTb[I][j] = U(I-nb+j, I)^T, LTb[I][j] = L(I+1+j, I)^T.
+//   UTb[I][j] = U(I,I)^{-T}   U(I-nb+j, I)^T
+//   LTb[I][j] = L(I,I)^{-T}   L(I+1+j, I)^T.
 struct BandOut {
     void *b[4];   // Lb, Ub, UTb, LTb (null: not stored)
 };
 
-__global__ void k_pack_band(int64_t n, int bw, int NT, int nb, const double *lu, BandOut o64, BandOut o32) {
+__global__ void k_pack_band(int64_t n, int bw, int NT, int nb, const double *lu, const double *Linv,
+                            const double *Uinv, BandOut o64, BandOut o32) {
     const int64_t total = (int64_t)NT * nb * TILE_ELEMS;
+    const bool mirror = o64.b[2] || o32.b[2];
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t tileidx = e / TILE_ELEMS;
@@ -91,18 +97,24 @@ __global__ void k_pack_band(int64_t n, int bw, int NT, int nb, const double *lu,
         const int64_t I = tileidx / nb;
         const int j = (int)(tileidx % nb);
         const int r = o >> 4, q = o & 15;
-        const int64_t i = I * TILE + r;
+        const int64_t base = I * TILE;
         const int64_t jl = (I - nb + j) * TILE + q;   // column in tile row I-nb+j
         const int64_t ju = (I + 1 + j) * TILE + q;    // column in tile row I+1+j
-        double v[4];
-        v[0] = (jl < i) ? lu_at(lu, n, bw, i, jl) : 0.0;   // L strictly lower
-        v[1] = (ju > i) ? lu_at(lu, n, bw, i, ju) : 0.0;   // U strictly upper
-        v[2] = (jl < i) ? lu_at(lu, n, bw, jl, i) : 0.0;   // U^T strictly lower
-        v[3] = (ju > i) ? lu_at(lu, n, bw, ju, i) : 0.0;   // L^T strictly upper
-        const int64_t base = tileidx * TILE_ELEMS;
+        const double *Li = Linv + I * TILE_ELEMS, *Ui = Uinv + I * TILE_ELEMS;
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < TILE; ++k) {
+            const int64_t i = base + k;
+            v[0] += Li[r * TILE + k] * lu_at(lu, n, bw, i, jl);        // L(I, J)[k][q]
+            v[1] += Ui[r * TILE + k] * lu_at(lu, n, bw, i, ju);        // U(I, J)[k][q]
+            if (mirror) {
+                v[2] += Ui[k * TILE + r] * lu_at(lu, n, bw, jl, i);    // U(J, I)[q][k]
+                v[3] += Li[k * TILE + r] * lu_at(lu, n, bw, ju, i);    // L(J, I)[q][k]
+            }
+        }
+        const int64_t dst = tileidx * TILE_ELEMS;
         for (int a = 0; a < 4; ++a) {
-            if (o64.b[a]) ((double *)o64.b[a])[base + aslot(false, r, q)] = v[a];
-            if (o32.b[a]) ((float *)o32.b[a])[base + aslot(true, r, q)] = (float)v[a];
+            if (o64.b[a]) ((double *)o64.b[a])[dst + aslot(false, r, q)] = v[a];
+            if (o32.b[a]) ((float *)o32.b[a])[dst + aslot(true, r, q)] = (float)v[a];
         }
     }
 }
@@ -135,66 +147,36 @@ __global__ void k_diag_inv(int64_t n, int bw, int NT, const double *lu, double *
     }
 }
 
-// Phase 2: diagonal inverses D and the "newest-tile" products E of every
-// tile row, stored as MFMA A operands (aslot layout), FP64 and/or FP32.
-//   forward L pass (ascending):  D = L_II^{-1},      E[I] = L(I,I-1) L_{I-1,I-1}^{-1}
-//   forward U pass (descending): D = U_II^{-1},      E[I] = U(I,I+1) U_{I+1,I+1}^{-1}
-//   adjoint U^T pass (asc.):     D = U_II^{-T},      E[I] = U(I-1,I)^T U_{I-1,I-1}^{-T}
-//   adjoint L^T pass (desc.):    D = L_II^{-T},      E[I] = L(I+1,I)^T L_{I+1,I+1}^{-T}
-// so that the newest band tile's contribution to row I is E[I] applied to
-// the pre-inverse residual s of the neighbouring row (y = D s).
-// One thread per (tile row, column).
+// Phase 2: diagonal inverses DL = L(I,I)^{-1}, DU = U(I,I)^{-1} and their
+// transposes as MFMA A operands (aslot layout), FP64 and/or FP32.  One
+// thread per (tile row, column).
 struct DiagOut {
     void *D[4];   // DL, DU, DLT, DUT
-    void *E[4];   // EL, EU, ELT, EUT
 };
 
-__global__ void k_pack_diag(int64_t n, int bw, int NT, const double *lu, const double *Linv,
-                            const double *Uinv, DiagOut o64, DiagOut o32) {
+__global__ void k_pack_diag(int NT, const double *Linv, const double *Uinv, DiagOut o64, DiagOut o32) {
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (tid >= (int64_t)NT * TILE) return;
     const int64_t I = tid / TILE;
     const int col = (int)(tid % TILE);
-    const int64_t base = I * TILE;
     const double *Li = Linv + I * TILE_ELEMS, *Ui = Uinv + I * TILE_ELEMS;
-    double e[4][TILE];
-    for (int r = 0; r < TILE; ++r) {
-        double el = 0, eu = 0, eut = 0, elt = 0;
-        for (int k = 0; k < TILE; ++k) {
-            if (I >= 1) {
-                // L(I, I-1)[r][k] * Linv_{I-1}[k][col]
-                el += lu_at(lu, n, bw, base + r, base - TILE + k) * Linv[(I - 1) * TILE_ELEMS + k * TILE + col];
-                // U(I-1, I)[k][r] * Uinv_{I-1}[col][k]
-                eut += lu_at(lu, n, bw, base - TILE + k, base + r) * Uinv[(I - 1) * TILE_ELEMS + col * TILE + k];
-            }
-            if (I + 1 < NT) {
-                // U(I, I+1)[r][k] * Uinv_{I+1}[k][col]
-                eu += lu_at(lu, n, bw, base + r, base + TILE + k) * Uinv[(I + 1) * TILE_ELEMS + k * TILE + col];
-                // L(I+1, I)[k][r] * Linv_{I+1}[col][k]
-                elt += lu_at(lu, n, bw, base + TILE + k, base + r) * Linv[(I + 1) * TILE_ELEMS + col * TILE + k];
-            }
-        }
-        e[0][r] = el; e[1][r] = eu; e[2][r] = elt; e[3][r] = eut;
-    }
     const int64_t off = I * TILE_ELEMS;
     for (int r = 0; r < TILE; ++r) {
-        // D entries (r, col) and transposes (col, r); E entries (r, col)
         const double dv[4] = {Li[r * TILE + col], Ui[r * TILE + col], Li[col * TILE + r], Ui[col * TILE + r]};
         for (int a = 0; a < 4; ++a) {
-            if (o64.D[a]) {
-                ((double *)o64.D[a])[off + aslot(false, r, col)] = dv[a];
-                ((double *)o64.E[a])[off + aslot(false, r, col)] = e[a][r];
-            }
-            if (o32.D[a]) {
-                ((float *)o32.D[a])[off + aslot(true, r, col)] = (float)dv[a];
-                ((float *)o32.E[a])[off + aslot(true, r, col)] = (float)e[a][r];
-            }
+            if (o64.D[a]) ((double *)o64.D[a])[off + aslot(false, r, col)] = dv[a];
+            if (o32.D[a]) ((float *)o32.D[a])[off + aslot(true, r, col)] = (float)dv[a];
         }
     }
 }
 
 hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu, const TileSet *t64,
                              const TileSet *t32, double *scratch, hipStream_t s) {
+    const int64_t th = (int64_t)NT * TILE;
+    double *Linv = scratch, *Uinv = scratch + (size_t)NT * TILE_ELEMS;
+    hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, n, bw, NT, lu, Linv, Uinv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int64_t total = (int64_t)NT * nb * TILE_ELEMS;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
@@ -205,23 +187,15 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
         b64.b[a] = t64 ? t64->a[bidx[a]] : nullptr;
         b32.b[a] = t32 ? t32->a[bidx[a]] : nullptr;
     }
-    hipLaunchKernelGGL(k_pack_band, dim3((unsigned)blocks), dim3(256), 0, s, n, bw, NT, nb, lu, b64, b32);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t th = (int64_t)NT * TILE;
-    double *Linv = scratch, *Uinv = scratch + (size_t)NT * TILE_ELEMS;
-    hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, n, bw, NT, lu, Linv, Uinv);
+    hipLaunchKernelGGL(k_pack_band, dim3((unsigned)blocks), dim3(256), 0, s, n, bw, NT, nb, lu, Linv, Uinv, b64, b32);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     DiagOut o64{}, o32{};
-    const int didx[4] = {TS_DL, TS_DU, TS_DLT, TS_DUT}, eidx[4] = {TS_EL, TS_EU, TS_ELT, TS_EUT};
+    const int didx[4] = {TS_DL, TS_DU, TS_DLT, TS_DUT};
     for (int a = 0; a < 4; ++a) {
         o64.D[a] = t64 ? t64->a[didx[a]] : nullptr;
-        o64.E[a] = t64 ? t64->a[eidx[a]] : nullptr;
         o32.D[a] = t32 ? t32->a[didx[a]] : nullptr;
-        o32.E[a] = t32 ? t32->a[eidx[a]] : nullptr;
     }
-    hipLaunchKernelGGL(k_pack_diag, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, n, bw, NT, lu, Linv,
-                       Uinv, o64, o32);
+    hipLaunchKernelGGL(k_pack_diag, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, NT, Linv, Uinv, o64, o32);
     return hipGetLastError();
 }
 

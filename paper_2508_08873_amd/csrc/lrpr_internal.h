@@ -18,16 +18,19 @@ namespace lrpr {
 //
 // The unknowns are cut into tile rows of 16 (NT = ceil(n/16)); the band of
 // half-width b spans nb = ceil(b/16) tiles on each side of the diagonal.
-//   Lb[I][j]  = L(I, I-nb+j),  j = 0..nb-1   (strictly-left band tiles of L)
-//   Ub[I][j]  = U(I, I+1+j),   j = 0..nb-1   (strictly-right band tiles of U)
-//   UTb[I][j] = U^T(I, I-nb+j)               (mirrored set, optional)
-//   LTb[I][j] = L^T(I, I+1+j)                (mirrored set, optional)
-//   DL[I], DU[I]   = inverses of the diagonal tiles L(I,I), U(I,I)
-//   DLT[I], DUT[I] = their transposes (adjoint sweeps)
-//   EL[I] = L(I,I-1) DL[I-1],   EU[I] = U(I,I+1) DU[I+1]
-//   EUT[I] = U(I-1,I)^T DUT[I-1], ELT[I] = L(I+1,I)^T DLT[I+1]
-// Tiles outside the matrix are zero; the diagonal tiles of the padded rows
-// beyond n are the identity.  Each tile has 256 elements.
+// With DL[I], DU[I] the inverses of the diagonal tiles L(I,I), U(I,I) and
+// DLT[I], DUT[I] their transposes, the band tiles are stored multiplied from
+// the left by their own row's inverse:
+//   Lb[I][j]  = DL[I]  L(I, I-nb+j),    j = 0..nb-1
+//   Ub[I][j]  = DU[I]  U(I, I+1+j),     j = 0..nb-1
+//   UTb[I][j] = DUT[I] U^T(I, I-nb+j)   (mirrored set, optional)
+//   LTb[I][j] = DLT[I] L^T(I, I+1+j)    (mirrored set, optional)
+// so that a substitution pass reads y_I = D_I r_I - sum_J A_IJ y_J.  The
+// transposes of the forward tiles are U^T(I,J) DUT[J] and L^T(I,J) DLT[J]:
+// the adjoint without a mirrored set runs the form s_I = r_I - sum_J B_IJ s_J,
+// y_I = D_I s_I on them.  Tiles outside the matrix are zero; the diagonal
+// tiles of the padded rows beyond n are the identity.  Each tile has 256
+// elements.
 //
 // Every tile is stored as MFMA A operands, lane-major: the four values lane l
 // feeds to the four 16x16x4 products of a 16x16x16 contraction sit together
@@ -44,7 +47,7 @@ constexpr int TILE_ELEMS = 256;
 // the sweep's prefetch window, reads land on zeros)
 inline int guard_rows(int nb) { return nb + 8; }
 
-enum { TS_LB, TS_UB, TS_UTB, TS_LTB, TS_DL, TS_DU, TS_DLT, TS_DUT, TS_EL, TS_EU, TS_ELT, TS_EUT, TS_COUNT };
+enum { TS_LB, TS_UB, TS_UTB, TS_LTB, TS_DL, TS_DU, TS_DLT, TS_DUT, TS_COUNT };
 
 struct TileSet {            // device arrays of one precision (pointers to tile row 0)
     void *a[TS_COUNT] = {};      // indexed by TS_*; UTb/LTb null without the mirrored set

@@ -7,26 +7,29 @@
 // adjoint (Sec. 2.1, step 3) solves M^T z = x with M^T = U^T L^T: forward
 // with U^T, back with L^T.  Both are the same two-pass sweep over band tiles:
 // the forward set holds L and U, the mirrored set U^T and L^T of the same LU.
-// Without a mirrored set the adjoint reads the forward tiles transposed.
 //
-// Blocking.  Rows are cut into tile rows of 16.  For tile row I of a pass
-//     y_I = D_I s_I,   s_I = r_I - sum_{bulk J} B_IJ y_J - E_I s_{I-1}
-// where the B_IJ are the nb-1 older band tiles, D_I is the inverse of the
-// diagonal tile and E_I = B_{I,I-1} D_{I-1} is the newest band tile times the
-// neighbour's inverse, so the row-to-row recurrence only runs through s.
-// Every product is a 16x16x16 contraction on the matrix cores
+// Blocking.  Rows are cut into tile rows of 16.  The band tiles are stored
+// multiplied from the left by their row's diagonal-tile inverse D_I, so a
+// pass reads, per tile row I,
+//     v_I = D_I r_I - sum_{bulk J} A_IJ v_J - A_{I,I-1} v_{I-1}      (left)
+// with v the pass's solution.  Without a mirrored set the adjoint reads the
+// forward tiles transposed, which are multiplied from the right instead:
+//     v_I = r_I - sum_{bulk J} B_IJ v_J - B_{I,I-1} v_{I-1},  y_I = D_I v_I
+// (right).  Either way the row-to-row recurrence runs through one 16x16x16
+// product with the newest tile; every product runs on the matrix cores
 // (v_mfma_*_16x16x4), 16 right-hand sides per workgroup.
 //
-// Waves of a workgroup (KW = 8):
-//   wave 0        finisher: s, t = E s, y = D s, ring and HBM store;
-//   waves 1..5    bulk: partial sums over the older band tiles, operands
+// Waves of a workgroup (KW = 8), one LDS barrier per tile row:
+//   wave 0        finisher: v = r - partials - t, ring store, t = E v;
+//   waves 1..5    bulk: partial sums over the nb-1 older band tiles, operands
 //                 prefetched PD-1 tile rows ahead into registers;
-//   wave 6        factor helper: prefetches D and E of coming rows;
-//   wave 7        state helper: prefetches the right-hand side rows.
-// The last nb solved tiles live in an LDS ring; helpers hand their operands
-// to the finisher through a triple-buffered LDS area.  One barrier per tile
-// row orders LDS traffic only, so prefetches stay in flight across it.
-// Narrow bands (nb <= 4) run one wave that does everything.
+//   wave 6        factor helper: hands the newest tile E of the coming row to
+//                 the finisher; writes the pass output (v, or D v) to HBM;
+//   wave 7        state helper: hands r (D (x + dt phi f), or x) to the
+//                 finisher.
+// The finisher computes row q after barrier q+1 from the bulk partials of row
+// q (computed between barriers q and q+1) and the hand-off of row q.  The last
+// nb solved tiles live in an LDS ring.  Narrow bands (nb <= 4) run one wave.
 #include "lrpr_internal.h"
 
 namespace lrpr {
@@ -78,6 +81,24 @@ template <> struct Mf<float> {
     }
 };
 
+constexpr int max5(int a, int b, int c, int d, int e) {
+    int m = a;
+    m = b > m ? b : m;
+    m = c > m ? c : m;
+    m = d > m ? d : m;
+    return e > m ? e : m;
+}
+
+// Distribution of the nb-1 older ("bulk") band tiles of a tile row over the
+// five bulk waves 1..5: wave w takes the contiguous range after the counts of
+// the waves before it.  Waves w and w+4 share a SIMD (and so its matrix core);
+// wave 0 (finisher) sits on SIMD 0 and the helpers on SIMDs 2 and 3.
+template <int C1, int C2, int C3, int C4, int C5>
+struct Split {
+    static constexpr int c1 = C1, c2 = C2, c3 = C3, c4 = C4, c5 = C5;
+    static constexpr int cmax = max5(C1, C2, C3, C4, C5);
+};
+
 // Barrier that orders LDS traffic only: outstanding global loads (the
 // prefetches of later tile rows) stay in flight across it.
 __device__ __forceinline__ void lds_barrier() {
@@ -88,25 +109,25 @@ __device__ __forceinline__ void lds_barrier() {
 
 // One pass (ascending or descending tile rows) over one 16-column group.
 //   band  : band tiles of the pass, nb per tile row (row I, index j)
-//   dtile : diagonal inverses; etile: newest-tile products (one per row)
-//   STRIDED: the band tiles are the forward set's, read transposed: tile
-//            (row J, index nb-1-j), each lane gathering its four values.
+//   dtile : diagonal-tile inverses (one per row)
+//   STRIDED: the band tiles are the forward set's, read transposed (tile (row
+//            J, index nb-1-j), each lane gathering its four values); the pass
+//            then runs the right form, otherwise the left form.
 // Registers and LDS hold 16x16 blocks in accumulator order: value i of lane
 // l is row Mf::row(l/16, i), column l%16 — the B operand of chunk i.
-template <typename T, int KW, int TPW, int PD, bool ASC, bool STRIDED>
+template <typename T, int KW, int PD, bool ASC, bool STRIDED>
 struct Pass {
     typedef typename Mf<T>::v4 v4;
     static constexpr int NBW = KW > 1 ? KW - 3 : 1;   // bulk waves
     const T *__restrict__ band;
     const T *__restrict__ dtile;
-    const T *__restrict__ etile;
     const T *__restrict__ zt;
     T *ring;
     int lane, w, g, c, n, NT, nb, RS, nbulk;
     int soff[4];   // STRIDED: position of this lane's chunk values in a forward tile
 
-    __device__ Pass(const SweepItem &it, const T *band_, const T *dtile_, const T *etile_, T *ring_)
-        : band(band_), dtile(dtile_), etile(etile_), zt((const T *)it.fac.zt), ring(ring_) {
+    __device__ Pass(const SweepItem &it, const T *band_, const T *dtile_, T *ring_)
+        : band(band_), dtile(dtile_), zt((const T *)it.fac.zt), ring(ring_) {
         lane = threadIdx.x & 63;
         w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform (scalar)
         g = lane >> 4;
@@ -131,12 +152,11 @@ struct Pass {
         if (STRIDED) return band + ((int64_t)J * nb + (nb - 1 - j)) * TILE_ELEMS;
         return band + ((int64_t)I * nb + j) * TILE_ELEMS;
     }
-    // bulk tile t of bulk wave wb.  Tile rows outside [0, NT) are zero guard
-    // rows of the tile arrays, so every address within the prefetch window is
-    // valid; surplus slots (idx >= nb-1) read the zero tile.
-    __device__ __forceinline__ bool bulk(int q, int wb, int t, int &j, int &J) const {
+    // bulk tile idx (0..nb-2) of row q.  Tile rows outside [0, NT) are zero
+    // guard rows of the tile arrays, so every address within the prefetch
+    // window is valid; surplus slots (idx >= nb-1) read the zero tile.
+    __device__ __forceinline__ bool bulk(int q, int idx, int &j, int &J) const {
         const int I = row_of(q);
-        const int idx = wb + NBW * t;
         j = ASC ? idx : idx + 1;
         J = ASC ? I - nb + j : I + 1 + j;
         return idx < nbulk;
@@ -149,14 +169,25 @@ struct Pass {
             Mf<T>::ld4(tp, lane, v);
         }
     }
+    // tiles st..st+cn-1 of row q into slots 0..cn-1 (loads are unconditional:
+    // slots >= cn read the zero tile)
     template <int NTP>
-    __device__ __forceinline__ void load_bulk(int q, int wb, T (&ab)[NTP][4]) const {
+    __device__ __forceinline__ void load_bulk(int q, int st, int cn, T (&ab)[NTP][4]) const {
         const int I = row_of(q);
 #pragma unroll
         for (int t = 0; t < NTP; ++t) {
             int j, J;
-            ld_tile(bulk(q, wb, t, j, J) ? tile_ptr(I, j, J) : zt, ab[t]);
+            const bool ok = bulk(q, st + t, j, J) && t < cn;
+            ld_tile(ok ? tile_ptr(I, j, J) : zt, ab[t]);
         }
+    }
+    // newest band tile of row q (J = I-1 ascending, I+1 descending)
+    __device__ __forceinline__ void load_newest(int q, T (&v)[4]) const {
+        const int I = row_of(q);
+        ld_tile(ASC ? tile_ptr(I, nb - 1, I - 1) : tile_ptr(I, 0, I + 1), v);
+    }
+    __device__ __forceinline__ void load_d(int q, T (&v)[4]) const {
+        Mf<T>::ld4(dtile + (int64_t)row_of(q) * TILE_ELEMS, lane, v);
     }
     // ring slot of tile row J given sI = slot of the current row I (J within
     // nb rows of I); invalid tiles read any slot (their A operand is zero and
@@ -167,20 +198,24 @@ struct Pass {
         sJ = (sJ >= RS) ? sJ - RS : sJ;
         return sJ;
     }
-    // two independent accumulator chains (they interleave on the matrix core)
+    // products of slots t < cn (a wave-uniform branch skips the rest); two
+    // accumulator chains interleave on the matrix core
     template <int NTP>
-    __device__ __forceinline__ v4 bulk_mma(int q, int wb, int sI, const T (&ab)[NTP][4]) const {
+    __device__ __forceinline__ v4 bulk_mma(int q, int sI, int st, int cn, const T (&ab)[NTP][4]) const {
         constexpr int NA = NTP < 2 ? NTP : 2;
         v4 acc[NA];
 #pragma unroll
         for (int a = 0; a < NA; ++a) acc[a] = v4{0, 0, 0, 0};
 #pragma unroll
         for (int t = 0; t < NTP; ++t) {
-            int j, J;
-            bulk(q, wb, t, j, J);
-            const T *rj = ring + slot_of(sI, j) * TILE_ELEMS;
+            if (t < cn) {
+                int j, J;
+                bulk(q, st + t, j, J);
+                const T *rj = ring + slot_of(sI, j) * TILE_ELEMS;
 #pragma unroll
-            for (int kc = 0; kc < 4; ++kc) acc[t % NA] = Mf<T>::mma(ab[t][kc], rj[64 * kc + lane], acc[t % NA]);
+                for (int kc = 0; kc < 4; ++kc)
+                    acc[t % NA] = Mf<T>::mma(ab[t][kc], rj[64 * kc + lane], acc[t % NA]);
+            }
         }
 #pragma unroll
         for (int a = 1; a < NA; ++a) acc[0] += acc[a];
@@ -188,12 +223,6 @@ struct Pass {
     }
     __device__ __forceinline__ int next_slot(int sI) const {
         return ASC ? (sI + 1 == RS ? 0 : sI + 1) : (sI == 0 ? RS - 1 : sI - 1);
-    }
-    // diagonal inverse of row q and newest-tile product of row q+1 (guard
-    // rows are zero)
-    __device__ __forceinline__ void load_de(int q, T (&dbv)[4], T (&ebv)[4]) const {
-        Mf<T>::ld4(dtile + (int64_t)row_of(q) * TILE_ELEMS, lane, dbv);
-        Mf<T>::ld4(etile + (int64_t)row_of(q + 1) * TILE_ELEMS, lane, ebv);
     }
     // right-hand side rows of row q (accumulator order), clamped into the
     // arrays: rows >= n, columns >= ncols and rows of q >= NT are never stored
@@ -209,15 +238,24 @@ struct Pass {
             fbv[i] = gld(fsrc + row * fstride);
         }
     }
+    // (D t) for t in accumulator order (t as B operand)
+    __device__ __forceinline__ v4 dmul(const T (&d)[4], const v4 &t) const {
+        v4 y = {0, 0, 0, 0};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) y = Mf<T>::mma(d[kc], t[kc], y);
+        return y;
+    }
 };
 
-template <typename T, int KW, int TPW, int PD, bool ASC, bool STRIDED>
+template <typename T, int KW, typename SP, int PD, bool ASC, bool STRIDED>
 __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restrict__ band,
-                                           const T *__restrict__ dtile, const T *__restrict__ etile, T *ring,
-                                           T *red, T *hand, bool with_src, int step, int nsteps) {
+                                           const T *__restrict__ dtile, T *ring, T *red, T *hand, bool with_src,
+                                           int step, int nsteps) {
     typedef typename Mf<T>::v4 v4;
-    typedef Pass<T, KW, TPW, PD, ASC, STRIDED> PS;
-    PS P(it, band, dtile, etile, ring);
+    typedef Pass<T, KW, PD, ASC, STRIDED> PS;
+    constexpr int TPW = SP::cmax;
+    constexpr bool LEFT = !STRIDED;   // left form: r = D (x + dt phi f); right form: y = D v
+    PS P(it, band, dtile, ring);
     const int NT = P.NT, lane = P.lane, g = P.g, c = P.c, n = P.n;
     const int NTp = (NT + PD - 1) / PD * PD;   // rows beyond NT are zero work
     T *X = (T *)it.X;
@@ -239,11 +277,12 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
     }
     T *sink = (T *)it.fac.sink;
     const int w = P.w;
-    // y of tile row Irow: into ring slot ri (accumulator order) and into X
-    auto store_y = [&](const v4 &y, T *ri, int Irow, bool ok) {
+    // pass output of tile row q (accumulator order) to X
+    auto store_out = [&](const v4 &y, int q) {
+        const int Irow = P.row_of(q);
+        const bool ok = q < NT;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            ri[i * 64 + lane] = y[i];
             const int row = Irow * TILE + Mf<T>::row(g, i);
             gst((ok && colok && row < n) ? X + row + (int64_t)c * ldx : sink + lane, y[i]);
         }
@@ -251,105 +290,78 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
     if (KW == 1) {
         // ---- single wave: everything, prefetching PD-1 rows ahead
         T abuf[PD][TPW][4];
-        T dbuf[PD][4], ebuf[PD][4], xbuf[PD][4], fbuf[PD][4];
+        T ebuf[PD][4], dbuf[PD][4], xbuf[PD][4], fbuf[PD][4];
 #pragma unroll
         for (int u = 0; u < PD - 1; ++u) {
-            P.load_bulk(u, 0, abuf[u]);
-            P.load_de(u, dbuf[u], ebuf[u]);
+            P.template load_bulk<TPW>(u, 0, TPW, abuf[u]);
+            P.load_newest(u + 1, ebuf[u]);
+            P.load_d(u, dbuf[u]);
             P.load_state(u, X, ldx, col, fsrc, fstride, xbuf[u], fbuf[u]);
         }
-        v4 tnext = {0, 0, 0, 0};
+        v4 t = {0, 0, 0, 0};
         int sI = P.row_of(0) % P.RS;
         for (int q0 = 0; q0 < NTp; q0 += PD) {
 #pragma unroll
             for (int u = 0; u < PD; ++u) {
                 const int q = q0 + u;
                 const int un = (u + PD - 1) % PD;
-                P.load_bulk(q + PD - 1, 0, abuf[un]);
-                P.load_de(q + PD - 1, dbuf[un], ebuf[un]);
+                P.template load_bulk<TPW>(q + PD - 1, 0, TPW, abuf[un]);
+                P.load_newest(q + PD, ebuf[un]);
+                P.load_d(q + PD - 1, dbuf[un]);
                 P.load_state(q + PD - 1, X, ldx, col, fsrc, fstride, xbuf[un], fbuf[un]);
                 __builtin_amdgcn_sched_barrier(0);
-                const bool okq = q < NT;
-                const int I = P.row_of(q);
-                const v4 a = P.bulk_mma(q, 0, sI, abuf[u]);
-                v4 sv;
+                const v4 a = P.template bulk_mma<TPW>(q, sI, 0, TPW, abuf[u]);
+                v4 r;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) sv[i] = (xbuf[u][i] + fs * fbuf[u][i]) - (a[i] + tnext[i]);
-                v4 y = {0, 0, 0, 0}, tn = {0, 0, 0, 0};
+                for (int i = 0; i < 4; ++i) r[i] = xbuf[u][i] + fs * fbuf[u][i];
+                if (LEFT) r = P.dmul(dbuf[u], r);
+                v4 v;
 #pragma unroll
-                for (int kc = 0; kc < 4; ++kc) {
-                    y = Mf<T>::mma(dbuf[u][kc], sv[kc], y);
-                    tn = Mf<T>::mma(ebuf[u][kc], sv[kc], tn);
-                }
-                tnext = tn;
-                store_y(y, ring + (okq ? sI : P.RS) * TILE_ELEMS, I, okq);
+                for (int i = 0; i < 4; ++i) v[i] = r[i] - (a[i] + t[i]);
+                T *ri = ring + (q < NT ? sI : P.RS) * TILE_ELEMS;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ri[i * 64 + lane] = v[i];
+                t = P.dmul(ebuf[u], v);
+                store_out(LEFT ? v : P.dmul(dbuf[u], v), q);
                 sI = P.next_slot(sI);
                 lds_barrier();
             }
         }
     } else if (w == 0) {
-        // ---- finisher.  With s_q = r_q - (bulk partials) - E_q s_{q-1}, the
-        //      row's solution is y_q = D_q s_q; the recurrence only needs
-        //      t_{q+1} = E_{q+1} s_q, and y_q is formed during the next row,
-        //      before the barrier that publishes it to the bulk waves.
-        v4 tnext = {0, 0, 0, 0};
-        v4 sprev = {0, 0, 0, 0};
-        T dprev[4] = {0, 0, 0, 0};
-        int sprev_slot = P.RS, Iprev = 0;
-        bool okprev = false;
+        // ---- finisher: row q after barrier q+1
+        v4 t = {0, 0, 0, 0};
         int sI = P.row_of(0) % P.RS;
-        lds_barrier();   // hand-off of row 0 is ready
+        lds_barrier();
         for (int q = 0; q < NTp; ++q) {
-            const bool okq = q < NT;
-            const int I = P.row_of(q);
-            const T *h = hand + (q % 3) * 4 * TILE_ELEMS;
-            {
-                v4 y = {0, 0, 0, 0};
-#pragma unroll
-                for (int kc = 0; kc < 4; ++kc) y = Mf<T>::mma(dprev[kc], sprev[kc], y);
-                store_y(y, ring + sprev_slot * TILE_ELEMS, Iprev, okprev);
-            }
-            T dcur[4], ecur[4], rcur[4];
-#pragma unroll
-            for (int kc = 0; kc < 4; ++kc) {
-                dcur[kc] = h[kc * 64 + lane];
-                ecur[kc] = h[TILE_ELEMS + kc * 64 + lane];
-            }
             lds_barrier();
-#pragma unroll
-            for (int i = 0; i < 4; ++i) rcur[i] = h[2 * TILE_ELEMS + i * 64 + lane];
-            v4 sv;
+            const T *h = hand + (q & 1) * 2 * TILE_ELEMS;
+            T ecur[4];
+            v4 v;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                T a = tnext[i];
+                T a = t[i];
 #pragma unroll
                 for (int ww = 0; ww < PS::NBW; ++ww) a += red[((q & 1) * PS::NBW + ww) * TILE_ELEMS + i * 64 + lane];
-                sv[i] = rcur[i] - a;
+                v[i] = h[TILE_ELEMS + i * 64 + lane] - a;
+                ecur[i] = h[i * 64 + lane];
             }
-            v4 tn = {0, 0, 0, 0};
+            T *ri = ring + (q < NT ? sI : P.RS) * TILE_ELEMS;
 #pragma unroll
-            for (int kc = 0; kc < 4; ++kc) tn = Mf<T>::mma(ecur[kc], sv[kc], tn);
-            tnext = tn;
-            sprev = sv;
-#pragma unroll
-            for (int kc = 0; kc < 4; ++kc) dprev[kc] = dcur[kc];
-            sprev_slot = okq ? sI : P.RS;
-            Iprev = I;
-            okprev = okq;
+            for (int i = 0; i < 4; ++i) ri[i * 64 + lane] = v[i];
+            t = P.dmul(ecur, v);
             sI = P.next_slot(sI);
         }
-        {
-            v4 y = {0, 0, 0, 0};
-#pragma unroll
-            for (int kc = 0; kc < 4; ++kc) y = Mf<T>::mma(dprev[kc], sprev[kc], y);
-            store_y(y, ring + sprev_slot * TILE_ELEMS, Iprev, okprev);
-        }
+        __syncthreads();
     } else if (w <= PS::NBW) {
-        // ---- bulk waves
+        // ---- bulk waves: tiles [st, st+cn) of row q between barriers q and
+        //      q+1, operands prefetched PD-1 rows ahead
         const int wb = w - 1;
+        const int cn = wb == 0 ? SP::c1 : wb == 1 ? SP::c2 : wb == 2 ? SP::c3 : wb == 3 ? SP::c4 : SP::c5;
+        const int st = wb == 0 ? 0 : wb == 1 ? SP::c1 : wb == 2 ? SP::c1 + SP::c2
+                     : wb == 3 ? SP::c1 + SP::c2 + SP::c3 : SP::c1 + SP::c2 + SP::c3 + SP::c4;
         T abuf[PD][TPW][4];
 #pragma unroll
-        for (int u = 0; u < PD - 1; ++u) P.load_bulk(u, wb, abuf[u]);
+        for (int u = 0; u < PD - 1; ++u) P.template load_bulk<TPW>(u, st, cn, abuf[u]);
         lds_barrier();
         int sI = P.row_of(0) % P.RS;
         for (int q0 = 0; q0 < NTp; q0 += PD) {
@@ -357,79 +369,120 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
             for (int u = 0; u < PD; ++u) {
                 const int q = q0 + u;
                 const int un = (u + PD - 1) % PD;
-                P.load_bulk(q + PD - 1, wb, abuf[un]);
+                P.template load_bulk<TPW>(q + PD - 1, st, cn, abuf[un]);
                 __builtin_amdgcn_sched_barrier(0);
-                const v4 acc = P.bulk_mma(q, wb, sI, abuf[u]);
+                const v4 acc = P.template bulk_mma<TPW>(q, sI, st, cn, abuf[u]);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) red[((q & 1) * PS::NBW + wb) * TILE_ELEMS + i * 64 + lane] = acc[i];
                 sI = P.next_slot(sI);
                 lds_barrier();
             }
         }
+        __syncthreads();
     } else {
-        // ---- helpers: stage the finisher's operands of row q+1 in hand[(q+1)%3]
-        //      (D and E from the factor helper, r = x + dt phi f from the state helper)
-        constexpr int PDH = 4;
-        T b0[PDH][4], b1[PDH][4];
-        const bool facw = (w == PS::NBW + 1);
+        // ---- helpers: between barriers q and q+1 they hand over row q's r and
+        //      row q+1's newest tile; the factor helper also writes the output
+        //      of row q-2 (in the ring since barrier q)
+#ifndef LRPR_PDH
+#define LRPR_PDH 3
+#endif
+        constexpr int PDH = LRPR_PDH;   // helpers' prefetch depth
         const int NTh = (NTp + PDH - 1) / PDH * PDH;
-        if (facw) {
-            auto post = [&](int q, const T (&v0)[4], const T (&v1)[4]) {
-                T *h = hand + (q % 3) * 4 * TILE_ELEMS;
+        if (w == PS::NBW + 1) {
+            // b0: newest tile of row q+1, b1: D of row q-2 (right form)
+            T b0[PDH][4], b1[PDH][4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    h[i * 64 + lane] = v0[i];
-                    h[TILE_ELEMS + i * 64 + lane] = v1[i];
-                }
-            };
-#pragma unroll
-            for (int u = 0; u < PDH - 1; ++u) P.load_de(u, b0[u], b1[u]);
-            post(0, b0[0], b1[0]);
+            for (int u = 0; u < PDH - 1; ++u) {
+                P.load_newest(u + 1, b0[u]);
+                if (!LEFT) P.load_d(u - 2, b1[u]);
+            }
             lds_barrier();
+            int so = P.row_of(0) % P.RS;   // ring slot of the next row to write out
             for (int q0 = 0; q0 < NTh; q0 += PDH) {
 #pragma unroll
                 for (int u = 0; u < PDH; ++u) {
                     const int q = q0 + u;
-                    P.load_de(q + PDH - 1, b0[(u + PDH - 1) % PDH], b1[(u + PDH - 1) % PDH]);
+                    const int un = (u + PDH - 1) % PDH;
+                    P.load_newest(q + PDH, b0[un]);
+                    if (!LEFT) P.load_d(q + PDH - 3, b1[un]);
                     __builtin_amdgcn_sched_barrier(0);
                     if (q < NTp) {
-                        post(q + 1, b0[(u + 1) % PDH], b1[(u + 1) % PDH]);
+                        T *h = hand + (q & 1) * 2 * TILE_ELEMS;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) h[i * 64 + lane] = b0[u][i];
+                        if (q >= 2) {
+                            const T *ro = ring + so * TILE_ELEMS;
+                            v4 v;
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) v[i] = ro[i * 64 + lane];
+                            store_out(LEFT ? v : P.dmul(b1[u], v), q - 2);
+                            so = P.next_slot(so);
+                        }
                         lds_barrier();
                     }
                 }
+            }
+            // rows NTp-2 (in the ring since barrier NTp) and NTp-1 (after the
+            // finisher's last row, one barrier later)
+            {
+                T d2[4];
+                if (!LEFT) P.load_d(NTp - 2, d2);
+                const T *ro = ring + so * TILE_ELEMS;
+                v4 v;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = ro[i * 64 + lane];
+                store_out(LEFT ? v : P.dmul(d2, v), NTp - 2);
+                so = P.next_slot(so);
+            }
+            __syncthreads();
+            {
+                T d1[4];
+                if (!LEFT) P.load_d(NTp - 1, d1);
+                const T *ro = ring + so * TILE_ELEMS;
+                v4 v;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = ro[i * 64 + lane];
+                store_out(LEFT ? v : P.dmul(d1, v), NTp - 1);
             }
         } else {
-            auto post = [&](int q, const T (&x)[4], const T (&fv)[4]) {
-                T *h = hand + (q % 3) * 4 * TILE_ELEMS + 2 * TILE_ELEMS;
+            // state helper: b0 x, b1 f, b2 D of row q
+            T b0[PDH][4], b1[PDH][4], b2[PDH][4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) h[i * 64 + lane] = x[i] + fs * fv[i];
-            };
-#pragma unroll
-            for (int u = 0; u < PDH - 1; ++u) P.load_state(u, X, ldx, col, fsrc, fstride, b0[u], b1[u]);
-            post(0, b0[0], b1[0]);
+            for (int u = 0; u < PDH - 1; ++u) {
+                P.load_state(u, X, ldx, col, fsrc, fstride, b0[u], b1[u]);
+                if (LEFT) P.load_d(u, b2[u]);
+            }
             lds_barrier();
             for (int q0 = 0; q0 < NTh; q0 += PDH) {
 #pragma unroll
                 for (int u = 0; u < PDH; ++u) {
                     const int q = q0 + u;
-                    P.load_state(q + PDH - 1, X, ldx, col, fsrc, fstride, b0[(u + PDH - 1) % PDH],
-                                 b1[(u + PDH - 1) % PDH]);
+                    const int un = (u + PDH - 1) % PDH;
+                    P.load_state(q + PDH - 1, X, ldx, col, fsrc, fstride, b0[un], b1[un]);
+                    if (LEFT) P.load_d(q + PDH - 1, b2[un]);
                     __builtin_amdgcn_sched_barrier(0);
                     if (q < NTp) {
-                        post(q + 1, b0[(u + 1) % PDH], b1[(u + 1) % PDH]);
+                        v4 r;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) r[i] = b0[u][i] + fs * b1[u][i];
+                        if (LEFT) r = P.dmul(b2[u], r);
+                        T *h = hand + (q & 1) * 2 * TILE_ELEMS + TILE_ELEMS;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) h[i * 64 + lane] = r[i];
                         lds_barrier();
                     }
                 }
             }
+            __syncthreads();
         }
     }
-    // end of pass: the next pass reads X rows stored by wave 0
+    // end of pass: the next pass reads X rows written by this one
     __syncthreads();
 }
 
 // ADJ: adjoint sweep, on the mirrored set or (STRIDED) the transposed
 // forward tiles.
-template <typename T, int KW, int TPW, int PD, bool ADJ, bool STRIDED>
+template <typename T, int KW, typename SP, int PD, bool ADJ, bool STRIDED>
 __global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__ items, int nitems,
                                                    int nsteps) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -440,63 +493,85 @@ __global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__
         for (int e = threadIdx.x; e < (it.fac.nb + 2) * TILE_ELEMS; e += blockDim.x) ring[e] = (T)0;
         __syncthreads();
         T *red = ring + (it.fac.nb + 2) * TILE_ELEMS;              // [2][KW-3][256]
-        T *hand = red + 2 * (KW > 1 ? KW - 3 : 1) * TILE_ELEMS;     // [3][4][256]
+        T *hand = red + 2 * (KW > 1 ? KW - 3 : 1) * TILE_ELEMS;     // [2][2][256]: E, r
         const void *const *a = it.fac.a;
         for (int step = 0; step < nsteps; ++step) {
             if (!ADJ) {
-                sweep_pass<T, KW, TPW, PD, true, false>(it, (const T *)a[TS_LB], (const T *)a[TS_DL],
-                                                        (const T *)a[TS_EL], ring, red, hand, it.f != nullptr,
-                                                        step, nsteps);
-                sweep_pass<T, KW, TPW, PD, false, false>(it, (const T *)a[TS_UB], (const T *)a[TS_DU],
-                                                         (const T *)a[TS_EU], ring, red, hand, false, step, nsteps);
+                sweep_pass<T, KW, SP, PD, true, false>(it, (const T *)a[TS_LB], (const T *)a[TS_DL], ring, red, hand,
+                                                       it.f != nullptr, step, nsteps);
+                sweep_pass<T, KW, SP, PD, false, false>(it, (const T *)a[TS_UB], (const T *)a[TS_DU], ring, red, hand,
+                                                        false, step, nsteps);
             } else if (!STRIDED) {
-                sweep_pass<T, KW, TPW, PD, true, false>(it, (const T *)a[TS_UTB], (const T *)a[TS_DUT],
-                                                        (const T *)a[TS_EUT], ring, red, hand, false, step, nsteps);
-                sweep_pass<T, KW, TPW, PD, false, false>(it, (const T *)a[TS_LTB], (const T *)a[TS_DLT],
-                                                         (const T *)a[TS_ELT], ring, red, hand, false, step, nsteps);
+                sweep_pass<T, KW, SP, PD, true, false>(it, (const T *)a[TS_UTB], (const T *)a[TS_DUT], ring, red,
+                                                       hand, false, step, nsteps);
+                sweep_pass<T, KW, SP, PD, false, false>(it, (const T *)a[TS_LTB], (const T *)a[TS_DLT], ring, red,
+                                                        hand, false, step, nsteps);
             } else {
-                sweep_pass<T, KW, TPW, PD, true, true>(it, (const T *)a[TS_UB], (const T *)a[TS_DUT],
-                                                       (const T *)a[TS_EUT], ring, red, hand, false, step, nsteps);
-                sweep_pass<T, KW, TPW, PD, false, true>(it, (const T *)a[TS_LB], (const T *)a[TS_DLT],
-                                                        (const T *)a[TS_ELT], ring, red, hand, false, step, nsteps);
+                sweep_pass<T, KW, SP, PD, true, true>(it, (const T *)a[TS_UB], (const T *)a[TS_DUT], ring, red, hand,
+                                                      false, step, nsteps);
+                sweep_pass<T, KW, SP, PD, false, true>(it, (const T *)a[TS_LB], (const T *)a[TS_DLT], ring, red, hand,
+                                                       false, step, nsteps);
             }
         }
     }
 }
 
-template <typename T, int KW, int TPW, int PD>
+template <typename T, int KW, typename SP, int PD>
 static hipError_t launch_t(bool adjoint, bool strided, int nitems, const SweepItem *d_items, int nsteps,
                            int max_nb, hipStream_t s) {
     // LDS: ring of nb+1 solved tiles (+1 dummy slot), double-buffered partial
-    // sums of the bulk waves, triple-buffered hand-off (D, E, r)
-    const size_t lds = (size_t)(max_nb + 2 + 2 * (KW > 1 ? KW - 3 : 1) + 12) * TILE_ELEMS * sizeof(T);
+    // sums of the bulk waves, double-buffered hand-off (E, r)
+    const size_t lds = (size_t)(max_nb + 2 + 2 * (KW > 1 ? KW - 3 : 1) + 4) * TILE_ELEMS * sizeof(T);
     const int grid = nitems < 65536 ? nitems : 65536;
     if (!adjoint)
-        hipLaunchKernelGGL((k_sweep<T, KW, TPW, PD, false, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
+        hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, false, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
                            nitems, nsteps);
     else if (!strided)
-        hipLaunchKernelGGL((k_sweep<T, KW, TPW, PD, true, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
+        hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, true, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
                            nitems, nsteps);
     else
-        hipLaunchKernelGGL((k_sweep<T, KW, TPW, PD, true, true>), dim3(grid), dim3(64 * KW), lds, s, d_items,
+        hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, true, true>), dim3(grid), dim3(64 * KW), lds, s, d_items,
                            nitems, nsteps);
     return hipGetLastError();
 }
 
-// KW > 1: wave 0 finishes tile rows, KW-3 bulk waves share the nb-1 older
-// band tiles (TPW = ceil((nb-1)/(KW-3)) each), two helper waves prefetch the
-// finisher's operands.  Narrow bands run on one wave.
+// Tile split and prefetch depth of the nb <= 16 class (compile-time tuning).
+#ifndef LRPR_SPLIT16_F64
+#define LRPR_SPLIT16_F64 2, 4, 4, 3, 2
+#endif
+#ifndef LRPR_PD16_F64
+#define LRPR_PD16_F64 3
+#endif
+#ifndef LRPR_SPLIT16_F32
+#define LRPR_SPLIT16_F32 2, 4, 4, 3, 2
+#endif
+#ifndef LRPR_PD16_F32
+#define LRPR_PD16_F32 5
+#endif
+
+// KW > 1: wave 0 finishes tile rows, five bulk waves share the nb-1 older
+// band tiles (Split: tiles per bulk wave), two helper waves stage the
+// finisher's operands and write the output.  Narrow bands run on one wave.
 template <typename T>
 static hipError_t launch_prec(bool adjoint, bool strided, int nitems, const SweepItem *d_items, int nsteps,
                               int max_nb, hipStream_t s) {
-    if (max_nb <= 1) return launch_t<T, 1, 1, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
-    if (max_nb <= 4) return launch_t<T, 1, 3, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    constexpr bool F64 = sizeof(T) == 8;
+    if (max_nb <= 1) return launch_t<T, 1, Split<1, 0, 0, 0, 0>, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    if (max_nb <= 4) return launch_t<T, 1, Split<3, 0, 0, 0, 0>, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
     if (max_nb <= 8)
-        return launch_t<T, 8, 2, sizeof(T) == 8 ? 4 : 6>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
-    if (max_nb <= 16)
-        return launch_t<T, 8, 3, sizeof(T) == 8 ? 4 : 5>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
-    if (max_nb <= 32) return launch_t<T, 8, 7, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
-    if (max_nb <= 64) return launch_t<T, 8, 13, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+        return launch_t<T, 8, Split<1, 2, 2, 1, 1>, F64 ? 4 : 6>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    if (max_nb <= 16) {
+        if constexpr (F64)
+            return launch_t<T, 8, Split<LRPR_SPLIT16_F64>, LRPR_PD16_F64>(adjoint, strided, nitems, d_items, nsteps,
+                                                                          max_nb, s);
+        else
+            return launch_t<T, 8, Split<LRPR_SPLIT16_F32>, LRPR_PD16_F32>(adjoint, strided, nitems, d_items, nsteps,
+                                                                          max_nb, s);
+    }
+    if (max_nb <= 32)
+        return launch_t<T, 8, Split<6, 7, 6, 6, 6>, F64 ? 2 : 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    if (max_nb <= 64)
+        return launch_t<T, 8, Split<13, 13, 13, 13, 11>, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
     return hipErrorInvalidValue;
 }
 
