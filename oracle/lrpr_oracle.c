@@ -94,6 +94,9 @@ int ora_band_lu(int n, int bw, double *band)
         double piv = BAND(band, bw, q, q);
         if (piv == 0.0 || !isfinite(piv)) return q + 1;
         int iend = imin(q + bw, n - 1);
+        /* rows of one pivot step are independent: every entry still receives
+         * its updates in pivot order (threads only for wide bands) */
+#pragma omp parallel for schedule(static) if (bw >= 128)
         for (int i = q + 1; i <= iend; i++) {
             double lij = BAND(band, bw, i, q) / piv;
             BAND(band, bw, i, q) = lij;
