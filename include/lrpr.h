@@ -97,7 +97,7 @@ lrpr_status lrpr_profile_read(lrpr_ctx ctx, double *ms, int64_t *launches, doubl
 
 /* ---- operator assembly and band LU (Sec. 4.4) --------------------------- */
 
-enum { LRPR_STORE_F64 = 1, LRPR_STORE_F32 = 2, LRPR_STORE_MIRROR = 4 };
+enum { LRPR_STORE_F64 = 1, LRPR_STORE_F32 = 2, LRPR_STORE_MIRROR = 4, LRPR_STORE_SPLIT = 8 };
 
 /* Assemble M = I + dt*A on the device and factor it M = L U by banded
  * Gaussian elimination without pivoting, in FP64 (the paper's fine solver
@@ -113,6 +113,12 @@ enum { LRPR_STORE_F64 = 1, LRPR_STORE_F32 = 2, LRPR_STORE_MIRROR = 4 };
  *                         U^T and L^T, so adjoint sweeps read contiguous
  *                         tiles (faster; doubles the band-tile memory,
  *                         about 2 n (2b+1) bytes per byte of precision).
+ *   LRPR_STORE_SPLIT (8)  for each precision kept, also the spikes of a
+ *                         partitioned substitution (same size as the
+ *                         forward band tiles), so that fine sweeps of few
+ *                         right-hand sides spread each column group over
+ *                         several compute units (same results up to
+ *                         rounding).
  * 0 means LRPR_STORE_F64; at least one of F64/F32 must be set.  Errors:
  * LRPR_ERR_ARG (bad descriptor or mask), LRPR_ERR_ZERO_PIVOT,
  * LRPR_ERR_NOMEM.  Synchronises the stream. */

@@ -1,11 +1,13 @@
 // Host side of the C ABI: contexts, factors, batched fine/adjoint sweeps.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
 
+#include "dense.h"
 #include "lrpr_internal.h"
 
 using namespace lrpr;
@@ -103,8 +105,125 @@ void lrpr_factor_destroy(lrpr_fac f) {
     if (f->lu) hipFree(f->lu);
     free_tiles(f->t64);
     free_tiles(f->t32);
+    for (void *p : {f->s64.S, f->s64.T, f->s32.S, f->s32.T, (void *)f->d_blk})
+        if (p) hipFree(p);
     delete f;
 }
+
+}  // extern "C"
+
+namespace lrpr {
+lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
+                      bool adjoint);
+FacView fac_view(lrpr_fac f, bool f32);
+lrpr_status ensure_items(lrpr_ctx ctx, size_t count);
+
+// Block starts of the partitioned solve: P ~ 24 blocks (balances the local
+// solves, NT/P tile rows, against the sequential chain, P steps of nb^2 tile
+// products), each at least 2 nb tile rows.
+static std::vector<int> split_blocks(int NT, int nb) {
+    int P = 24;
+    if (P > NT / (2 * nb)) P = NT / (2 * nb);
+    std::vector<int> blk;
+    if (P < 2) return blk;
+    for (int p = 0; p <= P; ++p) blk.push_back((int)((int64_t)NT * p / P));
+    return blk;
+}
+
+// Spikes S_p = L_pp^{-1} L_{p,p-1}[:, tail], T_p = U_pp^{-1} U_{p,p+1}[:, head]
+// of every stored precision: local sweeps of the coupling columns, packed
+// into tiles.
+static lrpr_status build_split(lrpr_ctx ctx, lrpr_fac f, const double *band) {
+    f->blk = split_blocks(f->NT, f->nb);
+    if (f->blk.empty()) return LRPR_OK;   // too few rows to partition
+    const int P = (int)f->blk.size() - 1, NT = f->NT, nb = f->nb;
+    hipStream_t st = ctx->stream;
+    hipError_t e;
+    const int64_t ld = (int64_t)NT * TILE;
+    const size_t dense = (size_t)ld * nb * TILE;
+    double *RL = nullptr, *RU = nullptr;
+    float *RL32 = nullptr, *RU32 = nullptr;
+    auto bail = [&](hipError_t err, const char *what) {
+        for (void *p : {(void *)RL, (void *)RU, (void *)RL32, (void *)RU32})
+            if (p) hipFree(p);
+        return fail(ctx, err == hipErrorOutOfMemory ? LRPR_ERR_NOMEM : LRPR_ERR_HIP,
+                    std::string(what) + ": " + hipGetErrorString(err));
+    };
+    if ((e = hipMalloc(&f->d_blk, sizeof(int) * (P + 1))) != hipSuccess) return bail(e, "block table");
+    if ((e = hipMemcpyAsync(f->d_blk, f->blk.data(), sizeof(int) * (P + 1), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return bail(e, "block table");
+    if ((e = hipMalloc(&RL, sizeof(double) * dense)) != hipSuccess || (e = hipMalloc(&RU, sizeof(double) * dense)) != hipSuccess)
+        return bail(e, "spike scratch");
+    if ((e = launch_spike_rhs(f->n, f->bw, NT, nb, P, f->d_blk, band, RL, RU, st)) != hipSuccess)
+        return bail(e, "spike right-hand sides");
+    // solve once, in FP64 when the factor keeps FP64 tiles (else FP32), then
+    // pack into every stored precision
+    const bool solve32 = !(f->mask & LRPR_STORE_F64);
+    void *L = RL, *U = RU;
+    if (solve32 || (f->mask & LRPR_STORE_F32)) {
+        if ((e = hipMalloc(&RL32, sizeof(float) * dense)) != hipSuccess ||
+            (e = hipMalloc(&RU32, sizeof(float) * dense)) != hipSuccess)
+            return bail(e, "spike scratch");
+    }
+    if (solve32) {
+        if ((e = launch_convert(0, 1, RL, RL32, (int64_t)dense, st)) != hipSuccess ||
+            (e = launch_convert(0, 1, RU, RU32, (int64_t)dense, st)) != hipSuccess)
+            return bail(e, "spike convert");
+        L = RL32;
+        U = RU32;
+    }
+    {
+        // local sweeps: L pass on the coupling columns of blocks 1..P-1, U pass
+        // on those of blocks 0..P-2 (nb column groups each)
+        const size_t esz = solve32 ? 4 : 8;
+        std::vector<SweepItem> items;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int p = (pass == 0 ? 1 : 0); p < (pass == 0 ? P : P - 1); ++p)
+                for (int cg = 0; cg < nb; ++cg) {
+                    SweepItem it{};
+                    it.fac = fac_view(f, solve32);
+                    it.X = (char *)(pass == 0 ? L : U) + (size_t)cg * TILE * ld * esz;
+                    it.ldx = ld;
+                    it.ncols = TILE;
+                    it.passes = pass == 0 ? 1 : 2;
+                    it.r0 = f->blk[p];
+                    it.r1 = f->blk[p + 1];
+                    it.fsteps = 1;
+                    items.push_back(it);
+                }
+        lrpr_status ls = ensure_items(ctx, items.size());
+        if (ls != LRPR_OK) return ls;
+        if ((e = hipMemcpyAsync(ctx->d_items, items.data(), items.size() * sizeof(SweepItem), hipMemcpyHostToDevice,
+                                st)) != hipSuccess)
+            return bail(e, "spike items");
+        if ((e = launch_sweep(false, false, solve32, (int)items.size(), ctx->d_items, 1, nb, st)) != hipSuccess)
+            return bail(e, "spike solves");
+    }
+    if (!solve32 && (f->mask & LRPR_STORE_F32)) {
+        if ((e = launch_convert(0, 1, RL, RL32, (int64_t)dense, st)) != hipSuccess ||
+            (e = launch_convert(0, 1, RU, RU32, (int64_t)dense, st)) != hipSuccess)
+            return bail(e, "spike convert");
+    }
+    for (int prec = 0; prec < 2; ++prec) {
+        const bool f32 = prec == 1;
+        if (!(f->mask & (f32 ? LRPR_STORE_F32 : LRPR_STORE_F64))) continue;
+        SplitSet &ss = f32 ? f->s32 : f->s64;
+        const size_t tiles = (size_t)NT * nb * TILE_ELEMS * (f32 ? 4 : 8);
+        if ((e = hipMalloc(&ss.S, tiles)) != hipSuccess || (e = hipMalloc(&ss.T, tiles)) != hipSuccess)
+            return bail(e, "spike tiles");
+        if ((e = launch_spike_pack(f32, NT, nb, f32 ? (void *)RL32 : (void *)RL, ld, ss.S, st)) != hipSuccess ||
+            (e = launch_spike_pack(f32, NT, nb, f32 ? (void *)RU32 : (void *)RU, ld, ss.T, st)) != hipSuccess)
+            return bail(e, "spike pack");
+    }
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "spike build");
+    for (void *p : {(void *)RL, (void *)RU, (void *)RL32, (void *)RU32})
+        if (p) hipFree(p);
+    f->P = P;
+    return LRPR_OK;
+}
+}  // namespace lrpr
+
+extern "C" {
 
 lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lrpr_fac *out) {
     if (!ctx || !op || !out) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: null argument");
@@ -112,7 +231,7 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
         !(op->c >= 0) || !std::isfinite(op->beta1) || !std::isfinite(op->beta2))
         return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: invalid operator descriptor");
     if (store_mask == 0) store_mask = LRPR_STORE_F64;
-    if ((store_mask & ~(LRPR_STORE_F64 | LRPR_STORE_F32 | LRPR_STORE_MIRROR)) ||
+    if ((store_mask & ~(LRPR_STORE_F64 | LRPR_STORE_F32 | LRPR_STORE_MIRROR | LRPR_STORE_SPLIT)) ||
         !(store_mask & (LRPR_STORE_F64 | LRPR_STORE_F32)))
         return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: store_mask must hold F64 and/or F32 (and optionally MIRROR)");
     const bool mirror = (store_mask & LRPR_STORE_MIRROR) != 0;
@@ -179,6 +298,10 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
         return cleanup(LRPR_ERR_HIP, std::string("factor: ") + hipGetErrorString(e));
     hipFree(scratch);
     scratch = nullptr;
+    if (store_mask & LRPR_STORE_SPLIT) {
+        const lrpr_status st = build_split(ctx, f, band);
+        if (st != LRPR_OK) return cleanup(st, std::string("lrpr_factor: partitioned solve: ") + ctx->err);
+    }
     if (store_mask & LRPR_STORE_F64) {
         f->lu = band;
     } else {
@@ -215,6 +338,9 @@ lrpr_status lrpr_factor_copy_lu(lrpr_ctx ctx, lrpr_fac f, double *lu_host) {
 // ---------------------------------------------------------------------------
 namespace lrpr {
 
+// narrow sweeps (at most this many 16-column groups) take the partitioned path
+constexpr int SPLIT_MAX_GROUPS = 32;
+
 FacView fac_view(lrpr_fac f, bool f32) {
     const TileSet &t = f32 ? f->t32 : f->t64;
     FacView v;
@@ -241,6 +367,119 @@ lrpr_status ensure_items(lrpr_ctx ctx, size_t count) {
     hipError_t e = hipMalloc(&ctx->d_items, cap * sizeof(SweepItem));
     if (e != hipSuccess) return hipfail(ctx, e, "sweep item buffer");
     ctx->items_cap = cap;
+    return LRPR_OK;
+}
+
+// Profiling record of one sweep: algorithmic work of 4 n b flops and 2 n s
+// bytes per RHS step, plus one read of each distinct factor per step; event
+// recorded before the launch.
+static hipError_t prof_begin(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, bool f32,
+                             lrpr_ctx_s::ProfRec &rec) {
+    const double s = f32 ? 4.0 : 8.0;
+    std::vector<lrpr_fac> seen;
+    for (int p = 0; p < npanels; ++p) {
+        const lrpr_panel &P = panels[p];
+        const double n = (double)P.F->n, b = (double)P.F->bw;
+        rec.flops += 4.0 * n * b * P.w * nsteps;
+        rec.bytes += 2.0 * n * s * P.w * nsteps;
+        rec.rhs_steps += (double)P.w * nsteps;
+        bool dup = false;
+        for (lrpr_fac q : seen) dup = dup || q == P.F;
+        if (!dup) {
+            seen.push_back(P.F);
+            rec.bytes += n * (2.0 * b + 1.0) * s * nsteps;
+        }
+    }
+    hipError_t e;
+    if ((e = hipEventCreate(&rec.a)) != hipSuccess || (e = hipEventCreate(&rec.b)) != hipSuccess) return e;
+    return hipEventRecord(rec.a, ctx->stream);
+}
+
+void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err);
+
+// Partitioned fine sweep (few column groups): per step, the L pass as local
+// solves of all blocks, chain, update; then the U pass the same way.
+static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels,
+                             const std::vector<SweepItem> &groups, int nsteps, bool f32, int max_nb) {
+    hipStream_t st = ctx->stream;
+    const size_t esz = f32 ? 4 : 8;
+    // factor of every group (items were built panel by panel)
+    std::vector<lrpr_fac> gf;
+    for (int p = 0; p < npanels; ++p)
+        for (int c0 = 0; c0 < panels[p].w; c0 += TILE) gf.push_back(panels[p].F);
+    std::vector<SweepItem> loc;
+    std::vector<SplitGroup> sg(groups.size());
+    size_t bnd_elems = 0;
+    int max_P = 0, max_rows = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const lrpr_fac F = gf[g];
+        max_P = std::max(max_P, F->P);
+        for (int p = 0; p < F->P; ++p) max_rows = std::max(max_rows, F->blk[p + 1] - F->blk[p]);
+        bnd_elems += (size_t)F->P * F->nb * TILE_ELEMS;
+    }
+    hipError_t e = hipSuccess;
+    char *bnd = (char *)ws_get(ctx, "split_bnd", bnd_elems * esz, &e);
+    SplitGroup *d_groups = (SplitGroup *)ws_get(ctx, "split_groups", sizeof(SplitGroup) * sg.size(), &e);
+    if (!bnd || !d_groups) return hipfail(ctx, e == hipSuccess ? hipErrorOutOfMemory : e, "split workspace");
+    size_t off = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (size_t g = 0; g < groups.size(); ++g) {
+            const lrpr_fac F = gf[g];
+            for (int p = 0; p < F->P; ++p) {
+                SweepItem it = groups[g];
+                it.r0 = F->blk[p];
+                it.r1 = F->blk[p + 1];
+                it.passes = pass == 0 ? 1 : 2;
+                if (pass == 1) {
+                    it.f = nullptr;
+                    it.fcol = nullptr;
+                    it.fscale = nullptr;
+                }
+                loc.push_back(it);
+            }
+        }
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const lrpr_fac F = gf[g];
+        const SplitSet &ss = f32 ? F->s32 : F->s64;
+        SplitGroup &G = sg[g];
+        G.X = groups[g].X;
+        G.ldx = groups[g].ldx;
+        G.ncols = groups[g].ncols;
+        G.n = (int)F->n;
+        G.NT = F->NT;
+        G.nb = F->nb;
+        G.P = F->P;
+        G.blk = F->d_blk;
+        G.S = ss.S;
+        G.T = ss.T;
+        G.bnd = bnd + off * esz;
+        off += (size_t)F->P * F->nb * TILE_ELEMS;
+    }
+    const int nL = (int)(loc.size() / 2);
+    lrpr_status ls = ensure_items(ctx, loc.size());
+    if (ls != LRPR_OK) return ls;
+    if ((e = hipMemcpyAsync(ctx->d_items, loc.data(), loc.size() * sizeof(SweepItem), hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(d_groups, sg.data(), sg.size() * sizeof(SplitGroup), hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
+        return hipfail(ctx, e, "split upload");
+    lrpr_ctx_s::ProfRec rec{};
+    if (ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
+        return hipfail(ctx, e, "profile event");
+    const int ng = (int)sg.size();
+    for (int step = 0; step < nsteps; ++step) {
+        if ((e = launch_sweep(false, false, f32, nL, ctx->d_items, 1, max_nb, st, step)) != hipSuccess ||
+            (e = launch_split_chain(f32, false, ng, d_groups, max_nb, st)) != hipSuccess ||
+            (e = launch_split_update(f32, false, ng, d_groups, max_P, max_rows, st)) != hipSuccess ||
+            (e = launch_sweep(false, false, f32, nL, ctx->d_items + nL, 1, max_nb, st, step)) != hipSuccess ||
+            (e = launch_split_chain(f32, true, ng, d_groups, max_nb, st)) != hipSuccess ||
+            (e = launch_split_update(f32, true, ng, d_groups, max_P, max_rows, st)) != hipSuccess)
+            return hipfail(ctx, e, "split sweep");
+    }
+    if (ctx->prof) {
+        if ((e = hipEventRecord(rec.b, st)) != hipSuccess) return hipfail(ctx, e, "profile event");
+        ctx->prof_recs.push_back(rec);
+    }
     return LRPR_OK;
 }
 
@@ -271,6 +510,10 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
             it.X = (char *)P.X + (size_t)c0 * P.ldx * esz;
             it.ldx = P.ldx;
             it.ncols = P.w - c0 < TILE ? P.w - c0 : TILE;
+            it.passes = 3;
+            it.r0 = 0;
+            it.r1 = P.F->NT;
+            it.fsteps = nsteps;
             it.pad_ = 0;
             it.f = adjoint ? nullptr : P.f;
             it.ldf = P.ldf;
@@ -283,34 +526,20 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
     if (max_nb > 64) return fail(ctx, LRPR_ERR_ARG, "sweep: half-bandwidth above 1023");
     hipError_t e = hipSetDevice(ctx->dev);
     if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+    // Few column groups on factors with spikes: partitioned passes, so that
+    // every group spreads over P compute units.
+    bool split = !adjoint && (int)items.size() <= SPLIT_MAX_GROUPS && max_nb <= (f32 ? 64 : 32);
+    for (int p = 0; p < npanels && split; ++p)
+        split = panels[p].w == 0 || (panels[p].F->P >= 2 && (f32 ? panels[p].F->s32.S : panels[p].F->s64.S));
+    if (split) return run_split(ctx, npanels, panels, items, nsteps, f32, max_nb);
     lrpr_status st = ensure_items(ctx, items.size());
     if (st != LRPR_OK) return st;
     e = hipMemcpyAsync(ctx->d_items, items.data(), items.size() * sizeof(SweepItem),
                        hipMemcpyHostToDevice, ctx->stream);
     if (e != hipSuccess) return hipfail(ctx, e, "sweep item upload");
     lrpr_ctx_s::ProfRec rec{};
-    if (ctx->prof) {
-        // algorithmic work: 4 n b flops and 2 n s bytes per RHS step, plus one
-        // read of each distinct factor per step
-        const double s = f32 ? 4.0 : 8.0;
-        std::vector<lrpr_fac> seen;
-        for (int p = 0; p < npanels; ++p) {
-            const lrpr_panel &P = panels[p];
-            const double n = (double)P.F->n, b = (double)P.F->bw;
-            rec.flops += 4.0 * n * b * P.w * nsteps;
-            rec.bytes += 2.0 * n * s * P.w * nsteps;
-            rec.rhs_steps += (double)P.w * nsteps;
-            bool dup = false;
-            for (lrpr_fac q : seen) dup = dup || q == P.F;
-            if (!dup) {
-                seen.push_back(P.F);
-                rec.bytes += n * (2.0 * b + 1.0) * s * nsteps;
-            }
-        }
-        if ((e = hipEventCreate(&rec.a)) != hipSuccess || (e = hipEventCreate(&rec.b)) != hipSuccess ||
-            (e = hipEventRecord(rec.a, ctx->stream)) != hipSuccess)
-            return hipfail(ctx, e, "profile event");
-    }
+    if (ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
+        return hipfail(ctx, e, "profile event");
     e = launch_sweep(adjoint, strided, f32, (int)items.size(), ctx->d_items, nsteps, max_nb, ctx->stream);
     if (e != hipSuccess) return hipfail(ctx, e, "sweep launch");
     if (ctx->prof) {

@@ -71,11 +71,41 @@ struct SweepItem {
     void *X;               // first column of the group
     int64_t ldx;
     int ncols;             // 1..16
+    int passes;            // bit 0: first pass (L, or U^T), bit 1: second pass (U, or L^T)
+    int r0, r1;            // tile rows [r0, r1) solved; rows outside are not coupled in
+    int fsteps;            // length of a column's fscale row
     int pad_;
     const void *f;         // sources (element type of the sweep) or null
     int64_t ldf;
     const int *fcol;       // per column (offset to the group's first column) or null
-    const double *fscale;  // per column x nsteps (offset) or null
+    const double *fscale;  // per column x fsteps (offset) or null
+};
+
+// Partitioned forward solves (narrow panels).  The tile rows are cut into P
+// blocks [blk[p], blk[p+1]) of at least 2 nb rows.  A substitution pass then
+// runs as: local solves of every block with its own diagonal block (the
+// sweep kernel on the block's range), a chain over the blocks for the nb
+// boundary tile rows, and a parallel update of every block:
+//   L pass: y_p = g_p - S_p y_{p-1}^tail,  S_p = L_pp^{-1} L_{p,p-1}[:, tail]
+//   U pass: x_p = h_p - T_p x_{p+1}^head,  T_p = U_pp^{-1} U_{p,p+1}[:, head]
+// where tail / head are the last / first nb tile rows of a block.  S and T
+// are stored like the band tiles: NT x nb tiles (MFMA A operands), row I of
+// block p holding S_p(I, .) (rows of block 0 unused) and T_p(I, .) (rows of
+// the last block unused).
+struct SplitSet {
+    void *S = nullptr;
+    void *T = nullptr;
+};
+
+// One 16-column group of a partitioned pass (chain and update kernels).
+struct SplitGroup {
+    void *X;               // first column of the group (n rows, ldx)
+    int64_t ldx;
+    int ncols;
+    int n, NT, nb, P;
+    const int *blk;        // device, P+1 block starts (tile rows)
+    const void *S, *T;     // spikes of the group's factor (precision of the pass)
+    void *bnd;             // P x nb tiles (accumulator order): solved tails (L) / heads (U)
 };
 
 }  // namespace lrpr
@@ -89,6 +119,11 @@ struct lrpr_factor_s {
     int mask = 0;                  // LRPR_STORE_* bits
     double *lu = nullptr;          // FP64 band LU, n x (2bw+1) row-major (kept with LRPR_STORE_F64)
     lrpr::TileSet t64, t32;
+    // partitioned forward solves (LRPR_STORE_SPLIT): P blocks, starts blk
+    int P = 0;
+    std::vector<int> blk;
+    int *d_blk = nullptr;
+    lrpr::SplitSet s64, s32;
 };
 
 struct lrpr_coarse_s {
@@ -137,6 +172,14 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
 // adjoint sweeps read the mirrored set unless `strided` (then the forward
 // tiles are read transposed)
 hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const SweepItem *d_items, int nsteps,
-                        int max_nb, hipStream_t s);
+                        int max_nb, hipStream_t s, int step0 = 0);
+// partitioned passes (split.hip)
+hipError_t launch_spike_rhs(int64_t n, int bw, int NT, int nb, int P, const int *d_blk, const double *lu,
+                            double *RL, double *RU, hipStream_t s);
+hipError_t launch_spike_pack(bool f32, int NT, int nb, const void *dense, int64_t ld, void *tiles, hipStream_t s);
+hipError_t launch_split_chain(bool f32, bool upper, int ngroups, const SplitGroup *d_groups, int max_nb,
+                              hipStream_t s);
+hipError_t launch_split_update(bool f32, bool upper, int ngroups, const SplitGroup *d_groups, int max_P,
+                               int max_rows, hipStream_t s);
 
 }  // namespace lrpr

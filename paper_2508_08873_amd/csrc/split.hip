@@ -1,0 +1,295 @@
+// Partitioned forward solves for narrow panels (few 16-column groups).
+//
+// A substitution pass is sequential in its tile rows, so a group of 16
+// right-hand sides keeps one compute unit busy for NT tile rows.  Cutting the
+// rows into P blocks lets P compute units work on one group (the classical
+// spike partitioning of a banded triangular solve):
+//   local:  g_p = L_pp^{-1} r_p for every block p (the sweep kernel on the
+//           block's range; rows before the block read as zero),
+//   chain:  y_p^tail = g_p^tail - S_p^tail y_{p-1}^tail, p = 1..P-1, with
+//           S_p = L_pp^{-1} L_{p,p-1}[:, tail] (tail: last nb tile rows),
+//   update: y_p = g_p - S_p y_{p-1}^tail for every row of every block,
+// and the mirror image for the back substitution with U (blocks from the
+// last one down, heads = first nb tile rows, T_p = U_pp^{-1} U_{p,p+1}[:, head]).
+// In exact arithmetic this is the same solve; every product runs on the
+// matrix cores (v_mfma_*_16x16x4).  The spikes S_p, T_p are computed once per
+// factor with the same local sweeps.
+#include "lrpr_internal.h"
+#include "tile_ops.h"
+
+namespace lrpr {
+
+__device__ inline double band_at(const double *lu, int64_t n, int bw, int64_t i, int64_t j) {
+    if (i < 0 || j < 0 || i >= n || j >= n) return 0.0;
+    const int64_t d = j - i;
+    if (d < -bw || d > bw) return 0.0;
+    return lu[i * (2 * bw + 1) + d + bw];
+}
+
+__device__ inline int block_of(const int *blk, int P, int I) {
+    int lo = 0, hi = P - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (blk[mid] <= I) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Right-hand sides of the spike solves, dense column-major (NT*16 rows, ld),
+// nb*16 columns: RL(i, j) = L(i, (blk[p]-nb)*16 + j) for the first nb tile
+// rows of each block p >= 1; RU(i, j) = U(i, blk[p+1]*16 + j) for the last nb
+// tile rows of each block p <= P-2; zero elsewhere.
+__global__ void k_spike_rhs(int64_t n, int bw, int NT, int nb, int P, const int *blk, const double *lu,
+                            double *RL, double *RU) {
+    const int64_t ld = (int64_t)NT * TILE;
+    const int64_t total = ld * nb * TILE;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % ld;
+        const int j = (int)(e / ld);
+        const int I = (int)(i / TILE);
+        const int p = block_of(blk, P, I);
+        double l = 0.0, u = 0.0;
+        if (p >= 1 && I < blk[p] + nb) l = band_at(lu, n, bw, i, (int64_t)(blk[p] - nb) * TILE + j);
+        if (p <= P - 2 && I >= blk[p + 1] - nb) u = band_at(lu, n, bw, i, (int64_t)blk[p + 1] * TILE + j);
+        RL[e] = l;
+        RU[e] = u;
+    }
+}
+
+hipError_t launch_spike_rhs(int64_t n, int bw, int NT, int nb, int P, const int *d_blk, const double *lu,
+                            double *RL, double *RU, hipStream_t s) {
+    const int64_t total = (int64_t)NT * TILE * nb * TILE;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_spike_rhs, dim3((unsigned)blocks), dim3(256), 0, s, n, bw, NT, nb, P, d_blk, lu, RL, RU);
+    return hipGetLastError();
+}
+
+// dense (NT*16 x nb*16, column-major, ld) -> NT x nb tiles, lane-major MFMA A
+// operands: element (m, k) of tile (I, s) is dense(I*16 + m, s*16 + k)
+template <typename T>
+__global__ void k_spike_pack(int NT, int nb, const T *dense, int64_t ld, T *tiles) {
+    const int64_t total = (int64_t)NT * nb * TILE_ELEMS;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t tile = e / TILE_ELEMS;
+        const int o = (int)(e % TILE_ELEMS);
+        const int64_t I = tile / nb;
+        const int s = (int)(tile % nb);
+        const int m = o >> 4, k = o & 15;
+        int g, kc;
+        Mf<T>::gk(k, g, kc);
+        tiles[tile * TILE_ELEMS + Mf<T>::slot(16 * g + m, kc)] = dense[(I * TILE + m) + (int64_t)(s * TILE + k) * ld];
+    }
+}
+
+hipError_t launch_spike_pack(bool f32, int NT, int nb, const void *dense, int64_t ld, void *tiles, hipStream_t s) {
+    const int64_t total = (int64_t)NT * nb * TILE_ELEMS;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (f32)
+        hipLaunchKernelGGL(k_spike_pack<float>, dim3((unsigned)blocks), dim3(256), 0, s, NT, nb, (const float *)dense,
+                           ld, (float *)tiles);
+    else
+        hipLaunchKernelGGL(k_spike_pack<double>, dim3((unsigned)blocks), dim3(256), 0, s, NT, nb,
+                           (const double *)dense, ld, (double *)tiles);
+    return hipGetLastError();
+}
+
+// tile row I of the group's columns, accumulator order (rows clamped into the
+// array: padded rows never feed a stored value)
+template <typename T>
+__device__ __forceinline__ void load_rows(const SplitGroup &G, int I, int lane, T (&v)[4]) {
+    const int g = lane >> 4, c = lane & 15;
+    const int col = c < G.ncols ? c : 0;
+    const T *X = (const T *)G.X;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int row = I * TILE + Mf<T>::row(g, i);
+        row = row < G.n ? row : G.n - 1;
+        v[i] = gld(X + row + (int64_t)col * G.ldx);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_rows(const SplitGroup &G, int I, int lane, const typename Mf<T>::v4 &v) {
+    const int g = lane >> 4, c = lane & 15;
+    if (c >= G.ncols) return;
+    T *X = (T *)G.X;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = I * TILE + Mf<T>::row(g, i);
+        if (row < G.n) gst(X + row + (int64_t)c * G.ldx, v[i]);
+    }
+}
+
+// Chain over the blocks of one group (one workgroup of 4 waves per group).
+// L (upper = false): bnd[0] = tail of block 0, bnd[p] = g_p^tail - S_p^tail
+// bnd[p-1], p = 1..P-1.  U: bnd[P-1] = head of the last block, bnd[p] =
+// h_p^head - T_p^head bnd[p+1].  Wave w computes the boundary tile rows
+// t = w, w+4, ...; the spike tiles (A operands, independent of the chain
+// values) stream through a PF-deep register ring across the steps, the
+// previous step's boundary tiles (B operands) sit in LDS, double-buffered.
+constexpr int CPF = 4;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_split_chain(const SplitGroup *groups, int upper) {
+    typedef typename Mf<T>::v4 v4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SplitGroup G = groups[blockIdx.x];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nb = G.nb, P = G.P;
+    T *prev = (T *)smem;   // [2][nb] tiles, accumulator order
+    const T *A = (const T *)(upper ? G.T : G.S);
+    T *bnd = (T *)G.bnd;
+    // boundary rows of the chain's k-th block
+    auto base_of = [&](int k) {
+        const int p = upper ? P - 1 - k : k;
+        return upper ? G.blk[p] : G.blk[p + 1] - nb;
+    };
+    auto block_of_k = [&](int k) { return upper ? P - 1 - k : k; };
+    // first block: its own solution
+    for (int t = w; t < nb; t += 4) {
+        T x[4];
+        load_rows(G, base_of(0) + t, lane, x);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            prev[t * TILE_ELEMS + i * 64 + lane] = x[i];
+            bnd[((int64_t)block_of_k(0) * nb + t) * TILE_ELEMS + i * 64 + lane] = x[i];
+        }
+    }
+    const int share = (nb + 3) / 4;                      // output tiles per wave (some may be void)
+    const int ips = (share * nb + CPF - 1) / CPF * CPF;  // items per step, ring-aligned
+    const int total = (P - 1) * ips;
+    // A operand of item idx (void items read the block's first spike tile)
+    auto a_ptr = [&](int idx) {
+        const int k = 1 + idx / ips;
+        const int i = idx % ips;
+        const int j = i / nb, s = i % nb;
+        const int t = w + 4 * j;
+        const int kk = k < P ? k : P - 1;
+        const int I = base_of(kk) + (t < nb && i < share * nb ? t : 0);
+        return A + ((int64_t)I * nb + (t < nb && i < share * nb ? s : 0)) * TILE_ELEMS;
+    };
+    T abuf[CPF][4];
+#pragma unroll
+    for (int u = 0; u < CPF - 1; ++u) Mf<T>::ld4(a_ptr(u < total ? u : 0), lane, abuf[u]);
+    v4 acc = {0, 0, 0, 0};
+    T x[4] = {0, 0, 0, 0};
+    for (int k = 1; k < P; ++k) {
+        __syncthreads();   // step k-1's boundary tiles are in prev[(k-1)&1]
+        const T *pin = prev + ((k - 1) & 1) * nb * TILE_ELEMS;
+        T *pout = prev + (k & 1) * nb * TILE_ELEMS;
+        const int base = base_of(k);
+        const int p = block_of_k(k);
+        for (int i0 = 0; i0 < ips; i0 += CPF) {
+#pragma unroll
+            for (int u = 0; u < CPF; ++u) {
+                const int idx = (k - 1) * ips + i0 + u;
+                const int nx = idx + CPF - 1;
+                Mf<T>::ld4(a_ptr(nx < total ? nx : 0), lane, abuf[(u + CPF - 1) % CPF]);
+                const int i = i0 + u;
+                const int j = i / nb, s = i % nb;
+                const int t = w + 4 * j;
+                const bool valid = i < share * nb && t < nb;
+                if (valid) {
+                    if (s == 0) load_rows(G, base + t, lane, x);
+                    const T *bs = pin + s * TILE_ELEMS;
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) acc = Mf<T>::mma(abuf[u][kc], bs[kc * 64 + lane], acc);
+                    if (s == nb - 1) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const T o = x[q] - acc[q];
+                            pout[t * TILE_ELEMS + q * 64 + lane] = o;
+                            bnd[((int64_t)p * nb + t) * TILE_ELEMS + q * 64 + lane] = o;
+                        }
+                        acc = v4{0, 0, 0, 0};
+                    }
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_split_chain(bool f32, bool upper, int ngroups, const SplitGroup *d_groups, int max_nb,
+                              hipStream_t s) {
+    if (ngroups <= 0) return hipSuccess;
+    const size_t lds = 2 * (size_t)max_nb * TILE_ELEMS * (f32 ? 4 : 8);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (f32)
+        hipLaunchKernelGGL(k_split_chain<float>, dim3(ngroups), dim3(256), lds, s, d_groups, upper ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_split_chain<double>, dim3(ngroups), dim3(256), lds, s, d_groups, upper ? 1 : 0);
+    return hipGetLastError();
+}
+
+// Update of every block with a neighbour: one workgroup (4 waves) per
+// (group, block, 4 tile rows); wave w updates tile row blk[p] + 4*chunk + w:
+// X(I) -= sum_s A(I, s) bnd[neighbour][s], operands through a CPF-deep ring.
+template <typename T>
+__global__ __launch_bounds__(256) void k_split_update(const SplitGroup *groups, int upper, int maxP, int chunks) {
+    typedef typename Mf<T>::v4 v4;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t unit = blockIdx.x;
+    const int64_t per_group = (int64_t)maxP * chunks;
+    const SplitGroup G = groups[unit / per_group];
+    const int rest = (int)(unit % per_group);
+    const int p = rest / chunks, chunk = rest % chunks;
+    if (p >= G.P) return;
+    if (upper ? p == G.P - 1 : p == 0) return;
+    const int I = G.blk[p] + 4 * chunk + w;
+    if (I >= G.blk[p + 1]) return;
+    const int nb = G.nb;
+    const T *A = (const T *)(upper ? G.T : G.S) + (int64_t)I * nb * TILE_ELEMS;
+    const T *b = (const T *)G.bnd + (int64_t)(upper ? p + 1 : p - 1) * nb * TILE_ELEMS;
+    T x[4];
+    load_rows(G, I, lane, x);
+    T abuf[CPF][4], bbuf[CPF][4];
+    auto fetch = [&](int s, T (&av)[4], T (&bv)[4]) {
+        const int ss = s < nb ? s : 0;
+        Mf<T>::ld4(A + (int64_t)ss * TILE_ELEMS, lane, av);
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) bv[kc] = gld(b + (int64_t)ss * TILE_ELEMS + kc * 64 + lane);
+    };
+#pragma unroll
+    for (int u = 0; u < CPF - 1; ++u) fetch(u, abuf[u], bbuf[u]);
+    v4 acc = {0, 0, 0, 0};
+    const int nsp = (nb + CPF - 1) / CPF * CPF;
+    for (int s0 = 0; s0 < nsp; s0 += CPF) {
+#pragma unroll
+        for (int u = 0; u < CPF; ++u) {
+            const int s = s0 + u;
+            fetch(s + CPF - 1, abuf[(u + CPF - 1) % CPF], bbuf[(u + CPF - 1) % CPF]);
+            if (s < nb) {
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) acc = Mf<T>::mma(abuf[u][kc], bbuf[u][kc], acc);
+            }
+        }
+    }
+    v4 o;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = x[q] - acc[q];
+    store_rows<T>(G, I, lane, o);
+}
+
+hipError_t launch_split_update(bool f32, bool upper, int ngroups, const SplitGroup *d_groups, int max_P,
+                               int max_rows, hipStream_t s) {
+    if (ngroups <= 0) return hipSuccess;
+    const int chunks = (max_rows + 3) / 4;
+    const int64_t grid = (int64_t)ngroups * max_P * chunks;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    if (f32)
+        hipLaunchKernelGGL(k_split_update<float>, dim3((unsigned)grid), dim3(256), 0, s, d_groups, upper ? 1 : 0,
+                           max_P, chunks);
+    else
+        hipLaunchKernelGGL(k_split_update<double>, dim3((unsigned)grid), dim3(256), 0, s, d_groups, upper ? 1 : 0,
+                           max_P, chunks);
+    return hipGetLastError();
+}
+
+}  // namespace lrpr

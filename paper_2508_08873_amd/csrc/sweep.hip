@@ -31,55 +31,9 @@
 // q (computed between barriers q and q+1) and the hand-off of row q.  The last
 // nb solved tiles live in an LDS ring.  Narrow bands (nb <= 4) run one wave.
 #include "lrpr_internal.h"
+#include "tile_ops.h"
 
 namespace lrpr {
-
-// Loads and stores through address space 1 compile to global_* instructions
-// (flat_* would also count against the LDS counter and be drained by every
-// LDS barrier, cancelling the prefetch).
-template <typename T> using gptr = __attribute__((address_space(1))) const T *;
-template <typename T> using gptr_mut = __attribute__((address_space(1))) T *;
-template <typename T> __device__ __forceinline__ T gld(const T *p) { return *(gptr<T>)p; }
-template <typename T> __device__ __forceinline__ void gst(T *p, T v) { *(gptr_mut<T>)p = v; }
-
-typedef double d2v __attribute__((ext_vector_type(2)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mf;
-
-// f64 16x16x4: A[m][k] in lane m+16k, B[k][n] in lane n+16k,
-// D[m][n] in lane n+16(m%4), register m/4.
-template <> struct Mf<double> {
-    typedef double v4 __attribute__((ext_vector_type(4)));
-    __device__ static inline v4 mma(double a, double b, v4 c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    // row held by register i of lane group g
-    __device__ static inline int row(int g, int i) { return 4 * i + g; }
-    // position of (lane l, chunk kc) in a lane-major tile
-    __device__ static inline int slot(int l, int kc) { return 128 * (kc >> 1) + 2 * l + (kc & 1); }
-    // (lane group, chunk) whose contraction index is k
-    __device__ static inline void gk(int k, int &g, int &kc) { g = k & 3; kc = k >> 2; }
-    __device__ static inline void ld4(const double *tile, int l, double (&v)[4]) {
-        const d2v a = *(gptr<d2v>)(tile + 2 * l), b = *(gptr<d2v>)(tile + 128 + 2 * l);
-        v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
-    }
-};
-
-// f32 16x16x4: A and B as above, D[m][n] in lane n+16(m/4), register m%4.
-template <> struct Mf<float> {
-    typedef float v4 __attribute__((ext_vector_type(4)));
-    __device__ static inline v4 mma(float a, float b, v4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    __device__ static inline int row(int g, int i) { return 4 * g + i; }
-    __device__ static inline int slot(int l, int kc) { return 4 * l + kc; }
-    __device__ static inline void gk(int k, int &g, int &kc) { g = k >> 2; kc = k & 3; }
-    __device__ static inline void ld4(const float *tile, int l, float (&v)[4]) {
-        const f4v a = *(gptr<f4v>)(tile + 4 * l);
-        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
-    }
-};
 
 constexpr int max5(int a, int b, int c, int d, int e) {
     int m = a;
@@ -123,7 +77,8 @@ struct Pass {
     const T *__restrict__ dtile;
     const T *__restrict__ zt;
     T *ring;
-    int lane, w, g, c, n, NT, nb, RS, nbulk;
+    int lane, w, g, c, n, NT, nb, RS, nbulk;   // NT: tile rows of the item's range
+    int r0, r1;                                 // the range [r0, r1) of tile rows
     int soff[4];   // STRIDED: position of this lane's chunk values in a forward tile
 
     __device__ Pass(const SweepItem &it, const T *band_, const T *dtile_, T *ring_)
@@ -133,7 +88,9 @@ struct Pass {
         g = lane >> 4;
         c = lane & 15;
         n = it.fac.n;
-        NT = it.fac.NT;
+        r0 = it.r0;
+        r1 = it.r1;
+        NT = r1 - r0;
         nb = it.fac.nb;
         RS = nb + 1;
         nbulk = nb - 1;
@@ -147,7 +104,7 @@ struct Pass {
             soff[kc] = Mf<T>::slot(16 * gp + Mf<T>::row(g, kc), kcp);
         }
     }
-    __device__ __forceinline__ int row_of(int q) const { return ASC ? q : NT - 1 - q; }
+    __device__ __forceinline__ int row_of(int q) const { return ASC ? r0 + q : r1 - 1 - q; }
     __device__ __forceinline__ const T *tile_ptr(int I, int j, int J) const {
         if (STRIDED) return band + ((int64_t)J * nb + (nb - 1 - j)) * TILE_ELEMS;
         return band + ((int64_t)I * nb + j) * TILE_ELEMS;
@@ -271,7 +228,7 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
         if (fc >= 0) {
             fsrc = (const T *)it.f + (int64_t)fc * it.ldf;
             fstride = 1;
-            const double sc = it.fscale ? it.fscale[(int64_t)c * nsteps + step] : 1.0;
+            const double sc = it.fscale ? it.fscale[(int64_t)c * it.fsteps + step] : 1.0;
             fs = (T)(it.fac.dt * sc);
         }
     }
@@ -480,37 +437,53 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
     __syncthreads();
 }
 
+// Zero the LDS ring before a pass: it must hold finite values only (zero
+// tiles multiply stale slots), and rows before the item's range must read as
+// zero (they are not coupled in).
+template <typename T>
+__device__ __forceinline__ void clear_ring(T *ring, int nb) {
+    for (int e = threadIdx.x; e < (nb + 2) * TILE_ELEMS; e += blockDim.x) ring[e] = (T)0;
+    __syncthreads();
+}
+
 // ADJ: adjoint sweep, on the mirrored set or (STRIDED) the transposed
-// forward tiles.
+// forward tiles.  Steps step0 .. step0+nsteps-1 (the step picks the source's
+// time factor); each item runs the passes its mask selects.
 template <typename T, int KW, typename SP, int PD, bool ADJ, bool STRIDED>
-__global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__ items, int nitems,
-                                                   int nsteps) {
+__global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__ items, int nitems, int nsteps,
+                                                   int step0) {
     extern __shared__ __align__(16) unsigned char smem[];
     for (int idx = blockIdx.x; idx < nitems; idx += gridDim.x) {
         const SweepItem it = items[idx];
         T *ring = (T *)smem;
-        // the ring must hold finite values only: zero tiles multiply stale slots
-        for (int e = threadIdx.x; e < (it.fac.nb + 2) * TILE_ELEMS; e += blockDim.x) ring[e] = (T)0;
-        __syncthreads();
         T *red = ring + (it.fac.nb + 2) * TILE_ELEMS;              // [2][KW-3][256]
         T *hand = red + 2 * (KW > 1 ? KW - 3 : 1) * TILE_ELEMS;     // [2][2][256]: E, r
         const void *const *a = it.fac.a;
-        for (int step = 0; step < nsteps; ++step) {
-            if (!ADJ) {
-                sweep_pass<T, KW, SP, PD, true, false>(it, (const T *)a[TS_LB], (const T *)a[TS_DL], ring, red, hand,
-                                                       it.f != nullptr, step, nsteps);
-                sweep_pass<T, KW, SP, PD, false, false>(it, (const T *)a[TS_UB], (const T *)a[TS_DU], ring, red, hand,
-                                                        false, step, nsteps);
-            } else if (!STRIDED) {
-                sweep_pass<T, KW, SP, PD, true, false>(it, (const T *)a[TS_UTB], (const T *)a[TS_DUT], ring, red,
-                                                       hand, false, step, nsteps);
-                sweep_pass<T, KW, SP, PD, false, false>(it, (const T *)a[TS_LTB], (const T *)a[TS_DLT], ring, red,
-                                                        hand, false, step, nsteps);
-            } else {
-                sweep_pass<T, KW, SP, PD, true, true>(it, (const T *)a[TS_UB], (const T *)a[TS_DUT], ring, red, hand,
-                                                      false, step, nsteps);
-                sweep_pass<T, KW, SP, PD, false, true>(it, (const T *)a[TS_LB], (const T *)a[TS_DLT], ring, red, hand,
-                                                       false, step, nsteps);
+        for (int s = 0; s < nsteps; ++s) {
+            const int step = step0 + s;
+            if (it.passes & 1) {
+                clear_ring(ring, it.fac.nb);
+                if (!ADJ)
+                    sweep_pass<T, KW, SP, PD, true, false>(it, (const T *)a[TS_LB], (const T *)a[TS_DL], ring, red,
+                                                           hand, it.f != nullptr, step, nsteps);
+                else if (!STRIDED)
+                    sweep_pass<T, KW, SP, PD, true, false>(it, (const T *)a[TS_UTB], (const T *)a[TS_DUT], ring, red,
+                                                           hand, false, step, nsteps);
+                else
+                    sweep_pass<T, KW, SP, PD, true, true>(it, (const T *)a[TS_UB], (const T *)a[TS_DUT], ring, red,
+                                                          hand, false, step, nsteps);
+            }
+            if (it.passes & 2) {
+                clear_ring(ring, it.fac.nb);
+                if (!ADJ)
+                    sweep_pass<T, KW, SP, PD, false, false>(it, (const T *)a[TS_UB], (const T *)a[TS_DU], ring, red,
+                                                            hand, false, step, nsteps);
+                else if (!STRIDED)
+                    sweep_pass<T, KW, SP, PD, false, false>(it, (const T *)a[TS_LTB], (const T *)a[TS_DLT], ring, red,
+                                                            hand, false, step, nsteps);
+                else
+                    sweep_pass<T, KW, SP, PD, false, true>(it, (const T *)a[TS_LB], (const T *)a[TS_DLT], ring, red,
+                                                           hand, false, step, nsteps);
             }
         }
     }
@@ -518,20 +491,20 @@ __global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__
 
 template <typename T, int KW, typename SP, int PD>
 static hipError_t launch_t(bool adjoint, bool strided, int nitems, const SweepItem *d_items, int nsteps,
-                           int max_nb, hipStream_t s) {
+                           int max_nb, hipStream_t s, int step0) {
     // LDS: ring of nb+1 solved tiles (+1 dummy slot), double-buffered partial
     // sums of the bulk waves, double-buffered hand-off (E, r)
     const size_t lds = (size_t)(max_nb + 2 + 2 * (KW > 1 ? KW - 3 : 1) + 4) * TILE_ELEMS * sizeof(T);
     const int grid = nitems < 65536 ? nitems : 65536;
     if (!adjoint)
         hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, false, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
-                           nitems, nsteps);
+                           nitems, nsteps, step0);
     else if (!strided)
         hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, true, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
-                           nitems, nsteps);
+                           nitems, nsteps, step0);
     else
         hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, true, true>), dim3(grid), dim3(64 * KW), lds, s, d_items,
-                           nitems, nsteps);
+                           nitems, nsteps, step0);
     return hipGetLastError();
 }
 
@@ -554,32 +527,32 @@ static hipError_t launch_t(bool adjoint, bool strided, int nitems, const SweepIt
 // finisher's operands and write the output.  Narrow bands run on one wave.
 template <typename T>
 static hipError_t launch_prec(bool adjoint, bool strided, int nitems, const SweepItem *d_items, int nsteps,
-                              int max_nb, hipStream_t s) {
+                              int max_nb, hipStream_t s, int step0) {
     constexpr bool F64 = sizeof(T) == 8;
-    if (max_nb <= 1) return launch_t<T, 1, Split<1, 0, 0, 0, 0>, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
-    if (max_nb <= 4) return launch_t<T, 1, Split<3, 0, 0, 0, 0>, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    if (max_nb <= 1) return launch_t<T, 1, Split<1, 0, 0, 0, 0>, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
+    if (max_nb <= 4) return launch_t<T, 1, Split<3, 0, 0, 0, 0>, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
     if (max_nb <= 8)
-        return launch_t<T, 8, Split<1, 2, 2, 1, 1>, F64 ? 4 : 6>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+        return launch_t<T, 8, Split<1, 2, 2, 1, 1>, F64 ? 4 : 6>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
     if (max_nb <= 16) {
         if constexpr (F64)
             return launch_t<T, 8, Split<LRPR_SPLIT16_F64>, LRPR_PD16_F64>(adjoint, strided, nitems, d_items, nsteps,
-                                                                          max_nb, s);
+                                                                          max_nb, s, step0);
         else
             return launch_t<T, 8, Split<LRPR_SPLIT16_F32>, LRPR_PD16_F32>(adjoint, strided, nitems, d_items, nsteps,
-                                                                          max_nb, s);
+                                                                          max_nb, s, step0);
     }
     if (max_nb <= 32)
-        return launch_t<T, 8, Split<6, 7, 6, 6, 6>, F64 ? 2 : 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+        return launch_t<T, 8, Split<6, 7, 6, 6, 6>, F64 ? 2 : 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
     if (max_nb <= 64)
-        return launch_t<T, 8, Split<13, 13, 13, 13, 11>, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+        return launch_t<T, 8, Split<13, 13, 13, 13, 11>, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const SweepItem *d_items, int nsteps,
-                        int max_nb, hipStream_t s) {
+                        int max_nb, hipStream_t s, int step0) {
     if (nitems <= 0 || nsteps <= 0) return hipSuccess;
-    if (f32) return launch_prec<float>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
-    return launch_prec<double>(adjoint, strided, nitems, d_items, nsteps, max_nb, s);
+    if (f32) return launch_prec<float>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
+    return launch_prec<double>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
 }
 
 }  // namespace lrpr

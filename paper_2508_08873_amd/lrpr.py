@@ -27,7 +27,7 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
 
 
 # lrpr_factor store_mask bits (include/lrpr.h)
-STORE_F64, STORE_F32, STORE_MIRROR = 1, 2, 4
+STORE_F64, STORE_F32, STORE_MIRROR, STORE_SPLIT = 1, 2, 4, 8
 
 
 class LrprError(RuntimeError):

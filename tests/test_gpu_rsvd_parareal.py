@@ -202,6 +202,21 @@ def test_parareal_fp32_fine(ctx, ora):
     assert np.linalg.norm(Ug - seq, axis=1).max() <= 1e-5 * scale
 
 
+def test_parareal_partitioned_fine(ctx, ora):
+    """Parareal whose fine solves take the partitioned path (factor kept with
+    spikes) reaches the same iterate as with plain sweeps."""
+    from paper_2508_08873_amd.lrpr import STORE_F64, STORE_MIRROR, STORE_SPLIT
+    P = inputs.tiny2d(nx=63, N=6, m=4, k=8, p=3)
+    ops, facs, oms, coarse = _build(ctx, ora, P, P.N, 0, mask=STORE_F64 | STORE_MIRROR | STORE_SPLIT)
+    u0 = P.u0()
+    res, seq, _ = _oracle_parareal(ora, P, ops, oms, u0, P.N, 1e-12)
+    out = _gpu_parareal(ctx, P, facs, coarse, [u0], 1e-12)
+    assert out["iters"][0] == res["iters"]
+    Ug = out["U"][0].cpu().numpy()
+    Uo = res["iterates"][-1]
+    assert np.linalg.norm(Ug - Uo, axis=1).max() <= 1e-11 * np.linalg.norm(Uo, axis=1).max()
+
+
 def test_parareal_rank_zero_exact_after_N(ctx, ora):
     """R = 0 (only b_n in G_n) still reaches the fine solution after N
     iterations."""

@@ -150,3 +150,49 @@ def test_zero_width_and_zero_steps_are_noops(ctx):
     ctx.fine_step_batched([{"F": F, "X": X}], 0, 0)
     torch.cuda.synchronize()
     assert torch.all(X == 1)
+
+
+SPLIT_CASES = [
+    ("2d_nx31", lambda: inputs.tiny2d(nx=31, m=3), 21),
+    ("2d_nx63", lambda: inputs.tiny2d(nx=63, m=3), 16),
+    ("2d_nx100", lambda: inputs.tiny2d(nx=100, m=2, beta=(-12.0, 25.0)), 40),
+    ("2d_nx255", lambda: inputs.tiny2d(nx=255, m=2, T=1.0 / 64), 7),
+]
+
+
+@pytest.mark.parametrize("name,mk,w", SPLIT_CASES, ids=[c[0] for c in SPLIT_CASES])
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_partitioned_fine_sweep_parity(ctx, ora, name, mk, w, prec):
+    """Fine sweeps of few column groups on factors kept with spikes run as
+    partitioned passes (local block solves, chain, update); same oracle
+    tolerance as the plain sweep."""
+    from paper_2508_08873_amd.lrpr import STORE_F32, STORE_F64, STORE_SPLIT
+    P = mk()
+    print("case", name, "prec", prec, flush=True)
+    op = ora.Operator(**P.op_params())
+    F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=STORE_F64 | STORE_F32 | STORE_SPLIT)
+    X0 = np.random.default_rng(4).standard_normal((P.n, w))
+    f = P.source()
+    fsc = np.stack([P.fscale(1 + (c % P.N)) for c in range(w)])[:, :P.m]
+    ref = op.fine(X0, P.m, f, None, fsc)
+    X = _to_dev(X0, prec)
+    spec = {"F": F, "X": X, "f": _to_dev(f.reshape(-1, 1), prec),
+            "fscale": torch.from_numpy(np.ascontiguousarray(fsc)).to("cuda", torch.float64)}
+    ctx.fine_step_batched([spec], P.m, prec)
+    torch.cuda.synchronize()
+    err = _colerr(X.double().cpu().numpy(), ref)
+    assert err <= TOL[prec], err
+
+
+def test_partitioned_equals_plain(ctx):
+    """Same input through a factor with and without spikes (FP64)."""
+    from paper_2508_08873_amd.lrpr import STORE_F64, STORE_SPLIT
+    P = inputs.tiny2d(nx=100, m=3)
+    Fp = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=STORE_F64)
+    Fs = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=STORE_F64 | STORE_SPLIT)
+    X0 = np.random.default_rng(8).standard_normal((P.n, 30))
+    Xp, Xs = _to_dev(X0, 0), _to_dev(X0, 0)
+    ctx.fine_step_batched([{"F": Fp, "X": Xp}], P.m, 0)
+    ctx.fine_step_batched([{"F": Fs, "X": Xs}], P.m, 0)
+    torch.cuda.synchronize()
+    assert _colerr(Xs.cpu().numpy(), Xp.cpu().numpy()) <= 1e-13
