@@ -122,7 +122,7 @@ lrpr_status ensure_items(lrpr_ctx ctx, size_t count);
 // solves, NT/P tile rows, against the sequential chain, P steps of nb^2 tile
 // products), each at least 2 nb tile rows.
 static std::vector<int> split_blocks(int NT, int nb) {
-    int P = 24;
+    int P = 24 < SPLIT_MAX_P ? 24 : SPLIT_MAX_P;
     if (P > NT / (2 * nb)) P = NT / (2 * nb);
     std::vector<int> blk;
     if (P < 2) return blk;
@@ -196,7 +196,7 @@ static lrpr_status build_split(lrpr_ctx ctx, lrpr_fac f, const double *band) {
         if ((e = hipMemcpyAsync(ctx->d_items, items.data(), items.size() * sizeof(SweepItem), hipMemcpyHostToDevice,
                                 st)) != hipSuccess)
             return bail(e, "spike items");
-        if ((e = launch_sweep(false, false, solve32, (int)items.size(), ctx->d_items, 1, nb, st)) != hipSuccess)
+        if ((e = launch_sweep(false, false, solve32, (int)items.size(), ctx->d_items, 1, nb, st, 0, true)) != hipSuccess)
             return bail(e, "spike solves");
     }
     if (!solve32 && (f->mask & LRPR_STORE_F32)) {
@@ -419,8 +419,16 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
     }
     hipError_t e = hipSuccess;
     char *bnd = (char *)ws_get(ctx, "split_bnd", bnd_elems * esz, &e);
+    // runs of consecutive groups on one factor (the update reads their spikes once)
+    std::vector<int2> runs;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        if (g > 0 && gf[g] == gf[g - 1]) ++runs.back().y;
+        else runs.push_back(make_int2((int)g, 1));
+    }
     SplitGroup *d_groups = (SplitGroup *)ws_get(ctx, "split_groups", sizeof(SplitGroup) * sg.size(), &e);
-    if (!bnd || !d_groups) return hipfail(ctx, e == hipSuccess ? hipErrorOutOfMemory : e, "split workspace");
+    int2 *d_runs = d_groups ? (int2 *)ws_get(ctx, "split_runs", sizeof(int2) * runs.size(), &e) : nullptr;
+    if (!bnd || !d_groups || !d_runs)
+        return hipfail(ctx, e == hipSuccess ? hipErrorOutOfMemory : e, "split workspace");
     size_t off = 0;
     for (int pass = 0; pass < 2; ++pass)
         for (size_t g = 0; g < groups.size(); ++g) {
@@ -461,19 +469,25 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
     if ((e = hipMemcpyAsync(ctx->d_items, loc.data(), loc.size() * sizeof(SweepItem), hipMemcpyHostToDevice, st)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(d_groups, sg.data(), sg.size() * sizeof(SplitGroup), hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(d_runs, runs.data(), runs.size() * sizeof(int2), hipMemcpyHostToDevice, st)) !=
             hipSuccess)
         return hipfail(ctx, e, "split upload");
     lrpr_ctx_s::ProfRec rec{};
     if (ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
         return hipfail(ctx, e, "profile event");
     const int ng = (int)sg.size();
+    bool uni = max_nb == 8 || max_nb == 16 || max_nb == 32;
+    for (const SplitGroup &G : sg) uni = uni && G.nb == max_nb;
+    const int nr = uni ? (int)runs.size() : 0;
+    const int2 *dr = uni ? d_runs : nullptr;
     for (int step = 0; step < nsteps; ++step) {
-        if ((e = launch_sweep(false, false, f32, nL, ctx->d_items, 1, max_nb, st, step)) != hipSuccess ||
-            (e = launch_split_chain(f32, false, ng, d_groups, max_nb, st)) != hipSuccess ||
-            (e = launch_split_update(f32, false, ng, d_groups, max_P, max_rows, st)) != hipSuccess ||
-            (e = launch_sweep(false, false, f32, nL, ctx->d_items + nL, 1, max_nb, st, step)) != hipSuccess ||
-            (e = launch_split_chain(f32, true, ng, d_groups, max_nb, st)) != hipSuccess ||
-            (e = launch_split_update(f32, true, ng, d_groups, max_P, max_rows, st)) != hipSuccess)
+        if ((e = launch_sweep(false, false, f32, nL, ctx->d_items, 1, max_nb, st, step, true)) != hipSuccess ||
+            (e = launch_split_chain(f32, false, ng, d_groups, max_nb, st, uni)) != hipSuccess ||
+            (e = launch_split_update(f32, false, ng, d_groups, max_P, max_rows, st, max_nb, nr, dr)) != hipSuccess ||
+            (e = launch_sweep(false, false, f32, nL, ctx->d_items + nL, 1, max_nb, st, step, true)) != hipSuccess ||
+            (e = launch_split_chain(f32, true, ng, d_groups, max_nb, st, uni)) != hipSuccess ||
+            (e = launch_split_update(f32, true, ng, d_groups, max_P, max_rows, st, max_nb, nr, dr)) != hipSuccess)
             return hipfail(ctx, e, "split sweep");
     }
     if (ctx->prof) {

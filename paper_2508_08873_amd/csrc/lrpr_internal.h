@@ -92,6 +92,8 @@ struct SweepItem {
 // are stored like the band tiles: NT x nb tiles (MFMA A operands), row I of
 // block p holding S_p(I, .) (rows of block 0 unused) and T_p(I, .) (rows of
 // the last block unused).
+constexpr int SPLIT_MAX_P = 64;   // most blocks of a partitioned factor
+
 struct SplitSet {
     void *S = nullptr;
     void *T = nullptr;
@@ -170,16 +172,22 @@ hipError_t launch_tile_lu(int64_t n, int bw, int NT, int nb, double *band, void 
 hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu, const TileSet *t64,
                              const TileSet *t32, double *scratch, hipStream_t s);
 // adjoint sweeps read the mirrored set unless `strided` (then the forward
-// tiles are read transposed)
+// tiles are read transposed); `local`: forward block solves of a partitioned
+// pass (same code, launched as k_sweep_local)
 hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const SweepItem *d_items, int nsteps,
-                        int max_nb, hipStream_t s, int step0 = 0);
+                        int max_nb, hipStream_t s, int step0 = 0, bool local = false);
 // partitioned passes (split.hip)
 hipError_t launch_spike_rhs(int64_t n, int bw, int NT, int nb, int P, const int *d_blk, const double *lu,
                             double *RL, double *RU, hipStream_t s);
 hipError_t launch_spike_pack(bool f32, int NT, int nb, const void *dense, int64_t ld, void *tiles, hipStream_t s);
+// uniform_nb: every group has nb == max_nb (enables the kernels specialised
+// on the band-tile count)
 hipError_t launch_split_chain(bool f32, bool upper, int ngroups, const SplitGroup *d_groups, int max_nb,
-                              hipStream_t s);
+                              hipStream_t s, bool uniform_nb);
+// d_runs (or null): nruns runs {first group, count} of consecutive groups on
+// one factor, every group with nb == max_nb in {8, 16, 32} (the spike tiles
+// are then read once per run)
 hipError_t launch_split_update(bool f32, bool upper, int ngroups, const SplitGroup *d_groups, int max_P,
-                               int max_rows, hipStream_t s);
+                               int max_rows, hipStream_t s, int max_nb, int nruns, const int2 *d_runs);
 
 }  // namespace lrpr

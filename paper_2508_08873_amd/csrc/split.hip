@@ -141,14 +141,17 @@ __global__ __launch_bounds__(256) void k_split_chain(const SplitGroup *groups, i
     const SplitGroup G = groups[blockIdx.x];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ int sblk[SPLIT_MAX_P + 1];
     const int nb = G.nb, P = G.P;
     T *prev = (T *)smem;   // [2][nb] tiles, accumulator order
     const T *A = (const T *)(upper ? G.T : G.S);
     T *bnd = (T *)G.bnd;
+    for (int i = threadIdx.x; i <= P; i += 256) sblk[i] = gld(G.blk + i);
+    __syncthreads();
     // boundary rows of the chain's k-th block
     auto base_of = [&](int k) {
         const int p = upper ? P - 1 - k : k;
-        return upper ? G.blk[p] : G.blk[p + 1] - nb;
+        return upper ? sblk[p] : sblk[p + 1] - nb;
     };
     auto block_of_k = [&](int k) { return upper ? P - 1 - k : k; };
     // first block: its own solution
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(256) void k_split_chain(const SplitGroup *groups, i
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             prev[t * TILE_ELEMS + i * 64 + lane] = x[i];
-            bnd[((int64_t)block_of_k(0) * nb + t) * TILE_ELEMS + i * 64 + lane] = x[i];
+            gst(bnd + ((int64_t)block_of_k(0) * nb + t) * TILE_ELEMS + i * 64 + lane, x[i]);
         }
     }
     const int share = (nb + 3) / 4;                      // output tiles per wave (some may be void)
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(256) void k_split_chain(const SplitGroup *groups, i
                         for (int q = 0; q < 4; ++q) {
                             const T o = x[q] - acc[q];
                             pout[t * TILE_ELEMS + q * 64 + lane] = o;
-                            bnd[((int64_t)p * nb + t) * TILE_ELEMS + q * 64 + lane] = o;
+                            gst(bnd + ((int64_t)p * nb + t) * TILE_ELEMS + q * 64 + lane, o);
                         }
                         acc = v4{0, 0, 0, 0};
                     }
@@ -215,15 +218,106 @@ __global__ __launch_bounds__(256) void k_split_chain(const SplitGroup *groups, i
     }
 }
 
+// Chain for a compile-time band-tile count NB: each output tile's NB spike
+// tiles are loaded together (and, for NB <= 16, the next tile's while the
+// current one multiplies), the B operands come from LDS.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_split_chain_nb(const SplitGroup *groups, int upper) {
+    typedef typename Mf<T>::v4 v4;
+    constexpr int NTW = (NB + 3) / 4;           // output tiles per wave per step
+    constexpr int NBUF = NB <= 16 ? 2 : 1;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int sblk[SPLIT_MAX_P + 1];       // block starts (LDS: no wait on the operand loads)
+    const SplitGroup G = groups[blockIdx.x];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int P = G.P;
+    T *prev = (T *)smem;   // [2][NB] tiles, accumulator order
+    const T *A = (const T *)(upper ? G.T : G.S);
+    T *bnd = (T *)G.bnd;
+    for (int i = threadIdx.x; i <= P; i += 256) sblk[i] = gld(G.blk + i);
+    __syncthreads();
+    auto base_of = [&](int k) {
+        const int p = upper ? P - 1 - k : k;
+        return upper ? sblk[p] : sblk[p + 1] - NB;
+    };
+    auto block_of_k = [&](int k) { return upper ? P - 1 - k : k; };
+    for (int t = w; t < NB; t += 4) {
+        T x[4];
+        load_rows(G, base_of(0) + t, lane, x);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            prev[t * TILE_ELEMS + i * 64 + lane] = x[i];
+            gst(bnd + ((int64_t)block_of_k(0) * NB + t) * TILE_ELEMS + i * 64 + lane, x[i]);
+        }
+    }
+    const int nq = (P - 1) * NTW;   // output tiles of this wave over the chain (some void)
+    auto load_q = [&](int q, T (&buf)[NB][4]) {
+        const int k = 1 + (q < nq ? q : 0) / NTW, j = (q < nq ? q : 0) % NTW;
+        const int t = w + 4 * j;
+        const int I = base_of(k) + (t < NB ? t : 0);
+#pragma unroll
+        for (int s = 0; s < NB; ++s) Mf<T>::ld4(A + ((int64_t)I * NB + s) * TILE_ELEMS, lane, buf[s]);
+    };
+    T ab[NBUF][NB][4];
+    if (NBUF == 2) load_q(0, ab[0]);
+    for (int q0 = 0; q0 < nq; q0 += NBUF) {
+#pragma unroll
+        for (int u = 0; u < NBUF; ++u) {
+            const int q = q0 + u;
+            if (q < nq) {
+                const int k = 1 + q / NTW, j = q % NTW;
+                if (j == 0) __syncthreads();   // step k-1's tiles are in prev[(k-1)&1]
+                if (NBUF == 2) load_q(q + 1, ab[u ^ 1]);
+                else load_q(q, ab[0]);
+                const int t = w + 4 * j;
+                if (t < NB) {
+                    const T *pin = prev + ((k - 1) & 1) * NB * TILE_ELEMS;
+                    T *pout = prev + (k & 1) * NB * TILE_ELEMS;
+                    const int I = base_of(k) + t;
+                    T x[4];
+                    load_rows(G, I, lane, x);
+                    v4 acc = {0, 0, 0, 0};
+#pragma unroll
+                    for (int s = 0; s < NB; ++s)
+#pragma unroll
+                        for (int kc = 0; kc < 4; ++kc)
+                            acc = Mf<T>::mma(ab[NBUF == 2 ? u : 0][s][kc], pin[s * TILE_ELEMS + kc * 64 + lane], acc);
+                    const int p = block_of_k(k);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const T o = x[i] - acc[i];
+                        pout[t * TILE_ELEMS + i * 64 + lane] = o;
+                        gst(bnd + ((int64_t)p * NB + t) * TILE_ELEMS + i * 64 + lane, o);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// nb of every group of a launch equals the launch's max_nb for the
+// specialised kernels (checked by the host)
 hipError_t launch_split_chain(bool f32, bool upper, int ngroups, const SplitGroup *d_groups, int max_nb,
-                              hipStream_t s) {
+                              hipStream_t s, bool uniform_nb) {
     if (ngroups <= 0) return hipSuccess;
     const size_t lds = 2 * (size_t)max_nb * TILE_ELEMS * (f32 ? 4 : 8);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const int up = upper ? 1 : 0;
+#define LRPR_CHAIN_NB(NBV)                                                                                     \
+    if (uniform_nb && max_nb == NBV) {                                                                         \
+        if (f32) hipLaunchKernelGGL((k_split_chain_nb<float, NBV>), dim3(ngroups), dim3(256), lds, s, d_groups, up); \
+        else hipLaunchKernelGGL((k_split_chain_nb<double, NBV>), dim3(ngroups), dim3(256), lds, s, d_groups, up);    \
+        return hipGetLastError();                                                                              \
+    }
+    LRPR_CHAIN_NB(8)
+    LRPR_CHAIN_NB(16)
+    LRPR_CHAIN_NB(32)
+#undef LRPR_CHAIN_NB
     if (f32)
-        hipLaunchKernelGGL(k_split_chain<float>, dim3(ngroups), dim3(256), lds, s, d_groups, upper ? 1 : 0);
+        hipLaunchKernelGGL(k_split_chain<float>, dim3(ngroups), dim3(256), lds, s, d_groups, up);
     else
-        hipLaunchKernelGGL(k_split_chain<double>, dim3(ngroups), dim3(256), lds, s, d_groups, upper ? 1 : 0);
+        hipLaunchKernelGGL(k_split_chain<double>, dim3(ngroups), dim3(256), lds, s, d_groups, up);
     return hipGetLastError();
 }
 
@@ -242,8 +336,8 @@ __global__ __launch_bounds__(256) void k_split_update(const SplitGroup *groups, 
     const int p = rest / chunks, chunk = rest % chunks;
     if (p >= G.P) return;
     if (upper ? p == G.P - 1 : p == 0) return;
-    const int I = G.blk[p] + 4 * chunk + w;
-    if (I >= G.blk[p + 1]) return;
+    const int I = gld(G.blk + p) + 4 * chunk + w;
+    if (I >= gld(G.blk + p + 1)) return;
     const int nb = G.nb;
     const T *A = (const T *)(upper ? G.T : G.S) + (int64_t)I * nb * TILE_ELEMS;
     const T *b = (const T *)G.bnd + (int64_t)(upper ? p + 1 : p - 1) * nb * TILE_ELEMS;
@@ -277,18 +371,100 @@ __global__ __launch_bounds__(256) void k_split_update(const SplitGroup *groups, 
     store_rows<T>(G, I, lane, o);
 }
 
+// Update for a compile-time band-tile count NB, one workgroup per (run of
+// groups on the same factor, block, 4 tile rows): the spike tiles of a row
+// (the same for every group of the run) are read once, the neighbour's
+// boundary tiles of each group are staged in LDS.  Wave w updates tile row
+// blk[p] + 4*chunk + w of every group of the run.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_split_update_nb(const SplitGroup *groups, const int2 *runs, int upper,
+                                                         int maxP, int chunks) {
+    typedef typename Mf<T>::v4 v4;
+    constexpr bool AREG = NB <= 16;   // spike row held in registers across the run
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *bl = (T *)smem;   // NB tiles
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t unit = blockIdx.x;
+    const int64_t per_run = (int64_t)maxP * chunks;
+    const int2 run = runs[unit / per_run];
+    const int rest = (int)(unit % per_run);
+    const int p = rest / chunks, chunk = rest % chunks;
+    const SplitGroup &G0 = groups[run.x];
+    const int P = G0.P;
+    if (p >= P) return;
+    if (upper ? p == P - 1 : p == 0) return;
+    const int b0 = gld(G0.blk + p), b1 = gld(G0.blk + p + 1);
+    if (b0 + 4 * chunk >= b1) return;   // whole workgroup: uniform exit
+    const int I = b0 + 4 * chunk + w;
+    const bool valid = I < b1;          // waves past the block still take part in the staging
+    const T *A = (const T *)(upper ? G0.T : G0.S) + (int64_t)(valid ? I : b0) * NB * TILE_ELEMS;
+    T a[AREG ? NB : 1][4];
+    if constexpr (AREG) {
+#pragma unroll
+        for (int s = 0; s < NB; ++s) Mf<T>::ld4(A + (int64_t)s * TILE_ELEMS, lane, a[s]);
+    }
+    const int nbr = upper ? p + 1 : p - 1;
+    for (int g = run.x; g < run.x + run.y; ++g) {
+        const SplitGroup &G = groups[g];
+        const T *b = (const T *)G.bnd + (int64_t)nbr * NB * TILE_ELEMS;
+        if (g != run.x) __syncthreads();   // previous group's tiles consumed
+        for (int e = threadIdx.x; e < NB * TILE_ELEMS; e += 256) bl[e] = gld(b + e);
+        __syncthreads();
+        if (!valid) continue;
+        T x[4];
+        load_rows(G, I, lane, x);
+        v4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < NB; ++s) {
+            T as[4];
+            if constexpr (AREG) {
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) as[kc] = a[s][kc];
+            } else {
+                Mf<T>::ld4(A + (int64_t)s * TILE_ELEMS, lane, as);
+            }
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) acc = Mf<T>::mma(as[kc], bl[s * TILE_ELEMS + kc * 64 + lane], acc);
+        }
+        v4 o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = x[q] - acc[q];
+        store_rows<T>(G, I, lane, o);
+    }
+}
+
 hipError_t launch_split_update(bool f32, bool upper, int ngroups, const SplitGroup *d_groups, int max_P,
-                               int max_rows, hipStream_t s) {
+                               int max_rows, hipStream_t s, int max_nb, int nruns, const int2 *d_runs) {
     if (ngroups <= 0) return hipSuccess;
     const int chunks = (max_rows + 3) / 4;
+    const int up = upper ? 1 : 0;
+    const size_t lds = (size_t)max_nb * TILE_ELEMS * (f32 ? 4 : 8);
+    if (d_runs) {
+        const int64_t grid = (int64_t)nruns * max_P * chunks;
+        if (grid > 0x7fffffff) return hipErrorInvalidValue;
+#define LRPR_UPDATE_NB(NBV)                                                                                    \
+        if (max_nb == NBV) {                                                                                   \
+            if (f32)                                                                                           \
+                hipLaunchKernelGGL((k_split_update_nb<float, NBV>), dim3((unsigned)grid), dim3(256), lds, s,   \
+                                   d_groups, d_runs, up, max_P, chunks);                                       \
+            else                                                                                               \
+                hipLaunchKernelGGL((k_split_update_nb<double, NBV>), dim3((unsigned)grid), dim3(256), lds, s,  \
+                                   d_groups, d_runs, up, max_P, chunks);                                       \
+            return hipGetLastError();                                                                          \
+        }
+        LRPR_UPDATE_NB(8)
+        LRPR_UPDATE_NB(16)
+        LRPR_UPDATE_NB(32)
+#undef LRPR_UPDATE_NB
+        return hipErrorInvalidValue;
+    }
     const int64_t grid = (int64_t)ngroups * max_P * chunks;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
     if (f32)
-        hipLaunchKernelGGL(k_split_update<float>, dim3((unsigned)grid), dim3(256), 0, s, d_groups, upper ? 1 : 0,
-                           max_P, chunks);
+        hipLaunchKernelGGL(k_split_update<float>, dim3((unsigned)grid), dim3(256), 0, s, d_groups, up, max_P, chunks);
     else
-        hipLaunchKernelGGL(k_split_update<double>, dim3((unsigned)grid), dim3(256), 0, s, d_groups, upper ? 1 : 0,
-                           max_P, chunks);
+        hipLaunchKernelGGL(k_split_update<double>, dim3((unsigned)grid), dim3(256), 0, s, d_groups, up, max_P, chunks);
     return hipGetLastError();
 }
 

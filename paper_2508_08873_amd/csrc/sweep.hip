@@ -224,11 +224,11 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
     int64_t fstride = 0;
     T fs = 0;
     if (with_src && colok) {
-        const int fc = it.fcol ? it.fcol[c] : 0;
+        const int fc = it.fcol ? gld(it.fcol + c) : 0;
         if (fc >= 0) {
             fsrc = (const T *)it.f + (int64_t)fc * it.ldf;
             fstride = 1;
-            const double sc = it.fscale ? it.fscale[(int64_t)c * it.fsteps + step] : 1.0;
+            const double sc = it.fscale ? gld(it.fscale + (int64_t)c * it.fsteps + step) : 1.0;
             fs = (T)(it.fac.dt * sc);
         }
     }
@@ -450,8 +450,8 @@ __device__ __forceinline__ void clear_ring(T *ring, int nb) {
 // forward tiles.  Steps step0 .. step0+nsteps-1 (the step picks the source's
 // time factor); each item runs the passes its mask selects.
 template <typename T, int KW, typename SP, int PD, bool ADJ, bool STRIDED>
-__global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__ items, int nitems, int nsteps,
-                                                   int step0) {
+__device__ __forceinline__ void sweep_items(const SweepItem *__restrict__ items, int nitems, int nsteps,
+                                            int step0) {
     extern __shared__ __align__(16) unsigned char smem[];
     for (int idx = blockIdx.x; idx < nitems; idx += gridDim.x) {
         const SweepItem it = items[idx];
@@ -489,14 +489,32 @@ __global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__
     }
 }
 
+template <typename T, int KW, typename SP, int PD, bool ADJ, bool STRIDED>
+__global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__ items, int nitems, int nsteps,
+                                                   int step0) {
+    sweep_items<T, KW, SP, PD, ADJ, STRIDED>(items, nitems, nsteps, step0);
+}
+
+// The local block solves of partitioned passes (forward items on row ranges):
+// the same code under its own name, so that profiles keep them apart from the
+// full-length sweeps.
+template <typename T, int KW, typename SP, int PD>
+__global__ __launch_bounds__(64 * KW) void k_sweep_local(const SweepItem *__restrict__ items, int nitems,
+                                                         int nsteps, int step0) {
+    sweep_items<T, KW, SP, PD, false, false>(items, nitems, nsteps, step0);
+}
+
 template <typename T, int KW, typename SP, int PD>
 static hipError_t launch_t(bool adjoint, bool strided, int nitems, const SweepItem *d_items, int nsteps,
-                           int max_nb, hipStream_t s, int step0) {
+                           int max_nb, hipStream_t s, int step0, bool local) {
     // LDS: ring of nb+1 solved tiles (+1 dummy slot), double-buffered partial
     // sums of the bulk waves, double-buffered hand-off (E, r)
     const size_t lds = (size_t)(max_nb + 2 + 2 * (KW > 1 ? KW - 3 : 1) + 4) * TILE_ELEMS * sizeof(T);
     const int grid = nitems < 65536 ? nitems : 65536;
-    if (!adjoint)
+    if (local)
+        hipLaunchKernelGGL((k_sweep_local<T, KW, SP, PD>), dim3(grid), dim3(64 * KW), lds, s, d_items, nitems,
+                           nsteps, step0);
+    else if (!adjoint)
         hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, false, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
                            nitems, nsteps, step0);
     else if (!strided)
@@ -527,32 +545,33 @@ static hipError_t launch_t(bool adjoint, bool strided, int nitems, const SweepIt
 // finisher's operands and write the output.  Narrow bands run on one wave.
 template <typename T>
 static hipError_t launch_prec(bool adjoint, bool strided, int nitems, const SweepItem *d_items, int nsteps,
-                              int max_nb, hipStream_t s, int step0) {
+                              int max_nb, hipStream_t s, int step0, bool local) {
     constexpr bool F64 = sizeof(T) == 8;
-    if (max_nb <= 1) return launch_t<T, 1, Split<1, 0, 0, 0, 0>, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
-    if (max_nb <= 4) return launch_t<T, 1, Split<3, 0, 0, 0, 0>, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
+    if (max_nb <= 1) return launch_t<T, 1, Split<1, 0, 0, 0, 0>, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, local);
+    if (max_nb <= 4) return launch_t<T, 1, Split<3, 0, 0, 0, 0>, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, local);
     if (max_nb <= 8)
-        return launch_t<T, 8, Split<1, 2, 2, 1, 1>, F64 ? 4 : 6>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
+        return launch_t<T, 8, Split<1, 2, 2, 1, 1>, F64 ? 4 : 6>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, local);
     if (max_nb <= 16) {
         if constexpr (F64)
             return launch_t<T, 8, Split<LRPR_SPLIT16_F64>, LRPR_PD16_F64>(adjoint, strided, nitems, d_items, nsteps,
-                                                                          max_nb, s, step0);
+                                                                          max_nb, s, step0, local);
         else
             return launch_t<T, 8, Split<LRPR_SPLIT16_F32>, LRPR_PD16_F32>(adjoint, strided, nitems, d_items, nsteps,
-                                                                          max_nb, s, step0);
+                                                                          max_nb, s, step0, local);
     }
     if (max_nb <= 32)
-        return launch_t<T, 8, Split<6, 7, 6, 6, 6>, F64 ? 2 : 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
+        return launch_t<T, 8, Split<6, 7, 6, 6, 6>, F64 ? 2 : 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, local);
     if (max_nb <= 64)
-        return launch_t<T, 8, Split<13, 13, 13, 13, 11>, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
+        return launch_t<T, 8, Split<13, 13, 13, 13, 11>, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, local);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const SweepItem *d_items, int nsteps,
-                        int max_nb, hipStream_t s, int step0) {
+                        int max_nb, hipStream_t s, int step0, bool local) {
     if (nitems <= 0 || nsteps <= 0) return hipSuccess;
-    if (f32) return launch_prec<float>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
-    return launch_prec<double>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0);
+    if (local && adjoint) return hipErrorInvalidValue;
+    if (f32) return launch_prec<float>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, local);
+    return launch_prec<double>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, local);
 }
 
 }  // namespace lrpr

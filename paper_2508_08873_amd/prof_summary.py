@@ -26,7 +26,7 @@ import statistics
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SWEEP_SOURCES = ["csrc/sweep.hip", "csrc/lrpr_internal.h", "csrc/factor.hip"]
+SWEEP_SOURCES = ["csrc/sweep.hip", "csrc/lrpr_internal.h", "csrc/factor.hip", "csrc/tile_ops.h"]
 
 
 def sweep_source_hash() -> str:
@@ -56,7 +56,8 @@ def main():
     ap.add_argument("--calib-write")
     ap.add_argument("--calib-bytes", type=float, default=0.0)
     ap.add_argument("--calib-kernel", default="copyBuffer")
-    ap.add_argument("--kernel", default="k_sweep")
+    ap.add_argument("--kernel", default="k_sweep<", help="substring of the kernel names summarised (the "
+                    "default excludes k_sweep_local, the partitioned block solves)")
     ap.add_argument("--bench")
     args = ap.parse_args()
 

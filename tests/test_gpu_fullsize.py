@@ -7,6 +7,7 @@ size.
   1e-5 FP32);
 * 511^2 operator with the time-dependent diffusion of its first slice
   (n = 261121, b = 511): the same, FP64 and FP32;
+* both operators through factors kept with spikes (partitioned fine sweeps);
 * the full 255^2 pipeline (64 slices, k = 40, p = 10, Parareal to 1e-10):
   singular values descending with sigma_1 <= 1 (diagonal dominance);
   orthonormal U_k, V_k; the low-rank error on a sampled slice and vector
@@ -45,9 +46,10 @@ def _oracle_op(ora, P, s=1):
     return _OPS[key]
 
 
-def _sampled_sweep(ctx, ora, P, prec, adjoint, mirror, nsteps, cols=(3, 14), seed=5):
+def _sampled_sweep(ctx, ora, P, prec, adjoint, mirror, nsteps, cols=(3, 14), seed=5, split=False):
     from paper_2508_08873_amd import lrpr
     mask = (lrpr.STORE_F64 if prec == 0 else lrpr.STORE_F32 | lrpr.STORE_F64) | (lrpr.STORE_MIRROR if mirror else 0)
+    mask |= lrpr.STORE_SPLIT if split else 0
     F = ctx.factor(P.dim, P.nx, P.nu_slice(1), P.beta, P.c, P.dt, store_mask=mask)
     X0 = np.random.default_rng(seed).standard_normal((P.n, 16))
     f = P.source()
@@ -81,6 +83,17 @@ def test_dar255_sweep_sampled(ctx, ora, adjoint, mirror):
 @pytest.mark.parametrize("adjoint", [False, True], ids=["fwd", "adj"])
 def test_dar511t_sweep_sampled(ctx, ora, prec, adjoint):
     err = _sampled_sweep(ctx, ora, inputs.dar511t(), prec, adjoint, mirror=False, nsteps=2)
+    assert err <= (1e-11 if prec == 0 else 1e-5), err
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("name", ["dar255", "dar511t"])
+def test_partitioned_sweep_sampled(ctx, ora, name, prec):
+    """Fine sweeps of one 16-column group through factors kept with spikes
+    (partitioned passes; 16 and 32 band tiles)."""
+    P = getattr(inputs, name)()
+    print("case", name, "prec", prec, flush=True)
+    err = _sampled_sweep(ctx, ora, P, prec, False, False, nsteps=2, split=True)
     assert err <= (1e-11 if prec == 0 else 1e-5), err
 
 

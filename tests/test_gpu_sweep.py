@@ -156,6 +156,7 @@ SPLIT_CASES = [
     ("2d_nx31", lambda: inputs.tiny2d(nx=31, m=3), 21),
     ("2d_nx63", lambda: inputs.tiny2d(nx=63, m=3), 16),
     ("2d_nx100", lambda: inputs.tiny2d(nx=100, m=2, beta=(-12.0, 25.0)), 40),
+    ("2d_nx128", lambda: inputs.tiny2d(nx=128, m=2, T=1.0 / 32), 33),
     ("2d_nx255", lambda: inputs.tiny2d(nx=255, m=2, T=1.0 / 64), 7),
 ]
 
