@@ -351,10 +351,10 @@ lrpr_status lrpr_coarse_apply(lrpr_ctx ctx, lrpr_coarse c, int s, int w, const d
     if (w == 0) return LRPR_OK;
     CK(hipSetDevice(ctx->dev), "hipSetDevice");
     hipError_t e;
-    const int64_t nch = lr_chunks(c->n[s]);
     const int k = c->k[s];
-    double *part = (double *)ws_get(ctx, "lr_part", sizeof(double) * (size_t)nch * std::max(k, 1) *
-                                                         std::min(w, std::max(1, 12288 / std::max(k, 1))), &e);
+    double *part = (double *)ws_get(
+        ctx, "lr_part", sizeof(double) * (size_t)lr_part_elems(c->n[s], k, std::min(w, std::max(1, 12288 / std::max(k, 1)))),
+        &e);
     if (!part) return herr(ctx, e, "workspace");
     LrArgs a{};
     a.U = c->U[s]; a.S = c->S[s]; a.V = c->V[s];
@@ -400,7 +400,7 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
     int *fcol = (int *)W("pr_fcol", sizeof(int) * (size_t)N * nreq);
     double *fsc = (double *)W("pr_fsc", sizeof(double) * (size_t)N * nreq * nsteps);
     const int64_t nch = lr_chunks(n);
-    double *part = (double *)W("pr_part", sizeof(double) * (size_t)nch * std::max(kmax, 1) * nreq);
+    double *part = (double *)W("pr_part", sizeof(double) * (size_t)lr_part_elems(n, kmax, nreq));
     double *incpart = (double *)W("pr_incpart", sizeof(double) * (size_t)nch * nreq);
     double *inc2 = (double *)W("pr_inc2", sizeof(double) * (size_t)N * nreq);
     int *active = (int *)W("pr_active", sizeof(int) * nreq);

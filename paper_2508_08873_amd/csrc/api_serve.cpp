@@ -191,7 +191,7 @@ lrpr_status launch_step(lrpr_server srv, Pipe &p) {
     SCK(hipMemcpyAsync(p.d_cmode, p.h_cmode.data(), sizeof(int) * w, hipMemcpyHostToDevice, st), "tables");
     const int64_t nch = lr_chunks(p.n);
     hipError_t he = hipSuccess;
-    double *part = (double *)ws_get(p.ctx, "sv_part", sizeof(double) * (size_t)nch * std::max(p.kmax, 1) * p.cap, &he);
+    double *part = (double *)ws_get(p.ctx, "sv_part", sizeof(double) * (size_t)lr_part_elems(p.n, p.kmax, p.cap), &he);
     double *incpart = (double *)ws_get(p.ctx, "sv_incpart", sizeof(double) * (size_t)nch * p.cap, &he);
     if (!part || !incpart) SCK(he == hipSuccess ? hipErrorOutOfMemory : he, "serve workspace");
     lrpr_coarse C = p.d.C;

@@ -51,7 +51,8 @@ struct LrArgs {            // low-rank apply / Parareal correction on w columns
     const double *fu64;        // F_n u (n x w), mode 2 (FP64) ...
     const float *fu32;         // ... or FP32
     const int *active;         // per column flag, or null
-    double *part;              // [chunks][k*w]
+    double *part;              // [chunks][k*w], then k*w coefficients (lr_part_elems)
+    double *coef;              // set by launch_lowrank
     double *incpart;           // [chunks][w]
     int64_t n;
     int k, w;
@@ -70,6 +71,8 @@ struct LrArgs {            // low-rank apply / Parareal correction on w columns
 
 int gram_chunks(int64_t nmax);
 int64_t lr_chunks(int64_t n);
+// doubles of the part workspace of a low-rank apply of rank k on w columns
+int64_t lr_part_elems(int64_t n, int k, int w);
 hipError_t launch_gram(bool f32, const GramJob *d_jobs, int njobs, int nchunks, double *part, double *G,
                        hipStream_t s);
 hipError_t launch_chol(const int *d_ls, int nslices, const double *G, double *R, double *Rinv, int *status,

@@ -449,67 +449,91 @@ __global__ __launch_bounds__(256) void k_signfix(const SignJob *jobs) {
 // ---------------------------------------------------------------------------
 // Low-rank apply and Parareal correction.
 //   dots:    part[chunk][r][c] = sum_{i in chunk} V[i][r] * x[i][c]
-//   combine: coef[r][c] = S[r] * sum_chunks part (fixed order, redundantly per
-//            block), g = U coef;  then either out = g, or the correction
+//   coef:    coef[r][c] = S[r] * sum over chunks of part (fixed order)
+//   combine: g = U coef;  then either out = g, or the correction
 //            u_new = Fu + g - gold, gold = g, with per-chunk partial sums of
 //            ||u_new - u_old||^2 for the increment.
-// x, out, Fu, gold, u: n x w column-major (ld n).
+// x, out, Fu, gold, u: n x w column-major (ld n).  Chunks are 256 rows (one
+// per thread), so that a 65025-row slice spreads over 255 workgroups; every
+// reduction runs in a fixed order, independent of w and of the other columns.
 // ---------------------------------------------------------------------------
-constexpr int LR_CHUNK = 2048;
+constexpr int LR_CHUNK = 256;
 constexpr int LR_THREADS = 256;
-constexpr int LR_RB = 8;   // rank block of the register tile
-constexpr int LR_CB = 8;   // column block of the register tile
+constexpr int LR_RB = 8;    // rank block of the dots tile
+constexpr int LR_CB = 8;    // column block
+constexpr int LR_UB = 16;   // U rows in flight per batch (combine)
+constexpr int LR_RED = 16;  // waves of the chunk reductions
 
 // part[chunk][r*w + c] = sum over the chunk's rows of V[i][r] x[i][c]
 __global__ __launch_bounds__(LR_THREADS) void k_lr_dots(LrArgs a) {
     __shared__ double red[LR_THREADS / 64][LR_RB * LR_CB];
-    const int64_t r0 = (int64_t)blockIdx.x * LR_CHUNK;
-    const int64_t r1 = (r0 + LR_CHUNK < a.n) ? r0 + LR_CHUNK : a.n;
+    const int64_t i = (int64_t)blockIdx.x * LR_CHUNK + threadIdx.x;
+    const bool in = i < a.n;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nk = a.k * a.w;
-    for (int rb = 0; rb < a.k; rb += LR_RB) {
-        for (int cb = 0; cb < a.w; cb += LR_CB) {
-            double acc[LR_RB][LR_CB];
+    for (int cb = 0; cb < a.w; cb += LR_CB) {
+        double xx[LR_CB];
 #pragma unroll
-            for (int i = 0; i < LR_RB; ++i)
+        for (int q = 0; q < LR_CB; ++q)
+            xx[q] = (!in || cb + q >= a.w) ? 0.0 : a.cu ? a.cu[cb + q][a.coff + i] : a.x[i + (int64_t)(cb + q) * a.n];
+        double vv[LR_RB];
 #pragma unroll
-                for (int j = 0; j < LR_CB; ++j) acc[i][j] = 0.0;
-            for (int64_t i = r0 + threadIdx.x; i < r1; i += LR_THREADS) {
-                double vv[LR_RB], xx[LR_CB];
+        for (int p = 0; p < LR_RB; ++p) vv[p] = (in && p < a.k) ? a.V[i + (int64_t)p * a.n] : 0.0;
+        for (int rb = 0; rb < a.k; rb += LR_RB) {
+            // next rank block in flight while this one reduces
+            double vn[LR_RB];
 #pragma unroll
-                for (int q = 0; q < LR_RB; ++q) vv[q] = (rb + q < a.k) ? a.V[i + (int64_t)(rb + q) * a.n] : 0.0;
-#pragma unroll
-                for (int q = 0; q < LR_CB; ++q)
-                    xx[q] = (cb + q >= a.w) ? 0.0
-                            : a.cu ? a.cu[cb + q][a.coff + i] : a.x[i + (int64_t)(cb + q) * a.n];
-#pragma unroll
-                for (int p = 0; p < LR_RB; ++p)
-#pragma unroll
-                    for (int q = 0; q < LR_CB; ++q) acc[p][q] += vv[p] * xx[q];
+            for (int p = 0; p < LR_RB; ++p) {
+                const int r = rb + LR_RB + p;
+                vn[p] = (in && r < a.k) ? a.V[i + (int64_t)r * a.n] : 0.0;
             }
 #pragma unroll
             for (int p = 0; p < LR_RB; ++p)
 #pragma unroll
-                for (int q = 0; q < LR_CB; ++q) {
-                    double v = acc[p][q];
-                    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-                    if (lane == 0) red[wv][p * LR_CB + q] = v;
-                }
+                for (int q = 0; q < LR_CB; ++q)
+                    if (rb + p < a.k && cb + q < a.w) {   // uniform
+                        double v = vv[p] * xx[q];
+                        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+                        if (lane == 0) red[wv][p * LR_CB + q] = v;
+                    }
             __syncthreads();
-            for (int e = threadIdx.x; e < LR_RB * LR_CB; e += LR_THREADS) {
-                const int p = e / LR_CB, q = e % LR_CB;
+            if (threadIdx.x < LR_RB * LR_CB) {
+                const int p = threadIdx.x / LR_CB, q = threadIdx.x % LR_CB;
                 if (rb + p < a.k && cb + q < a.w) {
                     double sum = 0.0;
-                    for (int t = 0; t < LR_THREADS / 64; ++t) sum += red[t][e];
+#pragma unroll
+                    for (int t = 0; t < LR_THREADS / 64; ++t) sum += red[t][threadIdx.x];
                     a.part[(int64_t)blockIdx.x * nk + (rb + p) * a.w + cb + q] = sum;
                 }
             }
             __syncthreads();
+#pragma unroll
+            for (int p = 0; p < LR_RB; ++p) vv[p] = vn[p];
         }
     }
 }
 
-// coef = S .* (sum over chunks of part) (fixed order, recomputed per block);
+// coef[e] = S[e / w] * sum over the nch chunks of part[ch][e]: 64 entries per
+// workgroup (one per lane), LR_RED waves take the chunks round-robin, the
+// wave partials add up in wave order.
+__global__ __launch_bounds__(64 * LR_RED) void k_lr_coef(const double *part, int64_t nch, int nk, int w,
+                                                         const double *S, double *coef) {
+    __shared__ double red[LR_RED][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
+    double sum = 0.0;
+    if (e < nk)
+        for (int64_t ch = wv; ch < nch; ch += LR_RED) sum += part[ch * nk + e];
+    red[wv][lane] = sum;
+    __syncthreads();
+    if (wv == 0 && e < nk) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < LR_RED; ++q) t += red[q][lane];
+        coef[e] = S[e / w] * t;
+    }
+}
+
 // g = U coef for the block's rows; mode 0: out = g; mode 1 (Parareal
 // initialisation): gold = g, out = g + bvec; mode 2 (correction):
 // u_new = Fu + g - gold, incpart += ||u_new - out||^2, out = u_new, gold = g.
@@ -520,15 +544,10 @@ __global__ __launch_bounds__(LR_THREADS) void k_lr_combine(LrArgs a) {
     extern __shared__ double coef[];   // [k*w]
     __shared__ double red[LR_THREADS / 64][LR_CB];
     const int nk = a.k * a.w;
-    const int64_t nch = (a.n + LR_CHUNK - 1) / LR_CHUNK;
-    for (int e = threadIdx.x; e < nk; e += LR_THREADS) {
-        double sum = 0.0;
-        for (int64_t ch = 0; ch < nch; ++ch) sum += a.part[ch * nk + e];
-        coef[e] = a.S[e / a.w] * sum;
-    }
+    for (int e = threadIdx.x; e < nk; e += LR_THREADS) coef[e] = a.coef[e];
     __syncthreads();
-    const int64_t r0 = (int64_t)blockIdx.x * LR_CHUNK;
-    const int64_t r1 = (r0 + LR_CHUNK < a.n) ? r0 + LR_CHUNK : a.n;
+    const int64_t i = (int64_t)blockIdx.x * LR_CHUNK + threadIdx.x;
+    const bool in = i < a.n;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const bool incs = a.mode == 2 || a.cu;
     for (int cb = 0; cb < a.w; cb += LR_CB) {
@@ -558,15 +577,20 @@ __global__ __launch_bounds__(LR_THREADS) void k_lr_combine(LrArgs a) {
                 if (a.mode == 0 && cb + q < a.w) md[q] = 0;
             }
         }
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += LR_THREADS) {
+        if (in) {
             double gs[LR_CB];
 #pragma unroll
             for (int q = 0; q < LR_CB; ++q) gs[q] = 0.0;
-            for (int r = 0; r < a.k; ++r) {
-                const double u = a.U[i + (int64_t)r * a.n];
+            for (int r0 = 0; r0 < a.k; r0 += LR_UB) {
+                double u[LR_UB];
 #pragma unroll
-                for (int q = 0; q < LR_CB; ++q)
-                    if (cb + q < a.w) gs[q] += u * coef[r * a.w + cb + q];
+                for (int p = 0; p < LR_UB; ++p) u[p] = r0 + p < a.k ? a.U[i + (int64_t)(r0 + p) * a.n] : 0.0;
+#pragma unroll
+                for (int p = 0; p < LR_UB; ++p)
+                    if (r0 + p < a.k)
+#pragma unroll
+                        for (int q = 0; q < LR_CB; ++q)
+                            if (cb + q < a.w) gs[q] += u[p] * coef[(r0 + p) * a.w + cb + q];
             }
 #pragma unroll
             for (int q = 0; q < LR_CB; ++q) {
@@ -605,12 +629,26 @@ __global__ __launch_bounds__(LR_THREADS) void k_lr_combine(LrArgs a) {
     }
 }
 
-// per column: inc2[c] = sum over chunks (fixed order) of incpart
-__global__ void k_inc_reduce(const double *incpart, int64_t nch, int w, double *inc2) {
-    for (int cc = threadIdx.x; cc < w; cc += blockDim.x) {
+// per column: inc2[c] = sum over chunks of incpart (LR_RED waves round-robin
+// over the chunks, lanes over columns, wave partials in wave order)
+__global__ __launch_bounds__(64 * LR_RED) void k_inc_reduce(const double *incpart, int64_t nch, int w,
+                                                            double *inc2) {
+    __shared__ double red[LR_RED][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < w; c0 += 64) {
+        const int cc = c0 + lane;
         double s = 0.0;
-        for (int64_t ch = 0; ch < nch; ++ch) s += incpart[ch * w + cc];
-        inc2[cc] = s;
+        if (cc < w)
+            for (int64_t ch = wv; ch < nch; ch += LR_RED) s += incpart[ch * w + cc];
+        red[wv][lane] = s;
+        __syncthreads();
+        if (wv == 0 && cc < w) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < LR_RED; ++q) t += red[q][lane];
+            inc2[cc] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -715,20 +753,27 @@ hipError_t launch_signfix(const SignJob *d_jobs, int njobs, int kmax, hipStream_
 }
 
 int64_t lr_chunks(int64_t n) { return (n + LR_CHUNK - 1) / LR_CHUNK; }
+int64_t lr_part_elems(int64_t n, int k, int w) { return (lr_chunks(n) + 1) * (int64_t)(k > 1 ? k : 1) * w; }
 
 hipError_t launch_lowrank(const LrArgs &a, hipStream_t s) {
     const unsigned nch = (unsigned)lr_chunks(a.n);
+    const int nk = a.k * a.w;
+    LrArgs b = a;
+    b.coef = a.part + (int64_t)nch * nk;   // after the chunk partials
     if (a.k > 0) {
-        hipLaunchKernelGGL(k_lr_dots, dim3(nch), dim3(LR_THREADS), 0, s, a);
+        hipLaunchKernelGGL(k_lr_dots, dim3(nch), dim3(LR_THREADS), 0, s, b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_lr_coef, dim3((nk + 63) / 64), dim3(64 * LR_RED), 0, s, (const double *)b.part,
+                           (int64_t)nch, nk, a.w, a.S, b.coef);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_lr_combine, dim3(nch), dim3(LR_THREADS), sizeof(double) * (size_t)(a.k * a.w + 1), s, a);
+    hipLaunchKernelGGL(k_lr_combine, dim3(nch), dim3(LR_THREADS), sizeof(double) * (size_t)(nk + 1), s, b);
     return hipGetLastError();
 }
 
 hipError_t launch_inc_reduce(const double *incpart, int64_t nch, int w, double *inc2, hipStream_t s) {
-    hipLaunchKernelGGL(k_inc_reduce, dim3(1), dim3(256), 0, s, incpart, nch, w, inc2);
+    hipLaunchKernelGGL(k_inc_reduce, dim3(1), dim3(64 * LR_RED), 0, s, incpart, nch, w, inc2);
     return hipGetLastError();
 }
 
