@@ -187,6 +187,31 @@ def plain_per_rhs(ctx, lrpr, P):
     return P.m / (p["ms"] / 1000.0)
 
 
+def fwd_adj_rates(ctx, lrpr, P, prec):
+    """Forward and adjoint band sweeps reported separately: the range finder's
+    width (N*l = 3200 RHS of the shared factor, m steps, no source), one
+    launch each, timed with the library's events."""
+    import torch
+    fp = 0 if prec == "f64" else 1
+    dt = torch.float64 if prec == "f64" else torch.float32
+    F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
+                   store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(12345)
+    X = torch.randn((P.N * P.l, P.n), generator=gen, device="cuda", dtype=dt).t()
+    out = {}
+    for name, call in (("forward", ctx.fine_step_batched), ("adjoint", ctx.adjoint_step_batched)):
+        ctx.profile(True)
+        call([{"F": F, "X": X}], P.m, fp)
+        p = ctx.profile_read()
+        ctx.profile(False)
+        out[name + "_rhs_steps_per_s"] = p["rhs_steps"] / (p["ms"] / 1000.0)
+        out[name + "_ms"] = p["ms"]
+    out["rhs"] = P.N * P.l
+    F.close()
+    return out
+
+
 def traffic_from_profile(prec):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary
     of this workload, if it was taken from the current sweep sources."""
@@ -306,6 +331,7 @@ def main():
         "roofline": roofline,
     }
     if not args.no_plain:
+        res["range_finder_sweeps_separately"] = fwd_adj_rates(ctx, lrpr, P, prec)
         res["plain_per_rhs_fp64_rhs_steps_per_s"] = plain_per_rhs(ctx, lrpr, P)
         res["batched_vs_plain_per_rhs"] = rr / res["plain_per_rhs_fp64_rhs_steps_per_s"]
     if not args.no_serve:
