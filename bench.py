@@ -1,6 +1,6 @@
 """Benchmark of the low-rank Parareal hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f64|f32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f32|f64]
 
 One step is one pass of the whole hot path over the 255x255
 diffusion-advection-reaction workload (n = 65025 unknowns, half-bandwidth
@@ -9,9 +9,14 @@ steps, rank k = 40, oversampling p = 10):
   1. assemble M = I + dt A and factor it (band LU, FP64) and pack the tiles;
   2. rSVD build of all 64 slices' transfer operators (3200 forward + 3200
      adjoint right-hand sides x 32 steps, CholeskyQR2, Jacobi SVD, rotation);
-  3. Parareal to max_n ||u^{k+1}_n - u^k_n|| < 1e-10 (b_n sweep, coarse
+  3. Parareal to max_n ||u^{k+1}_n - u^k_n|| < tol (b_n sweep, coarse
      initialisation, iterations of 64 batched fine solves + sequential
      low-rank correction).
+Precision: the fine solves and the range finder run in FP32 by default (FP32
+accumulation; tol 1e-6), with the LU, the CholeskyQR2 Gram and Cholesky, the
+Jacobi SVD and the Parareal correction and residual in FP64; --prec f64 runs
+everything in FP64 (tol 1e-10).  The f32 run also times the FP64 form once
+("fp64_side") and states the FP32 error against the FP64 oracle.
 Inputs (Omega, u0, f) are generated before the timed region and stay in HBM.
 `value` = fine-propagator RHS*steps per second of whole-step wall time.
 
@@ -29,6 +34,9 @@ import time
 import numpy as np
 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+# Parareal tolerance of the FP32 configuration: FP32 fine solves move the
+# fixed point by ~1e-6 relative, so it iterates to 1e-6 (FP64: 1e-10)
+TOL_F32 = 1e-6
 PEAK_HBM_GBS = 8000.0
 
 
@@ -37,7 +45,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--prec", choices=["f64", "f32"], default="f32",
+                    help="fine solves and range finder (LU, Gram/Cholesky, SVD and the Parareal correction are "
+                         "FP64 either way)")
+    ap.add_argument("--no-fp64-side", action="store_true", help="skip the FP64 side run of the f32 bench")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-cols", type=int, default=384)
@@ -239,50 +250,59 @@ def main():
 
     P = inputs.dar255(seed=args.seed)
     prec = args.prec
-    fp = 0 if prec == "f64" else 1
-    dt = torch.float64 if prec == "f64" else torch.float32
-    tol = P.tol if prec == "f64" else 1e-6
     ctx = lrpr.Context(0)
     # inputs, resident in HBM before the timed region
     gen = torch.Generator(device="cuda")
     gen.manual_seed(args.seed)
-    Om = torch.randn((P.N, P.l, P.n), generator=gen, device="cuda", dtype=torch.float64).to(dt)
+    Om64 = torch.randn((P.N, P.l, P.n), generator=gen, device="cuda", dtype=torch.float64)
     u0 = lrpr.colmajor(torch.from_numpy(P.u0().reshape(-1, 1)).to("cuda"))
     f = lrpr.colmajor(torch.from_numpy(P.source().reshape(-1, 1)).to("cuda"))
     fsc = torch.from_numpy(np.concatenate([P.fscale(s) for s in range(1, P.N + 1)])).to("cuda")
     torch.cuda.synchronize()
 
-    def one_step(times, recs):
-        ta = time.perf_counter()
-        F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
-                       store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR | lrpr.STORE_SPLIT)
-        tb = time.perf_counter()
-        coarse = ctx.rsvd_build([(F, P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, fp)
-        tc = time.perf_counter()
-        if recs is not None:
-            recs["range"].append(ctx.profile_read())
-        out = ctx.parareal_solve(coarse, [F] * P.N, P.m, u0, f, fsc, tol=tol, fine_prec=fp)
+    def pipeline(prec, steps, warmup):
+        """Time `steps` passes of the whole path (after `warmup` untimed ones)
+        in one precision of the fine solves and the range finder."""
+        fp = 0 if prec == "f64" else 1
+        Om = Om64 if prec == "f64" else Om64.to(torch.float32)
+        tol = P.tol if prec == "f64" else TOL_F32
         torch.cuda.synchronize()
-        td = time.perf_counter()
-        if recs is not None:
-            recs["parareal"].append(ctx.profile_read())
-        times.append((tb - ta, tc - tb, td - tc))
-        coarse.close()
-        F.close()
-        return out
 
-    for _ in range(args.warmup):
-        one_step([], None)
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    times = []
-    recs = {"range": [], "parareal": []}
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = one_step(times, recs)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.profile(False)
+        def one_step(times, recs):
+            ta = time.perf_counter()
+            F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
+                           store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR | lrpr.STORE_SPLIT)
+            tb = time.perf_counter()
+            coarse = ctx.rsvd_build([(F, P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, fp)
+            tc = time.perf_counter()
+            if recs is not None:
+                recs["range"].append(ctx.profile_read())
+            out = ctx.parareal_solve(coarse, [F] * P.N, P.m, u0, f, fsc, tol=tol, fine_prec=fp)
+            torch.cuda.synchronize()
+            td = time.perf_counter()
+            if recs is not None:
+                recs["parareal"].append(ctx.profile_read())
+            times.append((tb - ta, tc - tb, td - tc))
+            coarse.close()
+            F.close()
+            return out
+
+        for _ in range(warmup):
+            one_step([], None)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        times = []
+        recs = {"range": [], "parareal": []}
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = one_step(times, recs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.profile(False)
+        return times, recs, t1 - t0, out, tol
+
+    times, recs, wall, out, tol = pipeline(prec, args.steps, args.warmup)
+    t0, t1 = 0.0, wall
 
     def tot(key, field):
         return sum(r[field] for r in recs[key])
@@ -324,12 +344,23 @@ def main():
                                "(n=65025, b=255), nu=1, beta=(20,10), c=1, T=1, 64 slices x 32 implicit-Euler "
                                "steps, k=40, p=10; step = factor + rSVD build + Parareal to %g" % tol,
                    "rhs_steps_per_step": rhs_steps, "parareal_iters": out["iters"][0],
-                   "range_finder_and_fine_precision": prec},
+                   "range_finder_and_fine_precision": prec,
+                   "fp64_steps": "LU, CholeskyQR2 Gram/Cholesky, Jacobi SVD, Parareal correction and residual"},
         "rsvd_build_s": rsvd_s + fac_s, "factor_s": fac_s, "rsvd_only_s": rsvd_s, "parareal_s": pr_s,
         "sweep_kernel_s_per_step": (tot("range", "ms") + tot("parareal", "ms")) / 1000.0 / K,
         "range_finder_sweeps_rhs_steps_per_s": rr, "parareal_sweeps_rhs_steps_per_s": pr,
         "roofline": roofline,
     }
+    if prec == "f32" and not args.no_fp64_side:
+        # the same pipeline with FP64 fine solves and range finder (to 1e-10)
+        t64, r64, w64, o64, tol64 = pipeline("f64", 1, 1)
+        rs64 = sum(r["rhs_steps"] for k in r64 for r in r64[k])
+        res["fp64_side"] = {"ms_per_step": w64 * 1000.0, "value": rs64 / w64, "parareal_tol": tol64,
+                            "parareal_iters": o64["iters"][0], "factor_s": t64[0][0], "rsvd_only_s": t64[0][1],
+                            "parareal_s": t64[0][2],
+                            "range_finder_sweeps_rhs_steps_per_s":
+                                sum(r["rhs_steps"] for r in r64["range"]) /
+                                (sum(r["ms"] for r in r64["range"]) / 1000.0)}
     if not args.no_plain:
         res["range_finder_sweeps_separately"] = fwd_adj_rates(ctx, lrpr, P, prec)
         res["plain_per_rhs_fp64_rhs_steps_per_s"] = plain_per_rhs(ctx, lrpr, P)

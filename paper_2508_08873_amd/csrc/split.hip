@@ -133,6 +133,7 @@ __device__ __forceinline__ void store_rows(const SplitGroup &G, int I, int lane,
 // values) stream through a PF-deep register ring across the steps, the
 // previous step's boundary tiles (B operands) sit in LDS, double-buffered.
 constexpr int CPF = 4;
+constexpr int CHAIN_WAVES = 8;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_split_chain(const SplitGroup *groups, int upper) {
@@ -218,16 +219,26 @@ __global__ __launch_bounds__(256) void k_split_chain(const SplitGroup *groups, i
     }
 }
 
-// Chain for a compile-time band-tile count NB: each output tile's NB spike
-// tiles are loaded together (and, for NB <= 16, the next tile's while the
-// current one multiplies), the B operands come from LDS.
+// Chain for a compile-time band-tile count NB: CHAIN_WAVES waves (two per
+// SIMD) take the NB output tiles of a step round-robin.  The spike tiles (A
+// operands: they do not depend on the chain values) stream through a
+// register ring of CHAIN_RING chunks of two tiles that runs ahead across
+// output tiles and steps; the barrier between steps orders LDS only, so the
+// prefetches stay in flight across it.  The previous step's boundary tiles
+// (B operands) sit in LDS, double-buffered.
+constexpr int CHAIN_RING = 4;
+
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_split_chain_nb(const SplitGroup *groups, int upper) {
+__global__ __launch_bounds__(64 * CHAIN_WAVES) void k_split_chain_nb(const SplitGroup *groups, int upper) {
     typedef typename Mf<T>::v4 v4;
-    constexpr int NTW = (NB + 3) / 4;           // output tiles per wave per step
-    constexpr int NBUF = NB <= 16 ? 2 : 1;
+    constexpr int NW = CHAIN_WAVES;
+    constexpr int NTW = (NB + NW - 1) / NW;   // output tiles per wave per step
+    constexpr int CH = 2;                     // spike tiles per ring chunk
+    constexpr int NCH = NB / CH;              // chunks per output tile (a multiple of the ring depth)
+    constexpr int D = CHAIN_RING;
+    static_assert(NCH % D == 0, "ring depth must divide the chunks of an output tile");
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int sblk[SPLIT_MAX_P + 1];       // block starts (LDS: no wait on the operand loads)
+    __shared__ int sblk[SPLIT_MAX_P + 1];     // block starts (LDS: no wait on the operand loads)
     const SplitGroup G = groups[blockIdx.x];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -235,14 +246,14 @@ __global__ __launch_bounds__(256) void k_split_chain_nb(const SplitGroup *groups
     T *prev = (T *)smem;   // [2][NB] tiles, accumulator order
     const T *A = (const T *)(upper ? G.T : G.S);
     T *bnd = (T *)G.bnd;
-    for (int i = threadIdx.x; i <= P; i += 256) sblk[i] = gld(G.blk + i);
+    for (int i = threadIdx.x; i <= P; i += 64 * NW) sblk[i] = gld(G.blk + i);
     __syncthreads();
     auto base_of = [&](int k) {
         const int p = upper ? P - 1 - k : k;
         return upper ? sblk[p] : sblk[p + 1] - NB;
     };
     auto block_of_k = [&](int k) { return upper ? P - 1 - k : k; };
-    for (int t = w; t < NB; t += 4) {
+    for (int t = w; t < NB; t += NW) {
         T x[4];
         load_rows(G, base_of(0) + t, lane, x);
 #pragma unroll
@@ -252,45 +263,55 @@ __global__ __launch_bounds__(256) void k_split_chain_nb(const SplitGroup *groups
         }
     }
     const int nq = (P - 1) * NTW;   // output tiles of this wave over the chain (some void)
-    auto load_q = [&](int q, T (&buf)[NB][4]) {
-        const int k = 1 + (q < nq ? q : 0) / NTW, j = (q < nq ? q : 0) % NTW;
-        const int t = w + 4 * j;
-        const int I = base_of(k) + (t < NB ? t : 0);
-#pragma unroll
-        for (int s = 0; s < NB; ++s) Mf<T>::ld4(A + ((int64_t)I * NB + s) * TILE_ELEMS, lane, buf[s]);
+    // spike row of output item q (void and past-the-end items read a valid row)
+    auto a_row = [&](int q) {
+        const int qq = q < nq ? q : 0;
+        const int k = 1 + qq / NTW, t = w + NW * (qq % NTW);
+        return A + (int64_t)(base_of(k) + (t < NB ? t : 0)) * NB * TILE_ELEMS;
     };
-    T ab[NBUF][NB][4];
-    if (NBUF == 2) load_q(0, ab[0]);
-    for (int q0 = 0; q0 < nq; q0 += NBUF) {
+    auto load_chunk = [&](const T *row, int c, T (&buf)[CH][4]) {
 #pragma unroll
-        for (int u = 0; u < NBUF; ++u) {
-            const int q = q0 + u;
-            if (q < nq) {
-                const int k = 1 + q / NTW, j = q % NTW;
-                if (j == 0) __syncthreads();   // step k-1's tiles are in prev[(k-1)&1]
-                if (NBUF == 2) load_q(q + 1, ab[u ^ 1]);
-                else load_q(q, ab[0]);
-                const int t = w + 4 * j;
-                if (t < NB) {
-                    const T *pin = prev + ((k - 1) & 1) * NB * TILE_ELEMS;
-                    T *pout = prev + (k & 1) * NB * TILE_ELEMS;
-                    const int I = base_of(k) + t;
-                    T x[4];
-                    load_rows(G, I, lane, x);
-                    v4 acc = {0, 0, 0, 0};
+        for (int s = 0; s < CH; ++s) Mf<T>::ld4(row + (int64_t)(c * CH + s) * TILE_ELEMS, lane, buf[s]);
+    };
+    T ring[D][CH][4];
+    {
+        const T *r0 = a_row(0);
 #pragma unroll
-                    for (int s = 0; s < NB; ++s)
+        for (int c = 0; c < D - 1; ++c) load_chunk(r0, c, ring[c]);
+    }
+    for (int q = 0; q < nq; ++q) {
+        const int k = 1 + q / NTW, j = q % NTW;
+        if (j == 0) lds_barrier();   // step k-1's tiles are in prev[(k-1)&1]
+        const int t = w + NW * j;
+        const bool live = t < NB;
+        const T *pin = prev + ((k - 1) & 1) * NB * TILE_ELEMS;
+        const int I = base_of(k) + (live ? t : 0);
+        T x[4];
+        load_rows(G, I, lane, x);
+        const T *row_cur = a_row(q), *row_nxt = a_row(q + 1);
+        v4 acc = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};   // two accumulators: no product waits on the previous one
 #pragma unroll
-                        for (int kc = 0; kc < 4; ++kc)
-                            acc = Mf<T>::mma(ab[NBUF == 2 ? u : 0][s][kc], pin[s * TILE_ELEMS + kc * 64 + lane], acc);
-                    const int p = block_of_k(k);
+        for (int c = 0; c < NCH; ++c) {
+            // prefetch the chunk D-1 ahead in the wave's stream (next output tile past the end)
+            const int cn = c + D - 1;
+            if (cn < NCH) load_chunk(row_cur, cn, ring[cn % D]);
+            else load_chunk(row_nxt, cn - NCH, ring[cn % D]);
+            if (live) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const T o = x[i] - acc[i];
-                        pout[t * TILE_ELEMS + i * 64 + lane] = o;
-                        gst(bnd + ((int64_t)p * NB + t) * TILE_ELEMS + i * 64 + lane, o);
-                    }
+                for (int kc = 0; kc < 4; ++kc) {
+                    acc = Mf<T>::mma(ring[c % D][0][kc], pin[(c * CH) * TILE_ELEMS + kc * 64 + lane], acc);
+                    acc1 = Mf<T>::mma(ring[c % D][1][kc], pin[(c * CH + 1) * TILE_ELEMS + kc * 64 + lane], acc1);
                 }
+            }
+        }
+        if (live) {
+            T *pout = prev + (k & 1) * NB * TILE_ELEMS;
+            const int p = block_of_k(k);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const T o = x[i] - (acc[i] + acc1[i]);
+                pout[t * TILE_ELEMS + i * 64 + lane] = o;
+                gst(bnd + ((int64_t)p * NB + t) * TILE_ELEMS + i * 64 + lane, o);
             }
         }
     }
@@ -306,8 +327,12 @@ hipError_t launch_split_chain(bool f32, bool upper, int ngroups, const SplitGrou
     const int up = upper ? 1 : 0;
 #define LRPR_CHAIN_NB(NBV)                                                                                     \
     if (uniform_nb && max_nb == NBV) {                                                                         \
-        if (f32) hipLaunchKernelGGL((k_split_chain_nb<float, NBV>), dim3(ngroups), dim3(256), lds, s, d_groups, up); \
-        else hipLaunchKernelGGL((k_split_chain_nb<double, NBV>), dim3(ngroups), dim3(256), lds, s, d_groups, up);    \
+        if (f32)                                                                                               \
+            hipLaunchKernelGGL((k_split_chain_nb<float, NBV>), dim3(ngroups), dim3(64 * CHAIN_WAVES), lds, s,  \
+                               d_groups, up);                                                                  \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_split_chain_nb<double, NBV>), dim3(ngroups), dim3(64 * CHAIN_WAVES), lds, s, \
+                               d_groups, up);                                                                  \
         return hipGetLastError();                                                                              \
     }
     LRPR_CHAIN_NB(8)

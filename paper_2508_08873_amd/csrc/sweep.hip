@@ -53,14 +53,6 @@ struct Split {
     static constexpr int cmax = max5(C1, C2, C3, C4, C5);
 };
 
-// Barrier that orders LDS traffic only: outstanding global loads (the
-// prefetches of later tile rows) stay in flight across it.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 // One pass (ascending or descending tile rows) over one 16-column group.
 //   band  : band tiles of the pass, nb per tile row (row I, index j)
 //   dtile : diagonal-tile inverses (one per row)

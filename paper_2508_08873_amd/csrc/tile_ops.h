@@ -53,4 +53,12 @@ template <> struct Mf<float> {
     }
 };
 
+// Barrier that orders LDS traffic only: outstanding global loads (prefetches
+// of operands needed later) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 }  // namespace lrpr
