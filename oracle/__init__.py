@@ -70,6 +70,9 @@ def _load():
         lib.ora_rsvd.restype = ctypes.c_int
         lib.ora_rsvd.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int, _dp, ctypes.c_long, _dp, _dp, _dp]
+        lib.ora_rsvd_q.restype = ctypes.c_int
+        lib.ora_rsvd_q.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _dp, _dp, _dp]
         lib.ora_lowrank_apply.restype = None
         lib.ora_lowrank_apply.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int,
                                           _dp, _dp]
@@ -193,15 +196,16 @@ def jacobi_svd(M):
     return U, S, V
 
 
-def rsvd(op: Operator, m: int, k: int, p: int, Omega):
-    """Randomized SVD of T = M^{-m} (Sec. 2.1).  Returns (Uk, S_all, Vk)."""
+def rsvd(op: Operator, m: int, k: int, p: int, Omega, q: int = 0):
+    """Randomized SVD of T = M^{-m} (Sec. 2.1), with q power iterations
+    (range space span (T T^T)^q T Omega).  Returns (Uk, S_all, Vk)."""
     Omega = _fortran(Omega)
     n, l = Omega.shape
-    assert l == k + p and n == op.n
+    assert l == k + p and n == op.n and q >= 0
     Uk = np.zeros((n, k), order="F")
     Vk = np.zeros((n, k), order="F")
     S = np.zeros(l)
-    sw = _load().ora_rsvd(n, op.bw, _p(op.lu), m, k, p, _p(Omega), n, _p(Uk), _p(S), _p(Vk))
+    sw = _load().ora_rsvd_q(n, op.bw, _p(op.lu), m, k, p, q, _p(Omega), n, _p(Uk), _p(S), _p(Vk))
     if sw < 0:
         raise ArithmeticError("Jacobi SVD did not converge")
     return Uk, S, Vk

@@ -391,9 +391,24 @@ static void matmul(int m, int k, int nc, const double *A, long lda,
  * of Uk[:,r] with the largest magnitude (lowest index on ties) is positive.
  * Outputs: Uk, Vk: n x k (ld n); S: all l singular values of Mm.
  * Returns Jacobi sweep count (or -1).
+ *
+ * Power iterations (Sec. 2.1, for slowly decaying singular values): with
+ * q >= 1 the range space is W = span (T T^T)^q T Omega.  It is reached by q
+ * rounds of "orthonormalise, apply T^T, orthonormalise, apply T" after step
+ * 1, so that the small directions are not lost to rounding; steps 2-6 then
+ * run on the final Y.
  * ---------------------------------------------------------------------- */
+int ora_rsvd_q(int n, int bw, const double *lu, int m, int k, int p, int q,
+               const double *Omega, long ldo, double *Uk, double *S, double *Vk);
+
 int ora_rsvd(int n, int bw, const double *lu, int m, int k, int p,
              const double *Omega, long ldo, double *Uk, double *S, double *Vk)
+{
+    return ora_rsvd_q(n, bw, lu, m, k, p, 0, Omega, ldo, Uk, S, Vk);
+}
+
+int ora_rsvd_q(int n, int bw, const double *lu, int m, int k, int p, int q,
+               const double *Omega, long ldo, double *Uk, double *S, double *Vk)
 {
     const int l = k + p;
     double *Y = (double *)malloc(sizeof(double) * (size_t)n * l);
@@ -405,6 +420,14 @@ int ora_rsvd(int n, int bw, const double *lu, int m, int k, int p,
     double *Vh = (double *)malloc(sizeof(double) * (size_t)l * l);
     for (int c = 0; c < l; c++) memcpy(Y + (size_t)c * n, Omega + (size_t)c * ldo, sizeof(double) * n);
     ora_fine_steps(n, bw, lu, 0.0, m, Y, n, l, NULL, 0, NULL, NULL);     /* step 1 */
+    for (int it = 0; it < q; it++) {                                      /* power iterations */
+        ora_householder_qr(n, l, Y, n, Q, R);
+        memcpy(Y, Q, sizeof(double) * (size_t)n * l);
+        ora_adjoint_steps(n, bw, lu, m, Y, n, l);                         /* T^T Q */
+        ora_householder_qr(n, l, Y, n, Qz, R);
+        memcpy(Y, Qz, sizeof(double) * (size_t)n * l);
+        ora_fine_steps(n, bw, lu, 0.0, m, Y, n, l, NULL, 0, NULL, NULL);  /* T Qz */
+    }
     ora_householder_qr(n, l, Y, n, Q, R);                                /* step 2 */
     memcpy(Y, Q, sizeof(double) * (size_t)n * l);
     ora_adjoint_steps(n, bw, lu, m, Y, n, l);                             /* step 3 */

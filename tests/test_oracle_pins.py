@@ -221,6 +221,38 @@ def test_rsvd_brute_force_tiny2d(ora):
     assert sv[k] * (1 - 1e-10) <= err <= 2 * sv[k]
 
 
+def test_rsvd_power_iterations_definition(ora):
+    """Power iterations (Sec. 2.1): with q >= 1 the range space is
+    W = span (T T^T)^q T Omega, and the result is the rank-k truncated SVD of
+    P_W T.  Checked against that definition computed densely (numpy QR and
+    SVD of the dense T, no re-orthonormalisation: the slowly decaying case
+    keeps (T T^T)^q T Omega well conditioned), for a non-symmetric operator
+    where T T^T differs from T^2; the error ||T - Uk Sk Vk^T||_2 approaches
+    sigma_{k+1}(T) as q grows."""
+    P = inputs.tiny2d(nx=8, m=1, T=1.0 / 16)
+    op = ora.Operator(**P.op_params())
+    T = _dense_T(op, P.m)
+    sv = np.linalg.svd(T, compute_uv=False)
+    assert np.abs(T @ T.T - T @ T).max() > 1e-3 * sv[0] ** 2
+    k, p = 6, 2
+    Om = np.random.default_rng(11).standard_normal((P.n, k + p))
+    errs = []
+    for q in (0, 1, 2):
+        Uk, S, Vk = ora.rsvd(op, P.m, k, p, Om, q=q)
+        Y = T @ Om
+        for _ in range(q):
+            Y = T @ (T.T @ Y)
+        Qd, _ = np.linalg.qr(Y)
+        Ub, Sb, Vbt = np.linalg.svd(Qd.T @ T)
+        Pd = ((Qd @ Ub[:, :k]) * Sb[:k]) @ Vbt[:k]
+        Po = (Uk * S[:k]) @ Vk.T
+        assert np.linalg.norm(Po - Pd) <= 1e-12 * np.linalg.norm(Pd), q
+        assert np.abs(S - Sb).max() <= 1e-12 * Sb[0], q
+        errs.append(np.linalg.norm(T - Po, 2) / sv[k])
+    assert errs[0] > errs[1] > errs[2] >= 1.0 - 1e-12
+    assert errs[2] <= 1.02
+
+
 def test_sigma1_at_most_one(ora):
     """M is row and column diagonally dominant with excess >= 1, so
     ||M^{-1}||_2 <= 1 and sigma_{n,1} <= 1 (the delta <= 1 case of Thm. 1)."""
