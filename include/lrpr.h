@@ -205,6 +205,17 @@ typedef struct {
 lrpr_status lrpr_rsvd_build(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
                             int nsteps, lrpr_prec range_prec, lrpr_coarse *out,
                             double *sigma_host, int *fallback_host);
+/* The same build with q >= 0 power iterations (Sec. 2.1, for slowly
+ * decaying singular values): the range space becomes span (T T^T)^q T
+ * Omega, reached by q rounds of "orthonormalise Y (CholeskyQR2), Z = T^T Q,
+ * orthonormalise Z, Y = T Qz" after Y = T Omega; the steps after that are
+ * those of lrpr_rsvd_build.  Costs 2q more sweeps of every slice's panel.
+ * q = 0 is lrpr_rsvd_build.  fallback_host flags a slice if any of its
+ * orthonormalisations fell back to Householder.  Errors: as
+ * lrpr_rsvd_build; LRPR_ERR_ARG for q < 0. */
+lrpr_status lrpr_rsvd_build_q(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
+                              int nsteps, int q, lrpr_prec range_prec, lrpr_coarse *out,
+                              double *sigma_host, int *fallback_host);
 void lrpr_coarse_destroy(lrpr_coarse c);
 /* Device pointers (owned by the handle) of slice s: U (n x k), S (k+p
  * values), V (n x k); k and n of that slice. */

@@ -120,8 +120,14 @@ lrpr_status lrpr_coarse_get(lrpr_coarse c, int s, const double **U, const double
 
 lrpr_status lrpr_rsvd_build(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices, int nsteps,
                             lrpr_prec range_prec, lrpr_coarse *out, double *sigma_host, int *fallback_host) {
+    return lrpr_rsvd_build_q(ctx, nslices, slices, nsteps, 0, range_prec, out, sigma_host, fallback_host);
+}
+
+lrpr_status lrpr_rsvd_build_q(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices, int nsteps, int q,
+                              lrpr_prec range_prec, lrpr_coarse *out, double *sigma_host, int *fallback_host) {
     if (!ctx) return LRPR_ERR_ARG;
-    if (nslices <= 0 || !slices || !out || nsteps < 0 || (range_prec != LRPR_F64 && range_prec != LRPR_F32))
+    if (nslices <= 0 || !slices || !out || nsteps < 0 || q < 0 ||
+        (range_prec != LRPR_F64 && range_prec != LRPR_F32))
         return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: invalid arguments");
     const bool f32 = range_prec == LRPR_F32;
     const size_t esz = f32 ? sizeof(float) : sizeof(double);
@@ -265,7 +271,23 @@ lrpr_status lrpr_rsvd_build(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *sl
         return LRPR_OK;
     };
 
-    lrpr_status r = cholqr2(Y, f32, Q, RY);            // step 2
+    lrpr_status r;
+    // --- power iterations: Y <- T Qz with Qz = orth(T^T orth(Y)) ---------------
+    for (int it = 0; it < q; ++it) {
+        if ((r = cholqr2(Y, f32, Q, RY)) != LRPR_OK) return r;
+        CK(launch_convert(0, f32 ? 1 : 0, Q, Z, tot, st), "Q -> Z");
+        {
+            std::vector<lrpr_panel> P = make_panels(Z);
+            if ((r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, true)) != LRPR_OK) return r;
+        }
+        if ((r = cholqr2(Z, f32, QZ, RZ)) != LRPR_OK) return r;
+        CK(launch_convert(0, f32 ? 1 : 0, QZ, Y, tot, st), "Qz -> Y");
+        {
+            std::vector<lrpr_panel> P = make_panels(Y);
+            if ((r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, false)) != LRPR_OK) return r;
+        }
+    }
+    r = cholqr2(Y, f32, Q, RY);                        // step 2
     if (r != LRPR_OK) return r;
     // --- step 3: Z = T^T Q (adjoint sweep) ---------------------------------
     CK(launch_convert(0, f32 ? 1 : 0, Q, Z, tot, st), "Q -> Z");

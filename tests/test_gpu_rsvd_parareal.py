@@ -103,6 +103,38 @@ def test_rsvd_2d(ctx, ora, prec, nx, k, p):
         assert _prod_err(Ug, Sg2, Vg, Uo, So, Vo, k) <= tol
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("q", [1, 2])
+def test_rsvd_power_iterations(ctx, ora, prec, q):
+    """q power iterations (Sec. 2.1, lrpr_rsvd_build_q) on a slowly decaying
+    non-symmetric operator, three slices sharing one factor and one with its
+    own: sigma and products against the oracle's rSVD with the same q."""
+    from paper_2508_08873_amd import lrpr
+    P = inputs.tiny2d(nx=31, N=4, m=2, k=8, p=4, T=1.0 / 32, nu_of_t=True)
+    print("power iterations q", q, "prec", prec, flush=True)
+    ops, facs = [], []
+    for s in range(1, P.N + 1):
+        if s in (2, 3):
+            ops.append(ops[0])
+            facs.append(facs[0])
+            continue
+        pp = P.op_params(s)
+        ops.append(ora.Operator(**pp))
+        facs.append(ctx.factor(pp["dim"], pp["nx"], pp["nu"], pp["beta"], pp["c"], pp["dt"],
+                               store_mask=lrpr.STORE_F64 | lrpr.STORE_F32 | lrpr.STORE_MIRROR))
+    oms = [P.omega(s) for s in range(1, P.N + 1)]
+    dt = torch.float64 if prec == 0 else torch.float32
+    coarse = ctx.rsvd_build([(facs[s], P.k, P.p, _dev(oms[s], dt)) for s in range(P.N)], P.m, prec, q=q)
+    tol = 1e-11 if prec == 0 else 1e-5
+    l = P.k + P.p
+    for s in range(P.N):
+        Uo, So, Vo = ora.rsvd(ops[s], P.m, P.k, P.p, oms[s], q=q)
+        Sg = np.array(coarse.sigma[s * l:(s + 1) * l])
+        assert np.abs(Sg - So).max() <= tol * So[0], (s, np.abs(Sg - So).max() / So[0])
+        Ug, Sg2, Vg = _coarse_host(coarse, s, P.n)
+        assert _prod_err(Ug, Sg2, Vg, Uo, So, Vo, P.k) <= tol, s
+
+
 def test_rsvd_per_slice_factors(ctx, ora):
     """Time-dependent nu_n: every slice has its own factor (one launch); the
     factors are kept without the mirrored set, so the adjoint reads them
