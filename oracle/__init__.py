@@ -70,6 +70,9 @@ def _load():
         lib.ora_rsvd.restype = ctypes.c_int
         lib.ora_rsvd.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int, _dp, ctypes.c_long, _dp, _dp, _dp]
+        lib.ora_rsvd_two_sided.restype = ctypes.c_int
+        lib.ora_rsvd_two_sided.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, _dp, _dp, ctypes.c_long, _dp, _dp, _dp]
         lib.ora_rsvd_q.restype = ctypes.c_int
         lib.ora_rsvd_q.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _dp, _dp, _dp]
@@ -206,6 +209,24 @@ def rsvd(op: Operator, m: int, k: int, p: int, Omega, q: int = 0):
     Vk = np.zeros((n, k), order="F")
     S = np.zeros(l)
     sw = _load().ora_rsvd_q(n, op.bw, _p(op.lu), m, k, p, q, _p(Omega), n, _p(Uk), _p(S), _p(Vk))
+    if sw < 0:
+        raise ArithmeticError("Jacobi SVD did not converge")
+    return Uk, S, Vk
+
+
+def rsvd_two_sided(op: Operator, m: int, k: int, p: int, Omega, Psi):
+    """Randomized SVD with the adjoint on independent test vectors Psi
+    (Sec. 2.2): T ~ Q (Psi^T Q)^{-1} (T^T Psi)^T with Q = orth(T Omega),
+    truncated to rank k.  Returns (Uk, S_all, Vk)."""
+    Omega, Psi = _fortran(Omega), _fortran(Psi)
+    n, l = Omega.shape
+    assert l == k + p and n == op.n and Psi.shape == (n, l)
+    Uk = np.zeros((n, k), order="F")
+    Vk = np.zeros((n, k), order="F")
+    S = np.zeros(l)
+    sw = _load().ora_rsvd_two_sided(n, op.bw, _p(op.lu), m, k, p, _p(Omega), _p(Psi), n, _p(Uk), _p(S), _p(Vk))
+    if sw == -2:
+        raise ArithmeticError("Psi^T Q is singular")
     if sw < 0:
         raise ArithmeticError("Jacobi SVD did not converge")
     return Uk, S, Vk

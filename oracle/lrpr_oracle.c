@@ -450,6 +450,109 @@ int ora_rsvd_q(int n, int bw, const double *lu, int m, int k, int p, int q,
 }
 
 /* ------------------------------------------------------------------------
+ * Randomized SVD with the adjoint evaluated on independent test vectors
+ * (Sec. 2.2: more parallelism at some loss of accuracy, the two-sided
+ * sketch).  Reading: Psi (n x l) is a second Gaussian matrix drawn
+ * independently of Omega, so Z = T^T Psi does not wait for the range basis;
+ * with Q the orthonormal basis of Y = T Omega, the approximation is
+ *   T ~ Q X,  X = (Psi^T Q)^{-1} Psi^T T = (Psi^T Q)^{-1} Z^T,
+ * i.e. the operator that agrees with Q Q^T T on the test space Psi.  Its
+ * truncated SVD: X^T = Qx Rx (Householder), Q X = Q Rx^T Qx^T, and
+ * Rx^T = Uh diag(S) Vh^T (Jacobi);  Uk = Q Uh[:, :k],  Vk = Qx Vh[:, :k].
+ * X^T = Z (Psi^T Q)^{-T} is formed by Gaussian elimination with partial
+ * pivoting on (Psi^T Q)^T.  Signs as in ora_rsvd.  Returns the Jacobi sweep
+ * count, -1 if Jacobi did not converge, -2 if Psi^T Q is singular.
+ * ---------------------------------------------------------------------- */
+int ora_rsvd_two_sided(int n, int bw, const double *lu, int m, int k, int p,
+                       const double *Omega, const double *Psi, long ld,
+                       double *Uk, double *S, double *Vk)
+{
+    const int l = k + p;
+    double *Y = (double *)malloc(sizeof(double) * (size_t)n * l);
+    double *Z = (double *)malloc(sizeof(double) * (size_t)n * l);
+    double *Q = (double *)malloc(sizeof(double) * (size_t)n * l);
+    double *Qx = (double *)malloc(sizeof(double) * (size_t)n * l);
+    double *C = (double *)malloc(sizeof(double) * (size_t)l * l);
+    double *R = (double *)malloc(sizeof(double) * (size_t)l * l);
+    double *Mm = (double *)malloc(sizeof(double) * (size_t)l * l);
+    double *Uh = (double *)malloc(sizeof(double) * (size_t)l * l);
+    double *Vh = (double *)malloc(sizeof(double) * (size_t)l * l);
+    int *piv = (int *)malloc(sizeof(int) * (size_t)l);
+    int ret = 0;
+    for (int c = 0; c < l; c++) {
+        memcpy(Y + (size_t)c * n, Omega + (size_t)c * ld, sizeof(double) * n);
+        memcpy(Z + (size_t)c * n, Psi + (size_t)c * ld, sizeof(double) * n);
+    }
+    ora_fine_steps(n, bw, lu, 0.0, m, Y, n, l, NULL, 0, NULL, NULL);     /* Y = T Omega */
+    ora_adjoint_steps(n, bw, lu, m, Z, n, l);                             /* Z = T^T Psi */
+    ora_householder_qr(n, l, Y, n, Q, R);                                /* Y = Q R */
+    /* Ct = (Psi^T Q)^T = Q^T Psi, column-major l x l: Ct[i + j l] = q_i . psi_j */
+    for (int i = 0; i < l; i++)
+        for (int j = 0; j < l; j++) {
+            double acc = 0.0;
+            for (int r = 0; r < n; r++) acc += Q[r + (size_t)i * n] * Psi[r + (size_t)j * ld];
+            C[i + (size_t)j * l] = acc;
+        }
+    /* LU with partial pivoting of Ct: Ct = P^T L U (in place) */
+    for (int c = 0; c < l && ret == 0; c++) {
+        int pr = c;
+        for (int r = c + 1; r < l; r++) if (fabs(C[r + (size_t)c * l]) > fabs(C[pr + (size_t)c * l])) pr = r;
+        piv[c] = pr;
+        if (C[pr + (size_t)c * l] == 0.0) { ret = -2; break; }
+        if (pr != c)
+            for (int j = 0; j < l; j++) {
+                const double t = C[c + (size_t)j * l];
+                C[c + (size_t)j * l] = C[pr + (size_t)j * l];
+                C[pr + (size_t)j * l] = t;
+            }
+        for (int r = c + 1; r < l; r++) {
+            C[r + (size_t)c * l] /= C[c + (size_t)c * l];
+            for (int j = c + 1; j < l; j++) C[r + (size_t)j * l] -= C[r + (size_t)c * l] * C[c + (size_t)j * l];
+        }
+    }
+    if (ret == 0) {
+        /* X^T = Z Ct^{-1}: row z of Z gives x with Ct^T... solve x Ct = z, i.e. Ct^T x^T = z^T.
+         * With Ct = P^T L U: Ct^T = U^T L^T P, so solve U^T w = z^T, L^T v = w, x^T = P^T v. */
+        double *w = (double *)malloc(sizeof(double) * (size_t)l);
+        for (int r = 0; r < n; r++) {
+            for (int i = 0; i < l; i++) {                 /* U^T w = z (forward, U^T lower) */
+                double v = Z[r + (size_t)i * n];
+                for (int j = 0; j < i; j++) v -= C[j + (size_t)i * l] * w[j];
+                w[i] = v / C[i + (size_t)i * l];
+            }
+            for (int i = l - 1; i >= 0; i--) {            /* L^T v = w (backward, unit diagonal) */
+                double v = w[i];
+                for (int j = i + 1; j < l; j++) v -= C[j + (size_t)i * l] * w[j];
+                w[i] = v;
+            }
+            for (int i = l - 1; i >= 0; i--) {            /* undo the row swaps: x = P^T v */
+                const double t = w[i];
+                w[i] = w[piv[i]];
+                w[piv[i]] = t;
+            }
+            for (int i = 0; i < l; i++) Z[r + (size_t)i * n] = w[i];
+        }
+        free(w);
+        ora_householder_qr(n, l, Z, n, Qx, R);                           /* X^T = Qx Rx */
+        for (int i = 0; i < l; i++)
+            for (int j = 0; j < l; j++) Mm[i + (size_t)j * l] = R[j + (size_t)i * l];
+        ret = ora_jacobi_svd(l, Mm, Uh, S, Vh);                           /* Rx^T = Uh S Vh^T */
+        matmul(n, l, k, Q, n, Uh, l, Uk, n);
+        matmul(n, l, k, Qx, n, Vh, l, Vk, n);
+        for (int r = 0; r < k; r++) {
+            double *u = Uk + (size_t)r * n, *v = Vk + (size_t)r * n;
+            int im = 0;
+            for (int i = 1; i < n; i++) if (fabs(u[i]) > fabs(u[im])) im = i;
+            if (u[im] < 0) {
+                for (int i = 0; i < n; i++) { u[i] = -u[i]; v[i] = -v[i]; }
+            }
+        }
+    }
+    free(Y); free(Z); free(Q); free(Qx); free(C); free(R); free(Mm); free(Uh); free(Vh); free(piv);
+    return ret;
+}
+
+/* ------------------------------------------------------------------------
  * Linear part of the low-rank coarse solver, Sec. 2 (definition of G_n):
  * out = Uk (S .* (Vk^T v)) for w vectors v (columns of Vin); k inner
  * products followed by a combination of k vectors (Sec. 2.2, last

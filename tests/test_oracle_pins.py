@@ -253,6 +253,43 @@ def test_rsvd_power_iterations_definition(ora):
     assert errs[2] <= 1.02
 
 
+def test_rsvd_two_sided_definition(ora):
+    """Adjoint on independent test vectors (Sec. 2.2): the result is the
+    rank-k truncated SVD of Q (Psi^T Q)^{-1} Psi^T T with Q = orth(T Omega),
+    checked against that definition computed densely (numpy solve and SVD)
+    on a non-symmetric 8x8 grid; with l = n it reproduces T; with
+    Psi = Q it is the one-sided rSVD."""
+    P = inputs.tiny2d(nx=8, m=6, T=1.0)
+    op = ora.Operator(**P.op_params())
+    T = _dense_T(op, P.m)
+    sv = np.linalg.svd(T, compute_uv=False)
+    r = np.random.default_rng(21)
+    k, p = 6, 4
+    l = k + p
+    Om, Psi = r.standard_normal((P.n, l)), r.standard_normal((P.n, l))
+    Uk, S, Vk = ora.rsvd_two_sided(op, P.m, k, p, Om, Psi)
+    Qd, _ = np.linalg.qr(T @ Om)
+    Ad = Qd @ np.linalg.solve(Psi.T @ Qd, Psi.T @ T)
+    Ua, Sa, Vat = np.linalg.svd(Ad)
+    Pd = (Ua[:, :k] * Sa[:k]) @ Vat[:k]
+    Po = (Uk * S[:k]) @ Vk.T
+    assert np.linalg.norm(Po - Pd) <= 1e-10 * np.linalg.norm(Pd)
+    assert np.abs(S - Sa[:l]).max() <= 1e-10 * Sa[0]
+    # less accurate than the one-sided build on the same Omega, still of the order of sigma_{k+1}
+    U1, S1, V1 = ora.rsvd(op, P.m, k, p, Om)
+    e1 = np.linalg.norm(T - (U1 * S1[:k]) @ V1.T, 2)
+    e2 = np.linalg.norm(T - Po, 2)
+    assert sv[k] * (1 - 1e-10) <= e1 <= e2 <= 100 * sv[k]
+    # Psi = Q: Psi^T Q = I, X = Q^T T, the one-sided result
+    U3, S3, V3 = ora.rsvd_two_sided(op, P.m, k, p, Om, Qd)
+    assert np.abs(S3 - S1).max() <= 1e-12 * S1[0]
+    assert np.linalg.norm((U3 * S3[:k]) @ V3.T - (U1 * S1[:k]) @ V1.T) <= 1e-12 * np.linalg.norm(T)
+    # l = n: exact
+    n = P.n
+    Uk, S, Vk = ora.rsvd_two_sided(op, P.m, n, 0, r.standard_normal((n, n)), r.standard_normal((n, n)))
+    assert np.abs((Uk * S) @ Vk.T - T).max() <= 1e-10 * sv[0]
+
+
 def test_sigma1_at_most_one(ora):
     """M is row and column diagonally dominant with excess >= 1, so
     ||M^{-1}||_2 <= 1 and sigma_{n,1} <= 1 (the delta <= 1 case of Thm. 1)."""
