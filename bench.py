@@ -223,23 +223,27 @@ def fwd_adj_rates(ctx, lrpr, P, prec):
     return out
 
 
-def rsvd_power_iteration(ctx, lrpr, P, prec, Om):
-    """rSVD build of the 64 slices with q = 1 power iteration (2 more sweeps
-    of the 3200-column panel), timed once; eps = max_n sigma_{n,k+1} beside
-    the q = 0 build's."""
+def rsvd_variants(ctx, lrpr, P, prec, Om):
+    """rSVD build of the 64 slices, timed once each: the one-sided build
+    (q = 0), with q = 1 power iteration (2 more sweeps of the 3200-column
+    panel), and the two-sided build (adjoint on independent test vectors
+    Psi); eps = max_n sigma_{n,k+1} of each."""
     import torch
     fp = 0 if prec == "f64" else 1
     F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
                    store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(777)
+    Psi = torch.randn(Om.shape, generator=gen, device="cuda", dtype=torch.float64).to(Om.dtype)
     out = {}
-    for q in (0, 1):
+    for name, kw in (("q0", {}), ("q1", {"q": 1}), ("two_sided", {"psi": [Psi[s].t() for s in range(P.N)]})):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        coarse = ctx.rsvd_build([(F, P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, fp, q=q)
+        coarse = ctx.rsvd_build([(F, P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, fp, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         sig = np.array(coarse.sigma).reshape(P.N, P.l)
-        out["q%d" % q] = {"rsvd_s": dt, "eps_max_sigma_k1": float(sig[:, P.k].max())}
+        out[name] = {"rsvd_s": dt, "eps_max_sigma_k1": float(sig[:, P.k].max())}
         coarse.close()
     F.close()
     return out
@@ -385,7 +389,7 @@ def main():
                                 (sum(r["ms"] for r in r64["range"]) / 1000.0)}
     if not args.no_plain:
         res["range_finder_sweeps_separately"] = fwd_adj_rates(ctx, lrpr, P, prec)
-        res["rsvd_power_iteration"] = rsvd_power_iteration(
+        res["rsvd_variants"] = rsvd_variants(
             ctx, lrpr, P, prec, Om64 if prec == "f64" else Om64.to(torch.float32))
         res["plain_per_rhs_fp64_rhs_steps_per_s"] = plain_per_rhs(ctx, lrpr, P)
         res["batched_vs_plain_per_rhs"] = rr / res["plain_per_rhs_fp64_rhs_steps_per_s"]

@@ -216,6 +216,19 @@ lrpr_status lrpr_rsvd_build(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *sl
 lrpr_status lrpr_rsvd_build_q(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
                               int nsteps, int q, lrpr_prec range_prec, lrpr_coarse *out,
                               double *sigma_host, int *fallback_host);
+/* The build with the adjoint on independent test vectors (Sec. 2.2: more
+ * parallelism at some loss of accuracy).  psi: host array of nslices device
+ * pointers, each an n x (k+p) Gaussian matrix (column-major, ld n, element
+ * type of range_prec) drawn independently of the slice's Omega; read only.
+ *   Y = T Omega,  Z = T^T Psi (the adjoint sweep does not wait for Q);
+ *   Y = Q R (CholeskyQR2);  C = Psi^T Q;  X^T = Z C^{-T} (Gauss-Jordan
+ *   inverse of C, FP64);  X^T = Qx Rx;  Rx^T = Uh diag(S) Vh^T;
+ *   U_k = Q Uh[:, :k],  V_k = Qx Vh[:, :k],
+ * the rank-k truncation of Q (Psi^T Q)^{-1} Psi^T T.  Signs, outputs and
+ * errors as lrpr_rsvd_build; LRPR_ERR_QR_BREAKDOWN if Psi^T Q is singular. */
+lrpr_status lrpr_rsvd_build_two_sided(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
+                                      const void *const *psi, int nsteps, lrpr_prec range_prec,
+                                      lrpr_coarse *out, double *sigma_host, int *fallback_host);
 void lrpr_coarse_destroy(lrpr_coarse c);
 /* Device pointers (owned by the handle) of slice s: U (n x k), S (k+p
  * values), V (n x k); k and n of that slice. */

@@ -118,6 +118,14 @@ lrpr_status lrpr_coarse_get(lrpr_coarse c, int s, const double **U, const double
     return LRPR_OK;
 }
 
+}  // extern "C"
+
+static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
+                                   const void *const *psi, int nsteps, int q, lrpr_prec range_prec,
+                                   lrpr_coarse *out, double *sigma_host, int *fallback_host);
+
+extern "C" {
+
 lrpr_status lrpr_rsvd_build(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices, int nsteps,
                             lrpr_prec range_prec, lrpr_coarse *out, double *sigma_host, int *fallback_host) {
     return lrpr_rsvd_build_q(ctx, nslices, slices, nsteps, 0, range_prec, out, sigma_host, fallback_host);
@@ -125,6 +133,27 @@ lrpr_status lrpr_rsvd_build(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *sl
 
 lrpr_status lrpr_rsvd_build_q(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices, int nsteps, int q,
                               lrpr_prec range_prec, lrpr_coarse *out, double *sigma_host, int *fallback_host) {
+    return rsvd_build_impl(ctx, nslices, slices, nullptr, nsteps, q, range_prec, out, sigma_host, fallback_host);
+}
+
+lrpr_status lrpr_rsvd_build_two_sided(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
+                                      const void *const *psi, int nsteps, lrpr_prec range_prec, lrpr_coarse *out,
+                                      double *sigma_host, int *fallback_host) {
+    if (!ctx) return LRPR_ERR_ARG;
+    if (!psi) return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build_two_sided: psi is null");
+    for (int s = 0; s < nslices; ++s)
+        if (!psi[s]) return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build_two_sided: psi[s] is null");
+    return rsvd_build_impl(ctx, nslices, slices, psi, nsteps, 0, range_prec, out, sigma_host, fallback_host);
+}
+
+}  // extern "C"
+
+// Randomized SVD of every slice.  psi == null: one-sided (Sec. 2.1 steps 1-6,
+// q power iterations); psi != null: the adjoint runs on the independent test
+// vectors psi[s] and the core is (Psi^T Q)^{-1} (T^T Psi)^T (Sec. 2.2).
+static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
+                                   const void *const *psi, int nsteps, int q, lrpr_prec range_prec,
+                                   lrpr_coarse *out, double *sigma_host, int *fallback_host) {
     if (!ctx) return LRPR_ERR_ARG;
     if (nslices <= 0 || !slices || !out || nsteps < 0 || q < 0 ||
         (range_prec != LRPR_F64 && range_prec != LRPR_F32))
@@ -192,6 +221,11 @@ lrpr_status lrpr_rsvd_build_q(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *
         CK(hipMemcpyAsync((char *)Y + off[s] * esz, slices[s].Omega, (size_t)(off[s + 1] - off[s]) * esz,
                           hipMemcpyDeviceToDevice, st),
            "copy Omega");
+    if (psi)   // two-sided: Z = Psi, swept with the adjoint below without waiting for Q
+        for (int s = 0; s < nslices; ++s)
+            CK(hipMemcpyAsync((char *)Z + off[s] * esz, psi[s], (size_t)(off[s + 1] - off[s]) * esz,
+                              hipMemcpyDeviceToDevice, st),
+               "copy Psi");
     // consecutive slices with the same factor form one panel (contiguous blocks)
     auto make_panels = [&](void *base) {
         std::vector<lrpr_panel> P;
@@ -287,17 +321,54 @@ lrpr_status lrpr_rsvd_build_q(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *
             if ((r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, false)) != LRPR_OK) return r;
         }
     }
-    r = cholqr2(Y, f32, Q, RY);                        // step 2
-    if (r != LRPR_OK) return r;
-    // --- step 3: Z = T^T Q (adjoint sweep) ---------------------------------
-    CK(launch_convert(0, f32 ? 1 : 0, Q, Z, tot, st), "Q -> Z");
-    {
-        std::vector<lrpr_panel> P = make_panels(Z);
-        r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, true);
+    if (psi) {
+        // --- two-sided: Z = T^T Psi; C = Psi^T Q; X^T = Z C^{-T}; X^T = Qx Rx ---
+        {
+            std::vector<lrpr_panel> P = make_panels(Z);
+            if ((r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, true)) != LRPR_OK) return r;
+        }
+        if ((r = cholqr2(Y, f32, Q, RY)) != LRPR_OK) return r;
+        double *ones, *Cg, *Bt, *lpart;
+        int *stat3;
+        CK(mem.alloc(&ones, LMAX), "ones");
+        CK(mem.alloc(&Cg, SM * nslices), "Psi^T Q");
+        CK(mem.alloc(&Bt, SM * nslices), "C^-T");
+        CK(mem.alloc(&stat3, nslices), "status");
+        CK(mem.alloc(&lpart, (size_t)lr_part_elems(nmax, lmax, lmax)), "cross Gram partials");
+        CK(launch_fill(ones, LMAX, 1.0, st), "ones");
+        // FP64 copy of Psi in T2 (the caller's Psi is untouched; Z holds T^T Psi)
+        for (int s = 0; s < nslices; ++s) {
+            CK(launch_convert(f32 ? 1 : 0, 0, psi[s], T2 + off[s], off[s + 1] - off[s], st), "Psi -> FP64");
+            CK(launch_cross_gram(T2 + off[s], Q + off[s], slices[s].F->n, ls[s], ls[s], ones, lpart, Cg + SM * s,
+                                 st),
+               "Psi^T Q");
+        }
+        CK(launch_small_inv_t(d_ls, nslices, lmax, Cg, Bt, stat3, st), "(Psi^T Q)^-T");
+        std::vector<int> h3(nslices);
+        CK(hipMemcpyAsync(h3.data(), stat3, sizeof(int) * nslices, hipMemcpyDeviceToHost, st), "status");
+        CK(hipStreamSynchronize(st), "sync");
+        for (int s = 0; s < nslices; ++s)
+            if (h3[s]) return fail(ctx, LRPR_ERR_QR_BREAKDOWN, "lrpr_rsvd_build_two_sided: Psi^T Q is singular");
+        // X^T into Y (range precision, as Z in the one-sided build; Y is consumed)
+        for (int s = 0; s < nslices; ++s)
+            rj[s] = RowMatJob{(const char *)Z + off[s] * esz, slices[s].F->n, Bt + SM * s, (char *)Y + off[s] * esz,
+                              slices[s].F->n, slices[s].F->n, ls[s], ls[s], 0, 0};
+        CK(upload(d_rj, rj, st), "upload");
+        CK(launch_rowmat(f32 ? 1 : 0, f32 ? 1 : 0, d_rj, nslices, nmax, st), "Z C^-T");
+        if ((r = cholqr2(Y, f32, QZ, RZ)) != LRPR_OK) return r;
+    } else {
+        r = cholqr2(Y, f32, Q, RY);                    // step 2
+        if (r != LRPR_OK) return r;
+        // --- step 3: Z = T^T Q (adjoint sweep) -----------------------------
+        CK(launch_convert(0, f32 ? 1 : 0, Q, Z, tot, st), "Q -> Z");
+        {
+            std::vector<lrpr_panel> P = make_panels(Z);
+            r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, true);
+            if (r != LRPR_OK) return r;
+        }
+        r = cholqr2(Z, f32, QZ, RZ);                   // step 4
         if (r != LRPR_OK) return r;
     }
-    r = cholqr2(Z, f32, QZ, RZ);                       // step 4
-    if (r != LRPR_OK) return r;
     // --- step 5: Mm = Rz^T, small SVD --------------------------------------
     CK(launch_transpose_small(d_ls, nslices, RZ, Mm, st), "Rz^T");
     CK(launch_jacobi(d_ls, nslices, lmax, Mm, Uh, Sd, Vh, sweeps, st), "jacobi");
@@ -365,6 +436,8 @@ lrpr_status lrpr_rsvd_build_q(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *
     *out = c;
     return LRPR_OK;
 }
+
+extern "C" {
 
 lrpr_status lrpr_coarse_apply(lrpr_ctx ctx, lrpr_coarse c, int s, int w, const double *Vin, double *Out) {
     if (!ctx) return LRPR_ERR_ARG;

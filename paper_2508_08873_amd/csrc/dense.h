@@ -90,5 +90,12 @@ hipError_t launch_fillf(float *dst, int64_t count, float v, hipStream_t s);
 hipError_t launch_trmm_upper(const int *d_ls, int nslices, const double *R2, const double *R1, double *R,
                              hipStream_t s);
 hipError_t launch_transpose_small(const int *d_ls, int nslices, const double *R, double *Mm, hipStream_t s);
+// B = C^{-T} per slice (C row-major ld l, B row-major ld LMAX, both at s*LMAX*LMAX); status[s] = 1 if singular
+hipError_t launch_small_inv_t(const int *d_ls, int nslices, int lmax, const double *C, double *B, int *status,
+                              hipStream_t s);
+// out[r*w + c] = sum_i V[i][r] X[i][c] (V: n x k, X: n x w, FP64 column-major ld n); ones: >= k ones;
+// part: lr_part_elems(n, k, w) doubles
+hipError_t launch_cross_gram(const double *V, const double *X, int64_t n, int k, int w, const double *ones,
+                             double *part, double *out, hipStream_t s);
 
 }  // namespace lrpr

@@ -695,6 +695,85 @@ __global__ void k_transpose_small(const int *ls, const double *R, double *Mm) {
 }
 
 // ---------------------------------------------------------------------------
+// B = C^{-T} for one small l x l matrix per slice (Gauss-Jordan elimination
+// with partial pivoting in LDS, one workgroup per slice).  C: row-major ld l
+// at s*LMAX*LMAX; B: row-major ld LMAX at the same offset.  status[s] = 1 if
+// a pivot is zero or not finite (B is then not written).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_small_inv_t(const int *ls, const double *C, double *B, int *status) {
+    extern __shared__ double sm[];
+    const int s = blockIdx.x;
+    const int l = ls[s];
+    const int64_t off = (int64_t)s * LMAX * LMAX;
+    double *A = sm;              // l x l, row-major
+    double *V = sm + l * l;      // becomes C^{-1}
+    double *fac = V + l * l;     // column multipliers
+    __shared__ int piv;
+    __shared__ int bad;
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int e = tid; e < l * l; e += blockDim.x) {
+        A[e] = C[off + e];
+        V[e] = (e / l == e % l) ? 1.0 : 0.0;
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int c = 0; c < l; ++c) {
+        if (tid < 64) {   // pivot row: largest |A[r][c]|, r >= c (lowest index on ties)
+            int best = -1;
+            double bv = -1.0;
+            for (int r = c + lane; r < l; r += 64) {
+                const double v = fabs(A[r * l + c]);
+                if (v > bv) { bv = v; best = r; }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv, o);
+                const int ob = __shfl_xor(best, o);
+                if (ov > bv || (ov == bv && ob >= 0 && (best < 0 || ob < best))) { bv = ov; best = ob; }
+            }
+            if (lane == 0) {
+                piv = best;
+                if (!(bv > 0.0) || !isfinite(bv)) bad = 1;
+            }
+        }
+        __syncthreads();
+        if (bad) break;   // uniform: every thread reads the same flag after the barrier
+        const int pr = piv;
+        if (pr != c)
+            for (int j = tid; j < l; j += blockDim.x) {
+                double t = A[c * l + j];
+                A[c * l + j] = A[pr * l + j];
+                A[pr * l + j] = t;
+                t = V[c * l + j];
+                V[c * l + j] = V[pr * l + j];
+                V[pr * l + j] = t;
+            }
+        __syncthreads();
+        const double inv = 1.0 / A[c * l + c];
+        for (int r = tid; r < l; r += blockDim.x) fac[r] = r == c ? 0.0 : A[r * l + c];
+        __syncthreads();
+        for (int j = tid; j < l; j += blockDim.x) {
+            A[c * l + j] *= inv;
+            V[c * l + j] *= inv;
+        }
+        __syncthreads();
+        for (int e = tid; e < l * l; e += blockDim.x) {
+            const int r = e / l, j = e % l;
+            if (r != c) {
+                A[e] -= fac[r] * A[c * l + j];
+                V[e] -= fac[r] * V[c * l + j];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) status[s] = bad;
+    if (bad) return;
+    for (int e = tid; e < LMAX * LMAX; e += blockDim.x) {
+        const int i = e / LMAX, j = e % LMAX;
+        B[off + e] = (i < l && j < l) ? V[j * l + i] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 static unsigned blocks_for(int64_t count, int threads) {
@@ -799,6 +878,32 @@ hipError_t launch_fillf(float *dst, int64_t count, float v, hipStream_t s) {
 hipError_t launch_trmm_upper(const int *d_ls, int nslices, const double *R2, const double *R1, double *R,
                              hipStream_t s) {
     hipLaunchKernelGGL(k_trmm_upper, dim3(nslices), dim3(256), 0, s, d_ls, R2, R1, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_inv_t(const int *d_ls, int nslices, int lmax, const double *C, double *B, int *status,
+                              hipStream_t s) {
+    const size_t lds = sizeof(double) * (2 * (size_t)lmax * lmax + lmax);
+    hipLaunchKernelGGL(k_small_inv_t, dim3(nslices), dim3(256), lds, s, d_ls, C, B, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_cross_gram(const double *V, const double *X, int64_t n, int k, int w, const double *ones,
+                             double *part, double *out, hipStream_t s) {
+    LrArgs a{};
+    a.V = V;
+    a.x = X;
+    a.n = n;
+    a.k = k;
+    a.w = w;
+    a.part = part;
+    const unsigned nch = (unsigned)lr_chunks(n);
+    const int nk = k * w;
+    hipLaunchKernelGGL(k_lr_dots, dim3(nch), dim3(LR_THREADS), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lr_coef, dim3((nk + 63) / 64), dim3(64 * LR_RED), 0, s, (const double *)part, (int64_t)nch,
+                       nk, w, ones, out);
     return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-STREAMS = {"omega": 1, "u0": 2, "f": 3, "problem": 4, "arrivals": 5, "request": 6}
+STREAMS = {"omega": 1, "u0": 2, "f": 3, "problem": 4, "arrivals": 5, "request": 6, "psi": 7}
 
 
 def rng(seed: int, stream: str, *idx: int) -> np.random.Generator:
@@ -144,6 +144,12 @@ class Problem:
     def omega(self, n: int, dtype=np.float64) -> np.ndarray:
         """Gaussian test matrix Omega_n (n x l, column-major) of slice n."""
         r = rng(self.seed, "omega", self.pid, n)
+        return np.asfortranarray(r.standard_normal((self.l, self.n)).T).astype(dtype)
+
+    def psi(self, n: int, dtype=np.float64) -> np.ndarray:
+        """Second Gaussian test matrix Psi_n (n x l), independent of Omega_n,
+        for the adjoint evaluations of the two-sided build."""
+        r = rng(self.seed, "psi", self.pid, n)
         return np.asfortranarray(r.standard_normal((self.l, self.n)).T).astype(dtype)
 
 

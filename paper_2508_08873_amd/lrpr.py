@@ -20,6 +20,7 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_ZERO_PIVOT", 4: "ERR_QR
 EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_last_error",
            "lrpr_factor", "lrpr_factor_destroy", "lrpr_factor_info", "lrpr_factor_copy_lu",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build", "lrpr_rsvd_build_q",
+           "lrpr_rsvd_build_two_sided",
            "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_parareal_solve",
            "lrpr_profile_enable", "lrpr_profile_read",
            "lrpr_server_create", "lrpr_server_destroy", "lrpr_server_submit", "lrpr_server_progress",
@@ -190,9 +191,10 @@ class Context:
         self._check(self.lib.lrpr_adjoint_step_batched(self.h, len(specs), arr, int(nsteps), int(prec)))
 
     # -- rSVD -------------------------------------------------------------
-    def rsvd_build(self, slices, nsteps, range_prec=LRPR_F64, q=0):
+    def rsvd_build(self, slices, nsteps, range_prec=LRPR_F64, q=0, psi=None):
         """slices: list of (Factor, k, p, Omega tensor n x (k+p) column-major);
-        q power iterations (lrpr_rsvd_build_q)."""
+        q power iterations (lrpr_rsvd_build_q); psi: per-slice independent
+        adjoint test matrices (lrpr_rsvd_build_two_sided)."""
         arr = (SliceDesc * len(slices))()
         tot = 0
         for i, (F, k, p, Om) in enumerate(slices):
@@ -202,7 +204,11 @@ class Context:
         fb = (ctypes.c_int * max(len(slices), 1))()
         h = ctypes.c_void_p()
         self.sync_stream()
-        if q:
+        if psi is not None:
+            pp = (ctypes.c_void_p * len(slices))(*[t.data_ptr() for t in psi])
+            self._check(self.lib.lrpr_rsvd_build_two_sided(self.h, len(slices), arr, pp, int(nsteps),
+                                                           int(range_prec), ctypes.byref(h), sig, fb))
+        elif q:
             self._check(self.lib.lrpr_rsvd_build_q(self.h, len(slices), arr, int(nsteps), int(q), int(range_prec),
                                                    ctypes.byref(h), sig, fb))
         else:

@@ -135,6 +135,34 @@ def test_rsvd_power_iterations(ctx, ora, prec, q):
         assert _prod_err(Ug, Sg2, Vg, Uo, So, Vo, P.k) <= tol, s
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_rsvd_two_sided(ctx, ora, prec):
+    """Adjoint on independent test vectors (Sec. 2.2,
+    lrpr_rsvd_build_two_sided): sigma and products against the oracle's
+    two-sided build on the same Omega and Psi; two slices share a factor."""
+    from paper_2508_08873_amd import lrpr
+    P = inputs.tiny2d(nx=31, N=3, m=4, k=8, p=4, T=1.0 / 4)
+    print("two-sided prec", prec, flush=True)
+    pp = P.op_params(1)
+    op = ora.Operator(**pp)
+    F = ctx.factor(pp["dim"], pp["nx"], pp["nu"], pp["beta"], pp["c"], pp["dt"],
+                   store_mask=lrpr.STORE_F64 | lrpr.STORE_F32 | lrpr.STORE_MIRROR)
+    dt = torch.float64 if prec == 0 else torch.float32
+    oms = [P.omega(s) for s in range(1, P.N + 1)]
+    psis = [P.psi(s) for s in range(1, P.N + 1)]
+    d_psi = [_dev(x, dt) for x in psis]
+    coarse = ctx.rsvd_build([(F, P.k, P.p, _dev(oms[s], dt)) for s in range(P.N)], P.m, prec, psi=d_psi)
+    tol = 1e-11 if prec == 0 else 1e-5
+    l = P.k + P.p
+    for s in range(P.N):
+        Uo, So, Vo = ora.rsvd_two_sided(op, P.m, P.k, P.p, oms[s], psis[s])
+        Sg = np.array(coarse.sigma[s * l:(s + 1) * l])
+        print("slice", s, "sigma err", np.abs(Sg - So).max() / So[0], flush=True)
+        assert np.abs(Sg - So).max() <= tol * So[0], (s, np.abs(Sg - So).max() / So[0])
+        Ug, Sg2, Vg = _coarse_host(coarse, s, P.n)
+        assert _prod_err(Ug, Sg2, Vg, Uo, So, Vo, P.k) <= tol, s
+
+
 def test_rsvd_per_slice_factors(ctx, ora):
     """Time-dependent nu_n: every slice has its own factor (one launch); the
     factors are kept without the mirrored set, so the adjoint reads them
