@@ -73,6 +73,7 @@ template <int NW, int TPW>
 __global__ __launch_bounds__(64 * NW) void k_tile_lu(LuArgs a) {
     __shared__ double ubuf[2][256];   // U(K,J), accumulator order
     __shared__ double sd[256];        // diagonal tile, row-major
+    __shared__ double sd2[256];       // second buffer of the diagonal elimination
     __shared__ double sli[256];       // L(J,J)^{-1}, row-major
     __shared__ double sui[256];       // U(J,J)^{-1}, row-major
     __shared__ double st[NW][256];    // per-wave transposition buffer
@@ -109,6 +110,19 @@ __global__ __launch_bounds__(64 * NW) void k_tile_lu(LuArgs a) {
             wait_col(a, K);
             const int tK = K - J + nb;
             double *ub = ubuf[K & 1];
+            // the panel's L tiles of this wave's rows load while U(K,J) is formed
+            // (while registers allow: PRE tiles per wave)
+            constexpr bool PRE = TPW <= 9;
+            double lt[PRE ? TPW : 1][4];
+            if constexpr (PRE) {
+#pragma unroll
+                for (int s = 0; s < TPW; ++s) {
+                    const int t = w + NW * s;
+                    const int I = J - nb + t;
+                    if (t <= 2 * nb && I > K && I <= K + nb && I < NT)
+                        ld_a(a.Lt + ((int64_t)K * nb + (I - K - 1)) * TILE_ELEMS, lane, lt[s]);
+                }
+            }
             if (w == tK % NW) {
                 double li[4];
                 ld_a(a.Li + (int64_t)K * TILE_ELEMS, lane, li);
@@ -134,7 +148,12 @@ __global__ __launch_bounds__(64 * NW) void k_tile_lu(LuArgs a) {
                 const int I = J - nb + t;
                 if (t <= 2 * nb && I > K && I <= K + nb && I < NT) {
                     double l[4];
-                    ld_a(a.Lt + ((int64_t)K * nb + (I - K - 1)) * TILE_ELEMS, lane, l);
+                    if constexpr (PRE) {
+#pragma unroll
+                        for (int kc = 0; kc < 4; ++kc) l[kc] = lt[s][kc];
+                    } else {
+                        ld_a(a.Lt + ((int64_t)K * nb + (I - K - 1)) * TILE_ELEMS, lane, l);
+                    }
 #pragma unroll
                     for (int kc = 0; kc < 4; ++kc) acc[s] = mfma64(-l[kc], ubv[kc], acc[s]);
                 }
@@ -151,37 +170,76 @@ __global__ __launch_bounds__(64 * NW) void k_tile_lu(LuArgs a) {
         }
         __syncthreads();
         const int r = (tid >> 4) & 15, q = tid & 15;
+        // one barrier per pivot: step p reads buffer p%2 and writes the other
+        // (the multiplier l = A(r,p)/A(p,p) is recomputed by every thread of
+        // row r, bit-identical to the stored one)
         for (int p = 0; p < TILE; ++p) {
-            const double piv = sd[p * TILE + p];
+            const double *cur = (p & 1) ? sd2 : sd;
+            double *nxt = (p & 1) ? sd : sd2;
+            const double piv = cur[p * TILE + p];
             if (tid == 0 && (int64_t)J * TILE + p < n && !(piv != 0.0 && isfinite(piv)))
                 atomicMin(a.info, J * TILE + p + 1);
-            if (tid < 256 && r > p && q == p) sd[r * TILE + p] /= piv;
-            __syncthreads();
-            if (tid < 256 && r > p && q > p) sd[r * TILE + q] -= sd[r * TILE + p] * sd[p * TILE + q];
+            if (tid < 256) {
+                double v = cur[r * TILE + q];
+                if (r > p) {
+                    const double l = cur[r * TILE + p] / piv;
+                    if (q == p) v = l;
+                    else if (q > p) v -= l * cur[p * TILE + q];
+                }
+                nxt[r * TILE + q] = v;
+            }
             __syncthreads();
         }
-        // inverses of the unit-lower L(J,J) (threads 0..15, one column each)
-        // and of the upper U(J,J) (threads 16..31)
-        if (tid < TILE) {
-            double x[TILE];
+        // ---- inverses of the unit-lower L(J,J) (wave 0) and of U(J,J) (wave 1)
+        //      on the matrix cores.  With L = I + N (N strictly lower, N^16 = 0):
+        //      L^{-1} = (I - N)(I + N^2)(I + N^4)(I + N^8), an exact finite product;
+        //      U = D (I + N') with N' = D^{-1}(U - D) strictly upper, so
+        //      U^{-1} = (I - N')(I + N'^2)(I + N'^4)(I + N'^8) D^{-1}.
+        if (w < 2) {
+            const bool up = w == 1;
+            double *buf = st[w];
+            // N (or N') in accumulator layout
+            v4d N;
 #pragma unroll
-            for (int rr = 0; rr < TILE; ++rr) {
-                double v = (rr == tid) ? 1.0 : 0.0;
-#pragma unroll
-                for (int k = 0; k < rr; ++k) v -= sd[rr * TILE + k] * x[k];
-                x[rr] = v;
-                sli[rr * TILE + tid] = v;
+            for (int i = 0; i < 4; ++i) {
+                const int row = 4 * i + g;
+                const double x = sd[row * TILE + c];
+                N[i] = up ? (c > row ? x / sd[row * TILE + row] : 0.0) : (row > c ? x : 0.0);
             }
-        } else if (tid < 2 * TILE) {
-            const int cc = tid - TILE;
-            double x[TILE];
+            // X * Y with Y in accumulator layout (B operand), X staged through LDS
+            auto mm = [&](const v4d &X, const v4d &Y) {
 #pragma unroll
-            for (int rr = TILE - 1; rr >= 0; --rr) {
-                double v = (rr == cc) ? 1.0 : 0.0;
+                for (int i = 0; i < 4; ++i) buf[(4 * i + g) * TILE + c] = X[i];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                double xa[4];
 #pragma unroll
-                for (int k = rr + 1; k < TILE; ++k) v -= sd[rr * TILE + k] * x[k];
-                x[rr] = v / sd[rr * TILE + rr];
-                sui[rr * TILE + cc] = x[rr];
+                for (int kc = 0; kc < 4; ++kc) xa[kc] = buf[c * TILE + 4 * kc + g];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                v4d o = {0, 0, 0, 0};
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) o = mfma64(xa[kc], Y[kc], o);
+                return o;
+            };
+            v4d I4;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) I4[i] = (4 * i + g == c) ? 1.0 : 0.0;
+            const v4d N2 = mm(N, N);
+            v4d P = I4 - N;                       // (I - N)
+            P = P + mm(P, N2);                    // (I - N)(I + N^2)
+            const v4d N4 = mm(N2, N2);
+            P = P + mm(P, N4);
+            const v4d N8 = mm(N4, N4);
+            P = P + mm(P, N8);
+            double *dst = up ? sui : sli;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 4 * i + g;
+                // U^{-1} = (I + N')^{-1} D^{-1}: column c scaled by 1 / U(c,c)
+                dst[row * TILE + c] = up ? P[i] / sd[c * TILE + c] : P[i];
             }
         }
         __syncthreads();
