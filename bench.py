@@ -232,9 +232,10 @@ def rsvd_variants(ctx, lrpr, P, prec, Om):
     fp = 0 if prec == "f64" else 1
     F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
                    store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(777)
-    Psi = torch.randn(Om.shape, generator=gen, device="cuda", dtype=torch.float64).to(Om.dtype)
+    Psi = torch.empty(Om.shape, device="cuda", dtype=torch.float64)
+    for s_ in range(P.N):
+        ctx.randn(Psi[s_], 777, s_)
+    Psi = Psi.to(Om.dtype)
     out = {}
     for name, kw in (("q0", {}), ("q1", {"q": 1}), ("two_sided", {"psi": [Psi[s].t() for s in range(P.N)]})):
         torch.cuda.synchronize()
@@ -278,9 +279,10 @@ def main():
     prec = args.prec
     ctx = lrpr.Context(0)
     # inputs, resident in HBM before the timed region
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(args.seed)
-    Om64 = torch.randn((P.N, P.l, P.n), generator=gen, device="cuda", dtype=torch.float64)
+    # Omega_n: the library's on-device Philox4x32-10 Gaussians, stream n
+    Om64 = torch.empty((P.N, P.l, P.n), device="cuda", dtype=torch.float64)
+    for s_ in range(P.N):
+        ctx.randn(Om64[s_], args.seed, s_)
     u0 = lrpr.colmajor(torch.from_numpy(P.u0().reshape(-1, 1)).to("cuda"))
     f = lrpr.colmajor(torch.from_numpy(P.source().reshape(-1, 1)).to("cuda"))
     fsc = torch.from_numpy(np.concatenate([P.fscale(s) for s in range(1, P.N + 1)])).to("cuda")

@@ -95,6 +95,20 @@ lrpr_status lrpr_profile_enable(lrpr_ctx ctx, int enable);
 lrpr_status lrpr_profile_read(lrpr_ctx ctx, double *ms, int64_t *launches, double *flops, double *bytes,
                               double *rhs_steps);
 
+/* ---- Gaussian test matrices (Sec. 2.1, step 1) ---------------------------- */
+
+/* Fill dst (device, count elements of type prec) with standard Gaussians of
+ * the counter-based generator Philox4x32-10 (Salmon et al., SC'11) and the
+ * Box-Muller transform: element pair j of (seed, stream) comes from counter
+ * (j mod 2^32, j div 2^32, stream mod 2^32, stream div 2^32) and key
+ * (seed mod 2^32, seed div 2^32); the words (x0, x1), (x2, x3) give uniforms
+ * u = (floor((hi 2^32 + lo) / 2^11) + 1/2) 2^-53, and elements 2j, 2j+1 are
+ * sqrt(-2 ln u1) cos(2 pi u2) and sqrt(-2 ln u1) sin(2 pi u2), computed in
+ * FP64 (rounded once for LRPR_F32).  The result depends only on (seed,
+ * stream, element index), so any slice of a test matrix can be drawn on its
+ * own.  Stream-ordered on the context's stream.  Errors: LRPR_ERR_ARG. */
+lrpr_status lrpr_randn(lrpr_ctx ctx, void *dst, int64_t count, lrpr_prec prec, uint64_t seed, uint64_t stream);
+
 /* ---- operator assembly and band LU (Sec. 4.4) --------------------------- */
 
 enum { LRPR_STORE_F64 = 1, LRPR_STORE_F32 = 2, LRPR_STORE_MIRROR = 4, LRPR_STORE_SPLIT = 8 };

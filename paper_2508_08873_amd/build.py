@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "liblrpr.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["factor.hip", "lu.hip", "sweep.hip", "split.hip", "dense.hip", "api_core.cpp", "api_rsvd.cpp", "api_serve.cpp"]
+SOURCES = ["factor.hip", "lu.hip", "sweep.hip", "split.hip", "dense.hip", "rng.hip", "api_core.cpp", "api_rsvd.cpp",
+           "api_serve.cpp"]
 ARCH = os.environ.get("LRPR_ARCH", "gfx950")
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-Wno-unused-result"]

@@ -572,6 +572,18 @@ lrpr_status lrpr_fine_step_batched(lrpr_ctx ctx, int npanels, const lrpr_panel *
     return run_sweep(ctx, npanels, panels, nsteps, prec, false);
 }
 
+lrpr_status lrpr_randn(lrpr_ctx ctx, void *dst, int64_t count, lrpr_prec prec, uint64_t seed, uint64_t stream) {
+    if (!ctx) return LRPR_ERR_ARG;
+    if (count < 0 || (count > 0 && !dst) || (prec != LRPR_F64 && prec != LRPR_F32))
+        return fail(ctx, LRPR_ERR_ARG, "lrpr_randn: invalid arguments");
+    if (count == 0) return LRPR_OK;
+    hipError_t e = hipSetDevice(ctx->dev);
+    if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+    if ((e = launch_randn(prec == LRPR_F32, dst, count, seed, stream, ctx->stream)) != hipSuccess)
+        return hipfail(ctx, e, "randn");
+    return LRPR_OK;
+}
+
 lrpr_status lrpr_profile_enable(lrpr_ctx ctx, int enable) {
     if (!ctx) return LRPR_ERR_ARG;
     ctx->prof = enable != 0;

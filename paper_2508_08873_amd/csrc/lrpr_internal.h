@@ -176,6 +176,8 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
 // pass (same code, launched as k_sweep_local)
 hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const SweepItem *d_items, int nsteps,
                         int max_nb, hipStream_t s, int step0 = 0, bool local = false);
+// Gaussian fill, Philox4x32-10 + Box-Muller (rng.hip)
+hipError_t launch_randn(bool f32, void *dst, int64_t count, uint64_t seed, uint64_t stream, hipStream_t s);
 // partitioned passes (split.hip)
 hipError_t launch_spike_rhs(int64_t n, int bw, int NT, int nb, int P, const int *d_blk, const double *lu,
                             double *RL, double *RU, hipStream_t s);

@@ -22,7 +22,7 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build", "lrpr_rsvd_build_q",
            "lrpr_rsvd_build_two_sided",
            "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_parareal_solve",
-           "lrpr_profile_enable", "lrpr_profile_read",
+           "lrpr_profile_enable", "lrpr_profile_read", "lrpr_randn",
            "lrpr_server_create", "lrpr_server_destroy", "lrpr_server_submit", "lrpr_server_progress",
            "lrpr_server_stats", "lrpr_server_last_error"]
 
@@ -93,6 +93,7 @@ def load():
     lib.lrpr_parareal_solve.argtypes = [vp, vp, P(vp), i32, i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
     lib.lrpr_profile_enable.argtypes = [vp, i32]
     lib.lrpr_profile_read.argtypes = [vp, P(dbl), P(i64), P(dbl), P(dbl), P(dbl)]
+    lib.lrpr_randn.argtypes = [vp, vp, i64, i32, ctypes.c_uint64, ctypes.c_uint64]
     lib.lrpr_server_create.argtypes = [vp, i32, P(ServeOp), dbl, ctypes.c_size_t, i32, P(vp)]
     lib.lrpr_server_destroy.argtypes = [vp]
     lib.lrpr_server_destroy.restype = None
@@ -156,6 +157,16 @@ class Context:
         self._check(self.lib.lrpr_profile_read(self.h, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(fl),
                                                ctypes.byref(by), ctypes.byref(rs)))
         return {"ms": ms.value, "launches": nl.value, "flops": fl.value, "bytes": by.value, "rhs_steps": rs.value}
+
+    # -- random test matrices ---------------------------------------------
+    def randn(self, X, seed, stream):
+        """Fill the contiguous float64/float32 cuda tensor X with the library's
+        Philox4x32-10 + Box-Muller Gaussians of (seed, stream)."""
+        prec = LRPR_F64 if X.dtype == torch.float64 else LRPR_F32
+        self.sync_stream()
+        self._check(self.lib.lrpr_randn(self.h, ctypes.c_void_p(X.data_ptr()), ctypes.c_int64(X.numel()), int(prec),
+                                        ctypes.c_uint64(seed), ctypes.c_uint64(stream)))
+        return X
 
     # -- factor -----------------------------------------------------------
     def factor(self, dim, nx, nu, beta, c, dt, store_mask=1):

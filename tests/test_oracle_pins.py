@@ -448,3 +448,32 @@ def test_bound_constants_from_oversampled_sigma(ora):
     d, e = ora.bound_constants(sl, P.k)
     assert d == max(s.S[0] for s in sl) and e == max(s.S[P.k] for s in sl)
     assert d <= 1.0
+
+
+def test_philox_known_answers():
+    """The test-side Philox4x32-10 against the generator's published
+    known-answer vectors (those distributed with its reference
+    implementation): counter / key all zeros, all ones, and the hexadecimal
+    digits of pi."""
+    from oracle import philox
+    M = 0xFFFFFFFF
+    assert philox.philox4x32_10([0, 0, 0, 0], [0, 0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    assert philox.philox4x32_10([M] * 4, [M] * 2) == [0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]
+    assert philox.philox4x32_10([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0]) == \
+        [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]
+    # the vectorised form used for arrays agrees with the scalar one
+    w = philox._philox_vec(np.array([0, 1, 2**32 + 5], dtype=np.uint64), 7 + (3 << 32), 11 + (5 << 32))
+    for i, j in enumerate([0, 1, 2**32 + 5]):
+        ref = philox.philox4x32_10([j & M, j >> 32, 7, 3], [11, 5])
+        assert [int(x[i]) for x in w] == ref
+
+
+def test_philox_gaussians_moments():
+    """Box-Muller on the Philox uniforms: mean, variance and a tail
+    probability of a large draw within a few standard errors."""
+    from oracle import philox
+    z = philox.randn(400001, seed=2024, stream=3)
+    assert abs(z.mean()) < 5.0 / np.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 5.0 * np.sqrt(2.0 / z.size)
+    assert abs(np.mean(np.abs(z) > 2.0) - 0.0455) < 0.002
+    assert not np.array_equal(philox.randn(8, 2024, 3), philox.randn(8, 2024, 4))
