@@ -178,6 +178,85 @@ class Operator:
         return X
 
 
+# ---------------------------------------------------------------------------
+# SDIRK fine steppers (the Butcher tableaus of the paper's study of the time
+# discretisation, Sec. 4 "Effect of time discretization")
+# ---------------------------------------------------------------------------
+GAMMA_L = (2.0 - 2.0 ** 0.5) / 2.0
+TABLEAUS = {
+    # c, a (lower triangular), b
+    "sdirk2": ((1.0, 0.0), ((1.0, 0.0), (-1.0, 1.0)), (0.5, 0.5)),
+    "sdirk2l": ((GAMMA_L, 1.0), ((GAMMA_L, 0.0), (1.0 - GAMMA_L, GAMMA_L)), (1.0 - GAMMA_L, GAMMA_L)),
+}
+
+
+class Stepper:
+    """m steps of a two-stage SDIRK method for u' = -A u + f(t), stage by
+    stage from the tableau: with t the step's start,
+        (I + dt a_ii A) k_i = -A (u + dt sum_{l<i} a_il k_l) + f(t + c_i dt),
+        u_new = u + dt sum_i b_i k_i.
+    The diagonal entries are equal, so every stage solves with the one band
+    LU of I + a_11 dt A; A v comes from that matrix, A v = (M v - v) / (a_11 dt).
+    The source of column c at stage i of step j is fscale[c, 2j + i] f[:, fcol[c]].
+    The linear map of a step is a rational function of A, so its adjoint is
+    the same recurrence with A^T and M^T (adjoint)."""
+
+    def __init__(self, method, dim, nx, nu, beta, c, dt):
+        self.method = method
+        self.cs, self.a, self.b = TABLEAUS[method]
+        self.dt = float(dt)
+        self.g = self.a[0][0]
+        self.stage = Operator(dim, nx, nu, beta, c, self.g * self.dt)
+        self.n = self.stage.n
+
+    def _A(self, V, transpose=False):
+        st, b, n = self.stage, self.stage.bw, self.stage.n
+        out = np.zeros_like(V)
+        for d in range(-b, b + 1):
+            if transpose:   # (M^T v)_i = sum_d M[i - d, i] v[i - d]
+                lo, hi = max(0, d), min(n, n + d)
+                out[lo:hi] += st.band[lo - d:hi - d, d + b][:, None] * V[lo - d:hi - d]
+            else:           # (M v)_i = sum_d M[i, i + d] v[i + d]
+                lo, hi = max(0, -d), min(n, n - d)
+                out[lo:hi] += st.band[lo:hi, d + b][:, None] * V[lo + d:hi + d]
+        return (out - V) / (self.g * self.dt)
+
+    def _solve(self, V, transpose=False):
+        return self.stage.adjoint(V, 1) if transpose else self.stage.fine(V, 1)
+
+    def _run(self, X, m, transpose, f=None, fcol=None, fscale=None):
+        X = np.array(X, dtype=np.float64, copy=True)
+        if X.ndim == 1:
+            X = X.reshape(-1, 1)
+        w = X.shape[1]
+        if f is not None:
+            f = np.asarray(f, dtype=np.float64)
+            if f.ndim == 1:
+                f = f.reshape(-1, 1)
+            fcol = np.zeros(w, dtype=np.int64) if fcol is None else np.asarray(fcol)
+            F = f[:, fcol]
+            fscale = np.ones((w, 2 * m)) if fscale is None else np.broadcast_to(np.asarray(fscale, np.float64), (w, 2 * m))
+        for j in range(m):
+            K = []
+            for i in range(2):
+                Ui = X.copy()
+                for l in range(i):
+                    Ui += self.dt * self.a[i][l] * K[l]
+                rhs = -self._A(Ui, transpose)
+                if f is not None:
+                    rhs += F * fscale[:, 2 * j + i][None, :]
+                K.append(self._solve(rhs, transpose))
+            for i in range(2):
+                X += self.dt * self.b[i] * K[i]
+        return X
+
+    def fine(self, X, m, f=None, fcol=None, fscale=None):
+        return self._run(X, m, False, f, fcol, fscale)
+
+    def adjoint(self, X, m):
+        return self._run(X, m, True)
+
+
 def householder_qr(Y):
     Y = _fortran(Y)
     n, l = Y.shape

@@ -477,3 +477,87 @@ def test_philox_gaussians_moments():
     assert abs(z.var() - 1.0) < 5.0 * np.sqrt(2.0 / z.size)
     assert abs(np.mean(np.abs(z) > 2.0) - 0.0455) < 0.002
     assert not np.array_equal(philox.randn(8, 2024, 3), philox.randn(8, 2024, 4))
+
+
+# --------------------------------------------------------------------------
+# SDIRK fine steppers (Sec. 4, effect of the time discretisation)
+# --------------------------------------------------------------------------
+def _R(method, z):
+    """Stability functions of the two tableaus, worked out by hand from
+    y' = lambda y: SDIRK2 (2 - 2z - z^2) / (2 (1 - z)^2); SDIRK2-L
+    (1 + (1 - 2 gamma) z) / (1 - gamma z)^2, z = lambda dt."""
+    if method == "sdirk2":
+        return (2 - 2 * z - z * z) / (2 * (1 - z) ** 2)
+    g = (2 - math.sqrt(2)) / 2
+    return (1 + (1 - 2 * g) * z) / (1 - g * z) ** 2
+
+
+@pytest.mark.parametrize("method", ["sdirk2", "sdirk2l"])
+def test_sdirk_eigenpairs(ora, method):
+    """S^m v = R(-dt lambda)^m v on the 1D heat sine modes and on the 2D
+    upwind operator's right eigenvectors; the adjoint on its left ones.
+    SDIRK2 is not L-stable (|R| -> 1/2 for the stiffest modes), SDIRK2-L is."""
+    P = inputs.heat1d()
+    st = ora.Stepper(method, **P.op_params())
+    x = P.grid()[0]
+    h = 1.0 / 256
+    m = 4
+    for j in (1, 2, 7, 40, 128, 255):
+        lam = 4 / h ** 2 * math.sin(j * math.pi * h / 2) ** 2
+        mu = _R(method, -P.dt * lam) ** m
+        v = np.sin(j * math.pi * x)
+        assert np.linalg.norm(st.fine(v, m)[:, 0] - mu * v) <= 1e-12 * np.linalg.norm(v), j
+        assert np.linalg.norm(st.adjoint(v, m)[:, 0] - mu * v) <= 1e-12 * np.linalg.norm(v), j
+    zs = -P.dt * 4 / h ** 2
+    assert abs(_R("sdirk2", 1e6 * zs) + 0.5) < 1e-5 and abs(_R("sdirk2l", 1e6 * zs)) < 1e-5
+    nx, nu, c, dt, beta = 15, 1.0, 1.5, 1.0 / 512, (20.0, -10.0)
+    hh = 1.0 / (nx + 1)
+    st = ora.Stepper(method, 2, nx, nu, beta, c, dt)
+    lx, rx, lfx = _axis_eig(nx, nu, beta[0], hh)
+    ly, ry, lfy = _axis_eig(nx, nu, beta[1], hh)
+    for (j, l) in [(0, 0), (4, 6), (14, 14)]:
+        mu = _R(method, -dt * (lx[j] + ly[l] + c)) ** 3
+        v, w = np.kron(ry[l], rx[j]), np.kron(lfy[l], lfx[j])
+        assert np.linalg.norm(st.fine(v, 3)[:, 0] - mu * v) <= 1e-12 * np.linalg.norm(v)
+        assert np.linalg.norm(st.adjoint(w, 3)[:, 0] - mu * w) <= 1e-12 * np.linalg.norm(w)
+
+
+@pytest.mark.parametrize("method,order", [("sdirk2", 2), ("sdirk2l", 2)])
+def test_sdirk_second_order_with_source(ora, method, order):
+    """On the sine mode j = 2 with f = sin(2 pi x) cos(2 pi t) the amplitude
+    solves y' = -lambda y + cos(2 pi t); halving dt divides the error at
+    t = 1/8 by about 2^order.  This fixes the stage time levels c_i of the
+    source (a wrong level drops the order to 1)."""
+    h = 1.0 / 256
+    lam = 4 / h ** 2 * math.sin(2 * math.pi * h / 2) ** 2
+    T = 1.0 / 8
+    w2 = 2 * math.pi
+    # exact: y(0) = 1
+    A = lam / (lam ** 2 + w2 ** 2)
+    B = w2 / (lam ** 2 + w2 ** 2)
+    exact = (1 - A) * math.exp(-lam * T) + A * math.cos(w2 * T) + B * math.sin(w2 * T)
+    errs = []
+    for m in (32, 64, 128):
+        dt = T / m
+        st = ora.Stepper(method, 1, 255, 1.0, (0.0, 0.0), 0.0, dt)
+        x = np.arange(1, 256) * h
+        v = np.sin(w2 * x)
+        fsc = np.array([[math.cos(w2 * (j * dt + st.cs[i] * dt)) for j in range(m) for i in range(2)]])
+        out = st.fine(v, m, v, None, fsc)[:, 0]
+        y = out @ v / (v @ v)
+        errs.append(abs(y - exact))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 2 ** order * 0.8 < r1 < 2 ** order * 1.25 and 2 ** order * 0.8 < r2 < 2 ** order * 1.25, (errs, r1, r2)
+
+
+@pytest.mark.parametrize("method", ["sdirk2", "sdirk2l"])
+def test_sdirk_affine_and_adjoint_dot(ora, method):
+    P = inputs.tiny2d(nx=9)
+    st = ora.Stepper(method, **P.op_params())
+    r = np.random.default_rng(3)
+    X, Yv = r.standard_normal((P.n, 3)), r.standard_normal((P.n, 3))
+    f = P.source()
+    fsc = r.standard_normal((3, 2 * P.m))
+    FX, F0, TX = st.fine(X, P.m, f, None, fsc), st.fine(np.zeros((P.n, 3)), P.m, f, None, fsc), st.fine(X, P.m)
+    assert np.abs(FX - TX - F0).max() <= 1e-13 * np.abs(FX).max()
+    assert np.allclose(np.sum(TX * Yv, 0), np.sum(X * st.adjoint(Yv, P.m), 0), rtol=1e-12, atol=1e-15)
