@@ -137,8 +137,28 @@ enum { LRPR_STORE_F64 = 1, LRPR_STORE_F32 = 2, LRPR_STORE_MIRROR = 4, LRPR_STORE
  * LRPR_ERR_ARG (bad descriptor or mask), LRPR_ERR_ZERO_PIVOT,
  * LRPR_ERR_NOMEM.  Synchronises the stream. */
 lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lrpr_fac *out);
+
+/* Fine time steppers (the paper's study of the time discretisation, Sec. 4:
+ * two-stage SDIRK methods beside implicit Euler):
+ *   LRPR_STEP_EULER   implicit Euler (what lrpr_factor builds);
+ *   LRPR_STEP_SDIRK2  tableau c = (1, 0), a = [[1, 0], [-1, 1]], b = (1/2, 1/2):
+ *                     both stages solve with I + dt A, so the factor is the
+ *                     implicit-Euler one;
+ *   LRPR_STEP_SDIRK2L tableau c = (g, 1), a = [[g, 0], [1-g, g]], b = (1-g, g),
+ *                     g = (2 - sqrt 2)/2 (L-stable): the factor is of I + g dt A.
+ * A factor made with lrpr_factor_stepper carries its stepper: every sweep,
+ * rSVD build and Parareal solve on it takes nsteps steps of that method (two
+ * stage solves per step), and its source time factors hold two values per
+ * step, phi(t_j + c_1 dt) then phi(t_j + c_2 dt), so a column's fscale row
+ * has 2*nsteps entries (lrpr_parareal_solve: N x 2*nsteps).  The adjoint of
+ * a step is the same two-stage recurrence with M^T.  The factors of one call
+ * must share a stepper.  op->dt is the step size dt.  Errors: as
+ * lrpr_factor; LRPR_ERR_ARG for an unknown stepper. */
+enum { LRPR_STEP_EULER = 0, LRPR_STEP_SDIRK2 = 1, LRPR_STEP_SDIRK2L = 2 };
+lrpr_status lrpr_factor_stepper(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, int stepper,
+                                lrpr_fac *out);
 void lrpr_factor_destroy(lrpr_fac f);
-/* n = unknowns, bw = half-bandwidth, dt = step. */
+/* n = unknowns, bw = half-bandwidth, dt = step (of the factor's stepper). */
 lrpr_status lrpr_factor_info(lrpr_fac f, int64_t *n, int *bw, double *dt);
 /* Copy the FP64 band LU (kept with LRPR_STORE_F64) to host memory:
  * lu_host is n x (2*bw+1) row-major,
@@ -312,7 +332,8 @@ typedef struct lrpr_server_s *lrpr_server;
 typedef struct {
     lrpr_coarse C;          /* coarse propagators of the operator's N slices */
     const lrpr_fac *F;      /* host array of N factor handles (may alias one;
-                               must keep FP64 tiles); read at create time */
+                               must keep FP64 tiles, implicit-Euler stepper);
+                               read at create time */
     int nsteps;             /* implicit-Euler steps per slice */
     const double *fscale;   /* device, N*nsteps source time factors (as in
                                lrpr_parareal_solve) or NULL (= 1); copied */

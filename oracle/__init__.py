@@ -293,6 +293,26 @@ def rsvd(op: Operator, m: int, k: int, p: int, Omega, q: int = 0):
     return Uk, S, Vk
 
 
+def rsvd_general(op, m: int, k: int, p: int, Omega):
+    """Randomized SVD (Sec. 2.1, steps 1-6) through the operator's own fine
+    and adjoint maps (for the SDIRK steppers): Y = T Omega, Y = Q R, Z = T^T Q,
+    Z = Qz Rz, Rz^T = Uh diag(S) Vh^T, Uk = Q Uh[:, :k], Vk = Qz Vh[:, :k], the
+    pairs signed as in rsvd.  Returns (Uk, S_all, Vk)."""
+    Y = op.fine(np.asarray(Omega, np.float64), m)
+    Q, _ = householder_qr(Y)
+    Z = op.adjoint(Q, m)
+    Qz, Rz = householder_qr(Z)
+    Uh, S, Vh = jacobi_svd(np.asfortranarray(Rz.T))
+    Uk = Q @ Uh[:, :k]
+    Vk = Qz @ Vh[:, :k]
+    for r in range(k):
+        im = int(np.argmax(np.abs(Uk[:, r])))
+        if Uk[im, r] < 0:
+            Uk[:, r] *= -1.0
+            Vk[:, r] *= -1.0
+    return Uk, S, Vk
+
+
 def rsvd_two_sided(op: Operator, m: int, k: int, p: int, Omega, Psi):
     """Randomized SVD with the adjoint on independent test vectors Psi
     (Sec. 2.2): T ~ Q (Psi^T Q)^{-1} (T^T Psi)^T with Q = orth(T Omega),
@@ -358,7 +378,8 @@ def build_coarse(slices, k, p, omegas):
     """Set up all coarse solvers: rSVD of every F_n' and b_n = F_n 0."""
     for s, om in zip(slices, omegas):
         if k + p > 0:
-            s.Uk, s.S, s.Vk = rsvd(s.op, s.m, k, p, om)
+            build = rsvd if isinstance(s.op, Operator) else rsvd_general
+            s.Uk, s.S, s.Vk = build(s.op, s.m, k, p, om)
         else:
             s.Uk = np.zeros((s.op.n, 0))
             s.Vk = np.zeros((s.op.n, 0))

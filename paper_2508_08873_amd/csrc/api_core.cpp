@@ -249,6 +249,7 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
     f->NT = (int)((n + TILE - 1) / TILE);
     f->nb = (bw + TILE - 1) / TILE;
     f->mask = store_mask;
+    f->dt_step = op->dt;
     double *band = nullptr;
     void *scratch = nullptr;
     hipError_t e;
@@ -316,7 +317,21 @@ lrpr_status lrpr_factor_info(lrpr_fac f, int64_t *n, int *bw, double *dt) {
     if (!f) return LRPR_ERR_ARG;
     if (n) *n = f->n;
     if (bw) *bw = f->bw;
-    if (dt) *dt = f->op.dt;
+    if (dt) *dt = f->dt_step;
+    return LRPR_OK;
+}
+
+lrpr_status lrpr_factor_stepper(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, int stepper,
+                                lrpr_fac *out) {
+    if (!ctx || !op || !out) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_stepper: null argument");
+    if (stepper != LRPR_STEP_EULER && stepper != LRPR_STEP_SDIRK2 && stepper != LRPR_STEP_SDIRK2L)
+        return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_stepper: unknown stepper");
+    lrpr_op_desc o = *op;
+    if (stepper == LRPR_STEP_SDIRK2L) o.dt = op->dt * SDIRK2L_GAMMA;   // I + g dt A
+    lrpr_status r = lrpr_factor(ctx, &o, store_mask, out);
+    if (r != LRPR_OK) return r;
+    (*out)->stepper = stepper;
+    (*out)->dt_step = op->dt;
     return LRPR_OK;
 }
 
@@ -400,7 +415,8 @@ void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err);
 // Partitioned fine sweep (few column groups): per step, the L pass as local
 // solves of all blocks, chain, update; then the U pass the same way.
 static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels,
-                             const std::vector<SweepItem> &groups, int nsteps, bool f32, int max_nb) {
+                             const std::vector<SweepItem> &groups, int nsteps, bool f32, int max_nb, int step0,
+                             bool record) {
     hipStream_t st = ctx->stream;
     const size_t esz = f32 ? 4 : 8;
     // factor of every group (items were built panel by panel)
@@ -474,7 +490,7 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
             hipSuccess)
         return hipfail(ctx, e, "split upload");
     lrpr_ctx_s::ProfRec rec{};
-    if (ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
+    if (record && ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
         return hipfail(ctx, e, "profile event");
     const int ng = (int)sg.size();
     bool uni = max_nb == 8 || max_nb == 16 || max_nb == 32;
@@ -482,27 +498,26 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
     const int nr = uni ? (int)runs.size() : 0;
     const int2 *dr = uni ? d_runs : nullptr;
     for (int step = 0; step < nsteps; ++step) {
-        if ((e = launch_sweep(false, false, f32, nL, ctx->d_items, 1, max_nb, st, step, true)) != hipSuccess ||
+        if ((e = launch_sweep(false, false, f32, nL, ctx->d_items, 1, max_nb, st, step0 + step, true)) != hipSuccess ||
             (e = launch_split_chain(f32, false, ng, d_groups, max_nb, st, uni)) != hipSuccess ||
             (e = launch_split_update(f32, false, ng, d_groups, max_P, max_rows, st, max_nb, nr, dr)) != hipSuccess ||
-            (e = launch_sweep(false, false, f32, nL, ctx->d_items + nL, 1, max_nb, st, step, true)) != hipSuccess ||
+            (e = launch_sweep(false, false, f32, nL, ctx->d_items + nL, 1, max_nb, st, step0 + step, true)) != hipSuccess ||
             (e = launch_split_chain(f32, true, ng, d_groups, max_nb, st, uni)) != hipSuccess ||
             (e = launch_split_update(f32, true, ng, d_groups, max_P, max_rows, st, max_nb, nr, dr)) != hipSuccess)
             return hipfail(ctx, e, "split sweep");
     }
-    if (ctx->prof) {
+    if (record && ctx->prof) {
         if ((e = hipEventRecord(rec.b, st)) != hipSuccess) return hipfail(ctx, e, "profile event");
         ctx->prof_recs.push_back(rec);
     }
     return LRPR_OK;
 }
 
-// Validate panels and turn them into 16-column work items; launch one sweep.
-lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
-                      bool adjoint) {
-    if (!ctx) return LRPR_ERR_ARG;
-    if (npanels < 0 || (npanels > 0 && !panels) || nsteps < 0 || (prec != LRPR_F64 && prec != LRPR_F32))
-        return fail(ctx, LRPR_ERR_ARG, "sweep: invalid arguments");
+// Validate panels and turn them into 16-column work items; launch one sweep
+// of nsteps solve steps.  A column's source factors are fscale[c * fstride +
+// step0 + j], j < nsteps.  record: add a profile record for the launch.
+static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
+                                  bool adjoint, int fstride, int step0, bool record) {
     const bool f32 = prec == LRPR_F32;
     std::vector<SweepItem> items;
     int max_nb = 1;
@@ -527,12 +542,12 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
             it.passes = 3;
             it.r0 = 0;
             it.r1 = P.F->NT;
-            it.fsteps = nsteps;
+            it.fsteps = fstride;
             it.pad_ = 0;
             it.f = adjoint ? nullptr : P.f;
             it.ldf = P.ldf;
             it.fcol = (!adjoint && P.f && P.fcol) ? P.fcol + c0 : nullptr;
-            it.fscale = (!adjoint && P.f && P.fscale) ? P.fscale + (size_t)c0 * nsteps : nullptr;
+            it.fscale = (!adjoint && P.f && P.fscale) ? P.fscale + (size_t)c0 * fstride : nullptr;
             items.push_back(it);
         }
     }
@@ -545,19 +560,99 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
     bool split = !adjoint && (int)items.size() <= SPLIT_MAX_GROUPS && max_nb <= (f32 ? 64 : 32);
     for (int p = 0; p < npanels && split; ++p)
         split = panels[p].w == 0 || (panels[p].F->P >= 2 && (f32 ? panels[p].F->s32.S : panels[p].F->s64.S));
-    if (split) return run_split(ctx, npanels, panels, items, nsteps, f32, max_nb);
+    if (split) return run_split(ctx, npanels, panels, items, nsteps, f32, max_nb, step0, record);
     lrpr_status st = ensure_items(ctx, items.size());
     if (st != LRPR_OK) return st;
     e = hipMemcpyAsync(ctx->d_items, items.data(), items.size() * sizeof(SweepItem),
                        hipMemcpyHostToDevice, ctx->stream);
     if (e != hipSuccess) return hipfail(ctx, e, "sweep item upload");
     lrpr_ctx_s::ProfRec rec{};
-    if (ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
+    if (record && ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
         return hipfail(ctx, e, "profile event");
-    e = launch_sweep(adjoint, strided, f32, (int)items.size(), ctx->d_items, nsteps, max_nb, ctx->stream);
+    e = launch_sweep(adjoint, strided, f32, (int)items.size(), ctx->d_items, nsteps, max_nb, ctx->stream, step0);
     if (e != hipSuccess) return hipfail(ctx, e, "sweep launch");
-    if (ctx->prof) {
+    if (record && ctx->prof) {
         if ((e = hipEventRecord(rec.b, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "profile event");
+        ctx->prof_recs.push_back(rec);
+    }
+    return LRPR_OK;
+}
+
+// Sweeps of nsteps time steps of the panels' common stepper.  Implicit
+// Euler: one solve per step.  The two-stage SDIRK methods (both with a_11 =
+// a_22 = g, the factored matrix M = I + g dt A): with stage values U_i
+// (M U_i = r_i), the tableaus give
+//   stage 1: r_1 = u + g dt f(t + c_1 dt)
+//   stage 2: r_2 = u + beta (U_1 - u) + g dt f(t + c_2 dt)
+//   step:    u_new = U_1 + (U_2 - u) / 2 (SDIRK2),  u_new = U_2 (SDIRK2-L)
+// with beta = -1 (SDIRK2) and (1 - g) / g (SDIRK2-L).  Every linear map of
+// a step is a rational function of M, so the adjoint runs the same
+// combinations with M^T.
+lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
+                      bool adjoint) {
+    if (!ctx) return LRPR_ERR_ARG;
+    if (npanels < 0 || (npanels > 0 && !panels) || nsteps < 0 || (prec != LRPR_F64 && prec != LRPR_F32))
+        return fail(ctx, LRPR_ERR_ARG, "sweep: invalid arguments");
+    int stepper = -1;
+    for (int p = 0; p < npanels; ++p) {
+        if (!panels[p].F) return fail(ctx, LRPR_ERR_ARG, "sweep: panel with null factor");
+        if (panels[p].w <= 0) continue;
+        if (stepper >= 0 && panels[p].F->stepper != stepper)
+            return fail(ctx, LRPR_ERR_ARG, "sweep: the panels' factors use different time steppers");
+        stepper = panels[p].F->stepper;
+    }
+    if (stepper <= 0) return run_sweep_core(ctx, npanels, panels, nsteps, prec, adjoint, nsteps, 0, true);
+    if (nsteps == 0) return LRPR_OK;
+    const bool f32 = prec == LRPR_F32;
+    const size_t esz = f32 ? 4 : 8;
+    const double g = stepper == LRPR_STEP_SDIRK2L ? SDIRK2L_GAMMA : 1.0;
+    const double beta = stepper == LRPR_STEP_SDIRK2L ? (1.0 - g) / g : -1.0;
+    // stage workspaces: u and U_1 of every panel
+    std::vector<size_t> off(npanels + 1, 0);
+    for (int p = 0; p < npanels; ++p) off[p + 1] = off[p] + (size_t)panels[p].F->n * std::max(panels[p].w, 0);
+    hipError_t e = hipSetDevice(ctx->dev);
+    if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+    char *Wu = (char *)ws_get(ctx, "sdirk_u", off[npanels] * esz, &e);
+    char *Wv = Wu ? (char *)ws_get(ctx, "sdirk_v", off[npanels] * esz, &e) : nullptr;
+    if (!Wu || !Wv) return hipfail(ctx, e == hipSuccess ? hipErrorOutOfMemory : e, "SDIRK workspace");
+    hipStream_t st = ctx->stream;
+    // out = ca a + cb b + cc c on every panel; an operand is the panel (X) or a workspace
+    enum { OX = 0, OU = 1, OV = 2 };
+    auto comb = [&](int out, int a, double ca, int b, double cb, int c, double cc) -> hipError_t {
+        for (int p = 0; p < npanels; ++p) {
+            const lrpr_panel &P = panels[p];
+            if (P.w <= 0) continue;
+            auto ptr = [&](int o) -> void * {
+                return o == OX ? P.X : (o == OU ? Wu : Wv) + off[p] * esz;
+            };
+            auto ld = [&](int o) -> int64_t { return o == OX ? P.ldx : P.F->n; };
+            hipError_t ee = launch_combine3(f32, ptr(out), ld(out), ptr(a), ld(a), ca, b < 0 ? nullptr : ptr(b),
+                                            b < 0 ? 0 : ld(b), cb, c < 0 ? nullptr : ptr(c), c < 0 ? 0 : ld(c), cc,
+                                            P.F->n, P.w, st);
+            if (ee != hipSuccess) return ee;
+        }
+        return hipSuccess;
+    };
+    lrpr_ctx_s::ProfRec rec{};
+    if (ctx->prof) {
+        if ((e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
+            return hipfail(ctx, e, "profile event");
+        rec.flops *= 2;   // two stage solves per step
+    }
+    const int fstride = 2 * nsteps;
+    for (int j = 0; j < nsteps; ++j) {
+        lrpr_status r;
+        if ((e = comb(OU, OX, 1.0, -1, 0.0, -1, 0.0)) != hipSuccess) return hipfail(ctx, e, "SDIRK copy");
+        if ((r = run_sweep_core(ctx, npanels, panels, 1, prec, adjoint, fstride, 2 * j, false)) != LRPR_OK) return r;
+        if ((e = comb(OV, OX, 1.0, -1, 0.0, -1, 0.0)) != hipSuccess) return hipfail(ctx, e, "SDIRK copy");
+        if ((e = comb(OX, OU, 1.0 - beta, OV, beta, -1, 0.0)) != hipSuccess) return hipfail(ctx, e, "SDIRK stage");
+        if ((r = run_sweep_core(ctx, npanels, panels, 1, prec, adjoint, fstride, 2 * j + 1, false)) != LRPR_OK)
+            return r;
+        if (stepper == LRPR_STEP_SDIRK2 && (e = comb(OX, OX, 0.5, OV, 1.0, OU, -0.5)) != hipSuccess)
+            return hipfail(ctx, e, "SDIRK step");
+    }
+    if (ctx->prof) {
+        if ((e = hipEventRecord(rec.b, st)) != hipSuccess) return hipfail(ctx, e, "profile event");
         ctx->prof_recs.push_back(rec);
     }
     return LRPR_OK;

@@ -476,6 +476,8 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
     for (int s = 0; s < N; ++s) {
         if (!F[s] || F[s]->n != n || c->n[s] != n)
             return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: slices must share one size n");
+        if (F[s]->stepper != F[0]->stepper)
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: slices must share one time stepper");
         if ((f32 && !(F[s]->mask & LRPR_STORE_F32)) || (!f32 && !(F[s]->mask & LRPR_STORE_F64)))
             return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: factor lacks the requested precision");
         kmax = std::max(kmax, c->k[s]);
@@ -493,7 +495,8 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
     void *X = W("pr_x", esz * blk * N);
     void *fsrc = f ? W("pr_f", esz * blk) : nullptr;
     int *fcol = (int *)W("pr_fcol", sizeof(int) * (size_t)N * nreq);
-    double *fsc = (double *)W("pr_fsc", sizeof(double) * (size_t)N * nreq * nsteps);
+    const int fs = fac_stages(F[0]) * nsteps;      // source time factors per slice and column
+    double *fsc = (double *)W("pr_fsc", sizeof(double) * (size_t)N * nreq * fs);
     const int64_t nch = lr_chunks(n);
     double *part = (double *)W("pr_part", sizeof(double) * (size_t)lr_part_elems(n, kmax, nreq));
     double *incpart = (double *)W("pr_incpart", sizeof(double) * (size_t)nch * nreq);
@@ -505,10 +508,10 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
 
     // per-column source index and time factors: column (slice s, request r)
     std::vector<int> hfcol((size_t)N * nreq);
-    std::vector<double> hfsc((size_t)N * nreq * nsteps, 1.0);
+    std::vector<double> hfsc((size_t)N * nreq * fs, 1.0);
     std::vector<double> hphi;
     if (fscale) {
-        hphi.resize((size_t)N * nsteps);
+        hphi.resize((size_t)N * fs);
         CK(hipMemcpyAsync(hphi.data(), fscale, sizeof(double) * hphi.size(), hipMemcpyDeviceToHost, st), "fscale");
         CK(hipStreamSynchronize(st), "sync");
     }
@@ -516,7 +519,7 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
         for (int q = 0; q < nreq; ++q) {
             hfcol[(size_t)s * nreq + q] = q;
             if (fscale)
-                for (int j = 0; j < nsteps; ++j) hfsc[((size_t)s * nreq + q) * nsteps + j] = hphi[(size_t)s * nsteps + j];
+                for (int j = 0; j < fs; ++j) hfsc[((size_t)s * nreq + q) * fs + j] = hphi[(size_t)s * fs + j];
         }
     CK(upload(fcol, hfcol, st), "fcol");
     CK(upload(fsc, hfsc, st), "fscale");
@@ -538,7 +541,7 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
         p.f = fsrc;
         p.ldf = n;
         p.fcol = fsrc ? fcol + (size_t)s * nreq : nullptr;
-        p.fscale = fsrc ? fsc + (size_t)s * nreq * nsteps : nullptr;
+        p.fscale = fsrc ? fsc + (size_t)s * nreq * fs : nullptr;
         P.push_back(p);
     }
     // b_n = F_n 0

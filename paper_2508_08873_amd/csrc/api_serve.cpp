@@ -270,6 +270,9 @@ lrpr_status lrpr_server_create(lrpr_ctx ctx, int nops, const lrpr_serve_op *ops,
             if (!d.F[s] || d.F[s]->n != d.C->n[0] || d.C->n[s] != d.C->n[0] || !(d.F[s]->mask & LRPR_STORE_F64) ||
                 d.F[s]->dev != ctx->dev)
                 return fail(ctx, LRPR_ERR_ARG, "lrpr_server_create: slice factors must share n and keep FP64 tiles");
+        for (int s = 0; s < d.C->nslices; ++s)
+            if (d.F[s]->stepper != LRPR_STEP_EULER)
+                return fail(ctx, LRPR_ERR_ARG, "lrpr_server_create: served operators use implicit-Euler factors");
     }
     lrpr_server srv = new (std::nothrow) lrpr_server_s();
     if (!srv) return fail(ctx, LRPR_ERR_NOMEM, "lrpr_server_create: host allocation");

@@ -3,6 +3,8 @@
 // def_Parareal; G_n' from eq. spectral_G).  Everything here accumulates in
 // FP64; inputs of the range finder may be FP32.
 #include "lrpr_internal.h"
+#include <algorithm>
+
 #include "dense.h"
 
 namespace lrpr {
@@ -773,6 +775,22 @@ __global__ __launch_bounds__(256) void k_small_inv_t(const int *ls, const double
     }
 }
 
+// out = ca a + cb b + cc c, column by column (the stage combinations of the
+// SDIRK steppers)
+template <typename T>
+__global__ __launch_bounds__(256) void k_combine3(T *out, int64_t ldo, const T *a, int64_t lda, T ca, const T *b,
+                                                  int64_t ldb, T cb, const T *c, int64_t ldc, T cc, int64_t n, int w) {
+    const int64_t total = n * w;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t col = e / n, i = e - col * n;
+        T v = ca * a[i + col * lda];
+        if (b) v += cb * b[i + col * ldb];
+        if (c) v += cc * c[i + col * ldc];
+        out[i + col * ldo] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -904,6 +922,21 @@ hipError_t launch_cross_gram(const double *V, const double *X, int64_t n, int k,
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lr_coef, dim3((nk + 63) / 64), dim3(64 * LR_RED), 0, s, (const double *)part, (int64_t)nch,
                        nk, w, ones, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine3(bool f32, void *out, int64_t ldo, const void *a, int64_t lda, double ca, const void *b,
+                           int64_t ldb, double cb, const void *c, int64_t ldc, double cc, int64_t n, int w,
+                           hipStream_t s) {
+    const int64_t total = n * w;
+    if (total <= 0) return hipSuccess;
+    unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+    if (f32)
+        hipLaunchKernelGGL(k_combine3<float>, dim3(blocks), dim3(256), 0, s, (float *)out, ldo, (const float *)a, lda,
+                           (float)ca, (const float *)b, ldb, (float)cb, (const float *)c, ldc, (float)cc, n, w);
+    else
+        hipLaunchKernelGGL(k_combine3<double>, dim3(blocks), dim3(256), 0, s, (double *)out, ldo, (const double *)a,
+                           lda, ca, (const double *)b, ldb, cb, (const double *)c, ldc, cc, n, w);
     return hipGetLastError();
 }
 

@@ -119,6 +119,8 @@ struct lrpr_factor_s {
     int bw = 0;
     int NT = 0, nb = 0;
     int mask = 0;                  // LRPR_STORE_* bits
+    int stepper = 0;               // LRPR_STEP_*; the factored matrix is I + a_11 dt A
+    double dt_step = 0;            // the step dt (op.dt is a_11 dt)
     double *lu = nullptr;          // FP64 band LU, n x (2bw+1) row-major (kept with LRPR_STORE_F64)
     lrpr::TileSet t64, t32;
     // partitioned forward solves (LRPR_STORE_SPLIT): P blocks, starts blk
@@ -158,6 +160,10 @@ struct lrpr_ctx_s {
 
 namespace lrpr {
 
+constexpr double SDIRK2L_GAMMA = 0.29289321881345247560;   // (2 - sqrt 2) / 2
+// source time factors per step of a factor's stepper (one per stage)
+inline int fac_stages(const lrpr_factor_s *f) { return f->stepper == 0 ? 1 : 2; }
+
 // error helper: record message in ctx and return status
 lrpr_status fail(lrpr_ctx ctx, lrpr_status st, const std::string &msg);
 
@@ -176,6 +182,11 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
 // pass (same code, launched as k_sweep_local)
 hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const SweepItem *d_items, int nsteps,
                         int max_nb, hipStream_t s, int step0 = 0, bool local = false);
+// out = ca a + cb b + cc c on an n x w block (column-major, own leading
+// dimensions; c may be null), element type of the precision (dense.hip)
+hipError_t launch_combine3(bool f32, void *out, int64_t ldo, const void *a, int64_t lda, double ca, const void *b,
+                           int64_t ldb, double cb, const void *c, int64_t ldc, double cc, int64_t n, int w,
+                           hipStream_t s);
 // Gaussian fill, Philox4x32-10 + Box-Muller (rng.hip)
 hipError_t launch_randn(bool f32, void *dst, int64_t count, uint64_t seed, uint64_t stream, hipStream_t s);
 // partitioned passes (split.hip)

@@ -141,6 +141,13 @@ class Problem:
         t = self.t(n - 1) + (np.arange(self.m) + 1) * self.dt
         return self.phi(t)
 
+    def fscale_stages(self, n: int, cs) -> np.ndarray:
+        """phi at the stage times of a two-stage stepper with abscissae cs in
+        slice n: phi(t_{n-1} + (j + c_i) dt), j = 0..m-1, i = 0, 1 (step order)."""
+        j = np.repeat(np.arange(self.m), len(cs))
+        c = np.tile(np.asarray(cs, np.float64), self.m)
+        return self.phi(self.t(n - 1) + (j + c) * self.dt)
+
     def omega(self, n: int, dtype=np.float64) -> np.ndarray:
         """Gaussian test matrix Omega_n (n x l, column-major) of slice n."""
         r = rng(self.seed, "omega", self.pid, n)

@@ -18,7 +18,7 @@ LRPR_F64, LRPR_F32 = 0, 1
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_ZERO_PIVOT", 4: "ERR_QR_BREAKDOWN",
           5: "ERR_NOCONV", 6: "ERR_NONFINITE", 7: "ERR_HIP"}
 EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_last_error",
-           "lrpr_factor", "lrpr_factor_destroy", "lrpr_factor_info", "lrpr_factor_copy_lu",
+           "lrpr_factor", "lrpr_factor_stepper", "lrpr_factor_destroy", "lrpr_factor_info", "lrpr_factor_copy_lu",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build", "lrpr_rsvd_build_q",
            "lrpr_rsvd_build_two_sided",
            "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_parareal_solve",
@@ -29,6 +29,8 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
 
 # lrpr_factor store_mask bits (include/lrpr.h)
 STORE_F64, STORE_F32, STORE_MIRROR, STORE_SPLIT = 1, 2, 4, 8
+# lrpr_factor_stepper steppers
+STEP_EULER, STEP_SDIRK2, STEP_SDIRK2L = 0, 1, 2
 
 
 class LrprError(RuntimeError):
@@ -79,6 +81,7 @@ def load():
     lib.lrpr_last_error.argtypes = [vp]
     lib.lrpr_last_error.restype = ctypes.c_char_p
     lib.lrpr_factor.argtypes = [vp, P(OpDesc), i32, P(vp)]
+    lib.lrpr_factor_stepper.argtypes = [vp, P(OpDesc), i32, i32, P(vp)]
     lib.lrpr_factor_destroy.argtypes = [vp]
     lib.lrpr_factor_destroy.restype = None
     lib.lrpr_factor_info.argtypes = [vp, P(i64), P(i32), P(dbl)]
@@ -169,11 +172,15 @@ class Context:
         return X
 
     # -- factor -----------------------------------------------------------
-    def factor(self, dim, nx, nu, beta, c, dt, store_mask=1):
+    def factor(self, dim, nx, nu, beta, c, dt, store_mask=1, stepper=STEP_EULER):
         d = OpDesc(dim, nx, float(nu), float(beta[0]), float(beta[1]) if dim == 2 else 0.0, float(c), float(dt))
         h = ctypes.c_void_p()
         self.sync_stream()
-        self._check(self.lib.lrpr_factor(self.h, ctypes.byref(d), int(store_mask), ctypes.byref(h)))
+        if stepper == STEP_EULER:
+            self._check(self.lib.lrpr_factor(self.h, ctypes.byref(d), int(store_mask), ctypes.byref(h)))
+        else:
+            self._check(self.lib.lrpr_factor_stepper(self.h, ctypes.byref(d), int(store_mask), int(stepper),
+                                                     ctypes.byref(h)))
         return Factor(self, h)
 
     # -- sweeps -----------------------------------------------------------

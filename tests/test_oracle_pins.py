@@ -561,3 +561,16 @@ def test_sdirk_affine_and_adjoint_dot(ora, method):
     FX, F0, TX = st.fine(X, P.m, f, None, fsc), st.fine(np.zeros((P.n, 3)), P.m, f, None, fsc), st.fine(X, P.m)
     assert np.abs(FX - TX - F0).max() <= 1e-13 * np.abs(FX).max()
     assert np.allclose(np.sum(TX * Yv, 0), np.sum(X * st.adjoint(Yv, P.m), 0), rtol=1e-12, atol=1e-15)
+
+
+def test_rsvd_general_equals_rsvd(ora):
+    """The rSVD through an operator's own fine / adjoint maps (used for the
+    SDIRK steppers) reproduces the pinned band rSVD on an implicit-Euler
+    operator."""
+    P = inputs.tiny2d(nx=12, m=4, k=6, p=3)
+    op = ora.Operator(**P.op_params())
+    Om = P.omega(1)
+    U1, S1, V1 = ora.rsvd(op, P.m, P.k, P.p, Om)
+    U2, S2, V2 = ora.rsvd_general(op, P.m, P.k, P.p, Om)
+    assert np.abs(S1 - S2).max() <= 1e-13 * S1[0]
+    assert np.linalg.norm((U1 * S1[:P.k]) @ V1.T - (U2 * S2[:P.k]) @ V2.T) <= 1e-13 * S1[0]
