@@ -250,6 +250,42 @@ def rsvd_variants(ctx, lrpr, P, prec, Om):
     return out
 
 
+def stepper_study(ctx, lrpr, P, prec, Om):
+    """The paper's study of the time discretisation on this workload:
+    implicit Euler, SDIRK2 and SDIRK2-L as fine steppers (same Omega): rSVD
+    build time, eps = max_n sigma_{n,k+1} and sigma_{n,1} of the transfer
+    operators, Parareal iterations and time to the bench tolerance."""
+    import torch
+    fp = 0 if prec == "f64" else 1
+    tol = P.tol if prec == "f64" else TOL_F32
+    u0 = lrpr.colmajor(torch.from_numpy(P.u0().reshape(-1, 1)).to("cuda"))
+    f = lrpr.colmajor(torch.from_numpy(P.source().reshape(-1, 1)).to("cuda"))
+    cs = {lrpr.STEP_SDIRK2: (1.0, 0.0), lrpr.STEP_SDIRK2L: ((2 - math.sqrt(2)) / 2, 1.0)}
+    out = {}
+    for name, stp in (("euler", lrpr.STEP_EULER), ("sdirk2", lrpr.STEP_SDIRK2), ("sdirk2l", lrpr.STEP_SDIRK2L)):
+        F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
+                       store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR | lrpr.STORE_SPLIT, stepper=stp)
+        if stp == lrpr.STEP_EULER:
+            fsc = np.concatenate([P.fscale(s) for s in range(1, P.N + 1)])
+        else:
+            fsc = np.concatenate([P.fscale_stages(s, cs[stp]) for s in range(1, P.N + 1)])
+        fsc = torch.from_numpy(fsc).to("cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        coarse = ctx.rsvd_build([(F, P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, fp)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = ctx.parareal_solve(coarse, [F] * P.N, P.m, u0, f, fsc, tol=tol, fine_prec=fp)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sig = np.array(coarse.sigma).reshape(P.N, P.l)
+        out[name] = {"rsvd_s": t1 - t0, "parareal_s": t2 - t1, "parareal_iters": int(res["iters"][0]),
+                     "eps_max_sigma_k1": float(sig[:, P.k].max()), "delta_max_sigma_1": float(sig[:, 0].max())}
+        coarse.close()
+        F.close()
+    return out
+
+
 def traffic_from_profile(prec):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary
     of this workload, if it was taken from the current sweep sources."""
@@ -391,6 +427,7 @@ def main():
                                 (sum(r["ms"] for r in r64["range"]) / 1000.0)}
     if not args.no_plain:
         res["range_finder_sweeps_separately"] = fwd_adj_rates(ctx, lrpr, P, prec)
+        res["fine_steppers"] = stepper_study(ctx, lrpr, P, prec, Om64 if prec == "f64" else Om64.to(torch.float32))
         res["rsvd_variants"] = rsvd_variants(
             ctx, lrpr, P, prec, Om64 if prec == "f64" else Om64.to(torch.float32))
         res["plain_per_rhs_fp64_rhs_steps_per_s"] = plain_per_rhs(ctx, lrpr, P)
