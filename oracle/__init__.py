@@ -257,6 +257,34 @@ class Stepper:
         return self._run(X, m, True)
 
 
+class StepSequence:
+    """m implicit-Euler steps with per-step operators, step j solving with
+    M_j = I + dt_j A_j (time-dependent coefficients inside a slice):
+    T = M_m^{-1} ... M_1^{-1}; the adjoint is T^T = M_1^{-T} ... M_m^{-T}.
+    The source of column c at step j is fscale[c, j] f[:, fcol[c]]."""
+
+    def __init__(self, ops):
+        self.ops = [Operator(**o) for o in ops]
+        self.n = self.ops[0].n
+
+    def fine(self, X, m, f=None, fcol=None, fscale=None):
+        X = np.array(X, dtype=np.float64, copy=True)
+        if X.ndim == 1:
+            X = X.reshape(-1, 1)
+        w = X.shape[1]
+        if fscale is not None:
+            fscale = np.broadcast_to(np.asarray(fscale, np.float64), (w, m))
+        for j in range(m):
+            X = self.ops[j].fine(X, 1, f, fcol, None if fscale is None else fscale[:, j:j + 1])
+        return X
+
+    def adjoint(self, X, m):
+        X = np.array(X, dtype=np.float64, copy=True)
+        for j in reversed(range(m)):
+            X = self.ops[j].adjoint(X, 1)
+        return X
+
+
 def householder_qr(Y):
     Y = _fortran(Y)
     n, l = Y.shape

@@ -141,6 +141,19 @@ class Problem:
         t = self.t(n - 1) + (np.arange(self.m) + 1) * self.dt
         return self.phi(t)
 
+    def step_ops(self, n: int) -> list:
+        """Operator parameters of every implicit-Euler step of slice n
+        (1-based) for per-step operators: nu at the step's end time
+        t_{n-1} + (j+1) dt when nu depends on t, else the slice's."""
+        out = []
+        for j in range(self.m):
+            d = self.op_params(n)
+            if self.nu_of_t:
+                t = self.t(n - 1) + (j + 1) * self.dt
+                d["nu"] = 1.0 + 0.5 * math.sin(2.0 * math.pi * t)
+            out.append(d)
+        return out
+
     def fscale_stages(self, n: int, cs) -> np.ndarray:
         """phi at the stage times of a two-stage stepper with abscissae cs in
         slice n: phi(t_{n-1} + (j + c_i) dt), j = 0..m-1, i = 0, 1 (step order)."""

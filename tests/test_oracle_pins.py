@@ -574,3 +574,28 @@ def test_rsvd_general_equals_rsvd(ora):
     U2, S2, V2 = ora.rsvd_general(op, P.m, P.k, P.p, Om)
     assert np.abs(S1 - S2).max() <= 1e-13 * S1[0]
     assert np.linalg.norm((U1 * S1[:P.k]) @ V1.T - (U2 * S2[:P.k]) @ V2.T) <= 1e-13 * S1[0]
+
+
+def test_step_sequence_brute_force(ora):
+    """Per-step operators (time-dependent coefficients inside a slice): the
+    sequence map is M_m^{-1} ... M_1^{-1} and its adjoint the transposed
+    product, against dense inverses of the steps' matrices on a tiny grid;
+    with a source, x <- M_j^{-1} (x + dt_j phi_j f) step by step."""
+    P = inputs.tiny2d(nx=7, m=4, nu_of_t=True, T=1.0)
+    ops = P.step_ops(2)
+    assert len({o["nu"] for o in ops}) == P.m       # the coefficient changes every step
+    seq = ora.StepSequence(ops)
+    Ms = [ora.Operator(**o).dense() for o in ops]
+    T = np.eye(P.n)
+    for M in Ms:
+        T = np.linalg.solve(M, T)
+    r = np.random.default_rng(5)
+    X = r.standard_normal((P.n, 3))
+    assert np.abs(seq.fine(X, P.m) - T @ X).max() <= 1e-13 * np.abs(T @ X).max()
+    assert np.abs(seq.adjoint(X, P.m) - T.T @ X).max() <= 1e-13 * np.abs(T.T @ X).max()
+    f = P.source()
+    fsc = r.standard_normal((3, P.m))
+    Y = X.copy()
+    for j, M in enumerate(Ms):
+        Y = np.linalg.solve(M, Y + P.dt * f[:, None] * fsc[:, j][None, :])
+    assert np.abs(seq.fine(X, P.m, f, None, fsc) - Y).max() <= 1e-13 * np.abs(Y).max()
