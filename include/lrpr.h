@@ -154,9 +154,23 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
  * a step is the same two-stage recurrence with M^T.  The factors of one call
  * must share a stepper.  op->dt is the step size dt.  Errors: as
  * lrpr_factor; LRPR_ERR_ARG for an unknown stepper. */
-enum { LRPR_STEP_EULER = 0, LRPR_STEP_SDIRK2 = 1, LRPR_STEP_SDIRK2L = 2 };
+enum { LRPR_STEP_EULER = 0, LRPR_STEP_SDIRK2 = 1, LRPR_STEP_SDIRK2L = 2, LRPR_STEP_SEQUENCE = 3 };
 lrpr_status lrpr_factor_stepper(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, int stepper,
                                 lrpr_fac *out);
+
+/* Per-step operators inside a slice (time-dependent coefficients, the
+ * setting of the paper's later experiments, Sec. 4): one handle for m
+ * implicit-Euler steps whose step j solves with M_j = I + dt_j A_j, A_j and
+ * dt_j from ops[j] (all ops share dim and nx).  Each step is factored as by
+ * lrpr_factor with store_mask.  A sweep of nsteps <= m steps on the handle
+ * takes step j with M_j, j = 0..nsteps-1 (source time factor j of a column
+ * at step j, as for lrpr_factor); the adjoint is the transpose of that
+ * product, T^T = M_1^{-T} ... M_nsteps^{-T}: the transposed steps in reverse
+ * order.  rSVD builds and Parareal solves on such handles use this map
+ * (stepper LRPR_STEP_SEQUENCE; the server does not take them).  The handle
+ * owns its step factors (lrpr_factor_destroy frees them).  Errors: as
+ * lrpr_factor; LRPR_ERR_ARG for m < 1 or mismatched grids. */
+lrpr_status lrpr_factor_sequence(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, int store_mask, lrpr_fac *out);
 void lrpr_factor_destroy(lrpr_fac f);
 /* n = unknowns, bw = half-bandwidth, dt = step (of the factor's stepper). */
 lrpr_status lrpr_factor_info(lrpr_fac f, int64_t *n, int *bw, double *dt);

@@ -100,6 +100,8 @@ static hipError_t alloc_tiles(TileSet &t, int NT, int nb, size_t esz, bool mirro
 
 void lrpr_factor_destroy(lrpr_fac f) {
     if (!f) return;
+    for (lrpr_fac g : f->seq) lrpr_factor_destroy(g);
+    f->seq.clear();
     hipSetDevice(f->dev);
     hipDeviceSynchronize();
     if (f->lu) hipFree(f->lu);
@@ -318,6 +320,38 @@ lrpr_status lrpr_factor_info(lrpr_fac f, int64_t *n, int *bw, double *dt) {
     if (n) *n = f->n;
     if (bw) *bw = f->bw;
     if (dt) *dt = f->dt_step;
+    return LRPR_OK;
+}
+
+lrpr_status lrpr_factor_sequence(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, int store_mask, lrpr_fac *out) {
+    if (!ctx || !ops || !out || m < 1) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_sequence: invalid arguments");
+    for (int j = 1; j < m; ++j)
+        if (ops[j].dim != ops[0].dim || ops[j].nx != ops[0].nx)
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_sequence: the steps' operators must share dim and nx");
+    lrpr_fac h = new (std::nothrow) lrpr_factor_s();
+    if (!h) return fail(ctx, LRPR_ERR_NOMEM, "lrpr_factor_sequence: host allocation");
+    for (int j = 0; j < m; ++j) {
+        lrpr_fac g = nullptr;
+        lrpr_status r = lrpr_factor(ctx, &ops[j], store_mask, &g);
+        if (r != LRPR_OK) {
+            lrpr_factor_destroy(h);
+            return r;
+        }
+        h->seq.push_back(g);
+    }
+    // the handle carries the common shape; it holds no tiles of its own
+    const lrpr_fac g0 = h->seq[0];
+    h->dev = g0->dev;
+    h->op = g0->op;
+    h->n = g0->n;
+    h->bw = g0->bw;
+    h->NT = g0->NT;
+    h->nb = g0->nb;
+    h->mask = g0->mask;
+    h->P = g0->P;
+    h->stepper = LRPR_STEP_SEQUENCE;
+    h->dt_step = g0->dt_step;
+    *out = h;
     return LRPR_OK;
 }
 
@@ -603,6 +637,29 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
     }
     if (stepper <= 0) return run_sweep_core(ctx, npanels, panels, nsteps, prec, adjoint, nsteps, 0, true);
     if (nsteps == 0) return LRPR_OK;
+    if (stepper == LRPR_STEP_SEQUENCE) {
+        // step j with each panel's j-th factor; the adjoint in reverse order
+        for (int p = 0; p < npanels; ++p)
+            if (panels[p].w > 0 && (int)panels[p].F->seq.size() < nsteps)
+                return fail(ctx, LRPR_ERR_ARG, "sweep: more steps than the factor sequence holds");
+        std::vector<lrpr_panel> sp(panels, panels + npanels);
+        hipError_t e = hipSuccess;
+        lrpr_ctx_s::ProfRec rec{};
+        if (ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, prec == LRPR_F32, rec)) != hipSuccess)
+            return hipfail(ctx, e, "profile event");
+        for (int j = 0; j < nsteps; ++j) {
+            const int idx = adjoint ? nsteps - 1 - j : j;
+            for (int p = 0; p < npanels; ++p)
+                if (panels[p].w > 0) sp[p].F = panels[p].F->seq[idx];
+            lrpr_status r = run_sweep_core(ctx, npanels, sp.data(), 1, prec, adjoint, nsteps, idx, false);
+            if (r != LRPR_OK) return r;
+        }
+        if (ctx->prof) {
+            if ((e = hipEventRecord(rec.b, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "profile event");
+            ctx->prof_recs.push_back(rec);
+        }
+        return LRPR_OK;
+    }
     const bool f32 = prec == LRPR_F32;
     const size_t esz = f32 ? 4 : 8;
     const double g = stepper == LRPR_STEP_SDIRK2L ? SDIRK2L_GAMMA : 1.0;

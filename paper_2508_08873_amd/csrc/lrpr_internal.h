@@ -121,6 +121,7 @@ struct lrpr_factor_s {
     int mask = 0;                  // LRPR_STORE_* bits
     int stepper = 0;               // LRPR_STEP_*; the factored matrix is I + a_11 dt A
     double dt_step = 0;            // the step dt (op.dt is a_11 dt)
+    std::vector<lrpr_factor_s *> seq;   // LRPR_STEP_SEQUENCE: the owned per-step factors
     double *lu = nullptr;          // FP64 band LU, n x (2bw+1) row-major (kept with LRPR_STORE_F64)
     lrpr::TileSet t64, t32;
     // partitioned forward solves (LRPR_STORE_SPLIT): P blocks, starts blk
@@ -162,7 +163,7 @@ namespace lrpr {
 
 constexpr double SDIRK2L_GAMMA = 0.29289321881345247560;   // (2 - sqrt 2) / 2
 // source time factors per step of a factor's stepper (one per stage)
-inline int fac_stages(const lrpr_factor_s *f) { return f->stepper == 0 ? 1 : 2; }
+inline int fac_stages(const lrpr_factor_s *f) { return (f->stepper == 1 || f->stepper == 2) ? 2 : 1; }
 
 // error helper: record message in ctx and return status
 lrpr_status fail(lrpr_ctx ctx, lrpr_status st, const std::string &msg);

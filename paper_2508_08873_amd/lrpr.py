@@ -18,7 +18,7 @@ LRPR_F64, LRPR_F32 = 0, 1
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_ZERO_PIVOT", 4: "ERR_QR_BREAKDOWN",
           5: "ERR_NOCONV", 6: "ERR_NONFINITE", 7: "ERR_HIP"}
 EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_last_error",
-           "lrpr_factor", "lrpr_factor_stepper", "lrpr_factor_destroy", "lrpr_factor_info", "lrpr_factor_copy_lu",
+           "lrpr_factor", "lrpr_factor_stepper", "lrpr_factor_sequence", "lrpr_factor_destroy", "lrpr_factor_info", "lrpr_factor_copy_lu",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build", "lrpr_rsvd_build_q",
            "lrpr_rsvd_build_two_sided",
            "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_parareal_solve",
@@ -30,7 +30,7 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
 # lrpr_factor store_mask bits (include/lrpr.h)
 STORE_F64, STORE_F32, STORE_MIRROR, STORE_SPLIT = 1, 2, 4, 8
 # lrpr_factor_stepper steppers
-STEP_EULER, STEP_SDIRK2, STEP_SDIRK2L = 0, 1, 2
+STEP_EULER, STEP_SDIRK2, STEP_SDIRK2L, STEP_SEQUENCE = 0, 1, 2, 3
 
 
 class LrprError(RuntimeError):
@@ -82,6 +82,7 @@ def load():
     lib.lrpr_last_error.restype = ctypes.c_char_p
     lib.lrpr_factor.argtypes = [vp, P(OpDesc), i32, P(vp)]
     lib.lrpr_factor_stepper.argtypes = [vp, P(OpDesc), i32, i32, P(vp)]
+    lib.lrpr_factor_sequence.argtypes = [vp, P(OpDesc), i32, i32, P(vp)]
     lib.lrpr_factor_destroy.argtypes = [vp]
     lib.lrpr_factor_destroy.restype = None
     lib.lrpr_factor_info.argtypes = [vp, P(i64), P(i32), P(dbl)]
@@ -181,6 +182,19 @@ class Context:
         else:
             self._check(self.lib.lrpr_factor_stepper(self.h, ctypes.byref(d), int(store_mask), int(stepper),
                                                      ctypes.byref(h)))
+        return Factor(self, h)
+
+    def factor_sequence(self, ops, store_mask=1):
+        """Per-step operators: ops is a list of dicts (dim, nx, nu, beta, c, dt),
+        one per implicit-Euler step (lrpr_factor_sequence)."""
+        arr = (OpDesc * len(ops))()
+        for j, o in enumerate(ops):
+            b = o["beta"]
+            arr[j] = OpDesc(o["dim"], o["nx"], float(o["nu"]), float(b[0]), float(b[1]) if o["dim"] == 2 else 0.0,
+                            float(o["c"]), float(o["dt"]))
+        h = ctypes.c_void_p()
+        self.sync_stream()
+        self._check(self.lib.lrpr_factor_sequence(self.h, arr, len(ops), int(store_mask), ctypes.byref(h)))
         return Factor(self, h)
 
     # -- sweeps -----------------------------------------------------------
