@@ -286,6 +286,44 @@ def stepper_study(ctx, lrpr, P, prec, Om):
     return out
 
 
+def per_step_operators(ctx, lrpr, inputs, prec, seed):
+    """Per-step operators inside a slice (time-dependent coefficients): the
+    127^2 workload with nu changing every step, 16 slices x 8 steps = 128
+    band LUs, then the rSVD (k = 20, p = 5) and Parareal.  Reports the factor,
+    rSVD and Parareal times: here the band LU is the dominant cost."""
+    import torch
+    P = inputs.dar127s(seed=seed)
+    fp = 0 if prec == "f64" else 1
+    tol = P.tol if prec == "f64" else TOL_F32
+    mask = (1 if prec == "f64" else 3) | lrpr.STORE_MIRROR | lrpr.STORE_SPLIT
+    Om = torch.empty((P.N, P.l, P.n), device="cuda", dtype=torch.float64)
+    for s_ in range(P.N):
+        ctx.randn(Om[s_], seed + 1, s_)
+    Om = Om if prec == "f64" else Om.to(torch.float32)
+    u0 = lrpr.colmajor(torch.from_numpy(P.u0().reshape(-1, 1)).to("cuda"))
+    f = lrpr.colmajor(torch.from_numpy(P.source().reshape(-1, 1)).to("cuda"))
+    fsc = torch.from_numpy(np.concatenate([P.fscale(s) for s in range(1, P.N + 1)])).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    facs = [ctx.factor_sequence(P.step_ops(s), store_mask=mask) for s in range(1, P.N + 1)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    coarse = ctx.rsvd_build([(facs[s], P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, fp)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = ctx.parareal_solve(coarse, facs, P.m, u0, f, fsc, tol=tol, fine_prec=fp)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    sig = np.array(coarse.sigma).reshape(P.N, P.l)
+    coarse.close()
+    for F in facs:
+        F.close()
+    return {"workload": "dar127s: 127^2 grid, nu(t) per implicit-Euler step, 16 slices x 8 steps (128 band LUs), "
+                        "k=20, p=5, Parareal to %g" % tol,
+            "factors": P.N * P.m, "factor_s": t1 - t0, "rsvd_s": t2 - t1, "parareal_s": t3 - t2,
+            "parareal_iters": int(out["iters"][0]), "eps_max_sigma_k1": float(sig[:, P.k].max())}
+
+
 def traffic_from_profile(prec):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary
     of this workload, if it was taken from the current sweep sources."""
@@ -427,6 +465,7 @@ def main():
                                 (sum(r["ms"] for r in r64["range"]) / 1000.0)}
     if not args.no_plain:
         res["range_finder_sweeps_separately"] = fwd_adj_rates(ctx, lrpr, P, prec)
+        res["per_step_operators"] = per_step_operators(ctx, lrpr, inputs, prec, args.seed)
         res["fine_steppers"] = stepper_study(ctx, lrpr, P, prec, Om64 if prec == "f64" else Om64.to(torch.float32))
         res["rsvd_variants"] = rsvd_variants(
             ctx, lrpr, P, prec, Om64 if prec == "f64" else Om64.to(torch.float32))

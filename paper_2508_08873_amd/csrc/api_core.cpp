@@ -225,94 +225,124 @@ static lrpr_status build_split(lrpr_ctx ctx, lrpr_fac f, const double *band) {
 }
 }  // namespace lrpr
 
-extern "C" {
+namespace lrpr {
+void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err);
+}
 
-lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lrpr_fac *out) {
-    if (!ctx || !op || !out) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: null argument");
-    if ((op->dim != 1 && op->dim != 2) || op->nx < 1 || !(op->nu > 0) || !(op->dt > 0) ||
-        !(op->c >= 0) || !std::isfinite(op->beta1) || !std::isfinite(op->beta2))
-        return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: invalid operator descriptor");
+// Factor m operators of one grid together: assembly, then the band LUs in
+// batched launches (the matrices' workgroups run side by side), one check of
+// the pivots, tile packing and, with LRPR_STORE_SPLIT, the spikes.
+static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, int store_mask, lrpr_fac *outs) {
+    for (int j = 0; j < m; ++j) {
+        const lrpr_op_desc *op = &ops[j];
+        if ((op->dim != 1 && op->dim != 2) || op->nx < 1 || !(op->nu > 0) || !(op->dt > 0) || !(op->c >= 0) ||
+            !std::isfinite(op->beta1) || !std::isfinite(op->beta2) || op->dim != ops[0].dim || op->nx != ops[0].nx)
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: invalid operator descriptor");
+    }
     if (store_mask == 0) store_mask = LRPR_STORE_F64;
     if ((store_mask & ~(LRPR_STORE_F64 | LRPR_STORE_F32 | LRPR_STORE_MIRROR | LRPR_STORE_SPLIT)) ||
         !(store_mask & (LRPR_STORE_F64 | LRPR_STORE_F32)))
         return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: store_mask must hold F64 and/or F32 (and optionally MIRROR)");
     const bool mirror = (store_mask & LRPR_STORE_MIRROR) != 0;
-    const int64_t n = op->dim == 1 ? op->nx : (int64_t)op->nx * op->nx;
-    const int bw = op->dim == 1 ? 1 : op->nx;
+    const int64_t n = ops[0].dim == 1 ? ops[0].nx : (int64_t)ops[0].nx * ops[0].nx;
+    const int bw = ops[0].dim == 1 ? 1 : ops[0].nx;
     if (n >= (int64_t)1 << 31) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: n too large");
     if (bw > 1023) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: half-bandwidth above 1023");
     HIPCHK(hipSetDevice(ctx->dev), "hipSetDevice");
-    lrpr_fac f = new (std::nothrow) lrpr_factor_s();
-    if (!f) return fail(ctx, LRPR_ERR_NOMEM, "lrpr_factor: host allocation");
-    f->dev = ctx->dev;
-    f->op = *op;
-    f->n = n;
-    f->bw = bw;
-    f->NT = (int)((n + TILE - 1) / TILE);
-    f->nb = (bw + TILE - 1) / TILE;
-    f->mask = store_mask;
-    f->dt_step = op->dt;
-    double *band = nullptr;
-    void *scratch = nullptr;
-    hipError_t e;
-    auto cleanup = [&](lrpr_status st, const std::string &msg) {
-        if (band && band != f->lu) hipFree(band);
-        if (scratch) hipFree(scratch);
-        lrpr_factor_destroy(f);
-        return fail(ctx, st, msg);
+    const int NT = (int)((n + TILE - 1) / TILE), nb = (bw + TILE - 1) / TILE;
+    hipStream_t st = ctx->stream;
+    std::vector<lrpr_fac> fs(m, nullptr);
+    std::vector<double *> bands(m, nullptr);
+    std::vector<void *> scr(m, nullptr);
+    auto cleanup = [&](lrpr_status stt, const std::string &msg) {
+        hipStreamSynchronize(st);
+        for (int j = 0; j < m; ++j) {
+            if (bands[j] && (!fs[j] || bands[j] != fs[j]->lu)) hipFree(bands[j]);
+            if (scr[j]) hipFree(scr[j]);
+            if (fs[j]) lrpr_factor_destroy(fs[j]);
+        }
+        return fail(ctx, stt, msg);
     };
+    hipError_t e;
     // scratch: tile-LU panels and flags, later the diagonal-tile inverses
-    size_t sbytes = tile_lu_scratch_bytes(f->NT, f->nb);
-    const size_t inv_bytes = sizeof(double) * 2 * (size_t)f->NT * TILE_ELEMS;
+    size_t sbytes = tile_lu_scratch_bytes(NT, nb);
+    const size_t inv_bytes = sizeof(double) * 2 * (size_t)NT * TILE_ELEMS;
     if (inv_bytes > sbytes) sbytes = inv_bytes;
-    if ((e = hipMalloc(&band, sizeof(double) * (size_t)n * (2 * bw + 1))) != hipSuccess)
-        return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: band allocation");
-    if ((e = hipMalloc(&scratch, sbytes)) != hipSuccess)
-        return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: scratch allocation");
-    if ((e = launch_assemble(*op, n, bw, band, ctx->stream)) != hipSuccess)
-        return cleanup(LRPR_ERR_HIP, std::string("assemble: ") + hipGetErrorString(e));
-    int *d_info = nullptr, *d_err = nullptr;
-    if ((e = launch_tile_lu(n, bw, f->NT, f->nb, band, scratch, &d_info, &d_err, ctx->stream)) != hipSuccess)
-        return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
-    int flags[2] = {0, 0};
-    if ((e = hipMemcpyAsync(&flags[0], d_info, sizeof(int), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(&flags[1], d_err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
-        return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
-    if (flags[1] != 0) return cleanup(LRPR_ERR_HIP, "band LU: a panel wait timed out");
-    if (flags[0] != 0x7f7f7f7f) {
-        char msg[128];
-        snprintf(msg, sizeof msg, "lrpr_factor: zero or non-finite pivot at row %d", flags[0] - 1);
-        return cleanup(LRPR_ERR_ZERO_PIVOT, msg);
+    for (int j = 0; j < m; ++j) {
+        lrpr_fac f = new (std::nothrow) lrpr_factor_s();
+        if (!f) return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: host allocation");
+        fs[j] = f;
+        f->dev = ctx->dev;
+        f->op = ops[j];
+        f->n = n;
+        f->bw = bw;
+        f->NT = NT;
+        f->nb = nb;
+        f->mask = store_mask;
+        f->dt_step = ops[j].dt;
+        if ((e = hipMalloc(&bands[j], sizeof(double) * (size_t)n * (2 * bw + 1))) != hipSuccess)
+            return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: band allocation");
+        if ((e = hipMalloc(&scr[j], sbytes)) != hipSuccess)
+            return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: scratch allocation");
+        if ((e = launch_assemble(ops[j], n, bw, bands[j], st)) != hipSuccess)
+            return cleanup(LRPR_ERR_HIP, std::string("assemble: ") + hipGetErrorString(e));
     }
-    if (store_mask & LRPR_STORE_F64) {
-        if (alloc_tiles(f->t64, f->NT, f->nb, sizeof(double), mirror) != hipSuccess)
+    void *d_args = ws_get(ctx, "lu_args", tile_lu_args_bytes(m), &e);
+    if (!d_args) return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: LU argument buffer");
+    std::vector<int *> d_info(m), d_err(m);
+    if ((e = launch_tile_lu_batch(m, n, bw, NT, nb, bands.data(), scr.data(), d_info.data(), d_err.data(), d_args,
+                                  st)) != hipSuccess)
+        return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
+    std::vector<int> flags(2 * (size_t)m, 0);
+    for (int j = 0; j < m; ++j)
+        if ((e = hipMemcpyAsync(&flags[2 * j], d_info[j], sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(&flags[2 * j + 1], d_err[j], sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
+    if ((e = hipStreamSynchronize(st)) != hipSuccess)
+        return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
+    for (int j = 0; j < m; ++j) {
+        if (flags[2 * j + 1] != 0) return cleanup(LRPR_ERR_HIP, "band LU: a panel wait timed out");
+        if (flags[2 * j] != 0x7f7f7f7f) {
+            char msg[128];
+            snprintf(msg, sizeof msg, "lrpr_factor: zero or non-finite pivot at row %d", flags[2 * j] - 1);
+            return cleanup(LRPR_ERR_ZERO_PIVOT, msg);
+        }
+    }
+    for (int j = 0; j < m; ++j) {
+        lrpr_fac f = fs[j];
+        if ((store_mask & LRPR_STORE_F64) && alloc_tiles(f->t64, NT, nb, sizeof(double), mirror) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP64 tile allocation");
-    }
-    if (store_mask & LRPR_STORE_F32) {
-        if (alloc_tiles(f->t32, f->NT, f->nb, sizeof(float), mirror) != hipSuccess)
+        if ((store_mask & LRPR_STORE_F32) && alloc_tiles(f->t32, NT, nb, sizeof(float), mirror) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP32 tile allocation");
+        if ((e = launch_pack_tiles(n, bw, NT, nb, bands[j], (store_mask & LRPR_STORE_F64) ? &f->t64 : nullptr,
+                                   (store_mask & LRPR_STORE_F32) ? &f->t32 : nullptr, (double *)scr[j], st)) !=
+            hipSuccess)
+            return cleanup(LRPR_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
     }
-    if ((e = launch_pack_tiles(n, bw, f->NT, f->nb, band, (store_mask & LRPR_STORE_F64) ? &f->t64 : nullptr,
-                               (store_mask & LRPR_STORE_F32) ? &f->t32 : nullptr, (double *)scratch,
-                               ctx->stream)) != hipSuccess)
-        return cleanup(LRPR_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
-    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+    if ((e = hipStreamSynchronize(st)) != hipSuccess)
         return cleanup(LRPR_ERR_HIP, std::string("factor: ") + hipGetErrorString(e));
-    hipFree(scratch);
-    scratch = nullptr;
-    if (store_mask & LRPR_STORE_SPLIT) {
-        const lrpr_status st = build_split(ctx, f, band);
-        if (st != LRPR_OK) return cleanup(st, std::string("lrpr_factor: partitioned solve: ") + ctx->err);
+    for (int j = 0; j < m; ++j) {
+        hipFree(scr[j]);
+        scr[j] = nullptr;
     }
-    if (store_mask & LRPR_STORE_F64) {
-        f->lu = band;
-    } else {
-        hipFree(band);
+    for (int j = 0; j < m; ++j) {
+        if (store_mask & LRPR_STORE_SPLIT) {
+            const lrpr_status stt = build_split(ctx, fs[j], bands[j]);
+            if (stt != LRPR_OK) return cleanup(stt, std::string("lrpr_factor: partitioned solve: ") + ctx->err);
+        }
+        if (store_mask & LRPR_STORE_F64) fs[j]->lu = bands[j];
+        else hipFree(bands[j]);
+        bands[j] = nullptr;
     }
-    band = nullptr;
-    *out = f;
+    for (int j = 0; j < m; ++j) outs[j] = fs[j];
     return LRPR_OK;
+}
+
+extern "C" {
+
+lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lrpr_fac *out) {
+    if (!ctx || !op || !out) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: null argument");
+    return factor_batch(ctx, op, 1, store_mask, out);
 }
 
 lrpr_status lrpr_factor_info(lrpr_fac f, int64_t *n, int *bw, double *dt) {
@@ -330,14 +360,16 @@ lrpr_status lrpr_factor_sequence(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, i
             return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_sequence: the steps' operators must share dim and nx");
     lrpr_fac h = new (std::nothrow) lrpr_factor_s();
     if (!h) return fail(ctx, LRPR_ERR_NOMEM, "lrpr_factor_sequence: host allocation");
-    for (int j = 0; j < m; ++j) {
-        lrpr_fac g = nullptr;
-        lrpr_status r = lrpr_factor(ctx, &ops[j], store_mask, &g);
+    constexpr int CHUNK = 64;   // factors assembled and factored together (device memory in flight)
+    for (int j0 = 0; j0 < m; j0 += CHUNK) {
+        const int c = m - j0 < CHUNK ? m - j0 : CHUNK;
+        std::vector<lrpr_fac> gs(c, nullptr);
+        lrpr_status r = factor_batch(ctx, ops + j0, c, store_mask, gs.data());
         if (r != LRPR_OK) {
             lrpr_factor_destroy(h);
             return r;
         }
-        h->seq.push_back(g);
+        for (lrpr_fac g : gs) h->seq.push_back(g);
     }
     // the handle carries the common shape; it holds no tiles of its own
     const lrpr_fac g0 = h->seq[0];

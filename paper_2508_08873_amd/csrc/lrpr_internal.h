@@ -170,12 +170,12 @@ lrpr_status fail(lrpr_ctx ctx, lrpr_status st, const std::string &msg);
 
 // kernels launched from the host code (defined in the .hip sources)
 hipError_t launch_assemble(const lrpr_op_desc &op, int64_t n, int bw, double *band, hipStream_t s);
-// pipelined tile LU (lu.hip): scratch of tile_lu_scratch_bytes(NT, nb); on
-// return *info_dev / *err_dev point into it (pivot info: 0x7f7f7f7f if all
-// pivots are fine, else the first bad row + 1; err: nonzero on a wait time-out)
+// pipelined tile LU (lu.hip): scratch of tile_lu_scratch_bytes(NT, nb) per matrix
 size_t tile_lu_scratch_bytes(int NT, int nb);
-hipError_t launch_tile_lu(int64_t n, int bw, int NT, int nb, double *band, void *scratch, int **info_dev,
-                          int **err_dev, hipStream_t s);
+// count independent factorisations of one shape (band and scratch per matrix)
+hipError_t launch_tile_lu_batch(int count, int64_t n, int bw, int NT, int nb, double *const *bands,
+                                void *const *scratch, int **info_dev, int **err_dev, void *d_args, hipStream_t s);
+size_t tile_lu_args_bytes(int count);
 hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu, const TileSet *t64,
                              const TileSet *t32, double *scratch, hipStream_t s);
 // adjoint sweeps read the mirrored set unless `strided` (then the forward

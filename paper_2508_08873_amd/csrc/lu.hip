@@ -21,6 +21,8 @@
 // is bounded: on time-out it raises *err and the kernel runs to its end.
 // All P workgroups are resident together (P is a few dozen), and every wait
 // is for a lower column, so the pipeline always drains.
+#include <vector>
+
 #include "lrpr_internal.h"
 
 namespace lrpr {
@@ -70,13 +72,16 @@ __device__ __forceinline__ void wait_col(const LuArgs &a, int K) {
 }
 
 template <int NW, int TPW>
-__global__ __launch_bounds__(64 * NW) void k_tile_lu(LuArgs a) {
+__global__ __launch_bounds__(64 * NW) void k_tile_lu(const LuArgs *args, int P) {
     __shared__ double ubuf[2][256];   // U(K,J), accumulator order
     __shared__ double sd[256];        // diagonal tile, row-major
     __shared__ double sd2[256];       // second buffer of the diagonal elimination
     __shared__ double sli[256];       // L(J,J)^{-1}, row-major
     __shared__ double sui[256];       // U(J,J)^{-1}, row-major
     __shared__ double st[NW][256];    // per-wave transposition buffer
+    // workgroups [P*i, P*i + P) factor matrix i of the launch
+    const int wg = blockIdx.x % P;
+    const LuArgs a = args[blockIdx.x / P];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -85,7 +90,7 @@ __global__ __launch_bounds__(64 * NW) void k_tile_lu(LuArgs a) {
     const int64_t n = a.n, W = 2 * bw + 1;
     double *band = a.band;
 
-    for (int J = blockIdx.x; J < NT; J += gridDim.x) {
+    for (int J = wg; J < NT; J += P) {
         // ---- load tile column J (tile t = I - J + nb, owned by wave t % NW)
         v4d acc[TPW];
 #pragma unroll
@@ -302,39 +307,60 @@ size_t tile_lu_scratch_bytes(int NT, int nb) {
     return sizeof(double) * ((size_t)NT * nb + NT) * TILE_ELEMS + sizeof(int) * ((size_t)NT + 2);
 }
 
-hipError_t launch_tile_lu(int64_t n, int bw, int NT, int nb, double *band, void *scratch, int **info_dev,
-                          int **err_dev, hipStream_t s) {
-    LuArgs a;
-    a.n = n;
-    a.bw = bw;
-    a.NT = NT;
-    a.nb = nb;
-    a.band = band;
-    a.Lt = (double *)scratch;
-    a.Li = a.Lt + (size_t)NT * nb * TILE_ELEMS;
-    a.flag = (int *)(a.Li + (size_t)NT * TILE_ELEMS);
-    a.info = a.flag + NT;
-    a.err = a.info + 1;
-    a.spin_limit = 1 << 22;
-    *info_dev = a.info;
-    *err_dev = a.err;
-    hipError_t e;
-    if ((e = hipMemsetAsync(a.flag, 0, sizeof(int) * (size_t)NT, s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(a.info, 0x7f, sizeof(int), s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(a.err, 0, sizeof(int), s)) != hipSuccess) return e;
+// Several independent factorisations of one shape in one launch: P = nb + 9
+// workgroups per matrix, at most 256 workgroups per launch so that every
+// matrix's workgroups are resident together (their waits only involve each
+// other).  Each matrix i has its band, scratch (tile_lu_scratch_bytes) and
+// on return info_dev[i] / err_dev[i] point into its scratch (pivot info:
+// 0x7f7f7f7f if all pivots are fine, else the first bad row + 1; err:
+// nonzero on a wait time-out).  d_args: device space for count LuArgs.
+hipError_t launch_tile_lu_batch(int count, int64_t n, int bw, int NT, int nb, double *const *bands,
+                                void *const *scratch, int **info_dev, int **err_dev, void *d_args, hipStream_t s) {
+    std::vector<LuArgs> hv(count);
+    for (int i = 0; i < count; ++i) {
+        LuArgs &a = hv[i];
+        a.n = n;
+        a.bw = bw;
+        a.NT = NT;
+        a.nb = nb;
+        a.band = bands[i];
+        a.Lt = (double *)scratch[i];
+        a.Li = a.Lt + (size_t)NT * nb * TILE_ELEMS;
+        a.flag = (int *)(a.Li + (size_t)NT * TILE_ELEMS);
+        a.info = a.flag + NT;
+        a.err = a.info + 1;
+        a.spin_limit = 1 << 22;
+        info_dev[i] = a.info;
+        err_dev[i] = a.err;
+        hipError_t e;
+        if ((e = hipMemsetAsync(a.flag, 0, sizeof(int) * (size_t)NT, s)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(a.info, 0x7f, sizeof(int), s)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(a.err, 0, sizeof(int), s)) != hipSuccess) return e;
+    }
     int P = nb + 9;
     if (P > NT) P = NT;
-    if (nb <= 4)
-        hipLaunchKernelGGL((k_tile_lu<4, 3>), dim3(P), dim3(256), 0, s, a);
-    else if (nb <= 16)
-        hipLaunchKernelGGL((k_tile_lu<4, 9>), dim3(P), dim3(256), 0, s, a);
-    else if (nb <= 32)
-        hipLaunchKernelGGL((k_tile_lu<4, 17>), dim3(P), dim3(256), 0, s, a);
-    else if (nb <= 64)
-        hipLaunchKernelGGL((k_tile_lu<8, 17>), dim3(P), dim3(512), 0, s, a);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    const int per = P > 256 ? 1 : 256 / P;   // matrices per launch
+    LuArgs *dA = (LuArgs *)d_args;
+    hipError_t e = hipMemcpyAsync(dA, hv.data(), sizeof(LuArgs) * (size_t)count, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    for (int i0 = 0; i0 < count; i0 += per) {
+        const int c = count - i0 < per ? count - i0 : per;
+        const dim3 grid((unsigned)(c * P));
+        if (nb <= 4)
+            hipLaunchKernelGGL((k_tile_lu<4, 3>), grid, dim3(256), 0, s, dA + i0, P);
+        else if (nb <= 16)
+            hipLaunchKernelGGL((k_tile_lu<4, 9>), grid, dim3(256), 0, s, dA + i0, P);
+        else if (nb <= 32)
+            hipLaunchKernelGGL((k_tile_lu<4, 17>), grid, dim3(256), 0, s, dA + i0, P);
+        else if (nb <= 64)
+            hipLaunchKernelGGL((k_tile_lu<8, 17>), grid, dim3(512), 0, s, dA + i0, P);
+        else
+            return hipErrorInvalidValue;
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
+
+size_t tile_lu_args_bytes(int count) { return sizeof(LuArgs) * (size_t)count; }
 
 }  // namespace lrpr

@@ -192,6 +192,15 @@ def dar511t(seed: int = 0, **kw) -> Problem:
     return Problem(**d)
 
 
+def dar127s(seed: int = 0, **kw) -> Problem:
+    """Per-step operators: 127^2 grid, nu(t) = 1 + 0.5 sin(2 pi t) changing every
+    implicit-Euler step (one factor per step), 16 slices x 8 steps, k = 20, p = 5."""
+    d = dict(name="dar127s", dim=2, nx=127, nu=1.0, beta=(20.0, 10.0), c=1.0, T=1.0, N=16, m=8,
+             k=20, p=5, tol=1e-10, nu_of_t=True, seed=seed)
+    d.update(kw)
+    return Problem(**d)
+
+
 def uneven48(seed: int = 0, count: int = 48) -> list:
     """48 problems drawn in order: nx in {63,127,255,511}, nu ~ U[0.5,2],
     |beta| ~ U[0,30], theta ~ U[0,2pi), c ~ U[0,5], k ~ U{8..64}, p = floor(k/4),
