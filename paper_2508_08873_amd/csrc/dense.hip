@@ -174,31 +174,49 @@ __global__ __launch_bounds__(256) void k_chol(const int *ls, const double *G, do
 // ---------------------------------------------------------------------------
 // C = A B for every job: A n x l (type TA, ld lda), B l x nc (FP64, row-major
 // ld LMAX), C n x nc (type TC, ld ldc).  B is staged in LDS; one thread per
-// row; outputs in chunks of 16 columns.  With upper != 0, B is upper
+// row; outputs in chunks of 32 columns.  With upper != 0, B is upper
 // triangular (only k <= j terms are summed).
 // ---------------------------------------------------------------------------
+constexpr int RM_CB = 32;   // output columns per pass over a row of A
+
 template <typename TA, typename TC>
 __global__ __launch_bounds__(256) void k_rowmat(const RowMatJob *jobs) {
     __shared__ double Bs[LMAX * LMAX];
     const RowMatJob jb = jobs[blockIdx.y];
-    for (int e = threadIdx.x; e < LMAX * LMAX; e += blockDim.x) Bs[e] = jb.B[e];
+    {   // rows k < l of B (the only ones read), four loads in flight per thread
+        const int tot = jb.l * LMAX;
+        for (int e0 = 0; e0 < tot; e0 += 4 * (int)blockDim.x) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x;
+                v[u] = e < tot ? jb.B[e] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x;
+                if (e < tot) Bs[e] = v[u];
+            }
+        }
+    }
     __syncthreads();
     const TA *A = (const TA *)jb.A;
     TC *C = (TC *)jb.C;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < jb.n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        for (int j0 = 0; j0 < jb.nc; j0 += 16) {
-            double acc[16];
+        for (int j0 = 0; j0 < jb.nc; j0 += RM_CB) {
+            double acc[RM_CB];
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
-            const int kend = jb.upper ? ((j0 + 16 < jb.l) ? j0 + 16 : jb.l) : jb.l;
+            for (int jj = 0; jj < RM_CB; ++jj) acc[jj] = 0.0;
+            const int kend = jb.upper ? ((j0 + RM_CB < jb.l) ? j0 + RM_CB : jb.l) : jb.l;
+#pragma unroll 4
             for (int k = 0; k < kend; ++k) {
                 const double av = ld_as_double(A, i + (int64_t)k * jb.lda);
 #pragma unroll
-                for (int jj = 0; jj < 16; ++jj) acc[jj] += av * Bs[k * LMAX + j0 + jj];
+                for (int jj = 0; jj < RM_CB; ++jj) acc[jj] += av * Bs[k * LMAX + j0 + jj];
             }
 #pragma unroll
-            for (int jj = 0; jj < 16; ++jj)
+            for (int jj = 0; jj < RM_CB; ++jj)
                 if (j0 + jj < jb.nc) C[i + (int64_t)(j0 + jj) * jb.ldc] = (TC)acc[jj];
         }
     }

@@ -399,7 +399,8 @@ __global__ __launch_bounds__(256) void k_split_update(const SplitGroup *groups, 
 // Update for a compile-time band-tile count NB, one workgroup per (run of
 // groups on the same factor, block, 4 tile rows): the spike tiles of a row
 // (the same for every group of the run) are read once, the neighbour's
-// boundary tiles of each group are staged in LDS.  Wave w updates tile row
+// boundary tiles of each group are staged in LDS (the next group's are loaded
+// into registers while the current group multiplies).  Wave w updates tile row
 // blk[p] + 4*chunk + w of every group of the run.
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_split_update_nb(const SplitGroup *groups, const int2 *runs, int upper,
@@ -430,16 +431,29 @@ __global__ __launch_bounds__(256) void k_split_update_nb(const SplitGroup *group
         for (int s = 0; s < NB; ++s) Mf<T>::ld4(A + (int64_t)s * TILE_ELEMS, lane, a[s]);
     }
     const int nbr = upper ? p + 1 : p - 1;
+    // the neighbour's boundary tiles of a group: NB values per thread, all
+    // loads in flight together; the next group's load while this one multiplies
+    constexpr int PER = NB * TILE_ELEMS / 256;
+    T stg[PER];
+    auto stage_load = [&](int g) {
+        const T *b = (const T *)groups[g].bnd + (int64_t)nbr * NB * TILE_ELEMS;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) stg[i] = gld(b + threadIdx.x + i * 256);
+    };
+    constexpr bool PRE = PER * sizeof(T) <= 128;   // next group's tiles held in registers while they fit
+    if (PRE) stage_load(run.x);
     for (int g = run.x; g < run.x + run.y; ++g) {
         const SplitGroup &G = groups[g];
-        const T *b = (const T *)G.bnd + (int64_t)nbr * NB * TILE_ELEMS;
+        if (!PRE) stage_load(g);
         if (g != run.x) __syncthreads();   // previous group's tiles consumed
-        for (int e = threadIdx.x; e < NB * TILE_ELEMS; e += 256) bl[e] = gld(b + e);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) bl[threadIdx.x + i * 256] = stg[i];
         __syncthreads();
+        if (PRE && g + 1 < run.x + run.y) stage_load(g + 1);
         if (!valid) continue;
         T x[4];
         load_rows(G, I, lane, x);
-        v4 acc = {0, 0, 0, 0};
+        v4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};   // even / odd spike tiles
 #pragma unroll
         for (int s = 0; s < NB; ++s) {
             T as[4];
@@ -450,11 +464,12 @@ __global__ __launch_bounds__(256) void k_split_update_nb(const SplitGroup *group
                 Mf<T>::ld4(A + (int64_t)s * TILE_ELEMS, lane, as);
             }
 #pragma unroll
-            for (int kc = 0; kc < 4; ++kc) acc = Mf<T>::mma(as[kc], bl[s * TILE_ELEMS + kc * 64 + lane], acc);
+            for (int kc = 0; kc < 4; ++kc)
+                acc[s & 1] = Mf<T>::mma(as[kc], bl[s * TILE_ELEMS + kc * 64 + lane], acc[s & 1]);
         }
         v4 o;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) o[q] = x[q] - acc[q];
+        for (int q = 0; q < 4; ++q) o[q] = x[q] - (acc[0][q] + acc[1][q]);
         store_rows<T>(G, I, lane, o);
     }
 }
