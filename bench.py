@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-RHS FP64 run")
+    ap.add_argument("--no-ul", action="store_true",
+                    help="factor without the UL set (every step L U, unpaired substitution passes)")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--serve-duration", type=float, default=15.0, help="arrival window (s)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -94,7 +96,7 @@ def cpu_baseline_and_parity(ctx, lrpr, P, prec, ncols, nsteps, seed):
     t1 = time.perf_counter()
     dt = torch.float64 if prec == "f64" else torch.float32
     F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
-                   store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR | lrpr.STORE_SPLIT)
+                   store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR | lrpr.STORE_SPLIT | UL_MASK[0])
     X = lrpr.colmajor(torch.from_numpy(X0).to("cuda", dt))
     spec = {"F": F, "X": X, "f": lrpr.colmajor(torch.from_numpy(f.reshape(-1, 1)).to("cuda", dt)),
             "fscale": torch.from_numpy(np.ascontiguousarray(fsc)).to("cuda")}
@@ -206,7 +208,7 @@ def fwd_adj_rates(ctx, lrpr, P, prec):
     fp = 0 if prec == "f64" else 1
     dt = torch.float64 if prec == "f64" else torch.float32
     F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
-                   store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR)
+                   store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR | UL_MASK[0])
     gen = torch.Generator(device="cuda")
     gen.manual_seed(12345)
     X = torch.randn((P.N * P.l, P.n), generator=gen, device="cuda", dtype=dt).t()
@@ -231,7 +233,7 @@ def rsvd_variants(ctx, lrpr, P, prec, Om):
     import torch
     fp = 0 if prec == "f64" else 1
     F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
-                   store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR)
+                   store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR | UL_MASK[0])
     Psi = torch.empty(Om.shape, device="cuda", dtype=torch.float64)
     for s_ in range(P.N):
         ctx.randn(Psi[s_], 777, s_)
@@ -337,6 +339,10 @@ def traffic_from_profile(prec):
     return d["traffic_bytes_per_launch"], d
 
 
+# extra factor store flag of the timed path: the UL set (paired passes)
+UL_MASK = [0]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -349,6 +355,7 @@ def main():
     import torch
     from paper_2508_08873_amd import inputs, lrpr
 
+    UL_MASK[0] = 0 if args.no_ul else lrpr.STORE_UL
     P = inputs.dar255(seed=args.seed)
     prec = args.prec
     ctx = lrpr.Context(0)
@@ -373,7 +380,8 @@ def main():
         def one_step(times, recs):
             ta = time.perf_counter()
             F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
-                           store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR | lrpr.STORE_SPLIT)
+                           store_mask=(1 if prec == "f64" else 3) | lrpr.STORE_MIRROR | lrpr.STORE_SPLIT |
+                           UL_MASK[0])
             tb = time.perf_counter()
             coarse = ctx.rsvd_build([(F, P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, fp)
             tc = time.perf_counter()
@@ -426,7 +434,10 @@ def main():
     traffic, tsrc = traffic_from_profile(prec)
     roofline = {"bound": "mfma", "achieved": achieved_tf, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved_tf / peak, "traffic": traffic,
-                "kernel": "k_sweep (range-finder band sweeps: 3200 RHS x 32 implicit-Euler steps, fine + adjoint)",
+                "kernel": ("k_sweep + k_sweep_pair (range-finder band sweeps: 3200 RHS x 32 implicit-Euler steps, "
+                           "fine + adjoint; steps alternate L U / U' L', the first and last substitutions run "
+                           "alone and the other 62 in 31 pairs)") if UL_MASK[0] else
+                          "k_sweep (range-finder band sweeps: 3200 RHS x 32 implicit-Euler steps, fine + adjoint)",
                 "launches": prof["launches"], "avg_launch_ms": prof["ms"] / launches,
                 "algorithmic_flops_per_launch": prof["flops"] / launches,
                 "algorithmic_bytes_per_launch": prof["bytes"] / launches,
@@ -447,6 +458,7 @@ def main():
                                "steps, k=40, p=10; step = factor + rSVD build + Parareal to %g" % tol,
                    "rhs_steps_per_step": rhs_steps, "parareal_iters": out["iters"][0],
                    "range_finder_and_fine_precision": prec,
+                   "factorisations": "L U and U' L' (paired passes)" if UL_MASK[0] else "L U",
                    "fp64_steps": "LU, CholeskyQR2 Gram/Cholesky, Jacobi SVD, Parareal correction and residual"},
         "rsvd_build_s": rsvd_s + fac_s, "factor_s": fac_s, "rsvd_only_s": rsvd_s, "parareal_s": pr_s,
         "sweep_kernel_s_per_step": (tot("range", "ms") + tot("parareal", "ms")) / 1000.0 / K,

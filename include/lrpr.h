@@ -111,7 +111,7 @@ lrpr_status lrpr_randn(lrpr_ctx ctx, void *dst, int64_t count, lrpr_prec prec, u
 
 /* ---- operator assembly and band LU (Sec. 4.4) --------------------------- */
 
-enum { LRPR_STORE_F64 = 1, LRPR_STORE_F32 = 2, LRPR_STORE_MIRROR = 4, LRPR_STORE_SPLIT = 8 };
+enum { LRPR_STORE_F64 = 1, LRPR_STORE_F32 = 2, LRPR_STORE_MIRROR = 4, LRPR_STORE_SPLIT = 8, LRPR_STORE_UL = 16 };
 
 /* Assemble M = I + dt*A on the device and factor it M = L U by banded
  * Gaussian elimination without pivoting, in FP64 (the paper's fine solver
@@ -133,6 +133,18 @@ enum { LRPR_STORE_F64 = 1, LRPR_STORE_F32 = 2, LRPR_STORE_MIRROR = 4, LRPR_STORE
  *                         right-hand sides spread each column group over
  *                         several compute units (same results up to
  *                         rounding).
+ *   LRPR_STORE_UL (16)    for each precision kept (and mirrored with
+ *                         MIRROR), also the tiles of the UL factorisation
+ *                         M = U' L' (U' unit upper, L' lower: the LU of the
+ *                         row- and column-reversed matrix, factored in the
+ *                         same launch).  Implicit-Euler sweeps of two or
+ *                         more steps whose factors all carry it then
+ *                         alternate LU and UL steps, so that the last
+ *                         substitution of one step and the first of the next
+ *                         run in the same direction and share one pass over
+ *                         the rows; the state between them stays on chip.
+ *                         Same results up to rounding; doubles the tile
+ *                         memory.
  * 0 means LRPR_STORE_F64; at least one of F64/F32 must be set.  Errors:
  * LRPR_ERR_ARG (bad descriptor or mask), LRPR_ERR_ZERO_PIVOT,
  * LRPR_ERR_NOMEM.  Synchronises the stream. */

@@ -107,6 +107,8 @@ void lrpr_factor_destroy(lrpr_fac f) {
     if (f->lu) hipFree(f->lu);
     free_tiles(f->t64);
     free_tiles(f->t32);
+    free_tiles(f->t64r);
+    free_tiles(f->t32r);
     for (void *p : {f->s64.S, f->s64.T, f->s32.S, f->s32.T, (void *)f->d_blk})
         if (p) hipFree(p);
     delete f;
@@ -240,10 +242,11 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
             return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: invalid operator descriptor");
     }
     if (store_mask == 0) store_mask = LRPR_STORE_F64;
-    if ((store_mask & ~(LRPR_STORE_F64 | LRPR_STORE_F32 | LRPR_STORE_MIRROR | LRPR_STORE_SPLIT)) ||
+    if ((store_mask & ~(LRPR_STORE_F64 | LRPR_STORE_F32 | LRPR_STORE_MIRROR | LRPR_STORE_SPLIT | LRPR_STORE_UL)) ||
         !(store_mask & (LRPR_STORE_F64 | LRPR_STORE_F32)))
         return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: store_mask must hold F64 and/or F32 (and optionally MIRROR)");
     const bool mirror = (store_mask & LRPR_STORE_MIRROR) != 0;
+    const bool ul = (store_mask & LRPR_STORE_UL) != 0;
     const int64_t n = ops[0].dim == 1 ? ops[0].nx : (int64_t)ops[0].nx * ops[0].nx;
     const int bw = ops[0].dim == 1 ? 1 : ops[0].nx;
     if (n >= (int64_t)1 << 31) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: n too large");
@@ -251,15 +254,21 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
     HIPCHK(hipSetDevice(ctx->dev), "hipSetDevice");
     const int NT = (int)((n + TILE - 1) / TILE), nb = (bw + TILE - 1) / TILE;
     hipStream_t st = ctx->stream;
+    // matrices j < m: M_j (n rows); with LRPR_STORE_UL also j >= m: the
+    // reversed J diag(M_j, I) J (NT * 16 rows), whose LU is M_j's UL
+    const int mm = ul ? 2 * m : m;
+    const int64_t nrev = (int64_t)NT * TILE;
     std::vector<lrpr_fac> fs(m, nullptr);
-    std::vector<double *> bands(m, nullptr);
-    std::vector<void *> scr(m, nullptr);
+    std::vector<double *> bands(mm, nullptr);
+    std::vector<void *> scr(mm, nullptr);
+    std::vector<int64_t> rows(mm, n);
+    for (int j = m; j < mm; ++j) rows[j] = nrev;
     auto cleanup = [&](lrpr_status stt, const std::string &msg) {
         hipStreamSynchronize(st);
-        for (int j = 0; j < m; ++j) {
-            if (bands[j] && (!fs[j] || bands[j] != fs[j]->lu)) hipFree(bands[j]);
+        for (int j = 0; j < mm; ++j) {
+            if (bands[j] && (j >= m || !fs[j] || bands[j] != fs[j]->lu)) hipFree(bands[j]);
             if (scr[j]) hipFree(scr[j]);
-            if (fs[j]) lrpr_factor_destroy(fs[j]);
+            if (j < m && fs[j]) lrpr_factor_destroy(fs[j]);
         }
         return fail(ctx, stt, msg);
     };
@@ -280,31 +289,37 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
         f->nb = nb;
         f->mask = store_mask;
         f->dt_step = ops[j].dt;
-        if ((e = hipMalloc(&bands[j], sizeof(double) * (size_t)n * (2 * bw + 1))) != hipSuccess)
+    }
+    for (int j = 0; j < mm; ++j) {
+        if ((e = hipMalloc(&bands[j], sizeof(double) * (size_t)rows[j] * (2 * bw + 1))) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: band allocation");
         if ((e = hipMalloc(&scr[j], sbytes)) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: scratch allocation");
-        if ((e = launch_assemble(ops[j], n, bw, bands[j], st)) != hipSuccess)
+        if ((e = launch_assemble(ops[j % m], n, rows[j], bw, j >= m, bands[j], st)) != hipSuccess)
             return cleanup(LRPR_ERR_HIP, std::string("assemble: ") + hipGetErrorString(e));
     }
-    void *d_args = ws_get(ctx, "lu_args", tile_lu_args_bytes(m), &e);
+    void *d_args = ws_get(ctx, "lu_args", tile_lu_args_bytes(mm), &e);
     if (!d_args) return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: LU argument buffer");
-    std::vector<int *> d_info(m), d_err(m);
-    if ((e = launch_tile_lu_batch(m, n, bw, NT, nb, bands.data(), scr.data(), d_info.data(), d_err.data(), d_args,
-                                  st)) != hipSuccess)
+    std::vector<int *> d_info(mm), d_err(mm);
+    if ((e = launch_tile_lu_batch(mm, rows.data(), bw, NT, nb, bands.data(), scr.data(), d_info.data(),
+                                  d_err.data(), d_args, st)) != hipSuccess)
         return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
-    std::vector<int> flags(2 * (size_t)m, 0);
-    for (int j = 0; j < m; ++j)
+    std::vector<int> flags(2 * (size_t)mm, 0);
+    for (int j = 0; j < mm; ++j)
         if ((e = hipMemcpyAsync(&flags[2 * j], d_info[j], sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
             (e = hipMemcpyAsync(&flags[2 * j + 1], d_err[j], sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
             return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
     if ((e = hipStreamSynchronize(st)) != hipSuccess)
         return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
-    for (int j = 0; j < m; ++j) {
+    for (int j = 0; j < mm; ++j) {
         if (flags[2 * j + 1] != 0) return cleanup(LRPR_ERR_HIP, "band LU: a panel wait timed out");
         if (flags[2 * j] != 0x7f7f7f7f) {
             char msg[128];
-            snprintf(msg, sizeof msg, "lrpr_factor: zero or non-finite pivot at row %d", flags[2 * j] - 1);
+            if (j < m)
+                snprintf(msg, sizeof msg, "lrpr_factor: zero or non-finite pivot at row %d", flags[2 * j] - 1);
+            else   // row r of the reversed matrix is row nrev - 1 - r of the operator
+                snprintf(msg, sizeof msg, "lrpr_factor: zero or non-finite pivot of the UL factorisation at row %lld",
+                         (long long)(nrev - flags[2 * j]));
             return cleanup(LRPR_ERR_ZERO_PIVOT, msg);
         }
     }
@@ -314,16 +329,30 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP64 tile allocation");
         if ((store_mask & LRPR_STORE_F32) && alloc_tiles(f->t32, NT, nb, sizeof(float), mirror) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP32 tile allocation");
-        if ((e = launch_pack_tiles(n, bw, NT, nb, bands[j], (store_mask & LRPR_STORE_F64) ? &f->t64 : nullptr,
+        if ((e = launch_pack_tiles(n, bw, NT, nb, bands[j], false, (store_mask & LRPR_STORE_F64) ? &f->t64 : nullptr,
                                    (store_mask & LRPR_STORE_F32) ? &f->t32 : nullptr, (double *)scr[j], st)) !=
+            hipSuccess)
+            return cleanup(LRPR_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
+        if (!ul) continue;
+        if ((store_mask & LRPR_STORE_F64) && alloc_tiles(f->t64r, NT, nb, sizeof(double), mirror) != hipSuccess)
+            return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP64 UL tile allocation");
+        if ((store_mask & LRPR_STORE_F32) && alloc_tiles(f->t32r, NT, nb, sizeof(float), mirror) != hipSuccess)
+            return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP32 UL tile allocation");
+        if ((e = launch_pack_tiles(n, bw, NT, nb, bands[m + j], true,
+                                   (store_mask & LRPR_STORE_F64) ? &f->t64r : nullptr,
+                                   (store_mask & LRPR_STORE_F32) ? &f->t32r : nullptr, (double *)scr[m + j], st)) !=
             hipSuccess)
             return cleanup(LRPR_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
     }
     if ((e = hipStreamSynchronize(st)) != hipSuccess)
         return cleanup(LRPR_ERR_HIP, std::string("factor: ") + hipGetErrorString(e));
-    for (int j = 0; j < m; ++j) {
+    for (int j = 0; j < mm; ++j) {
         hipFree(scr[j]);
         scr[j] = nullptr;
+    }
+    for (int j = m; j < mm; ++j) {
+        hipFree(bands[j]);
+        bands[j] = nullptr;
     }
     for (int j = 0; j < m; ++j) {
         if (store_mask & LRPR_STORE_SPLIT) {
@@ -424,8 +453,12 @@ constexpr int SPLIT_MAX_GROUPS = 32;
 
 FacView fac_view(lrpr_fac f, bool f32) {
     const TileSet &t = f32 ? f->t32 : f->t64;
+    const TileSet &tr = f32 ? f->t32r : f->t64r;
     FacView v;
-    for (int a = 0; a < TS_COUNT; ++a) v.a[a] = t.a[a];
+    for (int a = 0; a < TS_COUNT; ++a) {
+        v.a[a] = t.a[a];
+        v.ar[a] = tr.a[a];
+    }
     v.zt = t.zt;
     v.sink = t.sink;
     v.n = (int)f->n;
@@ -627,6 +660,31 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
     for (int p = 0; p < npanels && split; ++p)
         split = panels[p].w == 0 || (panels[p].F->P >= 2 && (f32 ? panels[p].F->s32.S : panels[p].F->s64.S));
     if (split) return run_split(ctx, npanels, panels, items, nsteps, f32, max_nb, step0, record);
+    // Pass pairs when every factor carries the UL set (and, for the
+    // adjoint, its mirrored tiles) and all have the same band-tile count
+    // (tile arrays addressed with 32-bit byte offsets)
+    bool paired = nsteps >= 2 && sweep_pairable(max_nb) && !(adjoint && strided);
+    for (const SweepItem &it : items)
+        paired = paired && it.fac.nb == max_nb && it.fac.ar[TS_LB] && (!adjoint || it.fac.ar[TS_UTB]) &&
+                 (double)(it.fac.NT + 2 * guard_rows(max_nb)) * max_nb * TILE_ELEMS * (f32 ? 4 : 8) < 4.0e9;
+    const size_t ni = items.size();
+    if (paired) {
+        // [0, ni): first substitution of the first step; [ni, 2ni): second
+        // substitution of an L U step; [2ni, 3ni): second substitution of a
+        // U' L' step (the UL set's first-pass tiles, no source)
+        items.resize(3 * ni);
+        for (size_t i = 0; i < ni; ++i) {
+            items[i].passes = 1;
+            items[ni + i] = items[i];
+            items[ni + i].passes = 2;
+            SweepItem &r = items[2 * ni + i];
+            r = items[i];
+            for (int k = 0; k < TS_COUNT; ++k) r.fac.a[k] = r.fac.ar[k];
+            r.f = nullptr;
+            r.fcol = nullptr;
+            r.fscale = nullptr;
+        }
+    }
     lrpr_status st = ensure_items(ctx, items.size());
     if (st != LRPR_OK) return st;
     e = hipMemcpyAsync(ctx->d_items, items.data(), items.size() * sizeof(SweepItem),
@@ -635,8 +693,21 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
     lrpr_ctx_s::ProfRec rec{};
     if (record && ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
         return hipfail(ctx, e, "profile event");
-    e = launch_sweep(adjoint, strided, f32, (int)items.size(), ctx->d_items, nsteps, max_nb, ctx->stream, step0);
-    if (e != hipSuccess) return hipfail(ctx, e, "sweep launch");
+    if (!paired) {
+        e = launch_sweep(adjoint, strided, f32, (int)ni, ctx->d_items, nsteps, max_nb, ctx->stream, step0);
+        if (e != hipSuccess) return hipfail(ctx, e, "sweep launch");
+    } else {
+        // even steps (from step0) L U, odd steps U' L'; the second
+        // substitution of step s runs with the first of step s+1
+        e = launch_sweep(adjoint, false, f32, (int)ni, ctx->d_items, 1, max_nb, ctx->stream, step0);
+        for (int s = 0; s + 1 < nsteps && e == hipSuccess; ++s)
+            e = launch_sweep_pair(adjoint, (s & 1) != 0, f32, (int)ni, ctx->d_items, max_nb, ctx->stream,
+                                  step0 + s + 1);
+        if (e == hipSuccess)
+            e = launch_sweep(adjoint, false, f32, (int)ni, ctx->d_items + (((nsteps - 1) & 1) ? 2 * ni : ni), 1,
+                             max_nb, ctx->stream, step0 + nsteps - 1);
+        if (e != hipSuccess) return hipfail(ctx, e, "paired sweep launch");
+    }
     if (record && ctx->prof) {
         if ((e = hipEventRecord(rec.b, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "profile event");
         ctx->prof_recs.push_back(rec);

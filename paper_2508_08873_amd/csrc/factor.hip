@@ -11,43 +11,59 @@ namespace lrpr {
 // first-order upwind (the upwind neighbour is the west/south one for a
 // positive velocity component), homogeneous Dirichlet boundary.  One thread
 // per band entry.
+//
+// Reversed assembly (rev): the matrix J Mp J of N = 16 NT rows, with Mp =
+// diag(M, I) padded to whole tile rows and J the row reversal.  Its LU,
+// J Mp J = Lr Ur, gives the UL factorisation Mp = (J Lr J)(J Ur J): an upper
+// factor with unit diagonal times a lower one.
 // ---------------------------------------------------------------------------
-__global__ void k_assemble(lrpr_op_desc op, int64_t n, int bw, double *band) {
-    const int W = 2 * bw + 1;
-    const int64_t total = n * W;
+__device__ inline double m_entry(const lrpr_op_desc &op, int64_t n, int64_t i, int64_t jcol) {
+    if (jcol < 0 || jcol >= n) return 0.0;
     const double h = 1.0 / (double)(op.nx + 1);
     const double dif = op.nu / (h * h);
     const double b1 = op.beta1, b2 = op.dim == 2 ? op.beta2 : 0.0;
+    if (op.dim == 1) {
+        if (jcol == i) return 1.0 + op.dt * (2.0 * dif + fabs(b1) / h + op.c);
+        if (jcol == i - 1) return op.dt * (-dif - fmax(b1, 0.0) / h);
+        if (jcol == i + 1) return op.dt * (-dif - fmax(-b1, 0.0) / h);
+        return 0.0;
+    }
+    const int nx = op.nx;
+    const int64_t ix = i % nx;
+    if (jcol == i) return 1.0 + op.dt * (4.0 * dif + (fabs(b1) + fabs(b2)) / h + op.c);
+    if (jcol == i - 1 && ix > 0) return op.dt * (-dif - fmax(b1, 0.0) / h);
+    if (jcol == i + 1 && ix < nx - 1) return op.dt * (-dif - fmax(-b1, 0.0) / h);
+    if (jcol == i - nx) return op.dt * (-dif - fmax(b2, 0.0) / h);
+    if (jcol == i + nx) return op.dt * (-dif - fmax(-b2, 0.0) / h);
+    return 0.0;
+}
+
+// rows: n (plain) or N (reversed); n is the operator's size
+__global__ void k_assemble(lrpr_op_desc op, int64_t n, int64_t rows, int bw, bool rev, double *band) {
+    const int W = 2 * bw + 1;
+    const int64_t total = rows * W;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / W;
-        const int d = (int)(e - i * W);
-        const int64_t jcol = i - bw + d;
+        const int64_t r = e / W;
+        const int d = (int)(e - r * W);
+        const int64_t cidx = r - bw + d;
         double v = 0.0;
-        if (jcol >= 0 && jcol < n) {
-            if (op.dim == 1) {
-                if (jcol == i) v = 1.0 + op.dt * (2.0 * dif + fabs(b1) / h + op.c);
-                else if (jcol == i - 1) v = op.dt * (-dif - fmax(b1, 0.0) / h);
-                else if (jcol == i + 1) v = op.dt * (-dif - fmax(-b1, 0.0) / h);
-            } else {
-                const int nx = op.nx;
-                const int64_t ix = i % nx;
-                if (jcol == i) v = 1.0 + op.dt * (4.0 * dif + (fabs(b1) + fabs(b2)) / h + op.c);
-                else if (jcol == i - 1 && ix > 0) v = op.dt * (-dif - fmax(b1, 0.0) / h);
-                else if (jcol == i + 1 && ix < nx - 1) v = op.dt * (-dif - fmax(-b1, 0.0) / h);
-                else if (jcol == i - nx) v = op.dt * (-dif - fmax(b2, 0.0) / h);
-                else if (jcol == i + nx) v = op.dt * (-dif - fmax(-b2, 0.0) / h);
-            }
+        if (!rev) {
+            v = m_entry(op, n, r, cidx);
+        } else if (cidx >= 0 && cidx < rows) {
+            const int64_t i = rows - 1 - r, j = rows - 1 - cidx;
+            v = (i < n && j < n) ? m_entry(op, n, i, j) : (i == j ? 1.0 : 0.0);
         }
         band[e] = v;
     }
 }
 
-hipError_t launch_assemble(const lrpr_op_desc &op, int64_t n, int bw, double *band, hipStream_t s) {
-    const int64_t total = n * (2 * bw + 1);
+hipError_t launch_assemble(const lrpr_op_desc &op, int64_t n, int64_t rows, int bw, bool rev, double *band,
+                           hipStream_t s) {
+    const int64_t total = rows * (2 * bw + 1);
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(256), 0, s, op, n, bw, band);
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(256), 0, s, op, n, rows, bw, rev, band);
     return hipGetLastError();
 }
 
@@ -65,6 +81,30 @@ __device__ inline double lu_at(const double *lu, int64_t n, int bw, int64_t i, i
     if (d < -bw || d > bw) return 0.0;
     return lu[i * (2 * bw + 1) + d + bw];
 }
+
+// The two triangular factors of a band LU of `rows` rows, in the operator's
+// row order.  Plain (M = L U): lower = L (unit diagonal), upper = U, rows
+// beyond n padded with the identity.  Reversed (the LU Lr Ur of J Mp J):
+// upper = J Lr J (unit diagonal), lower = J Ur J, so that Mp = upper * lower.
+struct LuAcc {
+    const double *lu;
+    int64_t n, rows;
+    int bw;
+    bool rev;
+    __device__ double at(int64_t i, int64_t j) const {
+        return rev ? lu_at(lu, rows, bw, rows - 1 - i, rows - 1 - j) : lu_at(lu, n, bw, i, j);
+    }
+    // element (i, j) of the lower factor, j <= i
+    __device__ double lower(int64_t i, int64_t j) const {
+        if (j == i && !rev) return 1.0;
+        return at(i, j);
+    }
+    // element (i, j) of the upper factor, j >= i
+    __device__ double upper(int64_t i, int64_t j) const {
+        if (j == i && (rev || i >= n)) return 1.0;
+        return at(i, j);
+    }
+};
 
 // position of element (row m, contraction k) of an A-operand tile
 __device__ inline int aslot(bool f32, int m, int k) {
@@ -86,8 +126,8 @@ struct BandOut {
     void *b[4];   // Lb, Ub, UTb, LTb (null: not stored)
 };
 
-__global__ void k_pack_band(int64_t n, int bw, int NT, int nb, const double *lu, const double *Linv,
-                            const double *Uinv, BandOut o64, BandOut o32) {
+__global__ void k_pack_band(LuAcc F, int NT, int nb, const double *Linv, const double *Uinv, BandOut o64,
+                            BandOut o32) {
     const int64_t total = (int64_t)NT * nb * TILE_ELEMS;
     const bool mirror = o64.b[2] || o32.b[2];
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -104,11 +144,11 @@ __global__ void k_pack_band(int64_t n, int bw, int NT, int nb, const double *lu,
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         for (int k = 0; k < TILE; ++k) {
             const int64_t i = base + k;
-            v[0] += Li[r * TILE + k] * lu_at(lu, n, bw, i, jl);        // L(I, J)[k][q]
-            v[1] += Ui[r * TILE + k] * lu_at(lu, n, bw, i, ju);        // U(I, J)[k][q]
+            v[0] += Li[r * TILE + k] * F.lower(i, jl);        // L(I, J)[k][q]
+            v[1] += Ui[r * TILE + k] * F.upper(i, ju);        // U(I, J)[k][q]
             if (mirror) {
-                v[2] += Ui[k * TILE + r] * lu_at(lu, n, bw, jl, i);    // U(J, I)[q][k]
-                v[3] += Li[k * TILE + r] * lu_at(lu, n, bw, ju, i);    // L(J, I)[q][k]
+                v[2] += Ui[k * TILE + r] * F.upper(jl, i);    // U(J, I)[q][k]
+                v[3] += Li[k * TILE + r] * F.lower(ju, i);    // L(J, I)[q][k]
             }
         }
         const int64_t dst = tileidx * TILE_ELEMS;
@@ -121,25 +161,24 @@ __global__ void k_pack_band(int64_t n, int bw, int NT, int nb, const double *lu,
 
 // Phase 1: FP64 inverses of the diagonal tiles, natural row-major 16x16 per
 // tile row (scratch).  One thread per (tile row, column of the inverse).
-__global__ void k_diag_inv(int64_t n, int bw, int NT, const double *lu, double *Linv, double *Uinv) {
+__global__ void k_diag_inv(LuAcc F, int NT, double *Linv, double *Uinv) {
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (tid >= (int64_t)NT * TILE) return;
     const int64_t I = tid / TILE;
     const int col = (int)(tid % TILE);
     const int64_t base = I * TILE;
     double xl[TILE], xu[TILE];
-    // column `col` of L_II^{-1}: forward substitution on e_col (unit diagonal)
+    // column `col` of L_II^{-1}: forward substitution on e_col
     for (int r = 0; r < TILE; ++r) {
         double v = (r == col) ? 1.0 : 0.0;
-        for (int q = 0; q < r; ++q) v -= lu_at(lu, n, bw, base + r, base + q) * xl[q];
-        xl[r] = v;
+        for (int q = 0; q < r; ++q) v -= F.lower(base + r, base + q) * xl[q];
+        xl[r] = v / F.lower(base + r, base + r);
     }
-    // column `col` of U_II^{-1}: back substitution; padded rows are identity
+    // column `col` of U_II^{-1}: back substitution
     for (int r = TILE - 1; r >= 0; --r) {
         double v = (r == col) ? 1.0 : 0.0;
-        for (int q = r + 1; q < TILE; ++q) v -= lu_at(lu, n, bw, base + r, base + q) * xu[q];
-        const double d = (base + r < n) ? lu_at(lu, n, bw, base + r, base + r) : 1.0;
-        xu[r] = v / d;
+        for (int q = r + 1; q < TILE; ++q) v -= F.upper(base + r, base + q) * xu[q];
+        xu[r] = v / F.upper(base + r, base + r);
     }
     for (int r = 0; r < TILE; ++r) {
         Linv[I * TILE_ELEMS + r * TILE + col] = xl[r];
@@ -170,11 +209,12 @@ __global__ void k_pack_diag(int NT, const double *Linv, const double *Uinv, Diag
     }
 }
 
-hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu, const TileSet *t64,
+hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu, bool rev, const TileSet *t64,
                              const TileSet *t32, double *scratch, hipStream_t s) {
     const int64_t th = (int64_t)NT * TILE;
     double *Linv = scratch, *Uinv = scratch + (size_t)NT * TILE_ELEMS;
-    hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, n, bw, NT, lu, Linv, Uinv);
+    const LuAcc F{lu, n, (int64_t)NT * TILE, bw, rev};
+    hipLaunchKernelGGL(k_diag_inv, dim3((unsigned)((th + 127) / 128)), dim3(128), 0, s, F, NT, Linv, Uinv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t total = (int64_t)NT * nb * TILE_ELEMS;
@@ -187,7 +227,7 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
         b64.b[a] = t64 ? t64->a[bidx[a]] : nullptr;
         b32.b[a] = t32 ? t32->a[bidx[a]] : nullptr;
     }
-    hipLaunchKernelGGL(k_pack_band, dim3((unsigned)blocks), dim3(256), 0, s, n, bw, NT, nb, lu, Linv, Uinv, b64, b32);
+    hipLaunchKernelGGL(k_pack_band, dim3((unsigned)blocks), dim3(256), 0, s, F, NT, nb, Linv, Uinv, b64, b32);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     DiagOut o64{}, o32{};
     const int didx[4] = {TS_DL, TS_DU, TS_DLT, TS_DUT};

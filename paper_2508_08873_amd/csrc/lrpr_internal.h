@@ -57,8 +57,11 @@ struct TileSet {            // device arrays of one precision (pointers to tile 
 };
 
 // Device-side view of one factor, passed by value to the sweep kernels.
+// ar: the tiles of the UL factorisation M = U' L' in the same layout (Lb and
+// DL hold L', Ub and DU hold U'), or null.
 struct FacView {
     const void *a[TS_COUNT];
+    const void *ar[TS_COUNT];
     const void *zt;
     void *sink;
     int n, NT, nb;
@@ -124,6 +127,7 @@ struct lrpr_factor_s {
     std::vector<lrpr_factor_s *> seq;   // LRPR_STEP_SEQUENCE: the owned per-step factors
     double *lu = nullptr;          // FP64 band LU, n x (2bw+1) row-major (kept with LRPR_STORE_F64)
     lrpr::TileSet t64, t32;
+    lrpr::TileSet t64r, t32r;      // UL factorisation (LRPR_STORE_UL)
     // partitioned forward solves (LRPR_STORE_SPLIT): P blocks, starts blk
     int P = 0;
     std::vector<int> blk;
@@ -169,20 +173,33 @@ inline int fac_stages(const lrpr_factor_s *f) { return (f->stepper == 1 || f->st
 lrpr_status fail(lrpr_ctx ctx, lrpr_status st, const std::string &msg);
 
 // kernels launched from the host code (defined in the .hip sources)
-hipError_t launch_assemble(const lrpr_op_desc &op, int64_t n, int bw, double *band, hipStream_t s);
+// rev: assemble J diag(M, I) J with rows = 16 NT (its LU gives the UL factorisation of M)
+hipError_t launch_assemble(const lrpr_op_desc &op, int64_t n, int64_t rows, int bw, bool rev, double *band,
+                           hipStream_t s);
 // pipelined tile LU (lu.hip): scratch of tile_lu_scratch_bytes(NT, nb) per matrix
 size_t tile_lu_scratch_bytes(int NT, int nb);
-// count independent factorisations of one shape (band and scratch per matrix)
-hipError_t launch_tile_lu_batch(int count, int64_t n, int bw, int NT, int nb, double *const *bands,
+// count independent factorisations of one tile shape (rows ns[i], band and
+// scratch per matrix)
+hipError_t launch_tile_lu_batch(int count, const int64_t *ns, int bw, int NT, int nb, double *const *bands,
                                 void *const *scratch, int **info_dev, int **err_dev, void *d_args, hipStream_t s);
 size_t tile_lu_args_bytes(int count);
-hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu, const TileSet *t64,
+// rev: lu is the LU of the reversed matrix (16 NT rows); the sets then hold
+// the UL factors (Lb / DL: the lower factor, Ub / DU: the upper one)
+hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu, bool rev, const TileSet *t64,
                              const TileSet *t32, double *scratch, hipStream_t s);
 // adjoint sweeps read the mirrored set unless `strided` (then the forward
 // tiles are read transposed); `local`: forward block solves of a partitioned
 // pass (same code, launched as k_sweep_local)
 hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const SweepItem *d_items, int nsteps,
                         int max_nb, hipStream_t s, int step0 = 0, bool local = false);
+// One pass pair over full-range items whose factors all carry the UL set
+// (mirrored too for the adjoint) and have nb band tiles per row, with
+// sweep_pairable(nb).  Descending (asc false): the second substitution of an
+// L U step with the first of the next U' L' step; ascending: the second of a
+// U' L' step with the first of the next L U step.  stepB: pass B's step.
+hipError_t launch_sweep_pair(bool adjoint, bool asc, bool f32, int nitems, const SweepItem *d_items, int nb,
+                             hipStream_t s, int stepB);
+bool sweep_pairable(int nb);
 // out = ca a + cb b + cc c on an n x w block (column-major, own leading
 // dimensions; c may be null), element type of the precision (dense.hip)
 hipError_t launch_combine3(bool f32, void *out, int64_t ldo, const void *a, int64_t lda, double ca, const void *b,

@@ -314,12 +314,12 @@ size_t tile_lu_scratch_bytes(int NT, int nb) {
 // on return info_dev[i] / err_dev[i] point into its scratch (pivot info:
 // 0x7f7f7f7f if all pivots are fine, else the first bad row + 1; err:
 // nonzero on a wait time-out).  d_args: device space for count LuArgs.
-hipError_t launch_tile_lu_batch(int count, int64_t n, int bw, int NT, int nb, double *const *bands,
+hipError_t launch_tile_lu_batch(int count, const int64_t *ns, int bw, int NT, int nb, double *const *bands,
                                 void *const *scratch, int **info_dev, int **err_dev, void *d_args, hipStream_t s) {
     std::vector<LuArgs> hv(count);
     for (int i = 0; i < count; ++i) {
         LuArgs &a = hv[i];
-        a.n = n;
+        a.n = ns[i];
         a.bw = bw;
         a.NT = NT;
         a.nb = nb;

@@ -481,6 +481,459 @@ __device__ __forceinline__ void sweep_items(const SweepItem *__restrict__ items,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Pass pairs.  With both M = L U and M = U' L' stored, consecutive steps
+// alternate between the two factorisations, so that the second substitution
+// of one step and the first of the next run in the same direction:
+//   forward: U (step s) with U' (step s+1), then L' (s+1) with L (s+2);
+//   adjoint: L^T with L'^T, then U'^T with U^T.
+// Pass B (the first substitution of the later step) solves tile row q-2 in
+// the period where pass A solves row q.  Its right-hand side D_B (v_A + dt phi
+// f) is formed from pass A's solution while that is still in LDS, so the
+// state between the two passes never goes to HBM, and every barrier period
+// carries the matrix-core work of two tile rows.
+//
+// Waves (KW = 8), one LDS barrier per period; iteration q ends with barrier
+// q+1 (bulk, helpers) or starts with it (finisher):
+//   wave 0      finisher: rows q of A and q-2 of B, the two chains interleaved;
+//   waves 1..5  bulk: partial sums of rows q (A) and q-2 (B) over the older
+//               band tiles, each a fixed share of the 2 (nb-1) tiles;
+//   wave 6      factor helper: hands over the newest tiles of rows q+1 (A)
+//               and q-1 (B); writes B's solution of row q-4 to HBM;
+//   wave 7      state helper: hands over r_A = D_A x of row q (x from HBM)
+//               and r_B = D_B (v_A + dt phi f) of row q-2 (v_A from A's ring).
+// ---------------------------------------------------------------------------
+
+// Shares of the 2 (NB-1) combined bulk tiles (A's tiles first, then B's) of
+// the five bulk waves; waves w and w+4 share a SIMD, the finisher sits with
+// wave 4 and the state helper (two tile products per period) with wave 3.
+template <int C1, int C2, int C3, int C4, int C5>
+struct Split2 {
+    __host__ __device__ static constexpr int cn(int wb) {
+        return wb == 0 ? C1 : wb == 1 ? C2 : wb == 2 ? C3 : wb == 3 ? C4 : C5;
+    }
+    __host__ __device__ static constexpr int st(int wb) {
+        return (wb > 0 ? C1 : 0) + (wb > 1 ? C2 : 0) + (wb > 2 ? C3 : 0) + (wb > 3 ? C4 : 0);
+    }
+    __host__ __device__ static constexpr int total() { return C1 + C2 + C3 + C4 + C5; }
+    __host__ __device__ static constexpr bool hasA(int wb) { return cn(wb) > 0 && st(wb) < total() / 2; }
+    __host__ __device__ static constexpr bool hasB(int wb) { return cn(wb) > 0 && st(wb) + cn(wb) > total() / 2; }
+    // bit wb: bulk wave wb has tiles of pass A (maskA) / pass B (maskB)
+    static constexpr unsigned maskA =
+        (hasA(0) ? 1u : 0u) | (hasA(1) ? 2u : 0u) | (hasA(2) ? 4u : 0u) | (hasA(3) ? 8u : 0u) | (hasA(4) ? 16u : 0u);
+    static constexpr unsigned maskB =
+        (hasB(0) ? 1u : 0u) | (hasB(1) ? 2u : 0u) | (hasB(2) ? 4u : 0u) | (hasB(3) ? 8u : 0u) | (hasB(4) ? 16u : 0u);
+};
+
+constexpr int PAIR_PDH = 3;   // helpers' prefetch depth in pass pairs
+// tiles whose ring operands a bulk wave reads ahead of its products
+#ifndef LRPR_PAIR_RA32
+#define LRPR_PAIR_RA32 16
+#endif
+// prefetch depth (tile rows) of the bulk waves in pass pairs
+#ifndef LRPR_PAIR_PD32
+#define LRPR_PAIR_PD32 5
+#endif
+#ifndef LRPR_PAIR_PD64
+#define LRPR_PAIR_PD64 2
+#endif
+#ifndef LRPR_PAIR_RA64
+#define LRPR_PAIR_RA64 16
+#endif
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+
+// Buffer loads of lane-major tiles: an SGPR resource over a whole tile
+// array, one VGPR lane offset shared by every load, the tile's byte offset
+// in an SGPR (no per-lane 64-bit addresses to keep live across the prefetch).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+// (The 128-bit result is reinterpreted as a whole vector: casting its
+// elements one by one lets the compiler shrink the load to one dword.)
+template <typename T> struct BufTile;
+template <> struct BufTile<float> {
+    __device__ static inline void ld4(rsrc_t r, uint32_t voff, uint32_t soff, float (&v)[4]) {
+        const f4v x = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+        v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+    }
+};
+template <> struct BufTile<double> {
+    __device__ static inline void ld4(rsrc_t r, uint32_t voff, uint32_t soff, double (&v)[4]) {
+        const d2v x = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+        const d2v y =
+            __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff + 1024, 0));
+        v[0] = x[0]; v[1] = x[1]; v[2] = y[0]; v[3] = y[1];
+    }
+};
+
+// One pass of a pair (left form, full range, every factor of the launch
+// with NB band tiles per row).  Tile rows outside [0, NT) are clamped to
+// rows -1 and NT, guard rows of zero tiles.
+template <typename T, int NB, bool ASC>
+struct PairPass {
+    typedef typename Mf<T>::v4 v4;
+    static constexpr int RS = NB + 1;          // ring slots (+1 dummy slot at RS)
+    static constexpr int G = NB + 8;           // guard tile rows before and after the arrays
+    static constexpr uint32_t TB = TILE_ELEMS * sizeof(T);   // bytes per tile
+    rsrc_t rband, rdiag;                       // from guard row -G on
+    T *ring;
+    int NT, n, lane, g;
+    uint32_t voff;                             // this lane's byte offset in a tile
+    __device__ PairPass(const SweepItem &it, const T *band, const T *dtile, T *ring_) : ring(ring_) {
+        NT = it.fac.NT;
+        n = it.fac.n;
+        lane = threadIdx.x & 63;
+        g = lane >> 4;
+        voff = 16u * (uint32_t)lane;
+        const uint32_t rows = (uint32_t)(NT + 2 * G);
+        rband = make_rsrc(band - (int64_t)G * NB * TILE_ELEMS, rows * NB * TB);
+        rdiag = make_rsrc(dtile - (int64_t)G * TILE_ELEMS, rows * TB);
+    }
+    __device__ __forceinline__ int row_of(int q) const { return ASC ? q : NT - 1 - q; }
+    __device__ __forceinline__ int row_clamped(int q) const {
+        q = q < -1 ? -1 : (q > NT ? NT : q);
+        return row_of(q);
+    }
+    // byte offset of the band tiles of row q (bulk tile idx: j = idx ascending, idx + 1 descending)
+    __device__ __forceinline__ uint32_t row_off(int q) const { return (uint32_t)(row_clamped(q) + G) * NB * TB; }
+    static constexpr uint32_t bulk_off(int idx) { return (uint32_t)(ASC ? idx : idx + 1) * TB; }
+    // tile at byte offset `toff` within row offset `roff` (the row offset in
+    // the scalar operand, the tile's position in the lane's vector offset)
+    __device__ __forceinline__ void ld_band(uint32_t roff, uint32_t toff, T (&v)[4]) const {
+        BufTile<T>::ld4(rband, voff + toff, roff, v);
+    }
+    // ring slot of bulk tile idx, sI being the slot of the row being solved
+    __device__ __forceinline__ int slot(int sI, int idx) const {
+        const int s = sI + (ASC ? 1 : 2) + idx;
+        return s >= RS ? s - RS : s;
+    }
+    __device__ __forceinline__ int first_slot() const { return row_of(0) % RS; }
+    __device__ __forceinline__ int next_slot(int sI) const {
+        return ASC ? (sI + 1 == RS ? 0 : sI + 1) : (sI == 0 ? RS - 1 : sI - 1);
+    }
+    __device__ __forceinline__ void load_newest(int q, T (&v)[4]) const {
+        ld_band(row_off(q), (uint32_t)(ASC ? NB - 1 : 0) * TB, v);
+    }
+    __device__ __forceinline__ void load_d(int q, T (&v)[4]) const {
+        BufTile<T>::ld4(rdiag, voff, (uint32_t)(row_clamped(q) + G) * TB, v);
+    }
+    // rows of one column of a state array (accumulator order), clamped into [0, n)
+    __device__ __forceinline__ void load_rows(int q, const T *base, int64_t stride, T (&v)[4]) const {
+        const int I = row_of(q);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int row = I * TILE + Mf<T>::row(g, i);
+            row = row < 0 ? 0 : (row >= n ? n - 1 : row);
+            v[i] = gld(base + (int64_t)row * stride);
+        }
+    }
+    __device__ __forceinline__ v4 dmul(const T (&d)[4], const v4 &t) const {
+        v4 y = {0, 0, 0, 0};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) y = Mf<T>::mma(d[kc], t[kc], y);
+        return y;
+    }
+};
+
+template <typename T, int NB, typename SP, int PD, bool ASC, int WB>
+__device__ __forceinline__ void pair_bulk(const PairPass<T, NB, ASC> &PA, const PairPass<T, NB, ASC> &PB, T *red,
+                                          int NQ) {
+    typedef typename Mf<T>::v4 v4;
+    constexpr int ST = SP::st(WB), CN = SP::cn(WB), NBM = NB - 1, NBW = 5;
+    constexpr int RA = sizeof(T) == 8 ? LRPR_PAIR_RA64 : LRPR_PAIR_RA32;   // ring read-ahead (tiles)
+    static_assert(SP::total() == 2 * NBM, "the shares must cover both passes' bulk tiles");
+    const int lane = PA.lane;
+    T ab[PD][CN][4];
+    typedef PairPass<T, NB, ASC> PS;
+    // tiles of A's row q and B's row q-2
+    auto load = [&](int q, T (&buf)[CN][4]) {
+        const uint32_t oa = PA.row_off(q), ob = PB.row_off(q - 2);
+#pragma unroll
+        for (int t = 0; t < CN; ++t) {
+            const bool isB = ST + t >= NBM;
+            const int idx = isB ? ST + t - NBM : ST + t;
+            if (isB) PB.ld_band(ob, PS::bulk_off(idx), buf[t]);
+            else PA.ld_band(oa, PS::bulk_off(idx), buf[t]);
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < PD - 1; ++u) load(u, ab[u]);
+    lds_barrier();
+    int sA = PA.first_slot(), sB = sA;
+    for (int q0 = 0; q0 < NQ; q0 += PD) {
+#pragma unroll
+        for (int u = 0; u < PD; ++u) {
+            const int q = q0 + u;
+            load(q + PD - 1, ab[(u + PD - 1) % PD]);
+            __builtin_amdgcn_sched_barrier(0);
+            // ring operands (B operands, accumulator order) of the wave's tiles
+            T bv[CN][4];
+            auto ring_read = [&](int t) {
+                const bool isB = ST + t >= NBM;
+                const int idx = isB ? ST + t - NBM : ST + t;
+                const T *rj = isB ? PB.ring + PB.slot(sB, idx) * TILE_ELEMS : PA.ring + PA.slot(sA, idx) * TILE_ELEMS;
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) bv[t][kc] = rj[64 * kc + lane];
+            };
+            v4 a2[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, b2[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+            auto tile_mma = [&](int t) {
+                const bool isB = ST + t >= NBM;
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) {
+                    if (isB) b2[t & 1] = Mf<T>::mma(ab[u][t][kc], bv[t][kc], b2[t & 1]);
+                    else a2[t & 1] = Mf<T>::mma(ab[u][t][kc], bv[t][kc], a2[t & 1]);
+                }
+            };
+#pragma unroll
+            for (int t = 0; t < CN; ++t) ring_read(t);
+            if constexpr (RA >= CN) {
+                // every ring read issued before the first product
+                __builtin_amdgcn_sched_barrier(0);
+            } else {
+                // ring reads RA tiles ahead of the products (two LDS reads
+                // and four products per tile)
+                __builtin_amdgcn_sched_group_barrier(0x100, 2 * RA, 0);
+#pragma unroll
+                for (int t = 0; t + RA < CN; ++t) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, 4 * RA, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < CN; ++t) tile_mma(t);
+            T *rd = red + (q & 1) * 2 * NBW * TILE_ELEMS;
+            if constexpr ((SP::maskA >> WB) & 1u) {
+                const v4 acc = a2[0] + a2[1];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) rd[WB * TILE_ELEMS + i * 64 + lane] = acc[i];
+            }
+            if constexpr ((SP::maskB >> WB) & 1u) {
+                const v4 acc = b2[0] + b2[1];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) rd[(NBW + WB) * TILE_ELEMS + i * 64 + lane] = acc[i];
+            }
+            sA = PA.next_slot(sA);
+            if (q >= 2) sB = PB.next_slot(sB);
+            lds_barrier();
+        }
+    }
+}
+
+template <typename T, int NB, typename SP, int PD, bool ASC>
+__device__ __forceinline__ void sweep_pair(const SweepItem &it, const T *__restrict__ bandA,
+                                           const T *__restrict__ dA, const T *__restrict__ bandB,
+                                           const T *__restrict__ dB, T *ringA, T *ringB, T *red, T *hand,
+                                           bool with_src, int stepB) {
+    typedef typename Mf<T>::v4 v4;
+    typedef PairPass<T, NB, ASC> PS;
+    constexpr int NBW = 5, PDH = PAIR_PDH, RS = PS::RS;
+    constexpr int PQ = PD / gcd_c(PD, PDH) * PDH;   // both unroll depths divide the period count
+    PS PA(it, bandA, dA, ringA), PB(it, bandB, dB, ringB);
+    const int NT = PA.NT, lane = PA.lane, g = PA.g, n = PA.n;
+    const int c = lane & 15;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // A's rows 0..NT-1; B's rows trail by 2, and its output by 2 more
+    const int NQ = (NT + 4 + PQ - 1) / PQ * PQ;
+    T *X = (T *)it.X;
+    const int64_t ldx = it.ldx;
+    const bool colok = c < it.ncols;
+    const int col = colok ? c : 0;
+    // pass B's source: f(x) * dt * phi(t_stepB), or the zero tile
+    const T *fsrc = (const T *)it.fac.zt;
+    int64_t fstride = 0;
+    T fs = 0;
+    if (with_src && colok) {
+        const int fc = it.fcol ? gld(it.fcol + c) : 0;
+        if (fc >= 0) {
+            fsrc = (const T *)it.f + (int64_t)fc * it.ldf;
+            fstride = 1;
+            const double sc = it.fscale ? gld(it.fscale + (int64_t)c * it.fsteps + stepB) : 1.0;
+            fs = (T)(it.fac.dt * sc);
+        }
+    }
+    if (w == 0) {
+        v4 tA = {0, 0, 0, 0}, tB = {0, 0, 0, 0};
+        int sA = PA.first_slot(), sB = sA;
+        lds_barrier();
+        for (int q = 0; q < NQ; ++q) {
+            lds_barrier();
+            const T *h = hand + (q & 1) * 4 * TILE_ELEMS;   // E_A, r_A, E_B, r_B
+            const T *rd = red + (q & 1) * 2 * NBW * TILE_ELEMS;
+            T eA[4], eB[4];
+            v4 vA, vB;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                T a = tA[i], b = tB[i];
+#pragma unroll
+                for (int wb = 0; wb < NBW; ++wb) {
+                    if ((SP::maskA >> wb) & 1u) a += rd[wb * TILE_ELEMS + i * 64 + lane];
+                    if ((SP::maskB >> wb) & 1u) b += rd[(NBW + wb) * TILE_ELEMS + i * 64 + lane];
+                }
+                vA[i] = h[TILE_ELEMS + i * 64 + lane] - a;
+                vB[i] = h[3 * TILE_ELEMS + i * 64 + lane] - b;
+                eA[i] = h[i * 64 + lane];
+                eB[i] = h[2 * TILE_ELEMS + i * 64 + lane];
+            }
+            T *ra = ringA + (q < NT ? sA : RS) * TILE_ELEMS;
+            T *rb = ringB + ((q >= 2 && q - 2 < NT) ? sB : RS) * TILE_ELEMS;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                ra[i * 64 + lane] = vA[i];
+                rb[i * 64 + lane] = vB[i];
+            }
+            // t = E v for both chains, interleaved on the matrix core
+            v4 ya = {0, 0, 0, 0}, yb = {0, 0, 0, 0};
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) {
+                ya = Mf<T>::mma(eA[kc], vA[kc], ya);
+                yb = Mf<T>::mma(eB[kc], vB[kc], yb);
+            }
+            tA = ya;
+            tB = yb;
+            sA = PA.next_slot(sA);
+            if (q >= 2) sB = PB.next_slot(sB);
+        }
+        __syncthreads();
+    } else if (w <= NBW) {
+        switch (w) {
+            case 1: pair_bulk<T, NB, SP, PD, ASC, 0>(PA, PB, red, NQ); break;
+            case 2: pair_bulk<T, NB, SP, PD, ASC, 1>(PA, PB, red, NQ); break;
+            case 3: pair_bulk<T, NB, SP, PD, ASC, 2>(PA, PB, red, NQ); break;
+            case 4: pair_bulk<T, NB, SP, PD, ASC, 3>(PA, PB, red, NQ); break;
+            default: pair_bulk<T, NB, SP, PD, ASC, 4>(PA, PB, red, NQ); break;
+        }
+        __syncthreads();
+    } else if (w == NBW + 1) {
+        // factor helper
+        T bA[PDH][4], bB[PDH][4];
+#pragma unroll
+        for (int u = 0; u < PDH - 1; ++u) {
+            PA.load_newest(u + 1, bA[u]);
+            PB.load_newest(u - 1, bB[u]);
+        }
+        lds_barrier();
+        T *sink = (T *)it.fac.sink;
+        int so = PB.first_slot();
+        for (int q0 = 0; q0 < NQ; q0 += PDH) {
+#pragma unroll
+            for (int u = 0; u < PDH; ++u) {
+                const int q = q0 + u;
+                const int un = (u + PDH - 1) % PDH;
+                PA.load_newest(q + PDH, bA[un]);
+                PB.load_newest(q + PDH - 2, bB[un]);
+                __builtin_amdgcn_sched_barrier(0);
+                T *h = hand + (q & 1) * 4 * TILE_ELEMS;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    h[i * 64 + lane] = bA[u][i];
+                    h[2 * TILE_ELEMS + i * 64 + lane] = bB[u][i];
+                }
+                if (q >= 4) {
+                    // B's row q-4: in its ring since this period's barrier
+                    const int qo = q - 4;
+                    const T *ro = ringB + so * TILE_ELEMS;
+                    const int Irow = PB.row_of(qo);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = Irow * TILE + Mf<T>::row(g, i);
+                        const T v = ro[i * 64 + lane];
+                        gst((qo < NT && colok && row < n) ? X + row + (int64_t)c * ldx : sink + lane, v);
+                    }
+                    so = PB.next_slot(so);
+                }
+                lds_barrier();
+            }
+        }
+        __syncthreads();
+    } else {
+        // state helper
+        const T *xcol = X + (int64_t)col * ldx;
+        T xb[PDH][4], da[PDH][4], fb[PDH][4], db[PDH][4];
+#pragma unroll
+        for (int u = 0; u < PDH - 1; ++u) {
+            PA.load_rows(u, xcol, 1, xb[u]);
+            PA.load_d(u, da[u]);
+            PB.load_rows(u - 2, fsrc, fstride, fb[u]);
+            PB.load_d(u - 2, db[u]);
+        }
+        lds_barrier();
+        int so = PA.first_slot();
+        for (int q0 = 0; q0 < NQ; q0 += PDH) {
+#pragma unroll
+            for (int u = 0; u < PDH; ++u) {
+                const int q = q0 + u;
+                const int un = (u + PDH - 1) % PDH;
+                PA.load_rows(q + PDH - 1, xcol, 1, xb[un]);
+                PA.load_d(q + PDH - 1, da[un]);
+                PB.load_rows(q + PDH - 3, fsrc, fstride, fb[un]);
+                PB.load_d(q + PDH - 3, db[un]);
+                __builtin_amdgcn_sched_barrier(0);
+                v4 x;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) x[i] = xb[u][i];
+                const v4 rA = PA.dmul(da[u], x);
+                v4 rB = {0, 0, 0, 0};
+                if (q >= 2) {
+                    // A's row q-2: in its ring since this period's barrier
+                    const T *ro = ringA + so * TILE_ELEMS;
+                    v4 y;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) y[i] = ro[i * 64 + lane] + fs * fb[u][i];
+                    rB = PB.dmul(db[u], y);
+                    so = PA.next_slot(so);
+                }
+                T *h = hand + (q & 1) * 4 * TILE_ELEMS;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    h[TILE_ELEMS + i * 64 + lane] = rA[i];
+                    h[3 * TILE_ELEMS + i * 64 + lane] = rB[i];
+                }
+                lds_barrier();
+            }
+        }
+        __syncthreads();
+    }
+    // end of the pair: the next pass reads X rows written by this one
+    __syncthreads();
+}
+
+// One pass pair over every item (each item's factor carries the UL set and
+// has NB band tiles per row).  Descending pairs join the second substitution
+// of an L U step with the first of the following U' L' step; ascending pairs
+// the second substitution of a U' L' step with the first of the following
+// L U step.  stepB: the step of pass B (its source's time factor).
+template <typename T, int NB, typename SP, int PD, bool ASC, bool ADJ>
+__global__ __launch_bounds__(512) void k_sweep_pair(const SweepItem *__restrict__ items, int nitems, int stepB) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    for (int idx = blockIdx.x; idx < nitems; idx += gridDim.x) {
+        const SweepItem &it = items[idx];
+        T *ringA = (T *)smem;
+        T *ringB = ringA + (NB + 2) * TILE_ELEMS;
+        T *red = ringB + (NB + 2) * TILE_ELEMS;      // [2][2][5]
+        T *hand = red + 20 * TILE_ELEMS;             // [2][4]
+        const T *const *a = (const T *const *)it.fac.a;
+        const T *const *ar = (const T *const *)it.fac.ar;
+        // forward: U with U' (descending), L' with L (ascending);
+        // adjoint: L^T with L'^T (descending), U'^T with U^T (ascending)
+        const T *bA, *dA, *bB, *dB;
+        if (!ADJ) {
+            bA = ASC ? ar[TS_LB] : a[TS_UB];
+            dA = ASC ? ar[TS_DL] : a[TS_DU];
+            bB = ASC ? a[TS_LB] : ar[TS_UB];
+            dB = ASC ? a[TS_DL] : ar[TS_DU];
+        } else {
+            bA = ASC ? ar[TS_UTB] : a[TS_LTB];
+            dA = ASC ? ar[TS_DUT] : a[TS_DLT];
+            bB = ASC ? a[TS_UTB] : ar[TS_LTB];
+            dB = ASC ? a[TS_DUT] : ar[TS_DLT];
+        }
+        clear_ring(ringA, 2 * NB + 2);   // both rings
+        sweep_pair<T, NB, SP, PD, ASC>(it, bA, dA, bB, dB, ringA, ringB, red, hand, !ADJ && it.f != nullptr, stepB);
+    }
+}
+
 template <typename T, int KW, typename SP, int PD, bool ADJ, bool STRIDED>
 __global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__ items, int nitems, int nsteps,
                                                    int step0) {
@@ -535,6 +988,46 @@ static hipError_t launch_t(bool adjoint, bool strided, int nitems, const SweepIt
 // KW > 1: wave 0 finishes tile rows, five bulk waves share the nb-1 older
 // band tiles (Split: tiles per bulk wave), two helper waves stage the
 // finisher's operands and write the output.  Narrow bands run on one wave.
+template <typename T, int NB, typename SP, int PD>
+static hipError_t launch_pair_t(bool adjoint, bool asc, int nitems, const SweepItem *d_items, hipStream_t s,
+                                int stepB) {
+    // LDS: two rings, double-buffered partial sums of both passes, hand-offs
+    const size_t lds = (size_t)(2 * (NB + 2) + 20 + 8) * TILE_ELEMS * sizeof(T);
+    const int grid = nitems < 65536 ? nitems : 65536;
+    if (!adjoint && !asc)
+        hipLaunchKernelGGL((k_sweep_pair<T, NB, SP, PD, false, false>), dim3(grid), dim3(512), lds, s, d_items, nitems,
+                           stepB);
+    else if (!adjoint)
+        hipLaunchKernelGGL((k_sweep_pair<T, NB, SP, PD, true, false>), dim3(grid), dim3(512), lds, s, d_items, nitems,
+                           stepB);
+    else if (!asc)
+        hipLaunchKernelGGL((k_sweep_pair<T, NB, SP, PD, false, true>), dim3(grid), dim3(512), lds, s, d_items, nitems,
+                           stepB);
+    else
+        hipLaunchKernelGGL((k_sweep_pair<T, NB, SP, PD, true, true>), dim3(grid), dim3(512), lds, s, d_items, nitems,
+                           stepB);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_pair(bool adjoint, bool asc, bool f32, int nitems, const SweepItem *d_items, int nb,
+                             hipStream_t s, int stepB) {
+    if (nitems <= 0) return hipSuccess;
+    if (nb == 8) {
+        if (f32) return launch_pair_t<float, 8, Split2<2, 4, 3, 3, 2>, 5>(adjoint, asc, nitems, d_items, s, stepB);
+        return launch_pair_t<double, 8, Split2<2, 4, 3, 3, 2>, 3>(adjoint, asc, nitems, d_items, s, stepB);
+    }
+    if (nb == 16) {
+        if (f32)
+            return launch_pair_t<float, 16, Split2<5, 8, 7, 6, 4>, LRPR_PAIR_PD32>(adjoint, asc, nitems, d_items, s,
+                                                                                   stepB);
+        return launch_pair_t<double, 16, Split2<4, 7, 7, 7, 5>, LRPR_PAIR_PD64>(adjoint, asc, nitems, d_items, s,
+                                                                                 stepB);
+    }
+    return hipErrorInvalidValue;
+}
+
+bool sweep_pairable(int nb) { return nb == 8 || nb == 16; }
+
 template <typename T>
 static hipError_t launch_prec(bool adjoint, bool strided, int nitems, const SweepItem *d_items, int nsteps,
                               int max_nb, hipStream_t s, int step0, bool local) {

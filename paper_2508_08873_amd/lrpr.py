@@ -28,7 +28,7 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
 
 
 # lrpr_factor store_mask bits (include/lrpr.h)
-STORE_F64, STORE_F32, STORE_MIRROR, STORE_SPLIT = 1, 2, 4, 8
+STORE_F64, STORE_F32, STORE_MIRROR, STORE_SPLIT, STORE_UL = 1, 2, 4, 8, 16
 # lrpr_factor_stepper steppers
 STEP_EULER, STEP_SDIRK2, STEP_SDIRK2L, STEP_SEQUENCE = 0, 1, 2, 3
 
