@@ -677,13 +677,9 @@ __device__ __forceinline__ void pair_bulk(const PairPass<T, NB, ASC> &PA, const 
                 for (int kc = 0; kc < 4; ++kc) bv[t][kc] = rj[64 * kc + lane];
             };
             v4 a2[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, b2[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-            auto tile_mma = [&](int t) {
-                const bool isB = ST + t >= NBM;
-#pragma unroll
-                for (int kc = 0; kc < 4; ++kc) {
-                    if (isB) b2[t & 1] = Mf<T>::mma(ab[u][t][kc], bv[t][kc], b2[t & 1]);
-                    else a2[t & 1] = Mf<T>::mma(ab[u][t][kc], bv[t][kc], a2[t & 1]);
-                }
+            auto tile_mma = [&](int t, int kc) {
+                if (ST + t >= NBM) b2[t & 1] = Mf<T>::mma(ab[u][t][kc], bv[t][kc], b2[t & 1]);
+                else a2[t & 1] = Mf<T>::mma(ab[u][t][kc], bv[t][kc], a2[t & 1]);
             };
 #pragma unroll
             for (int t = 0; t < CN; ++t) ring_read(t);
@@ -701,8 +697,16 @@ __device__ __forceinline__ void pair_bulk(const PairPass<T, NB, ASC> &PA, const 
                 }
                 __builtin_amdgcn_sched_group_barrier(0x008, 4 * RA, 0);
             }
+            // tiles t and t+1 accumulate into different registers: their
+            // products alternate, so no product waits on the one before it
 #pragma unroll
-            for (int t = 0; t < CN; ++t) tile_mma(t);
+            for (int t = 0; t < CN; t += 2) {
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) {
+                    tile_mma(t, kc);
+                    if (t + 1 < CN) tile_mma(t + 1, kc);
+                }
+            }
             T *rd = red + (q & 1) * 2 * NBW * TILE_ELEMS;
             if constexpr ((SP::maskA >> WB) & 1u) {
                 const v4 acc = a2[0] + a2[1];
@@ -873,17 +877,19 @@ __device__ __forceinline__ void sweep_pair(const SweepItem &it, const T *__restr
                 v4 x;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) x[i] = xb[u][i];
-                const v4 rA = PA.dmul(da[u], x);
-                v4 rB = {0, 0, 0, 0};
-                if (q >= 2) {
-                    // A's row q-2: in its ring since this period's barrier
-                    const T *ro = ringA + so * TILE_ELEMS;
-                    v4 y;
+                // r_A = D_A x and r_B = D_B (v_A + dt phi f), products interleaved
+                // (B's row q-2 is negative, so D_B is the zero tile, before q = 2)
+                const T *ro = ringA + so * TILE_ELEMS;   // A's row q-2, in its ring since this barrier
+                v4 y;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) y[i] = ro[i * 64 + lane] + fs * fb[u][i];
-                    rB = PB.dmul(db[u], y);
-                    so = PA.next_slot(so);
+                for (int i = 0; i < 4; ++i) y[i] = ro[i * 64 + lane] + fs * fb[u][i];
+                v4 rA = {0, 0, 0, 0}, rB = {0, 0, 0, 0};
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) {
+                    rA = Mf<T>::mma(da[u][kc], x[kc], rA);
+                    rB = Mf<T>::mma(db[u][kc], y[kc], rB);
                 }
+                if (q >= 2) so = PA.next_slot(so);
                 T *h = hand + (q & 1) * 4 * TILE_ELEMS;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
