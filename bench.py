@@ -327,16 +327,17 @@ def per_step_operators(ctx, lrpr, inputs, prec, seed):
 
 
 def traffic_from_profile(prec):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
-    of this workload, if it was taken from the current sweep sources."""
+    """HBM bytes per range-finder sweep call from the committed rocprofv3
+    counter summary of this workload, if it was taken from the current sweep
+    sources."""
     from paper_2508_08873_amd import prof_summary
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_sweep_dar255_%s.json" % prec)
     if not os.path.exists(path):
         return None, None
     d = json.load(open(path))
-    if d.get("source_sha1") != prof_summary.sweep_source_hash() or "traffic_bytes_per_launch" not in d:
+    if d.get("source_sha1") != prof_summary.sweep_source_hash() or "traffic_bytes_per_sweep" not in d:
         return None, None
-    return d["traffic_bytes_per_launch"], d
+    return d["traffic_bytes_per_sweep"], d
 
 
 # extra factor store flag of the timed path: the UL set (paired passes)
@@ -422,15 +423,17 @@ def main():
     ms_per_step = (t1 - t0) * 1000.0 / K
     rhs_steps = allp["rhs_steps"] / K
     value = rhs_steps / (ms_per_step / 1000.0)
-    # roofline of the dominant kernel: the full-length k_sweep launches of the
-    # range finder (3200 RHS, fine and adjoint); the Parareal sweeps (64 RHS)
-    # run as partitioned passes, reported by rate below
+    # roofline of the dominant kernel: the range-finder sweeps (3200 RHS x 32
+    # steps, fine and adjoint; one library call each, timed with the library's
+    # events on its stream); the Parareal sweeps (64 RHS) run as partitioned
+    # passes, reported by rate below.  The unit of the per-call figures and of
+    # `traffic` (HBM bytes, rocprofv3 counters) is one sweep call.
     prof = {k: tot("range", k) for k in ("ms", "launches", "flops", "bytes", "rhs_steps")}
     sweep_s = prof["ms"] / 1000.0
     achieved_tf = prof["flops"] / sweep_s / 1e12 if sweep_s > 0 else 0.0
     achieved_gbs = prof["bytes"] / sweep_s / 1e9 if sweep_s > 0 else 0.0
     peak = PEAK_TFLOPS[prec]
-    launches = max(prof["launches"], 1)
+    calls = max(prof["launches"], 1)
     traffic, tsrc = traffic_from_profile(prec)
     roofline = {"bound": "mfma", "achieved": achieved_tf, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved_tf / peak, "traffic": traffic,
@@ -438,9 +441,10 @@ def main():
                            "fine + adjoint; steps alternate L U / U' L', the first and last substitutions run "
                            "alone and the other 62 in 31 pairs)") if UL_MASK[0] else
                           "k_sweep (range-finder band sweeps: 3200 RHS x 32 implicit-Euler steps, fine + adjoint)",
-                "launches": prof["launches"], "avg_launch_ms": prof["ms"] / launches,
-                "algorithmic_flops_per_launch": prof["flops"] / launches,
-                "algorithmic_bytes_per_launch": prof["bytes"] / launches,
+                "sweep_calls": prof["launches"], "avg_sweep_ms": prof["ms"] / calls,
+                "algorithmic_flops_per_sweep": prof["flops"] / calls,
+                "algorithmic_bytes_per_sweep": prof["bytes"] / calls,
+                "traffic_unit": "HBM bytes per sweep call",
                 "algorithmic_hbm_GBs": achieved_gbs, "hbm_frac": achieved_gbs / PEAK_HBM_GBS,
                 "traffic_source": tsrc["name"] if tsrc else None}
     fac_s = float(np.mean([t[0] for t in times]))

@@ -1,15 +1,21 @@
-"""Summaries of rocprofv3 output for the sweep kernel, written to profiles/.
+"""Summaries of rocprofv3 output for the range-finder sweeps, written to profiles/.
 
     python -m paper_2508_08873_amd.prof_summary --name NAME --command CMD \\
-        --stats DIR/kt_kernel_stats.csv \\
+        --stats DIR/kt_kernel_stats.csv --calls N \\
         [--fetch DIR/..._counter_collection.csv --write DIR/..._counter_collection.csv \\
-         --calib-fetch DIR/... --calib-write DIR/... --calib-bytes B] [--bench bench.json]
+         --fetch-calls M --calib-fetch DIR/... --calib-write DIR/... --calib-bytes B] [--bench bench.json]
+
+A range-finder sweep (one library call: 32 implicit-Euler steps of 3200
+right-hand sides) is one k_sweep launch, or, on factors with the UL set, two
+k_sweep launches (the first and last substitutions) and 31 k_sweep_pair
+launches.  --calls / --fetch-calls: the number of such calls in the traced /
+counted command; time and bytes are reported per call.
 
 Writes profiles/NAME.md (human-readable: per-kernel time table, HBM bytes per
-sweep launch, the calibration factors) and profiles/NAME.json (the figures
+sweep call, the calibration factors) and profiles/NAME.json (the figures
 bench.py reads for ``roofline.traffic``), both stamped with a hash of the
-sweep kernel's sources: bench.py reports the traffic only while the sources
-still hash to the same value.
+sweep's sources: bench.py reports the traffic only while the sources still
+hash to the same value.
 
 HBM bytes: FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled
 by (bytes a plain device copy of known size moves) / (what the same counter
@@ -26,7 +32,7 @@ import statistics
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SWEEP_SOURCES = ["csrc/sweep.hip", "csrc/lrpr_internal.h", "csrc/factor.hip", "csrc/tile_ops.h"]
+SWEEP_SOURCES = ["csrc/sweep.hip", "csrc/lrpr_internal.h", "csrc/factor.hip", "csrc/tile_ops.h", "csrc/api_core.cpp"]
 
 
 def sweep_source_hash() -> str:
@@ -37,10 +43,10 @@ def sweep_source_hash() -> str:
     return h.hexdigest()
 
 
-def _counter(path, match):
+def _counter(path, matches):
     vals = []
     for r in csv.DictReader(open(path)):
-        if match in r["Kernel_Name"]:
+        if any(m in r["Kernel_Name"] for m in matches):
             vals.append(float(r["Counter_Value"]) * 1024.0)
     return vals
 
@@ -56,8 +62,11 @@ def main():
     ap.add_argument("--calib-write")
     ap.add_argument("--calib-bytes", type=float, default=0.0)
     ap.add_argument("--calib-kernel", default="copyBuffer")
-    ap.add_argument("--kernel", default="k_sweep<", help="substring of the kernel names summarised (the "
-                    "default excludes k_sweep_local, the partitioned block solves)")
+    ap.add_argument("--kernel", default="k_sweep<,k_sweep_pair<",
+                    help="comma-separated substrings of the kernel names of a sweep (the default excludes "
+                         "k_sweep_local, the partitioned block solves)")
+    ap.add_argument("--calls", type=int, required=True, help="sweep calls in the traced command")
+    ap.add_argument("--fetch-calls", type=int, default=0, help="sweep calls in each counter command")
     ap.add_argument("--bench")
     args = ap.parse_args()
 
@@ -75,33 +84,34 @@ def main():
                                                            float(r["TotalDurationNs"]) / 1e6,
                                                            float(r["AverageNs"]) / 1e6,
                                                            100.0 * float(r["TotalDurationNs"]) / total))
-    sweep = [r for r in rows if args.kernel in r["Name"]]
-    calls = sum(int(r["Calls"]) for r in sweep)
-    avg_ms = sum(float(r["TotalDurationNs"]) for r in sweep) / max(calls, 1) / 1e6
+    pats = [k for k in args.kernel.split(",") if k]
+    sweep = [r for r in rows if any(k in r["Name"] for k in pats)]
+    launches = sum(int(r["Calls"]) for r in sweep)
+    per_call_ms = sum(float(r["TotalDurationNs"]) for r in sweep) / args.calls / 1e6
     out = {"name": args.name, "command": args.command, "kernel": args.kernel, "source_sha1": sweep_source_hash(),
-           "sweep_launches": calls, "sweep_avg_launch_ms": avg_ms}
-    lines += ["", "Sweep kernel (`%s`, all instantiations): %d launches, average %.3f ms per launch." %
-              (args.kernel, calls, avg_ms)]
+           "sweep_calls": args.calls, "sweep_launches": launches, "sweep_ms_per_call": per_call_ms}
+    lines += ["", "Range-finder sweeps (kernels matching %s, all instantiations): %d launches in %d sweep calls, "
+              "%.3f ms per call." % (", ".join("`%s`" % k for k in pats), launches, args.calls, per_call_ms)]
     if args.fetch and args.write and args.calib_fetch and args.calib_write and args.calib_bytes > 0:
         cf = _counter(args.calib_fetch, args.calib_kernel)
         cw = _counter(args.calib_write, args.calib_kernel)
         kf = args.calib_bytes / statistics.mean(cf)
         kw = args.calib_bytes / statistics.mean(cw)
-        f = _counter(args.fetch, args.kernel)
-        w = _counter(args.write, args.kernel)
-        fb = statistics.mean(f) * kf
-        wb = statistics.mean(w) * kw
-        out.update({"calib_factor_fetch": kf, "calib_factor_write": kw, "fetch_bytes_per_launch": fb,
-                    "write_bytes_per_launch": wb, "traffic_bytes_per_launch": fb + wb,
-                    "fetch_bytes_each": [x * kf for x in f], "write_bytes_each": [x * kw for x in w]})
+        f = _counter(args.fetch, pats)
+        w = _counter(args.write, pats)
+        nc = args.fetch_calls or args.calls
+        fb = sum(f) * kf / nc
+        wb = sum(w) * kw / nc
+        out.update({"calib_factor_fetch": kf, "calib_factor_write": kw, "fetch_bytes_per_sweep": fb,
+                    "write_bytes_per_sweep": wb, "traffic_bytes_per_sweep": fb + wb,
+                    "counted_dispatches": len(f), "counted_sweep_calls": nc})
         lines += ["", "HBM traffic (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`, separate runs of the same command):",
                   "",
                   "- copy calibration: a %.0f-byte device copy reads FETCH_SIZE x %.3f and WRITE_SIZE x %.3f of "
                   "the bytes it moves; the factors below undo that" % (args.calib_bytes, 1 / kf, 1 / kw),
                   "- factors: fetch x %.3f, write x %.3f" % (kf, kw),
-                  "- per sweep launch (mean over %d launches): fetch %.2f GB, write %.2f GB, total %.2f GB" %
-                  (len(f), fb / 1e9, wb / 1e9, (fb + wb) / 1e9),
-                  "- per launch: " + ", ".join("%.2f+%.2f GB" % (a * kf / 1e9, b * kw / 1e9) for a, b in zip(f, w))]
+                  "- per sweep call (%d dispatches over %d calls): fetch %.2f GB, write %.2f GB, total %.2f GB" %
+                  (len(f), nc, fb / 1e9, wb / 1e9, (fb + wb) / 1e9)]
     if args.bench:
         b = json.loads(open(args.bench).read().strip().splitlines()[-1])
         lines += ["", "Bench line of the same build:", "", "    " + json.dumps(b)]
