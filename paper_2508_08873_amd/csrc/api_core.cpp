@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "dense.h"
 #include "lrpr_internal.h"
@@ -79,7 +80,7 @@ static void free_tiles(TileSet &t) {
 
 // Tile arrays with guard_rows(nb) zero tile rows on both sides; the TileSet
 // pointers address tile row 0.  The mirrored band arrays only with `mirror`.
-static hipError_t alloc_tiles(TileSet &t, int NT, int nb, size_t esz, bool mirror) {
+static hipError_t alloc_tiles(TileSet &t, int NT, int nb, size_t esz, bool mirror, hipStream_t s) {
     const size_t G = (size_t)guard_rows(nb);
     const size_t rows = (size_t)NT + 2 * G;
     hipError_t e;
@@ -89,11 +90,11 @@ static hipError_t alloc_tiles(TileSet &t, int NT, int nb, size_t esz, bool mirro
         const size_t per_row = band ? (size_t)nb : 1;
         const size_t bytes = rows * per_row * TILE_ELEMS * esz;
         if ((e = hipMalloc(&t.alloc[a], bytes)) != hipSuccess) return e;
-        if ((e = hipMemset(t.alloc[a], 0, bytes)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(t.alloc[a], 0, bytes, s)) != hipSuccess) return e;
         t.a[a] = (char *)t.alloc[a] + G * per_row * TILE_ELEMS * esz;
     }
     if ((e = hipMalloc(&t.zt, TILE_ELEMS * esz)) != hipSuccess) return e;
-    if ((e = hipMemset(t.zt, 0, TILE_ELEMS * esz)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(t.zt, 0, TILE_ELEMS * esz, s)) != hipSuccess) return e;
     if ((e = hipMalloc(&t.sink, TILE_ELEMS * esz)) != hipSuccess) return e;
     return hipSuccess;
 }
@@ -121,6 +122,8 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
                       bool adjoint);
 FacView fac_view(lrpr_fac f, bool f32);
 lrpr_status ensure_items(lrpr_ctx ctx, size_t count);
+// workspace cached per context and purpose; grows on demand
+void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err);
 
 // Block starts of the partitioned solve: P ~ 24 blocks (balances the local
 // solves, NT/P tile rows, against the sequential chain, P steps of nb^2 tile
@@ -145,18 +148,23 @@ static lrpr_status build_split(lrpr_ctx ctx, lrpr_fac f, const double *band) {
     hipError_t e;
     const int64_t ld = (int64_t)NT * TILE;
     const size_t dense = (size_t)ld * nb * TILE;
+    // the dense spike staging arrays come from the context's workspaces
     double *RL = nullptr, *RU = nullptr;
     float *RL32 = nullptr, *RU32 = nullptr;
     auto bail = [&](hipError_t err, const char *what) {
-        for (void *p : {(void *)RL, (void *)RU, (void *)RL32, (void *)RU32})
-            if (p) hipFree(p);
         return fail(ctx, err == hipErrorOutOfMemory ? LRPR_ERR_NOMEM : LRPR_ERR_HIP,
                     std::string(what) + ": " + hipGetErrorString(err));
+    };
+    auto wsa = [&](auto **p, const char *key, size_t bytes) -> hipError_t {
+        hipError_t er = hipSuccess;
+        *p = (std::remove_pointer_t<decltype(p)>)ws_get(ctx, key, bytes, &er);
+        return *p ? hipSuccess : (er == hipSuccess ? hipErrorOutOfMemory : er);
     };
     if ((e = hipMalloc(&f->d_blk, sizeof(int) * (P + 1))) != hipSuccess) return bail(e, "block table");
     if ((e = hipMemcpyAsync(f->d_blk, f->blk.data(), sizeof(int) * (P + 1), hipMemcpyHostToDevice, st)) != hipSuccess)
         return bail(e, "block table");
-    if ((e = hipMalloc(&RL, sizeof(double) * dense)) != hipSuccess || (e = hipMalloc(&RU, sizeof(double) * dense)) != hipSuccess)
+    if ((e = wsa(&RL, "spike_rl", sizeof(double) * dense)) != hipSuccess ||
+        (e = wsa(&RU, "spike_ru", sizeof(double) * dense)) != hipSuccess)
         return bail(e, "spike scratch");
     if ((e = launch_spike_rhs(f->n, f->bw, NT, nb, P, f->d_blk, band, RL, RU, st)) != hipSuccess)
         return bail(e, "spike right-hand sides");
@@ -165,8 +173,8 @@ static lrpr_status build_split(lrpr_ctx ctx, lrpr_fac f, const double *band) {
     const bool solve32 = !(f->mask & LRPR_STORE_F64);
     void *L = RL, *U = RU;
     if (solve32 || (f->mask & LRPR_STORE_F32)) {
-        if ((e = hipMalloc(&RL32, sizeof(float) * dense)) != hipSuccess ||
-            (e = hipMalloc(&RU32, sizeof(float) * dense)) != hipSuccess)
+        if ((e = wsa(&RL32, "spike_rl32", sizeof(float) * dense)) != hipSuccess ||
+            (e = wsa(&RU32, "spike_ru32", sizeof(float) * dense)) != hipSuccess)
             return bail(e, "spike scratch");
     }
     if (solve32) {
@@ -220,8 +228,6 @@ static lrpr_status build_split(lrpr_ctx ctx, lrpr_fac f, const double *band) {
             return bail(e, "spike pack");
     }
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "spike build");
-    for (void *p : {(void *)RL, (void *)RU, (void *)RL32, (void *)RU32})
-        if (p) hipFree(p);
     f->P = P;
     return LRPR_OK;
 }
@@ -263,11 +269,15 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
     std::vector<void *> scr(mm, nullptr);
     std::vector<int64_t> rows(mm, n);
     for (int j = m; j < mm; ++j) rows[j] = nrev;
+    // Band arrays and scratch come from the context's cached workspaces,
+    // except the FP64 LU that a factor keeps (LRPR_STORE_F64): after the
+    // first factorisation of a shape, factoring frees no device memory.
+    const bool keep_lu = (store_mask & LRPR_STORE_F64) != 0;
+    std::vector<char> owned(mm, 0);   // bands[j] allocated here (kept by the factor)
     auto cleanup = [&](lrpr_status stt, const std::string &msg) {
         hipStreamSynchronize(st);
         for (int j = 0; j < mm; ++j) {
-            if (bands[j] && (j >= m || !fs[j] || bands[j] != fs[j]->lu)) hipFree(bands[j]);
-            if (scr[j]) hipFree(scr[j]);
+            if (bands[j] && owned[j] && (!fs[j] || bands[j] != fs[j]->lu)) hipFree(bands[j]);
             if (j < m && fs[j]) lrpr_factor_destroy(fs[j]);
         }
         return fail(ctx, stt, msg);
@@ -291,9 +301,19 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
         f->dt_step = ops[j].dt;
     }
     for (int j = 0; j < mm; ++j) {
-        if ((e = hipMalloc(&bands[j], sizeof(double) * (size_t)rows[j] * (2 * bw + 1))) != hipSuccess)
-            return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: band allocation");
-        if ((e = hipMalloc(&scr[j], sbytes)) != hipSuccess)
+        const size_t bbytes = sizeof(double) * (size_t)rows[j] * (2 * bw + 1);
+        char key[32];
+        if (j < m && keep_lu) {
+            if ((e = hipMalloc(&bands[j], bbytes)) != hipSuccess)
+                return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: band allocation");
+            owned[j] = 1;
+        } else {
+            snprintf(key, sizeof key, "fac_band%d", j);
+            if (!(bands[j] = (double *)ws_get(ctx, key, bbytes, &e)))
+                return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: band allocation");
+        }
+        snprintf(key, sizeof key, "fac_scr%d", j);
+        if (!(scr[j] = ws_get(ctx, key, sbytes, &e)))
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: scratch allocation");
         if ((e = launch_assemble(ops[j % m], n, rows[j], bw, j >= m, bands[j], st)) != hipSuccess)
             return cleanup(LRPR_ERR_HIP, std::string("assemble: ") + hipGetErrorString(e));
@@ -325,18 +345,18 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
     }
     for (int j = 0; j < m; ++j) {
         lrpr_fac f = fs[j];
-        if ((store_mask & LRPR_STORE_F64) && alloc_tiles(f->t64, NT, nb, sizeof(double), mirror) != hipSuccess)
+        if ((store_mask & LRPR_STORE_F64) && alloc_tiles(f->t64, NT, nb, sizeof(double), mirror, st) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP64 tile allocation");
-        if ((store_mask & LRPR_STORE_F32) && alloc_tiles(f->t32, NT, nb, sizeof(float), mirror) != hipSuccess)
+        if ((store_mask & LRPR_STORE_F32) && alloc_tiles(f->t32, NT, nb, sizeof(float), mirror, st) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP32 tile allocation");
         if ((e = launch_pack_tiles(n, bw, NT, nb, bands[j], false, (store_mask & LRPR_STORE_F64) ? &f->t64 : nullptr,
                                    (store_mask & LRPR_STORE_F32) ? &f->t32 : nullptr, (double *)scr[j], st)) !=
             hipSuccess)
             return cleanup(LRPR_ERR_HIP, std::string("pack: ") + hipGetErrorString(e));
         if (!ul) continue;
-        if ((store_mask & LRPR_STORE_F64) && alloc_tiles(f->t64r, NT, nb, sizeof(double), mirror) != hipSuccess)
+        if ((store_mask & LRPR_STORE_F64) && alloc_tiles(f->t64r, NT, nb, sizeof(double), mirror, st) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP64 UL tile allocation");
-        if ((store_mask & LRPR_STORE_F32) && alloc_tiles(f->t32r, NT, nb, sizeof(float), mirror) != hipSuccess)
+        if ((store_mask & LRPR_STORE_F32) && alloc_tiles(f->t32r, NT, nb, sizeof(float), mirror, st) != hipSuccess)
             return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: FP32 UL tile allocation");
         if ((e = launch_pack_tiles(n, bw, NT, nb, bands[m + j], true,
                                    (store_mask & LRPR_STORE_F64) ? &f->t64r : nullptr,
@@ -346,21 +366,13 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
     }
     if ((e = hipStreamSynchronize(st)) != hipSuccess)
         return cleanup(LRPR_ERR_HIP, std::string("factor: ") + hipGetErrorString(e));
-    for (int j = 0; j < mm; ++j) {
-        hipFree(scr[j]);
-        scr[j] = nullptr;
-    }
-    for (int j = m; j < mm; ++j) {
-        hipFree(bands[j]);
-        bands[j] = nullptr;
-    }
+    for (int j = m; j < mm; ++j) bands[j] = nullptr;   // workspace
     for (int j = 0; j < m; ++j) {
         if (store_mask & LRPR_STORE_SPLIT) {
             const lrpr_status stt = build_split(ctx, fs[j], bands[j]);
             if (stt != LRPR_OK) return cleanup(stt, std::string("lrpr_factor: partitioned solve: ") + ctx->err);
         }
-        if (store_mask & LRPR_STORE_F64) fs[j]->lu = bands[j];
-        else hipFree(bands[j]);
+        if (keep_lu) fs[j]->lu = bands[j];
         bands[j] = nullptr;
     }
     for (int j = 0; j < m; ++j) outs[j] = fs[j];

@@ -25,21 +25,23 @@ using namespace lrpr;
 
 namespace {
 
-struct Scoped {   // device allocations freed at scope exit (after a stream sync)
-    hipStream_t s;
-    std::vector<void *> ptrs;
-    explicit Scoped(hipStream_t st) : s(st) {}
-    ~Scoped() {
-        if (!ptrs.empty()) hipStreamSynchronize(s);
-        for (void *p : ptrs) hipFree(p);
-    }
+// Temporaries of one call, taken from the context's cached workspaces (one
+// slot per allocation, in call order): after the first call of a shape no
+// call allocates or frees device memory, so independent contexts on
+// separate streams never wait on each other here.
+struct Scoped {
+    lrpr_ctx ctx;
+    const char *prefix;
+    int count = 0;
+    Scoped(lrpr_ctx c, const char *pre) : ctx(c), prefix(pre) {}
     template <typename T>
-    hipError_t alloc(T **p, size_t count) {
-        void *q = nullptr;
-        hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 16);
-        if (e == hipSuccess) ptrs.push_back(q);
+    hipError_t alloc(T **p, size_t n) {
+        char key[48];
+        snprintf(key, sizeof key, "%s%d", prefix, count++);
+        hipError_t e = hipSuccess;
+        void *q = ws_get(ctx, key, n * sizeof(T) > 0 ? n * sizeof(T) : 16, &e);
         *p = (T *)q;
-        return e;
+        return q ? hipSuccess : (e == hipSuccess ? hipErrorOutOfMemory : e);
     }
 };
 
@@ -176,7 +178,7 @@ static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_d
     }
     CK(hipSetDevice(ctx->dev), "hipSetDevice");
     hipStream_t st = ctx->stream;
-    Scoped mem(st);
+    Scoped mem(ctx, "rsvd");
     // offsets of every slice's n x l block in the tall arenas
     std::vector<int64_t> off(nslices + 1, 0);
     std::vector<int> ls(nslices);
@@ -185,12 +187,10 @@ static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_d
         off[s + 1] = off[s] + slices[s].F->n * ls[s];
     }
     const int64_t tot = off[nslices];
-    void *Y = nullptr, *Z = nullptr;
+    char *Y = nullptr, *Z = nullptr;
     double *Q = nullptr, *QZ = nullptr, *T2 = nullptr;
-    CK(hipMalloc(&Y, tot * esz), "rsvd Y");
-    mem.ptrs.push_back(Y);
-    CK(hipMalloc(&Z, tot * esz), "rsvd Z");
-    mem.ptrs.push_back(Z);
+    CK(mem.alloc(&Y, tot * esz), "rsvd Y");
+    CK(mem.alloc(&Z, tot * esz), "rsvd Z");
     CK(mem.alloc(&Q, tot), "rsvd Q");
     CK(mem.alloc(&QZ, tot), "rsvd Qz");
     CK(mem.alloc(&T2, tot), "rsvd tmp");
