@@ -13,6 +13,9 @@ Parareal recursion and the error bounds, written in the paper's notation:
 * Affine fine solver F_n v = F_n' v + b_n with b_n = F_n 0: eq. (F_n_affine).
 * Low-rank coarse solver G_n: eq. (spectral_G); its linear part G_n'.
 * Randomized SVD: Sec. 2.1 steps 1-6 (in C).
+* Neumann boundaries (the variant of the first experiment, Sec. 4; in C), the
+  lumped-mass L^2 inner product and the randomized generalized SVD in it
+  (eq. svd with the inner product on V; NumPy, Gram-Schmidt in W).
 * a priori bound: Thm. 1, eq. (error_bound_eps_delta2);
   a posteriori bound: Thm. 3, eqs. (apost_bound), (apost_bound_sup).
 """
@@ -51,6 +54,9 @@ def _load():
         if not os.path.exists(_LIB_PATH):
             build(force=False)
         lib = ctypes.CDLL(_LIB_PATH)
+        lib.ora_assemble_neumann.restype = ctypes.c_int
+        lib.ora_assemble_neumann.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
         lib.ora_assemble.restype = ctypes.c_int
         lib.ora_assemble.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
@@ -107,14 +113,23 @@ class Operator:
     differences in place of finite elements).
     """
 
-    def __init__(self, dim, nx, nu, beta, c, dt):
+    def __init__(self, dim, nx, nu, beta, c, dt, bc="dirichlet"):
+        """bc: "dirichlet" (nx interior points per axis, h = 1/(nx+1)) or
+        "neumann" (nx points per axis including the boundary, h = 1/(nx-1),
+        mirrored ghost points; the variant of the paper's first experiment)."""
         self.dim, self.nx, self.nu, self.c, self.dt = dim, nx, float(nu), float(c), float(dt)
         self.beta = (float(beta[0]), float(beta[1]) if dim == 2 else 0.0)
+        self.bc = bc
         self.n = nx if dim == 1 else nx * nx
         self.bw = 1 if dim == 1 else nx
         lib = _load()
         self.band = np.zeros((self.n, 2 * self.bw + 1), dtype=np.float64)
-        lib.ora_assemble(dim, nx, self.nu, self.beta[0], self.beta[1], self.c, self.dt, _p(self.band))
+        if bc == "neumann":
+            assert nx >= 2
+            lib.ora_assemble_neumann(dim, nx, self.nu, self.beta[0], self.beta[1], self.c, self.dt, _p(self.band))
+        else:
+            assert bc == "dirichlet"
+            lib.ora_assemble(dim, nx, self.nu, self.beta[0], self.beta[1], self.c, self.dt, _p(self.band))
         self.lu = self.band.copy()
         info = lib.ora_band_lu(self.n, self.bw, _p(self.lu))
         if info != 0:
@@ -357,6 +372,80 @@ def rsvd_two_sided(op: Operator, m: int, k: int, p: int, Omega, Psi):
     if sw < 0:
         raise ArithmeticError("Jacobi SVD did not converge")
     return Uk, S, Vk
+
+
+def mass_weights(dim, nx, bc="dirichlet"):
+    """Lumped (trapezoidal) mass matrix of the grid, the diagonal weights of
+    the discrete L^2 inner product (u, v)_W = sum_i w_i u_i v_i.  Dirichlet:
+    every unknown is interior, w = h^dim.  Neumann: the boundary points carry
+    half the weight per axis (w_i = h/2 at both ends), so sum(w) = 1."""
+    if bc == "neumann":
+        h = 1.0 / (nx - 1)
+        w1 = np.full(nx, h)
+        w1[0] = w1[-1] = 0.5 * h
+    else:
+        h = 1.0 / (nx + 1)
+        w1 = np.full(nx, h)
+    if dim == 1:
+        return w1
+    return np.kron(w1, w1)   # index i + nx*j: w_i * w_j
+
+
+def orth_weighted(Y, w):
+    """Orthonormal basis of range(Y) in (u, v)_W (modified Gram-Schmidt, two
+    passes): Y = Q R with Q^T W Q = I, R upper triangular."""
+    Y = np.array(Y, dtype=np.float64)
+    n, l = Y.shape
+    Q = np.zeros((n, l))
+    R = np.zeros((l, l))
+    for j in range(l):
+        v = Y[:, j].copy()
+        for _ in range(2):
+            for i in range(j):
+                c = np.dot(Q[:, i] * w, v)
+                R[i, j] += c
+                v -= c * Q[:, i]
+        R[j, j] = math.sqrt(np.dot(v * w, v))
+        Q[:, j] = v / R[j, j]
+    return Q, R
+
+
+def rsvd_weighted(op, m, k, p, Omega, w):
+    """Randomized generalized SVD of T = F_n' in the inner product (u, v)_W
+    (eq. svd with the inner product on V; Sec. 2.1 steps 1-6 with every inner
+    product and the adjoint taken in W):
+      Y = T Omega;  Y = Q R  (Q^T W Q = I);
+      Z = T^* Q with the W-adjoint T^* = W^{-1} T^T W;  Z = Qz Rz;
+      Rz^T = Uh diag(S) Vh^T;  psi = Q Uh[:, :k],  phi = Qz Vh[:, :k],
+    so that T v ~ sum_r psi_r S_r (phi_r, v)_W.  Returns (Uk, S_all, Vk) with
+    Uk = psi and Vk = W phi (then G_n' v = Uk (S .* (Vk^T v)) as for the
+    Euclidean build); pairs signed as in rsvd."""
+    w = np.asarray(w, np.float64)
+    Y = op.fine(np.asarray(Omega, np.float64), m)
+    Q, _ = orth_weighted(Y, w)
+    Z = op.adjoint(Q * w[:, None], m) / w[:, None]
+    Qz, Rz = orth_weighted(Z, w)
+    Uh, S, Vht = np.linalg.svd(Rz.T)
+    Uk = Q @ Uh[:, :k]
+    Phi = Qz @ Vht.T[:, :k]
+    for r in range(k):
+        im = int(np.argmax(np.abs(Uk[:, r])))
+        if Uk[im, r] < 0:
+            Uk[:, r] *= -1.0
+            Phi[:, r] *= -1.0
+    return Uk, S, Phi * w[:, None]
+
+
+def neumann_eigenvalues(dim, nx, nu, c):
+    """Eigenvalues of A for the Neumann operator without advection: the
+    mirrored-ghost Laplacian has eigenvectors cos(j pi x_i) with eigenvalues
+    (4/h^2) sin^2(j pi h / 2), j = 0..nx-1, h = 1/(nx-1); in 2D the sums
+    over both axes."""
+    h = 1.0 / (nx - 1)
+    lam = 4.0 / (h * h) * np.sin(np.arange(nx) * math.pi * h / 2.0) ** 2
+    if dim == 2:
+        lam = (lam[:, None] + lam[None, :]).ravel()
+    return nu * lam + c
 
 
 def lowrank_apply(Uk, S, Vk, V):

@@ -81,6 +81,62 @@ int ora_assemble(int dim, int nx, double nu, double beta1, double beta2,
 }
 
 /* ------------------------------------------------------------------------
+ * The same operator with homogeneous Neumann boundaries (the paper's variant
+ * of its first experiment, Sec. 4): nx grid points per axis including both
+ * boundary points, h = 1/(nx-1), x_i = i h.  The boundary condition is
+ * imposed with a mirrored ghost point (u_{-1} = u_1, u_{nx} = u_{nx-2}), so
+ * the coefficient of the missing neighbour moves onto the mirrored one.
+ * Every row of A sums to c: constants are an eigenvector (the undamped
+ * constant mode when c = 0).  Returns the half-bandwidth.
+ * ------------------------------------------------------------------------ */
+static void neumann_axis(int i, int nx, double dif, double beta, double h,
+                         double *diag, double *lo, double *hi)
+{
+    const double bp = beta > 0 ? beta : 0.0, bm = beta < 0 ? -beta : 0.0;
+    double left = -dif - bp / h, right = -dif - bm / h;
+    *diag = 2.0 * dif + fabs(beta) / h;
+    if (i == 0)      { right += left; left = 0.0; }
+    if (i == nx - 1) { left += right; right = 0.0; }
+    *lo = left;
+    *hi = right;
+}
+
+int ora_assemble_neumann(int dim, int nx, double nu, double beta1, double beta2,
+                         double c, double dt, double *band)
+{
+    const double h = 1.0 / (double)(nx - 1);
+    const double dif = nu / (h * h);
+    int n, bw;
+    if (dim == 1) { n = nx; bw = 1; }
+    else          { n = nx * nx; bw = nx; }
+    memset(band, 0, sizeof(double) * (size_t)n * (size_t)(2 * bw + 1));
+    if (dim == 1) {
+        for (int i = 0; i < nx; i++) {
+            double d, lo, hi;
+            neumann_axis(i, nx, dif, beta1, h, &d, &lo, &hi);
+            BAND(band, bw, i, i) = 1.0 + dt * (d + c);
+            if (i > 0)      BAND(band, bw, i, i - 1) = dt * lo;
+            if (i < nx - 1) BAND(band, bw, i, i + 1) = dt * hi;
+        }
+    } else {
+        for (int j = 0; j < nx; j++) {
+            for (int i = 0; i < nx; i++) {
+                const int r = i + nx * j;
+                double dx, lx, hx, dy, ly, hy;
+                neumann_axis(i, nx, dif, beta1, h, &dx, &lx, &hx);
+                neumann_axis(j, nx, dif, beta2, h, &dy, &ly, &hy);
+                BAND(band, bw, r, r) = 1.0 + dt * (dx + dy + c);
+                if (i > 0)      BAND(band, bw, r, r - 1)  = dt * lx;
+                if (i < nx - 1) BAND(band, bw, r, r + 1)  = dt * hx;
+                if (j > 0)      BAND(band, bw, r, r - nx) = dt * ly;
+                if (j < nx - 1) BAND(band, bw, r, r + nx) = dt * hy;
+            }
+        }
+    }
+    return bw;
+}
+
+/* ------------------------------------------------------------------------
  * Banded LU without pivoting (Doolittle, right-looking, ascending loops).
  * The paper's fine solver factors the backward-Euler matrix with a direct
  * solver and reuses the factors for all right-hand sides of a step

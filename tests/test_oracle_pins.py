@@ -599,3 +599,118 @@ def test_step_sequence_brute_force(ora):
     for j, M in enumerate(Ms):
         Y = np.linalg.solve(M, Y + P.dt * f[:, None] * fsc[:, j][None, :])
     assert np.abs(seq.fine(X, P.m, f, None, fsc) - Y).max() <= 1e-13 * np.abs(Y).max()
+
+
+# ---------------------------------------------------------------------------
+# Neumann boundaries, the L^2 (lumped mass) inner product and the generalized
+# SVD (eq. svd with the inner product on V; the Neumann variant of the first
+# experiment, Sec. 4, with its rank-1 constant-mode coarse solver)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,nx", [(1, 9), (1, 2), (2, 5)])
+@pytest.mark.parametrize("beta", [(0.0, 0.0), (7.0, -3.0)])
+def test_neumann_operator_pins(ora, dim, nx, beta):
+    """Rows of A sum to c (constants are an eigenvector); without advection W A
+    is symmetric and the spectrum is the closed form of the mirrored-ghost
+    Laplacian, (4/h^2) sin^2(j pi h/2) per axis."""
+    nu, c, dt = 1.3, 0.4, 0.01
+    op = ora.Operator(dim, nx, nu, beta, c, dt, bc="neumann")
+    A = (op.dense() - np.eye(op.n)) / dt
+    assert np.abs(A.sum(axis=1) - c).max() <= 1e-9 * np.abs(A).max()
+    w = ora.mass_weights(dim, nx, "neumann")
+    assert abs(w.sum() - 1.0) <= 1e-14
+    if beta == (0.0, 0.0):
+        WA = w[:, None] * A
+        assert np.abs(WA - WA.T).max() <= 1e-12 * np.abs(WA).max()
+        ev = np.sort(np.linalg.eigvals(A).real)
+        assert np.abs(ev - np.sort(ora.neumann_eigenvalues(dim, nx, nu, c))).max() <= 1e-10 * ev.max()
+
+
+def test_mass_weights(ora):
+    w = ora.mass_weights(1, 7, "neumann")
+    assert np.allclose(w, [1 / 12, 1 / 6, 1 / 6, 1 / 6, 1 / 6, 1 / 6, 1 / 12])
+    assert np.allclose(ora.mass_weights(2, 3, "dirichlet"), np.full(9, 1 / 16))
+    w2 = ora.mass_weights(2, 4, "neumann")
+    assert abs(w2.sum() - 1.0) <= 1e-14 and abs(w2[0] - (1 / 6) ** 2) <= 1e-16
+
+
+def test_neumann_constant_mode_and_mass(ora):
+    """T 1 = (1 + dt c)^{-m} 1 with any advection; without advection the
+    W-mean decays by the same factor for every start vector (the undamped
+    constant mode for c = 0)."""
+    m, dt = 4, 0.02
+    for beta, c in (((5.0, 2.0), 0.0), ((0.0, 0.0), 0.7)):
+        op = ora.Operator(2, 6, 1.0, beta, c, dt, bc="neumann")
+        T1 = op.fine(np.ones((op.n, 1)), m)[:, 0]
+        assert np.abs(T1 - (1 + dt * c) ** -m).max() <= 1e-13
+    w = ora.mass_weights(2, 6, "neumann")
+    v = np.random.default_rng(3).standard_normal(op.n)
+    Tv = op.fine(v.reshape(-1, 1), m)[:, 0]
+    assert abs(w @ Tv - (1 + dt * c) ** -m * (w @ v)) <= 1e-13 * np.abs(v).max()
+
+
+@pytest.mark.parametrize("dim,nx", [(1, 9), (2, 4)])
+def test_weighted_rsvd_full_rank_closed_form(ora, dim, nx):
+    """At full rank (k + p = n) the randomized generalized SVD is exact: its
+    singular values are the closed-form spectrum of the W-self-adjoint T,
+    (1 + dt (nu lambda_j + c))^{-m}; psi and phi are W-orthonormal, the
+    factors reproduce T, and for c = 0 the leading pair is the constant mode
+    with sigma = 1."""
+    nu, dt, m = 0.8, 0.01, 3
+    for c in (0.0, 0.5):
+        op = ora.Operator(dim, nx, nu, (0.0, 0.0), c, dt, bc="neumann")
+        w = ora.mass_weights(dim, nx, "neumann")
+        n = op.n
+        Om = np.random.default_rng([dim, nx]).standard_normal((n, n))
+        Uk, S, Vk = ora.rsvd_weighted(op, m, n, 0, Om, w)
+        exact = np.sort((1.0 + dt * ora.neumann_eigenvalues(dim, nx, nu, c)) ** -m)[::-1]
+        assert np.abs(S - exact).max() <= 1e-12
+        I = np.eye(n)
+        assert np.abs(Uk.T @ (w[:, None] * Uk) - I).max() <= 1e-12
+        Phi = Vk / w[:, None]
+        assert np.abs(Phi.T @ (w[:, None] * Phi) - I).max() <= 1e-11
+        T = op.fine(np.eye(n), m)
+        assert np.abs(Uk @ (S[:, None] * Vk.T) - T).max() <= 1e-12
+        if c == 0.0:
+            assert abs(S[0] - 1.0) <= 1e-13
+            assert np.abs(Uk[:, 0] - 1.0).max() <= 1e-12   # ||1||_W = 1
+
+
+def test_weighted_rsvd_with_advection_matches_transformed_svd(ora):
+    """With advection T is not W-self-adjoint; its generalized singular values
+    are the ordinary ones of W^{1/2} T W^{-1/2} (a library SVD of that matrix),
+    and the full-rank build reproduces T."""
+    op = ora.Operator(2, 4, 1.0, (9.0, -4.0), 0.3, 0.02, bc="neumann")
+    w = ora.mass_weights(2, 4, "neumann")
+    n, m = op.n, 2
+    T = op.fine(np.eye(n), m)
+    sq = np.sqrt(w)
+    ref = np.linalg.svd(sq[:, None] * T / sq[None, :], compute_uv=False)
+    Uk, S, Vk = ora.rsvd_weighted(op, m, n, 0, np.random.default_rng(5).standard_normal((n, n)), w)
+    assert np.abs(S - ref).max() <= 1e-12
+    assert np.abs(Uk @ (S[:, None] * Vk.T) - T).max() <= 1e-12
+    # the Euclidean build gives other singular values: the inner product matters
+    _, Se, _ = ora.rsvd(op, m, n, 0, np.random.default_rng(5).standard_normal((n, n)))
+    assert np.abs(Se - ref).max() > 1e-6
+
+
+def test_constant_mode_coarse_solver_exact_on_constants(ora):
+    """The a priori rank-1 coarse solver of the Neumann experiment (R_n = 1,
+    sigma = 1, phi = psi = the constant function, L^2 inner product): G_n' is
+    the W-projection onto constants, T_n maps constants to themselves (c = 0),
+    so from a constant start Parareal is exact after one iteration."""
+    op = ora.Operator(1, 33, 1.0, (0.0, 0.0), 0.0, 1.0 / 256, bc="neumann")
+    w = ora.mass_weights(1, 33, "neumann")
+    m, N = 4, 8
+    slices = [ora.Slice(op, m) for _ in range(N)]
+    for s in slices:
+        s.Uk = np.ones((op.n, 1))
+        s.S = np.ones(1)
+        s.Vk = w.reshape(-1, 1).copy()
+        s.b = s.F(np.zeros(op.n))
+    v = np.random.default_rng(2).standard_normal(op.n)
+    assert np.abs(slices[0].Gp(v) - (w @ v)).max() <= 1e-14
+    u0 = np.full(op.n, 2.5)
+    seq = ora.sequential(slices, u0)
+    ref = ora.parareal(slices, u0, 1e-12)
+    assert ref["iters"] <= 1
+    assert np.abs(np.array(ref["iterates"][-1]) - np.array(seq)).max() <= 1e-12
