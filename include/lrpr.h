@@ -55,12 +55,20 @@ typedef enum {
 
 /* Operator of one time slice:  u_t = -A u + f  with A the finite-difference
  * discretisation of  -nu*Laplace(u) + beta.grad(u) + c*u  on the unit
- * interval (dim=1, n = nx interior points) or unit square (dim=2,
- * n = nx*nx, index i + nx*j with x fastest), h = 1/(nx+1), first-order
- * upwind advection, homogeneous Dirichlet boundary.  The fine step is
- * implicit Euler with step dt: (I + dt*A) x_new = x_old + dt*f(t_new).
- * Half-bandwidth b = 1 (dim=1) or nx (dim=2).  (The paper discretises with
- * finite elements; Sec. 4, first paragraph.) */
+ * interval (dim=1, n = nx points) or unit square (dim=2, n = nx*nx, index
+ * i + nx*j with x fastest), first-order upwind advection.  Boundary (bc):
+ *   LRPR_BC_DIRICHLET (0): homogeneous Dirichlet; the nx points per axis are
+ *     interior, h = 1/(nx+1);
+ *   LRPR_BC_NEUMANN (1): homogeneous Neumann (the variant of the paper's
+ *     first experiment, Sec. 4); the nx >= 2 points per axis include both
+ *     boundary points, h = 1/(nx-1), and the boundary condition is imposed
+ *     with a mirrored ghost point (u_{-1} = u_1), so every row of A sums to
+ *     c and constants are an eigenvector.
+ * The fine step is implicit Euler with step dt:
+ * (I + dt*A) x_new = x_old + dt*f(t_new).  Half-bandwidth b = 1 (dim=1) or
+ * nx (dim=2).  (The paper discretises with finite elements; Sec. 4, first
+ * paragraph.) */
+enum { LRPR_BC_DIRICHLET = 0, LRPR_BC_NEUMANN = 1 };
 typedef struct {
     int dim;       /* 1 or 2 */
     int nx;        /* interior points per axis, >= 1 */
@@ -69,7 +77,15 @@ typedef struct {
     double beta2;  /* advection velocity, y component (ignored for dim=1) */
     double c;      /* reaction, >= 0 */
     double dt;     /* implicit-Euler step, > 0 */
+    int bc;        /* LRPR_BC_DIRICHLET or LRPR_BC_NEUMANN */
 } lrpr_op_desc;
+
+/* Lumped (trapezoidal) mass of the operator's grid: the weights of the
+ * discrete L^2 inner product (u, v)_W = sum_i w_i u_i v_i, the inner product
+ * the paper takes for the Neumann constant mode (Sec. 4).  Dirichlet:
+ * w_i = h^dim; Neumann: a factor 1/2 per axis on boundary points, so the
+ * weights sum to 1.  w_host: host, n doubles.  Errors: LRPR_ERR_ARG. */
+lrpr_status lrpr_mass_weights(const lrpr_op_desc *op, double *w_host);
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -289,6 +305,31 @@ lrpr_status lrpr_rsvd_build_q(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *
 lrpr_status lrpr_rsvd_build_two_sided(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
                                       const void *const *psi, int nsteps, lrpr_prec range_prec,
                                       lrpr_coarse *out, double *sigma_host, int *fallback_host);
+/* The build in the inner product (u, v)_W = sum_i w_i u_i v_i (eq. svd with
+ * the inner product on V: the generalized SVD of F_n'; Sec. 4 takes the L^2
+ * inner product of the discretisation).  The result satisfies
+ *   T v ~ sum_r psi_r S_r (phi_r, v)_W,  psi and phi W-orthonormal,
+ * and is stored as U_k = psi, V_k = W phi, so that the coarse apply and
+ * Parareal use it unchanged (G_n' v = U_k (S_k .* (V_k^T v))).  Computed as
+ * the build of lrpr_rsvd_build_q for W^{1/2} T W^{-1/2} (the test matrix
+ * Omega is taken in those coordinates), mapped back.  Signs: the
+ * largest-magnitude entry of psi_r is positive.
+ * weights: host array of nslices device pointers, each n positive doubles
+ *   (not checked), or NULL entries for the Euclidean inner product.
+ * Other arguments, outputs and errors as lrpr_rsvd_build_q. */
+lrpr_status lrpr_rsvd_build_w(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
+                              const double *const *weights, int nsteps, int q, lrpr_prec range_prec,
+                              lrpr_coarse *out, double *sigma_host, int *fallback_host);
+/* A coarse handle from given factors: a priori coarse spaces such as the
+ * rank-1 constant mode of the Neumann experiment (Sec. 4: R_n = 1, sigma =
+ * 1, phi = psi = the constant function in the L^2 inner product, i.e. U = 1,
+ * S = 1, V = W 1).  Per slice s: F[s] its factor (gives n), k[s] >= 1, and
+ * device FP64 arrays U[s] (n x k, ld n), S[s] (k values) and V[s] (n x k, ld
+ * n), copied into the handle; G_n' v = U (S .* (V^T v)).  Errors:
+ * LRPR_ERR_ARG, LRPR_ERR_NOMEM.  Synchronises. */
+lrpr_status lrpr_coarse_from_factors(lrpr_ctx ctx, int nslices, const lrpr_fac *F, const int *k,
+                                     const double *const *U, const double *const *S, const double *const *V,
+                                     lrpr_coarse *out);
 void lrpr_coarse_destroy(lrpr_coarse c);
 /* Device pointers (owned by the handle) of slice s: U (n x k), S (k+p
  * values), V (n x k); k and n of that slice. */

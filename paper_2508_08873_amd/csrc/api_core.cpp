@@ -244,7 +244,8 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
     for (int j = 0; j < m; ++j) {
         const lrpr_op_desc *op = &ops[j];
         if ((op->dim != 1 && op->dim != 2) || op->nx < 1 || !(op->nu > 0) || !(op->dt > 0) || !(op->c >= 0) ||
-            !std::isfinite(op->beta1) || !std::isfinite(op->beta2) || op->dim != ops[0].dim || op->nx != ops[0].nx)
+            !std::isfinite(op->beta1) || !std::isfinite(op->beta2) || op->dim != ops[0].dim || op->nx != ops[0].nx ||
+            (op->bc != LRPR_BC_DIRICHLET && op->bc != LRPR_BC_NEUMANN) || (op->bc == LRPR_BC_NEUMANN && op->nx < 2))
             return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: invalid operator descriptor");
     }
     if (store_mask == 0) store_mask = LRPR_STORE_F64;
@@ -380,6 +381,24 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
 }
 
 extern "C" {
+
+lrpr_status lrpr_mass_weights(const lrpr_op_desc *op, double *w_host) {
+    if (!op || !w_host || (op->dim != 1 && op->dim != 2) || op->nx < 1 ||
+        (op->bc != LRPR_BC_DIRICHLET && op->bc != LRPR_BC_NEUMANN) || (op->bc == LRPR_BC_NEUMANN && op->nx < 2))
+        return LRPR_ERR_ARG;
+    const int nx = op->nx;
+    const bool neu = op->bc == LRPR_BC_NEUMANN;
+    const double h = neu ? 1.0 / (nx - 1) : 1.0 / (nx + 1);
+    std::vector<double> w1(nx, h);
+    if (neu) w1[0] = w1[nx - 1] = 0.5 * h;
+    if (op->dim == 1) {
+        for (int i = 0; i < nx; ++i) w_host[i] = w1[i];
+    } else {
+        for (int j = 0; j < nx; ++j)
+            for (int i = 0; i < nx; ++i) w_host[i + (size_t)nx * j] = w1[i] * w1[j];
+    }
+    return LRPR_OK;
+}
 
 lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lrpr_fac *out) {
     if (!ctx || !op || !out) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor: null argument");

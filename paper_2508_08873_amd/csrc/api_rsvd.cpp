@@ -124,7 +124,8 @@ lrpr_status lrpr_coarse_get(lrpr_coarse c, int s, const double **U, const double
 
 static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
                                    const void *const *psi, int nsteps, int q, lrpr_prec range_prec,
-                                   lrpr_coarse *out, double *sigma_host, int *fallback_host);
+                                   lrpr_coarse *out, double *sigma_host, int *fallback_host,
+                                   const double *const *weights = nullptr);
 
 extern "C" {
 
@@ -136,6 +137,70 @@ lrpr_status lrpr_rsvd_build(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *sl
 lrpr_status lrpr_rsvd_build_q(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices, int nsteps, int q,
                               lrpr_prec range_prec, lrpr_coarse *out, double *sigma_host, int *fallback_host) {
     return rsvd_build_impl(ctx, nslices, slices, nullptr, nsteps, q, range_prec, out, sigma_host, fallback_host);
+}
+
+lrpr_status lrpr_rsvd_build_w(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
+                              const double *const *weights, int nsteps, int q, lrpr_prec range_prec,
+                              lrpr_coarse *out, double *sigma_host, int *fallback_host) {
+    if (!ctx) return LRPR_ERR_ARG;
+    if (!weights) return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build_w: weights is null");
+    return rsvd_build_impl(ctx, nslices, slices, nullptr, nsteps, q, range_prec, out, sigma_host, fallback_host,
+                           weights);
+}
+
+lrpr_status lrpr_coarse_from_factors(lrpr_ctx ctx, int nslices, const lrpr_fac *F, const int *k,
+                                     const double *const *U, const double *const *S, const double *const *V,
+                                     lrpr_coarse *out) {
+    if (!ctx) return LRPR_ERR_ARG;
+    if (nslices <= 0 || !F || !k || !U || !S || !V || !out)
+        return fail(ctx, LRPR_ERR_ARG, "lrpr_coarse_from_factors: invalid arguments");
+    for (int s = 0; s < nslices; ++s)
+        if (!F[s] || k[s] < 1 || (int64_t)k[s] > F[s]->n || !U[s] || !S[s] || !V[s] || F[s]->dev != ctx->dev)
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_coarse_from_factors: invalid slice");
+    hipError_t e = hipSetDevice(ctx->dev);
+    if (e != hipSuccess) return herr(ctx, e, "hipSetDevice");
+    lrpr_coarse c = new (std::nothrow) lrpr_coarse_s();
+    if (!c) return fail(ctx, LRPR_ERR_NOMEM, "coarse handle");
+    c->dev = ctx->dev;
+    c->nslices = nslices;
+    c->n.resize(nslices);
+    c->k.resize(nslices);
+    c->l.resize(nslices);
+    c->U.assign(nslices, nullptr);
+    c->V.assign(nslices, nullptr);
+    c->S.assign(nslices, nullptr);
+    c->F.resize(nslices);
+    auto bail = [&](lrpr_status stt, const char *msg) {
+        lrpr_coarse_destroy(c);
+        return fail(ctx, stt, msg);
+    };
+    hipStream_t st = ctx->stream;
+    for (int s = 0; s < nslices; ++s) {
+        const int64_t n = F[s]->n;
+        c->n[s] = n;
+        c->k[s] = c->l[s] = k[s];
+        c->F[s] = F[s];
+        const size_t nk = (size_t)n * k[s];
+        if (hipMalloc(&c->U[s], nk * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->V[s], nk * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->S[s], (size_t)k[s] * sizeof(double)) != hipSuccess)
+            return bail(LRPR_ERR_NOMEM, "coarse factors");
+        if (hipMemcpyAsync(c->U[s], U[s], nk * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(c->V[s], V[s], nk * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(c->S[s], S[s], (size_t)k[s] * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return bail(LRPR_ERR_HIP, "copy factors");
+    }
+    size_t tot = 0;
+    for (int s = 0; s < nslices; ++s) tot += (size_t)k[s];
+    std::vector<double> hs(tot);   // sized before the copies are queued
+    for (int s = 0, at = 0; s < nslices; at += k[s], ++s)
+        if (hipMemcpyAsync(hs.data() + at, S[s], (size_t)k[s] * sizeof(double), hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
+            return bail(LRPR_ERR_HIP, "copy S");
+    if (hipStreamSynchronize(st) != hipSuccess) return bail(LRPR_ERR_HIP, "coarse factors");
+    c->sigma = hs;
+    *out = c;
+    return LRPR_OK;
 }
 
 lrpr_status lrpr_rsvd_build_two_sided(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
@@ -153,9 +218,15 @@ lrpr_status lrpr_rsvd_build_two_sided(lrpr_ctx ctx, int nslices, const lrpr_slic
 // Randomized SVD of every slice.  psi == null: one-sided (Sec. 2.1 steps 1-6,
 // q power iterations); psi != null: the adjoint runs on the independent test
 // vectors psi[s] and the core is (Psi^T Q)^{-1} (T^T Psi)^T (Sec. 2.2).
+// weights (or null): per slice null or n positive doubles; the build then
+// runs for W^{1/2} T W^{-1/2}: every forward sweep's input is scaled by
+// W^{-1/2} and its output by W^{1/2}, every adjoint sweep's input by W^{1/2}
+// and its output by W^{-1/2}, and the factors are mapped back at the end
+// (U_k by W^{-1/2}, V_k by W^{1/2}) before the signs are fixed.
 static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
                                    const void *const *psi, int nsteps, int q, lrpr_prec range_prec,
-                                   lrpr_coarse *out, double *sigma_host, int *fallback_host) {
+                                   lrpr_coarse *out, double *sigma_host, int *fallback_host,
+                                   const double *const *weights) {
     if (!ctx) return LRPR_ERR_ARG;
     if (nslices <= 0 || !slices || !out || nsteps < 0 || q < 0 ||
         (range_prec != LRPR_F64 && range_prec != LRPR_F32))
@@ -243,9 +314,37 @@ static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_d
         }
         return P;
     };
+    // W^{+-1/2} row scaling of every weighted slice's block of an arena
+    bool weighted = false;
+    for (int s = 0; weights && s < nslices; ++s) weighted = weighted || weights[s];
+    auto wscale = [&](void *base, bool up) -> hipError_t {
+        for (int s = 0; weighted && s < nslices; ++s) {
+            if (!weights[s]) continue;
+            hipError_t he = launch_row_scale(f32, (char *)base + off[s] * esz, slices[s].F->n, ls[s], weights[s],
+                                             up, st);
+            if (he != hipSuccess) return he;
+        }
+        return hipSuccess;
+    };
+    // forward / adjoint sweep of the (transformed) operator on a panel arena
+    auto fwd = [&](void *base) -> lrpr_status {
+        if (hipError_t he = wscale(base, false); he != hipSuccess) return herr(ctx, he, "weights");
+        std::vector<lrpr_panel> P = make_panels(base);
+        lrpr_status rr = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, false);
+        if (rr != LRPR_OK) return rr;
+        if (hipError_t he = wscale(base, true); he != hipSuccess) return herr(ctx, he, "weights");
+        return LRPR_OK;
+    };
+    auto adj = [&](void *base) -> lrpr_status {
+        if (hipError_t he = wscale(base, true); he != hipSuccess) return herr(ctx, he, "weights");
+        std::vector<lrpr_panel> P = make_panels(base);
+        lrpr_status rr = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, true);
+        if (rr != LRPR_OK) return rr;
+        if (hipError_t he = wscale(base, false); he != hipSuccess) return herr(ctx, he, "weights");
+        return LRPR_OK;
+    };
     {
-        std::vector<lrpr_panel> P = make_panels(Y);
-        lrpr_status r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, false);
+        lrpr_status r = fwd(Y);
         if (r != LRPR_OK) return r;
     }
 
@@ -310,23 +409,14 @@ static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_d
     for (int it = 0; it < q; ++it) {
         if ((r = cholqr2(Y, f32, Q, RY)) != LRPR_OK) return r;
         CK(launch_convert(0, f32 ? 1 : 0, Q, Z, tot, st), "Q -> Z");
-        {
-            std::vector<lrpr_panel> P = make_panels(Z);
-            if ((r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, true)) != LRPR_OK) return r;
-        }
+        if ((r = adj(Z)) != LRPR_OK) return r;
         if ((r = cholqr2(Z, f32, QZ, RZ)) != LRPR_OK) return r;
         CK(launch_convert(0, f32 ? 1 : 0, QZ, Y, tot, st), "Qz -> Y");
-        {
-            std::vector<lrpr_panel> P = make_panels(Y);
-            if ((r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, false)) != LRPR_OK) return r;
-        }
+        if ((r = fwd(Y)) != LRPR_OK) return r;
     }
     if (psi) {
         // --- two-sided: Z = T^T Psi; C = Psi^T Q; X^T = Z C^{-T}; X^T = Qx Rx ---
-        {
-            std::vector<lrpr_panel> P = make_panels(Z);
-            if ((r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, true)) != LRPR_OK) return r;
-        }
+        if ((r = adj(Z)) != LRPR_OK) return r;
         if ((r = cholqr2(Y, f32, Q, RY)) != LRPR_OK) return r;
         double *ones, *Cg, *Bt, *lpart;
         int *stat3;
@@ -361,11 +451,7 @@ static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_d
         if (r != LRPR_OK) return r;
         // --- step 3: Z = T^T Q (adjoint sweep) -----------------------------
         CK(launch_convert(0, f32 ? 1 : 0, Q, Z, tot, st), "Q -> Z");
-        {
-            std::vector<lrpr_panel> P = make_panels(Z);
-            r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, range_prec, true);
-            if (r != LRPR_OK) return r;
-        }
+        if ((r = adj(Z)) != LRPR_OK) return r;
         r = cholqr2(Z, f32, QZ, RZ);                   // step 4
         if (r != LRPR_OK) return r;
     }
@@ -410,6 +496,12 @@ static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_d
         rj[s] = RowMatJob{QZ + off[s], c->n[s], Vh + SM * s, c->V[s], c->n[s], c->n[s], ls[s], slices[s].k, 0, 0};
     if (upload(d_rj, rj, st) != hipSuccess || launch_rowmat(0, 0, d_rj, nslices, nmax, st) != hipSuccess)
         return bail(LRPR_ERR_HIP, "V_k = Qz Vh");
+    for (int s = 0; weighted && s < nslices; ++s) {
+        if (!weights[s]) continue;
+        if (launch_row_scale(false, c->U[s], c->n[s], slices[s].k, weights[s], false, st) != hipSuccess ||
+            launch_row_scale(false, c->V[s], c->n[s], slices[s].k, weights[s], true, st) != hipSuccess)
+            return bail(LRPR_ERR_HIP, "weights");
+    }
     std::vector<SignJob> sj(nslices);
     for (int s = 0; s < nslices; ++s) sj[s] = SignJob{c->U[s], c->V[s], c->n[s], slices[s].k, 0};
     if (upload(d_sj, sj, st) != hipSuccess || launch_signfix(d_sj, nslices, kmax, st) != hipSuccess)

@@ -98,4 +98,7 @@ hipError_t launch_small_inv_t(const int *d_ls, int nslices, int lmax, const doub
 hipError_t launch_cross_gram(const double *V, const double *X, int64_t n, int k, int w, const double *ones,
                              double *part, double *out, hipStream_t s);
 
+// X[i, :] *= sqrt(w_i) (up) or /= sqrt(w_i); X n x cols column-major, ld n
+hipError_t launch_row_scale(bool f32, void *X, int64_t n, int64_t cols, const double *w, bool up, hipStream_t s);
+
 }  // namespace lrpr

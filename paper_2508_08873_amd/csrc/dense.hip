@@ -963,4 +963,34 @@ hipError_t launch_transpose_small(const int *d_ls, int nslices, const double *R,
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Row scaling by the square roots of positive weights: X[i, j] *= sqrt(w_i)
+// (up) or /= sqrt(w_i), X n x cols column-major with leading dimension n, in
+// the element type of the panel (FP32 panels scale in FP64 and round).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_row_scale(T *X, int64_t n, int64_t cols, const double *w, int up) {
+    const int64_t total = n * cols;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const double s = sqrt(w[e % n]);
+        const double x = (double)X[e];
+        X[e] = (T)(up ? x * s : x / s);
+    }
+}
+
+hipError_t launch_row_scale(bool f32, void *X, int64_t n, int64_t cols, const double *w, bool up, hipStream_t s) {
+    const int64_t total = n * cols;
+    if (total <= 0) return hipSuccess;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (f32)
+        hipLaunchKernelGGL(k_row_scale<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float *)X, n, cols, w,
+                           up ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_row_scale<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double *)X, n, cols, w,
+                           up ? 1 : 0);
+    return hipGetLastError();
+}
+
 }  // namespace lrpr

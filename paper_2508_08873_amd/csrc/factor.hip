@@ -7,17 +7,18 @@ namespace lrpr {
 // ---------------------------------------------------------------------------
 // Assembly of M = I + dt*A into band storage n x (2b+1), row-major, entry
 // (i, j) at i*(2b+1) + j - i + b.  A: finite differences of
-// -nu*Laplace + beta.grad + c on the unit interval/square, h = 1/(nx+1),
-// first-order upwind (the upwind neighbour is the west/south one for a
-// positive velocity component), homogeneous Dirichlet boundary.  One thread
-// per band entry.
+// -nu*Laplace + beta.grad + c on the unit interval/square, first-order
+// upwind (the upwind neighbour is the west/south one for a positive velocity
+// component); homogeneous Dirichlet (h = 1/(nx+1), interior points) or
+// Neumann (h = 1/(nx-1), boundary points included, mirrored ghost points)
+// boundary.  One thread per band entry.
 //
 // Reversed assembly (rev): the matrix J Mp J of N = 16 NT rows, with Mp =
 // diag(M, I) padded to whole tile rows and J the row reversal.  Its LU,
 // J Mp J = Lr Ur, gives the UL factorisation Mp = (J Lr J)(J Ur J): an upper
 // factor with unit diagonal times a lower one.
 // ---------------------------------------------------------------------------
-__device__ inline double m_entry(const lrpr_op_desc &op, int64_t n, int64_t i, int64_t jcol) {
+__device__ inline double dirichlet_entry(const lrpr_op_desc &op, int64_t n, int64_t i, int64_t jcol) {
     if (jcol < 0 || jcol >= n) return 0.0;
     const double h = 1.0 / (double)(op.nx + 1);
     const double dif = op.nu / (h * h);
@@ -36,6 +37,43 @@ __device__ inline double m_entry(const lrpr_op_desc &op, int64_t n, int64_t i, i
     if (jcol == i - nx) return op.dt * (-dif - fmax(b2, 0.0) / h);
     if (jcol == i + nx) return op.dt * (-dif - fmax(-b2, 0.0) / h);
     return 0.0;
+}
+
+// Neumann: the 1D stencil of point p on an axis of nx points, with the
+// coefficient of a neighbour beyond the boundary moved onto the mirrored one
+// (ghost point u_{-1} = u_1, u_{nx} = u_{nx-2}); off = -1 / +1 for the lower /
+// upper neighbour, 0 for the diagonal part.
+__device__ inline double neumann_axis(int p, int nx, double dif, double beta, double h, int off) {
+    const double lo = -dif - fmax(beta, 0.0) / h, hi = -dif - fmax(-beta, 0.0) / h;
+    if (off == 0) return 2.0 * dif + fabs(beta) / h;
+    if (off < 0) return p == 0 ? 0.0 : (p == nx - 1 ? lo + hi : lo);
+    return p == nx - 1 ? 0.0 : (p == 0 ? hi + lo : hi);
+}
+
+__device__ inline double neumann_entry(const lrpr_op_desc &op, int64_t n, int64_t i, int64_t jcol) {
+    if (jcol < 0 || jcol >= n) return 0.0;
+    const int nx = op.nx;
+    const double h = 1.0 / (double)(nx - 1);
+    const double dif = op.nu / (h * h);
+    if (op.dim == 1) {
+        const int d = (int)(jcol - i);
+        if (d < -1 || d > 1) return 0.0;
+        const double a = neumann_axis((int)i, nx, dif, op.beta1, h, d);
+        return d == 0 ? 1.0 + op.dt * (a + op.c) : op.dt * a;
+    }
+    const int ix = (int)(i % nx), iy = (int)(i / nx);
+    if (jcol == i)
+        return 1.0 + op.dt * (neumann_axis(ix, nx, dif, op.beta1, h, 0) + neumann_axis(iy, nx, dif, op.beta2, h, 0) +
+                              op.c);
+    if (jcol == i - 1 && ix > 0) return op.dt * neumann_axis(ix, nx, dif, op.beta1, h, -1);
+    if (jcol == i + 1 && ix < nx - 1) return op.dt * neumann_axis(ix, nx, dif, op.beta1, h, 1);
+    if (jcol == i - nx) return op.dt * neumann_axis(iy, nx, dif, op.beta2, h, -1);
+    if (jcol == i + nx) return op.dt * neumann_axis(iy, nx, dif, op.beta2, h, 1);
+    return 0.0;
+}
+
+__device__ inline double m_entry(const lrpr_op_desc &op, int64_t n, int64_t i, int64_t jcol) {
+    return op.bc == LRPR_BC_NEUMANN ? neumann_entry(op, n, i, jcol) : dirichlet_entry(op, n, i, jcol);
 }
 
 // rows: n (plain) or N (reversed); n is the operator's size

@@ -20,7 +20,7 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_ZERO_PIVOT", 4: "ERR_QR
 EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_last_error",
            "lrpr_factor", "lrpr_factor_stepper", "lrpr_factor_sequence", "lrpr_factor_destroy", "lrpr_factor_info", "lrpr_factor_copy_lu",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build", "lrpr_rsvd_build_q",
-           "lrpr_rsvd_build_two_sided",
+           "lrpr_rsvd_build_two_sided", "lrpr_rsvd_build_w", "lrpr_coarse_from_factors", "lrpr_mass_weights",
            "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_parareal_solve",
            "lrpr_profile_enable", "lrpr_profile_read", "lrpr_randn",
            "lrpr_server_create", "lrpr_server_destroy", "lrpr_server_submit", "lrpr_server_progress",
@@ -31,6 +31,8 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
 STORE_F64, STORE_F32, STORE_MIRROR, STORE_SPLIT, STORE_UL = 1, 2, 4, 8, 16
 # lrpr_factor_stepper steppers
 STEP_EULER, STEP_SDIRK2, STEP_SDIRK2L, STEP_SEQUENCE = 0, 1, 2, 3
+# lrpr_op_desc boundary conditions
+BC_DIRICHLET, BC_NEUMANN = 0, 1
 
 
 class LrprError(RuntimeError):
@@ -42,7 +44,7 @@ class LrprError(RuntimeError):
 class OpDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("nu", ctypes.c_double),
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("c", ctypes.c_double),
-                ("dt", ctypes.c_double)]
+                ("dt", ctypes.c_double), ("bc", ctypes.c_int)]
 
 
 class Panel(ctypes.Structure):
@@ -90,6 +92,9 @@ def load():
     lib.lrpr_fine_step_batched.argtypes = [vp, i32, P(Panel), i32, i32]
     lib.lrpr_adjoint_step_batched.argtypes = [vp, i32, P(Panel), i32, i32]
     lib.lrpr_rsvd_build.argtypes = [vp, i32, P(SliceDesc), i32, i32, P(vp), vp, vp]
+    lib.lrpr_rsvd_build_w.argtypes = [vp, i32, P(SliceDesc), vp, i32, i32, i32, P(vp), vp, vp]
+    lib.lrpr_coarse_from_factors.argtypes = [vp, i32, vp, vp, vp, vp, vp, P(vp)]
+    lib.lrpr_mass_weights.argtypes = [P(OpDesc), vp]
     lib.lrpr_coarse_destroy.argtypes = [vp]
     lib.lrpr_coarse_destroy.restype = None
     lib.lrpr_coarse_get.argtypes = [vp, i32, P(vp), P(vp), P(vp), P(i32), P(i64)]
@@ -116,6 +121,24 @@ def load():
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _opdesc(dim, nx, nu, beta, c, dt, bc=BC_DIRICHLET):
+    return OpDesc(dim, nx, float(nu), float(beta[0]), float(beta[1]) if dim == 2 else 0.0, float(c), float(dt),
+                  int(bc))
+
+
+def mass_weights(dim, nx, bc=BC_DIRICHLET):
+    """Lumped-mass weights of the grid (lrpr_mass_weights, host), as a NumPy array."""
+    import numpy as np
+    lib = load()
+    n = nx if dim == 1 else nx * nx
+    w = np.zeros(n, dtype=np.float64)
+    d = _opdesc(dim, nx, 1.0, (0.0, 0.0), 0.0, 1.0, bc)
+    st = lib.lrpr_mass_weights(ctypes.byref(d), w.ctypes.data_as(ctypes.c_void_p))
+    if st != 0:
+        raise LrprError(st, "lrpr_mass_weights")
+    return w
 
 
 class Context:
@@ -173,8 +196,8 @@ class Context:
         return X
 
     # -- factor -----------------------------------------------------------
-    def factor(self, dim, nx, nu, beta, c, dt, store_mask=1, stepper=STEP_EULER):
-        d = OpDesc(dim, nx, float(nu), float(beta[0]), float(beta[1]) if dim == 2 else 0.0, float(c), float(dt))
+    def factor(self, dim, nx, nu, beta, c, dt, store_mask=1, stepper=STEP_EULER, bc=BC_DIRICHLET):
+        d = _opdesc(dim, nx, nu, beta, c, dt, bc)
         h = ctypes.c_void_p()
         self.sync_stream()
         if stepper == STEP_EULER:
@@ -190,8 +213,7 @@ class Context:
         arr = (OpDesc * len(ops))()
         for j, o in enumerate(ops):
             b = o["beta"]
-            arr[j] = OpDesc(o["dim"], o["nx"], float(o["nu"]), float(b[0]), float(b[1]) if o["dim"] == 2 else 0.0,
-                            float(o["c"]), float(o["dt"]))
+            arr[j] = _opdesc(o["dim"], o["nx"], o["nu"], b, o["c"], o["dt"], o.get("bc", BC_DIRICHLET))
         h = ctypes.c_void_p()
         self.sync_stream()
         self._check(self.lib.lrpr_factor_sequence(self.h, arr, len(ops), int(store_mask), ctypes.byref(h)))
@@ -223,10 +245,12 @@ class Context:
         self._check(self.lib.lrpr_adjoint_step_batched(self.h, len(specs), arr, int(nsteps), int(prec)))
 
     # -- rSVD -------------------------------------------------------------
-    def rsvd_build(self, slices, nsteps, range_prec=LRPR_F64, q=0, psi=None):
+    def rsvd_build(self, slices, nsteps, range_prec=LRPR_F64, q=0, psi=None, weights=None):
         """slices: list of (Factor, k, p, Omega tensor n x (k+p) column-major);
         q power iterations (lrpr_rsvd_build_q); psi: per-slice independent
-        adjoint test matrices (lrpr_rsvd_build_two_sided)."""
+        adjoint test matrices (lrpr_rsvd_build_two_sided); weights: per-slice
+        float64 cuda tensors of n inner-product weights, or None entries
+        (lrpr_rsvd_build_w)."""
         arr = (SliceDesc * len(slices))()
         tot = 0
         for i, (F, k, p, Om) in enumerate(slices):
@@ -236,7 +260,11 @@ class Context:
         fb = (ctypes.c_int * max(len(slices), 1))()
         h = ctypes.c_void_p()
         self.sync_stream()
-        if psi is not None:
+        if weights is not None:
+            ww = (ctypes.c_void_p * len(slices))(*[t.data_ptr() if t is not None else None for t in weights])
+            self._check(self.lib.lrpr_rsvd_build_w(self.h, len(slices), arr, ww, int(nsteps), int(q),
+                                                   int(range_prec), ctypes.byref(h), sig, fb))
+        elif psi is not None:
             pp = (ctypes.c_void_p * len(slices))(*[t.data_ptr() for t in psi])
             self._check(self.lib.lrpr_rsvd_build_two_sided(self.h, len(slices), arr, pp, int(nsteps),
                                                            int(range_prec), ctypes.byref(h), sig, fb))
@@ -247,6 +275,23 @@ class Context:
             self._check(self.lib.lrpr_rsvd_build(self.h, len(slices), arr, int(nsteps), int(range_prec),
                                                  ctypes.byref(h), sig, fb))
         return Coarse(self, h, [F for (F, _, _, _) in slices], list(sig)[:tot], list(fb)[:len(slices)])
+
+    def coarse_from_factors(self, factors, U, S, V):
+        """A priori coarse solvers (lrpr_coarse_from_factors): per slice float64
+        cuda tensors U (n x k column-major), S (k,), V (n x k column-major)."""
+        N = len(factors)
+        fa = (ctypes.c_void_p * N)(*[F.h.value for F in factors])
+        ks = (ctypes.c_int * N)(*[int(u.shape[1]) for u in U])
+        up = (ctypes.c_void_p * N)(*[u.data_ptr() for u in U])
+        sp = (ctypes.c_void_p * N)(*[x.data_ptr() for x in S])
+        vp = (ctypes.c_void_p * N)(*[v.data_ptr() for v in V])
+        h = ctypes.c_void_p()
+        self.sync_stream()
+        self._check(self.lib.lrpr_coarse_from_factors(self.h, N, fa, ks, up, sp, vp, ctypes.byref(h)))
+        sig = []
+        for x in S:
+            sig += [float(v) for v in x.cpu()]
+        return Coarse(self, h, list(factors), sig, [0] * N)
 
     # -- Parareal ---------------------------------------------------------
     def parareal_solve(self, coarse, factors, nsteps, u0, f=None, fscale=None, tol=1e-10, max_iter=None,

@@ -12,6 +12,7 @@ import re
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -52,12 +53,21 @@ def test_binding_lists_every_declared_symbol():
 
 def test_struct_layouts():
     from paper_2508_08873_amd import lrpr
-    # lrpr_op_desc: int, int, 5 doubles
-    assert ctypes.sizeof(lrpr.OpDesc) == 8 + 5 * 8
+    # lrpr_op_desc: int, int, 5 doubles, int (+pad)
+    assert ctypes.sizeof(lrpr.OpDesc) == 8 + 5 * 8 + 8
     # lrpr_panel: F, X, ldx, w(+pad), f, ldf, fcol, fscale
     assert ctypes.sizeof(lrpr.Panel) == 8 * 8
     # lrpr_slice_desc: F, k, p, Omega
     assert ctypes.sizeof(lrpr.SliceDesc) == 8 + 4 + 4 + 8
+
+
+def test_mass_weights_host_entry_point(ora):
+    """lrpr_mass_weights is host code: against the oracle's lumped mass."""
+    from paper_2508_08873_amd import lrpr
+    for dim, nx, bc, name in ((1, 7, 1, "neumann"), (2, 5, 1, "neumann"), (1, 6, 0, "dirichlet"), (2, 3, 0, "dirichlet")):
+        assert np.array_equal(lrpr.mass_weights(dim, nx, bc), ora.mass_weights(dim, nx, name))
+    with pytest.raises(lrpr.LrprError):
+        lrpr.mass_weights(1, 1, lrpr.BC_NEUMANN)
 
 
 def test_null_context_is_an_argument_error(lib):
