@@ -235,6 +235,52 @@ def fwd_adj_rates(ctx, lrpr, P, prec):
     return out
 
 
+def neumann_study(ctx, lrpr, seed):
+    """The Neumann variant of the paper's first experiment (Sec. 4): 1D heat
+    equation with homogeneous Neumann boundaries (255 points, nu = 1, 16
+    slices x 32 implicit-Euler steps on [0, 4]: every non-constant mode
+    decays by at least exp(-pi^2/4) per slice), whose constant mode is not
+    damped.  Parareal to 1e-8 (at most N iterations) with four coarse
+    solvers G_n = G_n' + b_n: G_n' = 0; the a priori rank-1 constant mode
+    (U = 1, S = 1, V = W 1, L^2 inner product of the lumped mass W); the
+    rank-8 randomized generalized SVD in that inner product; and the rank-8
+    Euclidean rSVD."""
+    import torch
+    nx, N, m, T = 255, 16, 32, 4.0
+    dt = T / (N * m)
+    F = ctx.factor(1, nx, 1.0, (0.0, 0.0), 0.0, dt, store_mask=lrpr.STORE_F64 | lrpr.STORE_MIRROR | lrpr.STORE_SPLIT,
+                   bc=lrpr.BC_NEUMANN)
+    x = np.linspace(0.0, 1.0, nx)
+    r = np.random.default_rng([seed, 255])
+    u0 = 1.0 + np.cos(np.pi * x) + 0.5 * np.cos(4 * np.pi * x) + 0.05 * r.standard_normal(nx)
+    f = np.exp(-40.0 * (x - 0.3) ** 2)
+    fsc = np.cos(0.5 * np.pi * dt * np.arange(1, N * m + 1))
+    dev = lambda a: lrpr.colmajor(torch.from_numpy(np.ascontiguousarray(a).reshape(nx, -1)).to("cuda"))
+    w = lrpr.mass_weights(1, nx, lrpr.BC_NEUMANN)
+    wd = torch.from_numpy(w).to("cuda")
+    k, p = 8, 4
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed * 7 + 1)
+    Om = torch.randn((N, k + p, nx), generator=gen, device="cuda", dtype=torch.float64)
+    one = torch.ones(1, dtype=torch.float64, device="cuda")
+    coarse = {
+        "zero": ctx.coarse_from_factors([F] * N, [dev(np.zeros(nx))] * N, [0 * one] * N, [dev(np.zeros(nx))] * N),
+        "constant_mode_rank1": ctx.coarse_from_factors([F] * N, [dev(np.ones(nx))] * N, [one] * N, [dev(w)] * N),
+        "rsvd_L2_rank8": ctx.rsvd_build([(F, k, p, Om[s].t()) for s in range(N)], m, 0, weights=[wd] * N),
+        "rsvd_euclidean_rank8": ctx.rsvd_build([(F, k, p, Om[s].t()) for s in range(N)], m, 0),
+    }
+    out = {"workload": "heat1d Neumann: 255 points, nu=1, 16 slices x 32 steps, T=4, tol 1e-8"}
+    for name, C in coarse.items():
+        t0 = time.perf_counter()
+        o = ctx.parareal_solve(C, [F] * N, m, dev(u0), dev(f), torch.from_numpy(fsc).to("cuda"), tol=1e-8,
+                               max_iter=N)
+        torch.cuda.synchronize()
+        out[name] = {"iters": o["iters"][0], "converged": o["status"] == 0, "s": time.perf_counter() - t0}
+        C.close()
+    F.close()
+    return out
+
+
 def rsvd_variants(ctx, lrpr, P, prec, Om):
     """rSVD build of the 64 slices, timed once each: the one-sided build
     (q = 0), with q = 1 power iteration (2 more sweeps of the 3200-column
@@ -578,6 +624,7 @@ def main():
     if not args.no_plain:
         res["range_finder_sweeps_separately"] = fwd_adj_rates(ctx, lrpr, P, prec)
         res["per_step_operators"] = per_step_operators(ctx, lrpr, inputs, prec, args.seed)
+        res["neumann_constant_mode"] = neumann_study(ctx, lrpr, args.seed)
         res["fine_steppers"] = stepper_study(ctx, lrpr, P, prec, Om64 if prec == "f64" else Om64.to(torch.float32))
         res["rsvd_variants"] = rsvd_variants(
             ctx, lrpr, P, prec, Om64 if prec == "f64" else Om64.to(torch.float32))
