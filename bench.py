@@ -19,10 +19,11 @@ everything in FP64 (tol 1e-10).  The f32 run also times the FP64 form once
 ("fp64_side") and states the FP32 error against the FP64 oracle.
 Inputs (Omega, u0, f) are generated before the timed region and stay in HBM.
 `value` = fine-propagator RHS*steps per second of whole-step wall time, with
-the K timed steps spread over --pipelines independent pipelines (default 2:
-two library contexts, each on its own HIP stream, driven by its own host
+the K timed steps spread over --pipelines independent pipelines (default 3:
+three library contexts, each on its own HIP stream, driven by its own host
 thread), so that one step's LU, Parareal chain and small kernels fill the
-compute units the other's range-finder sweep leaves free.  Each step is still
+compute units another's range-finder sweep leaves free (2 pipelines: 282 ms
+per step, 3: 259 ms, 4: 286 ms on the 255^2 workload).  Each step is still
 the whole path for one problem; the per-step latency of one pipeline alone,
 its phase times and the sweep roofline come from a separate single-pipeline
 timed run of K steps ("latency").
@@ -51,9 +52,9 @@ PEAK_HBM_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--pipelines", type=int, default=2,
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--pipelines", type=int, default=3,
                     help="independent pipelines (context + stream + host thread) sharing the timed steps")
     ap.add_argument("--prec", choices=["f64", "f32"], default="f32",
                     help="fine solves and range finder (LU, Gram/Cholesky, SVD and the Parareal correction are "
