@@ -101,10 +101,14 @@ void lrpr_coarse_destroy(lrpr_coarse c) {
     if (!c) return;
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
-    for (size_t s = 0; s < c->U.size(); ++s) {
-        if (c->U[s]) hipFree(c->U[s]);
-        if (c->V[s]) hipFree(c->V[s]);
-        if (c->S[s]) hipFree(c->S[s]);
+    if (c->block) {
+        hipFree(c->block);
+    } else {
+        for (size_t s = 0; s < c->U.size(); ++s) {
+            if (c->U[s]) hipFree(c->U[s]);
+            if (c->V[s]) hipFree(c->V[s]);
+            if (c->S[s]) hipFree(c->S[s]);
+        }
     }
     delete c;
 }
@@ -474,16 +478,25 @@ static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_d
         lrpr_coarse_destroy(c);
         return fail(ctx, stt, msg);
     };
+    // every slice's U_k, V_k and S in one allocation (one device allocation
+    // per build instead of three per slice)
+    // (each array starts on a 256-byte boundary)
+    auto pad = [](size_t e) { return (e + 31) / 32 * 32; };
+    size_t elems = 0;
+    for (int s = 0; s < nslices; ++s)
+        elems += 2 * pad((size_t)slices[s].F->n * std::max(slices[s].k, 1)) + pad(LMAX);
+    if (hipMalloc(&c->block, elems * sizeof(double)) != hipSuccess) return bail(LRPR_ERR_NOMEM, "coarse factors");
+    size_t at = 0;
     for (int s = 0; s < nslices; ++s) {
         c->n[s] = slices[s].F->n;
         c->k[s] = slices[s].k;
         c->l[s] = ls[s];
         c->F[s] = slices[s].F;
-        const size_t nk = (size_t)c->n[s] * std::max(slices[s].k, 1);
-        if (hipMalloc(&c->U[s], nk * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->V[s], nk * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->S[s], LMAX * sizeof(double)) != hipSuccess)
-            return bail(LRPR_ERR_NOMEM, "coarse factors");
+        const size_t nk = pad((size_t)c->n[s] * std::max(slices[s].k, 1));
+        c->U[s] = c->block + at;
+        c->V[s] = c->block + at + nk;
+        c->S[s] = c->block + at + 2 * nk;
+        at += 2 * nk + pad(LMAX);
         if (hipMemcpyAsync(c->S[s], Sd + (size_t)LMAX * s, LMAX * sizeof(double), hipMemcpyDeviceToDevice, st) !=
             hipSuccess)
             return bail(LRPR_ERR_HIP, "copy S");

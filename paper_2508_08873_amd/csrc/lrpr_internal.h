@@ -140,7 +140,8 @@ struct lrpr_coarse_s {
     int nslices = 0;
     std::vector<int64_t> n;
     std::vector<int> k, l;
-    std::vector<double *> U, S, V;  // device, per slice
+    std::vector<double *> U, S, V;  // device, per slice (inside `block` when that is set)
+    double *block = nullptr;        // one allocation holding every slice's U, S, V
     std::vector<double> sigma;      // host copy of all singular values, per slice
     std::vector<lrpr_fac> F;     // factors the slices were built from (not owned)
 };

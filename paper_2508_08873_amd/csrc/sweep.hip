@@ -910,8 +910,13 @@ __device__ __forceinline__ void sweep_pair(const SweepItem &it, const T *__restr
 // of an L U step with the first of the following U' L' step; ascending pairs
 // the second substitution of a U' L' step with the first of the following
 // L U step.  stepB: the step of pass B (its source's time factor).
+// minimum waves per SIMD of the FP32 pair kernels (4 fits two workgroups per
+// compute unit at prefetch depth 2; measured slower than one at depth 5)
+#ifndef LRPR_PAIR_WG32
+#define LRPR_PAIR_WG32 1
+#endif
 template <typename T, int NB, typename SP, int PD, bool ASC, bool ADJ>
-__global__ __launch_bounds__(512) void k_sweep_pair(const SweepItem *__restrict__ items, int nitems, int stepB) {
+__global__ __launch_bounds__(512, sizeof(T) == 4 ? LRPR_PAIR_WG32 : 1) void k_sweep_pair(const SweepItem *__restrict__ items, int nitems, int stepB) {
     extern __shared__ __align__(16) unsigned char smem[];
     for (int idx = blockIdx.x; idx < nitems; idx += gridDim.x) {
         const SweepItem &it = items[idx];
