@@ -90,7 +90,15 @@ lrpr_status lrpr_mass_weights(const lrpr_op_desc *op, double *w_host);
 /* ---- context ------------------------------------------------------------ */
 
 /* Create a context on HIP device `device`, queueing work on `hip_stream`
- * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle.
+ * A context caches the device workspaces its calls need (work-item arrays,
+ * LU bands and scratch, spike staging, the rSVD panels and small matrices,
+ * Parareal state): they grow to the largest shape met and are freed by
+ * lrpr_ctx_destroy (about 7 GB for a 255^2 rSVD build of 64 slices x 50
+ * columns), so that calls after the first of a shape allocate and free no
+ * temporaries.  Contexts share no state: independent contexts on separate
+ * streams, driven from separate host threads, run concurrently.  One context
+ * must not be used from two threads at once. */
 lrpr_status lrpr_ctx_create(int device, void *hip_stream, lrpr_ctx *out);
 void lrpr_ctx_destroy(lrpr_ctx ctx);
 /* Replace the stream used by later calls. */
