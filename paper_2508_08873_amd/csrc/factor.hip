@@ -151,10 +151,8 @@ __device__ inline int aslot(bool f32, int m, int k) {
     return 128 * (kc >> 1) + 2 * l + (kc & 1);
 }
 
-// One thread per element (tile row I, band index j, row r, column q) of the
-// band tiles; writes the FP64 and/or FP32 copies of the band tiles multiplied
-// from the left by their row's diagonal-tile inverse (Linv, Uinv: FP64,
-// row-major per tile row, from k_diag_inv):
+// Band tiles multiplied from the left by their row's diagonal-tile inverse
+// (Linv, Uinv: FP64, row-major per tile row, from k_diag_inv):
 //   Lb[I][j]  = L(I,I)^{-1}   L(I, I-nb+j)
 //   Ub[I][j]  = U(I,I)^{-1}   U(I, I+1+j)
 // and, when requested, the mirrored set
@@ -164,10 +162,31 @@ struct BandOut {
     void *b[4];   // Lb, Ub, UTb, LTb (null: not stored)
 };
 
-__global__ void k_pack_band(LuAcc F, int NT, int nb, const double *Linv, const double *Uinv, BandOut o64,
-                            BandOut o32) {
+// Element (row r, column q) of band tile j of tile row I in set a (0 Lb,
+// 1 Ub, 2 UTb, 3 LTb), FP64.
+__device__ inline double band_elem(const LuAcc &F, int nb, const double *Linv, const double *Uinv, int64_t I,
+                                   int j, int r, int q, int a) {
+    const int64_t base = I * TILE;
+    const int64_t jl = (I - nb + j) * TILE + q;   // column in tile row I-nb+j
+    const int64_t ju = (I + 1 + j) * TILE + q;    // column in tile row I+1+j
+    const double *Li = Linv + I * TILE_ELEMS, *Ui = Uinv + I * TILE_ELEMS;
+    double v = 0.0;
+    for (int k = 0; k < TILE; ++k) {
+        const int64_t i = base + k;
+        switch (a) {
+            case 0: v += Li[r * TILE + k] * F.lower(i, jl); break;   // L(I, J)[k][q]
+            case 1: v += Ui[r * TILE + k] * F.upper(i, ju); break;   // U(I, J)[k][q]
+            case 2: v += Ui[k * TILE + r] * F.upper(jl, i); break;   // U(J, I)[q][k]
+            default: v += Li[k * TILE + r] * F.lower(ju, i); break;  // L(J, I)[q][k]
+        }
+    }
+    return v;
+}
+
+// FP64 band tiles: one thread per element (tile row I, band index j, row r,
+// column q).
+__global__ void k_pack_band(LuAcc F, int NT, int nb, const double *Linv, const double *Uinv, BandOut o64) {
     const int64_t total = (int64_t)NT * nb * TILE_ELEMS;
-    const bool mirror = o64.b[2] || o32.b[2];
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t tileidx = e / TILE_ELEMS;
@@ -175,26 +194,72 @@ __global__ void k_pack_band(LuAcc F, int NT, int nb, const double *Linv, const d
         const int64_t I = tileidx / nb;
         const int j = (int)(tileidx % nb);
         const int r = o >> 4, q = o & 15;
-        const int64_t base = I * TILE;
-        const int64_t jl = (I - nb + j) * TILE + q;   // column in tile row I-nb+j
-        const int64_t ju = (I + 1 + j) * TILE + q;    // column in tile row I+1+j
-        const double *Li = Linv + I * TILE_ELEMS, *Ui = Uinv + I * TILE_ELEMS;
-        double v[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int k = 0; k < TILE; ++k) {
-            const int64_t i = base + k;
-            v[0] += Li[r * TILE + k] * F.lower(i, jl);        // L(I, J)[k][q]
-            v[1] += Ui[r * TILE + k] * F.upper(i, ju);        // U(I, J)[k][q]
-            if (mirror) {
-                v[2] += Ui[k * TILE + r] * F.upper(jl, i);    // U(J, I)[q][k]
-                v[3] += Li[k * TILE + r] * F.lower(ju, i);    // L(J, I)[q][k]
-            }
-        }
-        const int64_t dst = tileidx * TILE_ELEMS;
-        for (int a = 0; a < 4; ++a) {
-            if (o64.b[a]) ((double *)o64.b[a])[dst + aslot(false, r, q)] = v[a];
-            if (o32.b[a]) ((float *)o32.b[a])[dst + aslot(true, r, q)] = (float)v[a];
-        }
+        const int64_t dst = tileidx * TILE_ELEMS + aslot(false, r, q);
+        for (int a = 0; a < 4; ++a)
+            if (o64.b[a]) ((double *)o64.b[a])[dst] = band_elem(F, nb, Linv, Uinv, I, j, r, q, a);
     }
+}
+
+// Row-sum-keeping FP32 rounding of one row of `count` entries; elem(t)
+// returns the FP64 value and the FP32 destination of entry t.  Every entry
+// is rounded; the FP64 sum of the rounding errors goes into the largest
+// entry, and what that entry's rounding leaves into the smallest entry of
+// at least 2^-12 of the largest, whose finer spacing holds it to about
+// 2^-12 of one rounding of the largest.
+template <class Elem>
+__device__ inline void round_row_keep_sum(float *out, int count, Elem elem) {
+    double err = 0.0, vmax = 0.0;
+    int64_t at = -1;
+    for (int t = 0; t < count; ++t) {
+        int64_t dst;
+        const double v = elem(t, dst);
+        const float f = (float)v;
+        out[dst] = f;
+        err += v - (double)f;
+        if (fabs(v) > fabs(vmax)) { vmax = v; at = dst; }
+    }
+    if (at < 0) return;
+    const double want = (double)out[at] + err;
+    out[at] = (float)want;
+    const double res = want - (double)out[at];
+    if (res == 0.0) return;
+    const double lo = fabs(vmax) * (1.0 / 4096.0);
+    double best = fabs(vmax);
+    int64_t at2 = -1;
+    for (int t = 0; t < count; ++t) {
+        int64_t dst;
+        const double a = fabs(elem(t, dst));
+        if (dst != at && a >= lo && a < best) { best = a; at2 = dst; }
+    }
+    if (at2 >= 0) out[at2] = (float)((double)out[at2] + res);
+}
+
+// FP32 copies keep every row's sum.  A substitution row computes
+// x_i = sum_k D[i][k] r_k - sum_c B[i][c] x_c; on smooth vectors only the row
+// sums of D and B act, and for a constant-coefficient operator the factor
+// entries, hence their FP32 rounding errors, are the same in every interior
+// row, so plain rounding shifts the smooth modes' decay rate coherently,
+// once per step.  Each row is rounded by round_row_keep_sum.
+//
+// Band tiles: one thread per (set, tile row I, row r) walks the nb x 16
+// entries of its row, read from the FP64 tiles of the set when they are
+// stored (src64), else computed as k_pack_band does (the same values).
+__global__ void k_pack_band32(LuAcc F, int NT, int nb, const double *Linv, const double *Uinv, BandOut src64,
+                              BandOut o32) {
+    const int64_t rows = (int64_t)NT * TILE;
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (tid >= 4 * rows) return;
+    const int a = (int)(tid / rows);
+    if (!o32.b[a]) return;
+    const int64_t I = (tid % rows) / TILE;
+    const int r = (int)(tid % TILE);
+    round_row_keep_sum((float *)o32.b[a], nb * TILE, [&](int t, int64_t &dst) {
+        const int j = t / TILE, q = t % TILE;
+        const int64_t tile = (I * nb + j) * TILE_ELEMS;
+        dst = tile + aslot(true, r, q);
+        return src64.b[a] ? ((const double *)src64.b[a])[tile + aslot(false, r, q)]
+                          : band_elem(F, nb, Linv, Uinv, I, j, r, q, a);
+    });
 }
 
 // Phase 1: FP64 inverses of the diagonal tiles, natural row-major 16x16 per
@@ -225,25 +290,39 @@ __global__ void k_diag_inv(LuAcc F, int NT, double *Linv, double *Uinv) {
 }
 
 // Phase 2: diagonal inverses DL = L(I,I)^{-1}, DU = U(I,I)^{-1} and their
-// transposes as MFMA A operands (aslot layout), FP64 and/or FP32.  One
-// thread per (tile row, column).
+// transposes as MFMA A operands (aslot layout), FP64 and/or FP32.
 struct DiagOut {
     void *D[4];   // DL, DU, DLT, DUT
 };
 
+// Element (r, c) of diagonal set a (0 DL, 1 DU, 2 DLT, 3 DUT) of tile row I.
+__device__ inline double diag_elem(const double *Linv, const double *Uinv, int64_t I, int r, int c, int a) {
+    const double *Li = Linv + I * TILE_ELEMS, *Ui = Uinv + I * TILE_ELEMS;
+    switch (a) {
+        case 0: return Li[r * TILE + c];
+        case 1: return Ui[r * TILE + c];
+        case 2: return Li[c * TILE + r];
+        default: return Ui[c * TILE + r];
+    }
+}
+
+// One thread per (tile row, row r): FP64 copies as they are, FP32 copies
+// with the row sum kept (as k_pack_band32).
 __global__ void k_pack_diag(int NT, const double *Linv, const double *Uinv, DiagOut o64, DiagOut o32) {
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (tid >= (int64_t)NT * TILE) return;
     const int64_t I = tid / TILE;
-    const int col = (int)(tid % TILE);
-    const double *Li = Linv + I * TILE_ELEMS, *Ui = Uinv + I * TILE_ELEMS;
+    const int r = (int)(tid % TILE);
     const int64_t off = I * TILE_ELEMS;
-    for (int r = 0; r < TILE; ++r) {
-        const double dv[4] = {Li[r * TILE + col], Ui[r * TILE + col], Li[col * TILE + r], Ui[col * TILE + r]};
-        for (int a = 0; a < 4; ++a) {
-            if (o64.D[a]) ((double *)o64.D[a])[off + aslot(false, r, col)] = dv[a];
-            if (o32.D[a]) ((float *)o32.D[a])[off + aslot(true, r, col)] = (float)dv[a];
-        }
+    for (int a = 0; a < 4; ++a) {
+        if (o64.D[a])
+            for (int c = 0; c < TILE; ++c)
+                ((double *)o64.D[a])[off + aslot(false, r, c)] = diag_elem(Linv, Uinv, I, r, c, a);
+        if (o32.D[a])
+            round_row_keep_sum((float *)o32.D[a], TILE, [&](int c, int64_t &dst) {
+                dst = off + aslot(true, r, c);
+                return diag_elem(Linv, Uinv, I, r, c, a);
+            });
     }
 }
 
@@ -265,8 +344,15 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
         b64.b[a] = t64 ? t64->a[bidx[a]] : nullptr;
         b32.b[a] = t32 ? t32->a[bidx[a]] : nullptr;
     }
-    hipLaunchKernelGGL(k_pack_band, dim3((unsigned)blocks), dim3(256), 0, s, F, NT, nb, Linv, Uinv, b64, b32);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (t64) {
+        hipLaunchKernelGGL(k_pack_band, dim3((unsigned)blocks), dim3(256), 0, s, F, NT, nb, Linv, Uinv, b64);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (t32) {
+        hipLaunchKernelGGL(k_pack_band32, dim3((unsigned)((4 * th + 127) / 128)), dim3(128), 0, s, F, NT, nb, Linv,
+                           Uinv, b64, b32);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     DiagOut o64{}, o32{};
     const int didx[4] = {TS_DL, TS_DU, TS_DLT, TS_DUT};
     for (int a = 0; a < 4; ++a) {

@@ -8,7 +8,14 @@ size.
 * 511^2 operator with the time-dependent diffusion of its first slice
   (n = 261121, b = 511): the same, FP64 and FP32;
 * both operators through factors kept with spikes (partitioned fine sweeps);
-* the full 255^2 pipeline (64 slices, k = 40, p = 10, Parareal to 1e-10):
+* the timed configuration (255^2, FP32 fine solves and range finder, factors
+  with the UL set so that substitutions run in pairs): one sweep of all 3200
+  range-finder columns x 32 steps, forward and adjoint, on three sampled
+  columns (1e-5); the FP32 rSVD build of 64 slices on the library's Philox
+  Omega, one slice against the oracle's rSVD on the oracle's own draws
+  (1e-5); the FP32-fine Parareal iterate a fixed point of the oracle's F_n
+  on sampled slices;
+* the full 255^2 pipeline in FP64 (64 slices, k = 40, p = 10, Parareal to 1e-10):
   singular values descending with sigma_1 <= 1 (diagonal dominance);
   orthonormal U_k, V_k; the low-rank error on a sampled slice and vector
   against the oracle's T_n v, within a few sigma_{k+1} (eq.
@@ -151,3 +158,111 @@ def test_dar255_parareal_fixed_point(ctx, ora, dar255_run):
     for n_ in (1, 20, 64):
         ref = op.fine(U[n_ - 1].reshape(-1, 1), P.m, dar255_run["f"], None, P.fscale(n_).reshape(1, -1))[:, 0]
         assert np.linalg.norm(U[n_] - ref) <= 1e-9 * scale, n_
+
+
+# -- the timed configuration: FP32 fine solves and range finder on factors kept
+# with the UL set (steps alternate L U / U' L', substitutions paired), 64 slices
+# x (k + p) = 3200 range-finder columns x 32 steps in one sweep call
+
+@pytest.fixture(scope="module")
+def timed_factor(ctx):
+    from paper_2508_08873_amd import lrpr
+    P = inputs.dar255()
+    F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
+                   store_mask=lrpr.STORE_F64 | lrpr.STORE_F32 | lrpr.STORE_MIRROR | lrpr.STORE_SPLIT | lrpr.STORE_UL)
+    yield P, F
+    F.close()
+
+
+@pytest.mark.parametrize("adjoint", [False, True], ids=["fwd", "adj"])
+def test_timed_config_sweep_sampled(ctx, ora, timed_factor, adjoint):
+    """One FP32 sweep of all 3200 columns over the 32 steps of a slice; three
+    columns (first, inside, last group) from host draws, recomputed by the
+    oracle; every other column is filled with torch Gaussians."""
+    P, F = timed_factor
+    w = P.N * P.l
+    cols = (0, 1633, w - 1)
+    print("timed config sweep, adjoint", adjoint, "w", w, flush=True)
+    Xs = np.random.default_rng([21, int(adjoint)]).standard_normal((P.n, len(cols)))
+    Xs = Xs.astype(np.float32).astype(np.float64)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(21)
+    X = torch.randn((w, P.n), generator=gen, device="cuda", dtype=torch.float32).t()
+    for j, c in enumerate(cols):
+        X[:, c] = torch.from_numpy(Xs[:, j]).to("cuda", torch.float32)
+    spec = {"F": F, "X": X}
+    fsc = np.stack([P.fscale(1 + c // P.l) for c in range(w)])
+    f = P.source()
+    if adjoint:
+        ctx.adjoint_step_batched([spec], P.m, 1)
+    else:
+        spec["f"] = _dev(f.reshape(-1, 1), torch.float32)
+        spec["fscale"] = torch.from_numpy(np.ascontiguousarray(fsc)).to("cuda")
+        ctx.fine_step_batched([spec], P.m, 1)
+    got = X[:, list(cols)].double().cpu().numpy()
+    op = _oracle_op(ora, P)
+    ref = op.adjoint(Xs, P.m) if adjoint else op.fine(Xs, P.m, f, None, fsc[list(cols)])
+    err = float(np.max(np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)))
+    assert err <= 1e-5, err
+
+
+@pytest.fixture(scope="module")
+def timed_run(ctx, timed_factor):
+    """The FP32 rSVD build and Parareal (to 1e-6) of the timed step, with
+    Omega_n the library's Philox Gaussians of (seed 0, stream n)."""
+    P, F = timed_factor
+    Om = torch.empty((P.N, P.l, P.n), device="cuda", dtype=torch.float64)
+    for s in range(P.N):
+        ctx.randn(Om[s], 0, s)
+    Om32 = Om.to(torch.float32)
+    del Om
+    coarse = ctx.rsvd_build([(F, P.k, P.p, Om32[s].t()) for s in range(P.N)], P.m, 1)
+    del Om32
+    u0, f = P.u0(), P.source()
+    fsc = torch.from_numpy(np.concatenate([P.fscale(s) for s in range(1, P.N + 1)])).to("cuda")
+    out = ctx.parareal_solve(coarse, [F] * P.N, P.m, _dev(u0.reshape(-1, 1)), _dev(f.reshape(-1, 1)), fsc,
+                             tol=1e-6, fine_prec=1)
+    torch.cuda.synchronize()
+    yield {"P": P, "coarse": coarse, "out": out, "u0": u0, "f": f}
+    coarse.close()
+
+
+def test_timed_config_rsvd_sampled_slice(ctx, ora, timed_run):
+    """Slice 17 of the FP32 build against the oracle's randomized SVD on the
+    same Omega (the oracle's own Philox4x32-10 + Box-Muller draws, rounded to
+    FP32 as the library's range finder sees them): singular values and the
+    coarse product on sampled vectors within 1e-5 (relative to sigma_1 and
+    to the product's norm)."""
+    from oracle import philox
+    from paper_2508_08873_amd.lrpr import device_view
+    P, coarse = timed_run["P"], timed_run["coarse"]
+    s = 16
+    print("timed config rsvd, slice", s + 1, flush=True)
+    Om = philox.randn(P.l * P.n, 0, s).reshape(P.l, P.n).T.astype(np.float32).astype(np.float64)
+    Uo, So, Vo = ora.rsvd(_oracle_op(ora, P), P.m, P.k, P.p, Om)
+    Sg = np.array(coarse.sigma[s * P.l:(s + 1) * P.l])
+    assert np.abs(Sg - So).max() <= 1e-5 * So[0], np.abs(Sg - So).max() / So[0]
+    k, n, U, S, V = coarse.get(s)
+    Ug, Vg = device_view(U, n, k).cpu().numpy(), device_view(V, n, k).cpu().numpy()
+    Sk = device_view(S, P.l, 1).cpu().numpy()[:k, 0]
+    X = np.random.default_rng(3).standard_normal((n, 4))
+    Pg, Po = Ug @ (Sk[:, None] * (Vg.T @ X)), Uo @ (So[:k, None] * (Vo.T @ X))
+    assert np.linalg.norm(Pg - Po) <= 1e-5 * np.linalg.norm(Po)
+    # U_k = Q Uh and V_k = Q_Z Vh with Q, Q_Z orthonormalised from FP32 panels
+    assert np.abs(Ug.T @ Ug - np.eye(k)).max() <= 1e-5
+    assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-5
+
+
+def test_timed_config_parareal_fixed_point(ctx, ora, timed_run):
+    """The FP32-fine Parareal iterate converged to 1e-6 satisfies
+    u_n = F_n u_{n-1} on sampled slices to the FP32 fine solves' rounding
+    (1e-5 of the largest state norm), F_n the oracle's FP64 propagator."""
+    P, out = timed_run["P"], timed_run["out"]
+    assert out["status"] == 0 and out["iters"][0] <= P.N
+    U = out["U"][0].cpu().numpy()
+    assert np.array_equal(U[0], timed_run["u0"])
+    op = _oracle_op(ora, P)
+    scale = np.linalg.norm(U, axis=1).max()
+    for n_ in (1, 33, 64):
+        ref = op.fine(U[n_ - 1].reshape(-1, 1), P.m, timed_run["f"], None, P.fscale(n_).reshape(1, -1))[:, 0]
+        assert np.linalg.norm(U[n_] - ref) <= 1e-5 * scale, n_
