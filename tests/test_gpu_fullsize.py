@@ -203,6 +203,7 @@ def test_timed_config_sweep_sampled(ctx, ora, timed_factor, adjoint):
     op = _oracle_op(ora, P)
     ref = op.adjoint(Xs, P.m) if adjoint else op.fine(Xs, P.m, f, None, fsc[list(cols)])
     err = float(np.max(np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)))
+    print("timed config sweep error", err, flush=True)
     assert err <= 1e-5, err
 
 
@@ -241,13 +242,15 @@ def test_timed_config_rsvd_sampled_slice(ctx, ora, timed_run):
     Om = philox.randn(P.l * P.n, 0, s).reshape(P.l, P.n).T.astype(np.float32).astype(np.float64)
     Uo, So, Vo = ora.rsvd(_oracle_op(ora, P), P.m, P.k, P.p, Om)
     Sg = np.array(coarse.sigma[s * P.l:(s + 1) * P.l])
-    assert np.abs(Sg - So).max() <= 1e-5 * So[0], np.abs(Sg - So).max() / So[0]
     k, n, U, S, V = coarse.get(s)
     Ug, Vg = device_view(U, n, k).cpu().numpy(), device_view(V, n, k).cpu().numpy()
     Sk = device_view(S, P.l, 1).cpu().numpy()[:k, 0]
     X = np.random.default_rng(3).standard_normal((n, 4))
     Pg, Po = Ug @ (Sk[:, None] * (Vg.T @ X)), Uo @ (So[:k, None] * (Vo.T @ X))
-    assert np.linalg.norm(Pg - Po) <= 1e-5 * np.linalg.norm(Po)
+    es, ep = np.abs(Sg - So).max() / So[0], np.linalg.norm(Pg - Po) / np.linalg.norm(Po)
+    print("timed config rsvd: sigma error", es, "product error", ep, flush=True)
+    assert es <= 1e-5, es
+    assert ep <= 1e-5, ep
     # U_k = Q Uh and V_k = Q_Z Vh with Q, Q_Z orthonormalised from FP32 panels
     assert np.abs(Ug.T @ Ug - np.eye(k)).max() <= 1e-5
     assert np.abs(Vg.T @ Vg - np.eye(k)).max() <= 1e-5
@@ -265,4 +268,6 @@ def test_timed_config_parareal_fixed_point(ctx, ora, timed_run):
     scale = np.linalg.norm(U, axis=1).max()
     for n_ in (1, 33, 64):
         ref = op.fine(U[n_ - 1].reshape(-1, 1), P.m, timed_run["f"], None, P.fscale(n_).reshape(1, -1))[:, 0]
-        assert np.linalg.norm(U[n_] - ref) <= 1e-5 * scale, n_
+        e = np.linalg.norm(U[n_] - ref) / scale
+        print("timed config parareal: slice", n_, "fixed-point residual", e, flush=True)
+        assert e <= 1e-5, n_
