@@ -278,7 +278,11 @@ def test_fp32_smooth_mode_accuracy(ctx, ora):
     255^2 operator (L U factors, unpaired passes) shrink the smooth grid
     modes sin(pi x) sin(pi y) and sin(2 pi x) sin(pi y) by less than 1e-6
     forward and 3e-6 adjoint relative to the oracle (measured 3e-7 and
-    2e-6; plainly rounded tiles gave 2.1e-6 and 3.9e-6)."""
+    2e-6; plainly rounded tiles gave 2.1e-6 and 3.9e-6).  The remaining
+    error is the FP32 rounding of the partial sums, which is also nearly the
+    same in every interior row; its size depends on how the kernel groups
+    the band tiles, so a change of that grouping can move it within the
+    FP32 target and needs these bounds re-measured."""
     from paper_2508_08873_amd import lrpr
     P = inputs.dar255()
     F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
