@@ -532,7 +532,7 @@ constexpr int PAIR_PDH = 3;   // helpers' prefetch depth in pass pairs
 #endif
 // prefetch depth (tile rows) of the bulk waves in pass pairs
 #ifndef LRPR_PAIR_PD32
-#define LRPR_PAIR_PD32 5
+#define LRPR_PAIR_PD32 6
 #endif
 #ifndef LRPR_PAIR_PD64
 #define LRPR_PAIR_PD64 2
@@ -911,7 +911,7 @@ __device__ __forceinline__ void sweep_pair(const SweepItem &it, const T *__restr
 // the second substitution of a U' L' step with the first of the following
 // L U step.  stepB: the step of pass B (its source's time factor).
 // minimum waves per SIMD of the FP32 pair kernels (4 fits two workgroups per
-// compute unit at prefetch depth 2; measured slower than one at depth 5)
+// compute unit at prefetch depth 2; measured slower than one at depth 5 or 6)
 #ifndef LRPR_PAIR_WG32
 #define LRPR_PAIR_WG32 1
 #endif
