@@ -245,7 +245,10 @@ typedef struct {
  *     (I + dt*A) x_{j+1} = x_j + dt * fscale[c][j] * f[:, fcol[c]]
  * through the panel's band LU (forward then back substitution).  Without a
  * source this is the transfer operator T = M^{-nsteps} (= F_n').  All panels
- * run in one launch; panels may use different factors and sizes.
+ * run in one launch; panels may use different factors and sizes.  When every
+ * factor keeps spikes (LRPR_STORE_SPLIT) and the launch has at most 32
+ * sixteen-column groups, the partitioned passes run; otherwise the plain (or
+ * paired) substitution.  The two round differently (same solve).
  * Errors: LRPR_ERR_ARG (null/mismatched arguments, missing FP32 factor). */
 lrpr_status lrpr_fine_step_batched(lrpr_ctx ctx, int npanels, const lrpr_panel *panels,
                                    int nsteps, lrpr_prec prec);
@@ -379,8 +382,13 @@ lrpr_status lrpr_coarse_apply(lrpr_ctx ctx, lrpr_coarse c, int s, int w, const d
  *   apost_host  host double[nreq*N] or NULL: a posteriori bound (eq.
  *            apost_bound) of the last iterate, per slice, with
  *            delta = max_n sigma_{n,1}, eps = max_n sigma_{n,k+1}.
+ * Fine solves on factors that keep spikes always take the partitioned
+ * passes, and every column's arithmetic is independent of the others, so a
+ * problem's results are the same bit for bit whatever nreq and the other
+ * problems are.
  * Returns LRPR_ERR_NOCONV (with all outputs written) if some problem
- * did not reach tol within max_iter iterations (max_iter < N).
+ * did not reach tol within max_iter iterations (max_iter < N);
+ * LRPR_ERR_NONFINITE if an increment is not finite (outputs not written).
  * Synchronises. */
 lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, int nsteps,
                                 lrpr_prec fine_prec, int nreq, const double *u0, const double *f,
@@ -398,7 +406,9 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
  * sweep and one coarse sweep per step; requests that arrive while a step is
  * on the GPU join the operator's next step.  Operators step independently
  * on their own streams.  A request's result does not depend on which other
- * requests share its steps.
+ * requests share its steps: every column's arithmetic is independent of the
+ * others, and on factors that keep spikes the fine sweeps take the
+ * partitioned passes at any batch width.
  *
  * Threading: one host thread per server.  Calls that overlap on one server
  * are not supported. */

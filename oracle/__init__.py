@@ -491,6 +491,40 @@ class Slice:
         return lowrank_apply(self.Uk, self.S, self.Vk, v)[:, 0]
 
 
+def fine_all(slices, vs):
+    """[F_n v_n for every slice n]: the fine solves of one Parareal
+    iteration, which are independent across slices (Sec. 2.2).  Consecutive
+    slices with the same operator, step count and source run as the columns
+    of one call (each column's arithmetic is that of a call of its own)."""
+    out = [None] * len(slices)
+    i = 0
+    while i < len(slices):
+        s = slices[i]
+        j = i + 1
+        if isinstance(getattr(s, "op", None), Operator):
+            while (j < len(slices) and getattr(slices[j], "op", None) is s.op and slices[j].m == s.m
+                   and slices[j].f is s.f):
+                j += 1
+        if j == i + 1:
+            out[i] = s.F(vs[i])
+        else:
+            X = np.stack([np.asarray(vs[q], np.float64) for q in range(i, j)], axis=1)
+            if s.f is None:
+                Y = s.op.fine(X, s.m)
+            else:
+                fsc = None
+                if s.fscale is not None:
+                    fsc = np.stack([np.broadcast_to(np.asarray(slices[q].fscale, np.float64), (s.m,))
+                                    for q in range(i, j)])
+                else:
+                    fsc = np.ones((j - i, s.m))
+                Y = s.op.fine(X, s.m, s.f, None, fsc)
+            for q in range(i, j):
+                out[q] = Y[:, q - i].copy()
+        i = j
+    return out
+
+
 def build_coarse(slices, k, p, omegas):
     """Set up all coarse solvers: rSVD of every F_n' and b_n = F_n 0."""
     for s, om in zip(slices, omegas):
@@ -501,7 +535,8 @@ def build_coarse(slices, k, p, omegas):
             s.Uk = np.zeros((s.op.n, 0))
             s.Vk = np.zeros((s.op.n, 0))
             s.S = np.zeros(0)
-        s.b = s.F(np.zeros(s.op.n))
+    for s, b in zip(slices, fine_all(slices, [np.zeros(s.op.n) for s in slices])):
+        s.b = b
 
 
 def sequential(slices, u0):
@@ -539,7 +574,7 @@ def parareal(slices, u0, tol, max_iter=None):
     incrs = []
     k = 0
     while k < max_iter:
-        Fu = [None] + [slices[n - 1].F(cur[n - 1]) for n in range(1, N + 1)]
+        Fu = [None] + fine_all(slices, cur[:N])
         new = [u0.copy()]
         gnew = [None]
         for n in range(1, N + 1):

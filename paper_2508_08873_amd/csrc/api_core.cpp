@@ -118,8 +118,6 @@ void lrpr_factor_destroy(lrpr_fac f) {
 }  // extern "C"
 
 namespace lrpr {
-lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
-                      bool adjoint);
 FacView fac_view(lrpr_fac f, bool f32);
 lrpr_status ensure_items(lrpr_ctx ctx, size_t count);
 // workspace cached per context and purpose; grows on demand
@@ -481,6 +479,8 @@ namespace lrpr {
 
 // narrow sweeps (at most this many 16-column groups) take the partitioned path
 constexpr int SPLIT_MAX_GROUPS = 32;
+// most consecutive groups on one factor whose update shares a spike read
+constexpr int SPLIT_RUN_GROUPS = 8;
 
 FacView fac_view(lrpr_fac f, bool f32) {
     const TileSet &t = f32 ? f->t32 : f->t64;
@@ -566,9 +566,11 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
     hipError_t e = hipSuccess;
     char *bnd = (char *)ws_get(ctx, "split_bnd", bnd_elems * esz, &e);
     // runs of consecutive groups on one factor (the update reads their spikes once)
+    // (at most SPLIT_RUN_GROUPS groups per run, so wide launches still spread
+    // the update over many workgroups; a group's arithmetic is the same in any run)
     std::vector<int2> runs;
     for (size_t g = 0; g < groups.size(); ++g) {
-        if (g > 0 && gf[g] == gf[g - 1]) ++runs.back().y;
+        if (g > 0 && gf[g] == gf[g - 1] && runs.back().y < SPLIT_RUN_GROUPS) ++runs.back().y;
         else runs.push_back(make_int2((int)g, 1));
     }
     SplitGroup *d_groups = (SplitGroup *)ws_get(ctx, "split_groups", sizeof(SplitGroup) * sg.size(), &e);
@@ -647,7 +649,7 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
 // of nsteps solve steps.  A column's source factors are fscale[c * fstride +
 // step0 + j], j < nsteps.  record: add a profile record for the launch.
 static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
-                                  bool adjoint, int fstride, int step0, bool record) {
+                                  bool adjoint, int fstride, int step0, bool record, bool split_any_width) {
     const bool f32 = prec == LRPR_F32;
     std::vector<SweepItem> items;
     int max_nb = 1;
@@ -686,8 +688,10 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
     hipError_t e = hipSetDevice(ctx->dev);
     if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
     // Few column groups on factors with spikes: partitioned passes, so that
-    // every group spreads over P compute units.
-    bool split = !adjoint && (int)items.size() <= SPLIT_MAX_GROUPS && max_nb <= (f32 ? 64 : 32);
+    // every group spreads over P compute units.  With split_any_width the
+    // choice does not depend on the launch's width.
+    bool split = !adjoint && ((int)items.size() <= SPLIT_MAX_GROUPS || split_any_width) &&
+                 max_nb <= (f32 ? 64 : 32);
     for (int p = 0; p < npanels && split; ++p)
         split = panels[p].w == 0 || (panels[p].F->P >= 2 && (f32 ? panels[p].F->s32.S : panels[p].F->s64.S));
     if (split) return run_split(ctx, npanels, panels, items, nsteps, f32, max_nb, step0, record);
@@ -757,7 +761,7 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
 // a step is a rational function of M, so the adjoint runs the same
 // combinations with M^T.
 lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
-                      bool adjoint) {
+                      bool adjoint, bool split_any_width) {
     if (!ctx) return LRPR_ERR_ARG;
     if (npanels < 0 || (npanels > 0 && !panels) || nsteps < 0 || (prec != LRPR_F64 && prec != LRPR_F32))
         return fail(ctx, LRPR_ERR_ARG, "sweep: invalid arguments");
@@ -769,7 +773,7 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
             return fail(ctx, LRPR_ERR_ARG, "sweep: the panels' factors use different time steppers");
         stepper = panels[p].F->stepper;
     }
-    if (stepper <= 0) return run_sweep_core(ctx, npanels, panels, nsteps, prec, adjoint, nsteps, 0, true);
+    if (stepper <= 0) return run_sweep_core(ctx, npanels, panels, nsteps, prec, adjoint, nsteps, 0, true, split_any_width);
     if (nsteps == 0) return LRPR_OK;
     if (stepper == LRPR_STEP_SEQUENCE) {
         // step j with each panel's j-th factor; the adjoint in reverse order
@@ -785,7 +789,7 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
             const int idx = adjoint ? nsteps - 1 - j : j;
             for (int p = 0; p < npanels; ++p)
                 if (panels[p].w > 0) sp[p].F = panels[p].F->seq[idx];
-            lrpr_status r = run_sweep_core(ctx, npanels, sp.data(), 1, prec, adjoint, nsteps, idx, false);
+            lrpr_status r = run_sweep_core(ctx, npanels, sp.data(), 1, prec, adjoint, nsteps, idx, false, split_any_width);
             if (r != LRPR_OK) return r;
         }
         if (ctx->prof) {
@@ -834,10 +838,13 @@ lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int n
     for (int j = 0; j < nsteps; ++j) {
         lrpr_status r;
         if ((e = comb(OU, OX, 1.0, -1, 0.0, -1, 0.0)) != hipSuccess) return hipfail(ctx, e, "SDIRK copy");
-        if ((r = run_sweep_core(ctx, npanels, panels, 1, prec, adjoint, fstride, 2 * j, false)) != LRPR_OK) return r;
+        if ((r = run_sweep_core(ctx, npanels, panels, 1, prec, adjoint, fstride, 2 * j, false, split_any_width)) !=
+            LRPR_OK)
+            return r;
         if ((e = comb(OV, OX, 1.0, -1, 0.0, -1, 0.0)) != hipSuccess) return hipfail(ctx, e, "SDIRK copy");
         if ((e = comb(OX, OU, 1.0 - beta, OV, beta, -1, 0.0)) != hipSuccess) return hipfail(ctx, e, "SDIRK stage");
-        if ((r = run_sweep_core(ctx, npanels, panels, 1, prec, adjoint, fstride, 2 * j + 1, false)) != LRPR_OK)
+        if ((r = run_sweep_core(ctx, npanels, panels, 1, prec, adjoint, fstride, 2 * j + 1, false, split_any_width)) !=
+            LRPR_OK)
             return r;
         if (stepper == LRPR_STEP_SDIRK2 && (e = comb(OX, OX, 0.5, OV, 1.0, OU, -0.5)) != hipSuccess)
             return hipfail(ctx, e, "SDIRK step");

@@ -14,8 +14,6 @@
 
 namespace lrpr {
 FacView fac_view(lrpr_fac f, bool f32);
-lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
-                      bool adjoint);
 
 // Workspace cached per context and purpose; grows on demand.
 void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err);
@@ -587,7 +585,9 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
             return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: factor lacks the requested precision");
         kmax = std::max(kmax, c->k[s]);
     }
-    if (max_iter > N) max_iter = N;
+    // iterations are capped at N (Parareal is exact there); max_iter stays the
+    // row stride of incr_host
+    const int kcap = std::min(max_iter, N);
     CK(hipSetDevice(ctx->dev), "hipSetDevice");
     hipStream_t st = ctx->stream;
     const size_t blk = (size_t)n * nreq;           // one slice's n x nreq block
@@ -652,7 +652,7 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
     // b_n = F_n 0
     if (f32) CK(launch_fillf((float *)X, (int64_t)blk * N, 0.0f, st), "zero");
     else CK(launch_fill((double *)X, (int64_t)blk * N, 0.0, st), "zero");
-    lrpr_status r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, fine_prec, false);
+    lrpr_status r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, fine_prec, false, true);
     if (r != LRPR_OK) return r;
     CK(launch_convert(f32 ? 1 : 0, 0, X, Bv, (int64_t)blk * N, st), "b_n");
     // u^0: u^0_0 = u0, u^0_n = G_n' u^0_{n-1} + b_n
@@ -673,10 +673,10 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
     std::vector<double> last_inc((size_t)N * nreq, 0.0), hinc((size_t)N * nreq);
     std::vector<int> conv(nreq, 0);
     int nactive = nreq;
-    for (int k = 0; k < max_iter && nactive > 0; ++k) {
+    for (int k = 0; k < kcap && nactive > 0; ++k) {
         // fine solves of all slices from u^k_{n-1}, one batched launch
         CK(launch_convert(0, f32 ? 1 : 0, Ucur, X, (int64_t)blk * N, st), "u -> X");
-        r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, fine_prec, false);
+        r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, fine_prec, false, true);
         if (r != LRPR_OK) return r;
         // sequential correction sweep
         for (int s = 0; s < N; ++s) {

@@ -40,8 +40,6 @@
 #include "lrpr_internal.h"
 
 namespace lrpr {
-lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
-                      bool adjoint);
 void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err);
 }  // namespace lrpr
 
@@ -172,7 +170,7 @@ lrpr_status launch_step(lrpr_server srv, Pipe &p) {
             s = e;
         }
     }
-    lrpr_status rs = run_sweep(p.ctx, (int)panels.size(), panels.data(), p.d.nsteps, LRPR_F64, false);
+    lrpr_status rs = run_sweep(p.ctx, (int)panels.size(), panels.data(), p.d.nsteps, LRPR_F64, false, true);
     if (rs != LRPR_OK) return sfail(srv, rs, std::string("serve sweep: ") + lrpr_last_error(p.ctx));
     // column tables of the coarse sweep
     p.h_cu.resize(w);

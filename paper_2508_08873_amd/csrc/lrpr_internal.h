@@ -173,6 +173,14 @@ inline int fac_stages(const lrpr_factor_s *f) { return (f->stepper == 1 || f->st
 // error helper: record message in ctx and return status
 lrpr_status fail(lrpr_ctx ctx, lrpr_status st, const std::string &msg);
 
+// Batched sweeps of nsteps steps of the panels' stepper (api_core.cpp).
+// Forward sweeps on factors that all carry spikes take the partitioned passes
+// when the launch has few column groups, or always with split_any_width: a
+// column's arithmetic then does not depend on how many other columns share
+// the launch (Parareal and the server rely on this).
+lrpr_status run_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
+                      bool adjoint, bool split_any_width = false);
+
 // kernels launched from the host code (defined in the .hip sources)
 // rev: assemble J diag(M, I) J with rows = 16 NT (its LU gives the UL factorisation of M)
 hipError_t launch_assemble(const lrpr_op_desc &op, int64_t n, int64_t rows, int bw, bool rev, double *band,

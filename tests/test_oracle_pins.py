@@ -440,14 +440,79 @@ def test_error_bounds_hold(ora):
 
 
 def test_bound_constants_from_oversampled_sigma(ora):
-    P = inputs.heat1d()
-    P.N = 3
-    op = ora.Operator(**P.op_params())
-    sl = _slices(ora, P, [op] * 3)
+    """delta and eps (eq. bounds_delta_eps) against the singular values of
+    the dense transfer operators of three slices with different nu: delta is
+    within the interlacing bracket just below the largest sigma_1(T_n), eps
+    within the bracket below the largest sigma_{k+1}(T_n), and with l = n (a complete sketch) eps is exactly the
+    largest sigma_{k+1}(T_n)."""
+    P = inputs.tiny2d(nx=7, N=3, m=5, k=4, p=3, nu_of_t=True, T=0.15)
+    ops = [ora.Operator(**P.op_params(n)) for n in range(1, 4)]
+    svs = [np.linalg.svd(_dense_T(op, P.m), compute_uv=False) for op in ops]
+    assert len({round(sv[0], 12) for sv in svs}) == 3          # the slices differ
+    sl = _slices(ora, P, ops)
     ora.build_coarse(sl, P.k, P.p, [P.omega(n) for n in range(1, 4)])
     d, e = ora.bound_constants(sl, P.k)
-    assert d == max(s.S[0] for s in sl) and e == max(s.S[P.k] for s in sl)
+    s1 = max(sv[0] for sv in svs)
+    assert s1 * (1 - 1e-3) <= d <= s1 * (1 + 1e-12)
+    top = max(sv[P.k] for sv in svs)
+    assert 0.5 * top <= e <= top * (1 + 1e-10)
     assert d <= 1.0
+    r = np.random.default_rng(11)
+    for s, op in zip(sl, ops):
+        s.Uk, s.S, s.Vk = ora.rsvd(op, P.m, P.k, P.n - P.k, r.standard_normal((P.n, P.n)))
+    d, e = ora.bound_constants(sl, P.k)
+    assert abs(e - top) <= 1e-12 * d and abs(d - max(sv[0] for sv in svs)) <= 1e-12 * d
+
+
+class _ScalarSlice:
+    """A one-unknown slice: F v = a v + b, G' v = g v (duck-typed like Slice)."""
+
+    def __init__(self, a, g, b):
+        self.a, self.g, self.b = a, g, np.array([b])
+
+    def F(self, v):
+        return self.a * np.asarray(v) + self.b
+
+    def Gp(self, v):
+        return self.g * np.asarray(v)
+
+
+def test_apost_bound_is_attained_by_scalar_parareal(ora):
+    """Thm. 3 from both sides: for scalar slices F' = delta > 0 and
+    G' = delta - eps >= 0 with positive data, every term of the error
+    recursion e_n = (F' - G')(u^{k-1}_{n-1} - u^k_{n-1}) + F' e_{n-1} has the
+    same sign, so eq. apost_bound holds with equality.  A dropped term, a
+    wrong power of delta or a wrong summation range breaks the equality."""
+    for delta, eps, N in ((0.7, 0.2, 6), (1.3, 0.45, 5), (0.4, 0.4, 7)):
+        sl = [_ScalarSlice(delta, delta - eps, 0.3 * (i + 1)) for i in range(N)]
+        seq = ora.sequential(sl, np.array([1.0]))
+        res = ora.parareal(sl, np.array([1.0]), tol=0.0, max_iter=N - 1)
+        for k in range(1, N):
+            err = np.abs(res["iterates"][k] - seq)[1:, 0]
+            inc = np.abs(res["iterates"][k] - res["iterates"][k - 1])[1:, 0]
+            post = ora.apost_bound(delta, eps, inc)
+            assert np.abs(err - post).max() <= 1e-13 * max(1.0, post.max()), (delta, eps, k)
+            # eq. apost_bound_sup for delta < 1
+            if delta < 1:
+                assert err.max() <= eps / (1 - delta) * inc.max() * (1 + 1e-12)
+
+
+def test_apost_and_apriori_bounds_hand_values(ora):
+    """Values worked out by hand for delta = 1/2, eps = 1/10:
+    a posteriori with increments (1, 2, 4, 8): n = 1: 0; n = 2: 0.1 * 1;
+    n = 3: 0.1 * (0.5 * 1 + 2) = 0.25; n = 4: 0.1 * (0.25 + 1 + 4) = 0.525.
+    A priori with ||b_m|| = (1, 2, 3, 4):
+    k = 1, n = 3: 2 * 0.1 * (3 * 0.25 * 1 + 2 * 0.5 * 2) = 0.55;
+    k = 2, n = 3: 2 * 0.01 * (3 * 0.5 * 1) = 0.03;
+    k = 2, n = 4: 2 * 0.01 * (6 * 0.25 * 1 + 3 * 0.5 * 2) = 0.09;
+    k = n: no term, 0."""
+    post = ora.apost_bound(0.5, 0.1, [1.0, 2.0, 4.0, 8.0])
+    assert np.allclose(post, [0.0, 0.1, 0.25, 0.525], rtol=1e-15, atol=0)
+    b = [1.0, 2.0, 3.0, 4.0]
+    assert abs(ora.apriori_bound(0.5, 0.1, b, 1, 3) - 0.55) <= 1e-15
+    assert abs(ora.apriori_bound(0.5, 0.1, b, 2, 3) - 0.03) <= 1e-16
+    assert abs(ora.apriori_bound(0.5, 0.1, b, 2, 4) - 0.09) <= 1e-16
+    assert ora.apriori_bound(0.5, 0.1, b, 3, 3) == 0.0
 
 
 def test_philox_known_answers():
