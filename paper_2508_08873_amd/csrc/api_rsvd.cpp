@@ -698,13 +698,16 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
         for (int q = 0; q < nreq; ++q) {
             if (!hact[q]) continue;
             double mx = 0.0;
+            bool finite = true;
             for (int s = 0; s < N; ++s) {
                 const double v = hinc[(size_t)s * nreq + q];
                 last_inc[(size_t)s * nreq + q] = std::sqrt(v);
+                finite = finite && std::isfinite(v);   // std::max would drop a NaN
                 mx = std::max(mx, v);
             }
             const double inc = std::sqrt(mx);
-            if (!std::isfinite(inc)) return fail(ctx, LRPR_ERR_NONFINITE, "non-finite Parareal increment");
+            if (!finite || !std::isfinite(inc))
+                return fail(ctx, LRPR_ERR_NONFINITE, "non-finite Parareal increment");
             incr[(size_t)q * max_iter + k] = inc;
             iters[q] = k + 1;
             if (inc < tol || k + 1 >= N) {

@@ -49,7 +49,7 @@ def test_nonfinite_pivot(ctx, dim, nx):
     # nu * dt / h^2 overflows: every pivot is infinite
     with pytest.raises(lrpr.LrprError) as ei:
         ctx.factor(dim, nx, 1e300, (0.0, 0.0), 0.0, 1e300, store_mask=lrpr.STORE_F64)
-    assert ei.value.args[0] == 3
+    assert ei.value.status == 3
     # the context stays usable
     F = ctx.factor(dim, nx, 1.0, (0.0, 0.0), 0.0, 1e-3, store_mask=lrpr.STORE_F64)
     F.close()
@@ -62,7 +62,7 @@ def test_nonfinite_increment(ctx):
     u0[5] = np.nan
     with pytest.raises(lrpr.LrprError) as ei:
         ctx.parareal_solve(coarse, [F] * P.N, P.m, _dev(u0), _dev(P.source()), fsc, tol=1e-12)
-    assert ei.value.args[0] == 6
+    assert ei.value.status == 6
     # a finite problem on the same context still solves
     out = ctx.parareal_solve(coarse, [F] * P.N, P.m, _dev(P.u0()), _dev(P.source()), fsc, tol=1e-12)
     assert out["status"] == 0
