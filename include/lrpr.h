@@ -354,6 +354,18 @@ lrpr_status lrpr_coarse_get(lrpr_coarse c, int s, const double **U, const double
 lrpr_status lrpr_coarse_apply(lrpr_ctx ctx, lrpr_coarse c, int s, int w, const double *Vin,
                               double *Out);
 
+/* The same apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no device memory is allocated or freed.  Its scratch (chunk partials and
+ * coefficients, (ceil(n/256) + 1) * k * min(w, 12288/k) doubles) lives in a
+ * fixed array of 16 MiB per GPU, held until the process ends; a call whose
+ * scratch would exceed it returns LRPR_ERR_ARG and writes nothing.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (from two contexts, streams or threads) race and must be serialised by
+ * the caller.  Results equal lrpr_coarse_apply's.  Asynchronous. */
+lrpr_status lrpr_coarse_apply_noalloc(lrpr_ctx ctx, lrpr_coarse c, int s, int w, const double *Vin,
+                                      double *Out);
+
 /* ---- Parareal with the low-rank coarse propagator (Sec. 2) -------------- */
 
 /* Parareal with the low-rank coarse solvers of c (Sec. 2, eq.

@@ -43,7 +43,7 @@ lrpr_status lrpr_ctx_create(int device, void *hip_stream, lrpr_ctx *out) {
     if (!ctx) return LRPR_ERR_NOMEM;
     ctx->dev = device;
     ctx->stream = (hipStream_t)hip_stream;
-    if (hipSetDevice(device) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess || lrpr::noalloc_scratch_init(device, nullptr) != hipSuccess) {
         delete ctx;
         return LRPR_ERR_HIP;
     }

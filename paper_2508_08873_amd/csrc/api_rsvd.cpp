@@ -60,6 +60,10 @@ hipError_t upload(T *dst, const std::vector<T> &src, hipStream_t s) {
     return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
+}  // namespace
+
+namespace lrpr {
+
 // Low-rank apply over w columns, split so that k*w fits the kernel's LDS.
 hipError_t lowrank_cols(LrArgs a, double *part, double *incpart, hipStream_t s) {
     const int maxw = std::max(1, 12288 / std::max(a.k, 1));
@@ -84,11 +88,7 @@ hipError_t lowrank_cols(LrArgs a, double *part, double *incpart, hipStream_t s) 
     return hipSuccess;
 }
 
-}  // namespace
-
-namespace lrpr {
-void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err);
-}
+}  // namespace lrpr
 
 // ---------------------------------------------------------------------------
 // rSVD build

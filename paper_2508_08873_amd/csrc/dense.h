@@ -69,6 +69,10 @@ struct LrArgs {            // low-rank apply / Parareal correction on w columns
     int64_t coff;
 };
 
+// Low-rank apply / Parareal correction over a.w columns (api_rsvd.cpp), in
+// passes of at most 12288/k columns; part holds lr_part_elems(n, k, min(w,
+// 12288/k)) doubles, incpart (or null) [chunks][w] increment partials.
+hipError_t lowrank_cols(LrArgs a, double *part, double *incpart, hipStream_t s);
 int gram_chunks(int64_t nmax);
 int64_t lr_chunks(int64_t n);
 // doubles of the part workspace of a low-rank apply of rank k on w columns

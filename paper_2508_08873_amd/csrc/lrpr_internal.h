@@ -173,6 +173,10 @@ inline int fac_stages(const lrpr_factor_s *f) { return (f->stepper == 1 || f->st
 // error helper: record message in ctx and return status
 lrpr_status fail(lrpr_ctx ctx, lrpr_status st, const std::string &msg);
 
+// Device address of the fixed scratch array of lrpr_coarse_apply_noalloc on
+// device dev (noalloc.hip); dev must be current.  Looked up once per device.
+hipError_t noalloc_scratch_init(int dev, double **out);
+
 // Batched sweeps of nsteps steps of the panels' stepper (api_core.cpp).
 // Forward sweeps on factors that all carry spikes take the partitioned passes
 // when the launch has few column groups, or always with split_any_width: a

@@ -21,7 +21,8 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
            "lrpr_factor", "lrpr_factor_stepper", "lrpr_factor_sequence", "lrpr_factor_destroy", "lrpr_factor_info", "lrpr_factor_copy_lu",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build", "lrpr_rsvd_build_q",
            "lrpr_rsvd_build_two_sided", "lrpr_rsvd_build_w", "lrpr_coarse_from_factors", "lrpr_mass_weights",
-           "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_parareal_solve",
+           "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_coarse_apply_noalloc",
+           "lrpr_parareal_solve",
            "lrpr_profile_enable", "lrpr_profile_read", "lrpr_randn",
            "lrpr_server_create", "lrpr_server_destroy", "lrpr_server_submit", "lrpr_server_progress",
            "lrpr_server_stats", "lrpr_server_last_error"]
@@ -99,6 +100,7 @@ def load():
     lib.lrpr_coarse_destroy.restype = None
     lib.lrpr_coarse_get.argtypes = [vp, i32, P(vp), P(vp), P(vp), P(i32), P(i64)]
     lib.lrpr_coarse_apply.argtypes = [vp, vp, i32, i32, vp, vp]
+    lib.lrpr_coarse_apply_noalloc.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.lrpr_parareal_solve.argtypes = [vp, vp, P(vp), i32, i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
     lib.lrpr_profile_enable.argtypes = [vp, i32]
     lib.lrpr_profile_read.argtypes = [vp, P(dbl), P(i64), P(dbl), P(dbl), P(dbl)]
@@ -357,6 +359,15 @@ class Coarse:
         out = torch.empty_like(Vin)
         self.ctx.sync_stream()
         self.ctx._check(self.ctx.lib.lrpr_coarse_apply(self.ctx.h, self.h, s, Vin.shape[1], _ptr(Vin), _ptr(out)))
+        return out
+
+    def apply_noalloc(self, s, Vin, out=None):
+        """lrpr_coarse_apply_noalloc into out (allocated here if None)."""
+        if out is None:
+            out = torch.empty_like(Vin)
+        self.ctx.sync_stream()
+        self.ctx._check(self.ctx.lib.lrpr_coarse_apply_noalloc(self.ctx.h, self.h, s, Vin.shape[1], _ptr(Vin),
+                                                               _ptr(out)))
         return out
 
     def close(self):
