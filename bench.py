@@ -52,8 +52,15 @@ PEAK_HBM_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["dar511t", "dar255"], default="dar511t",
+                    help="timed workload: the 511^2 time-dependent one (default; the 255^2 results ride along "
+                         "as a side field) or the 255^2 one alone")
+    ap.add_argument("--no-side", action="store_true", help="dar511t: skip the 255^2 side run")
+    ap.add_argument("--c1-steps", type=int, default=6, help="timed steps of the 255^2 side run")
+    ap.add_argument("--fp64-steps", type=int, default=5, help="timed steps of the 255^2 FP64 side run")
+    ap.add_argument("--c2-cpu-cols", type=int, default=64, help="oracle sample width on the 511^2 operator")
     ap.add_argument("--pipelines", type=int, default=3,
                     help="independent pipelines (context + stream + host thread) sharing the timed steps")
     ap.add_argument("--prec", choices=["f64", "f32"], default="f32",
@@ -192,11 +199,15 @@ def serve_bench(ctx, lrpr, inputs, seed, rate, duration):
             "failed": int(sum(1 for v in iters.values() if v < 0)), "per_operator": per_op}
 
 
-def plain_per_rhs(ctx, lrpr, P):
+def plain_per_rhs(ctx, lrpr, P, reps=8):
     """Plain per-RHS FP64 form: one right-hand side through the fine
-    propagator (m steps, with source) per call, timed with events."""
+    propagator (m steps, with source) per call, on the library's best
+    single-RHS path (a factor with spikes: the partitioned passes spread the
+    column over P compute units), timed with the library's events over
+    `reps` calls.  The HBM fraction uses the algorithmic bytes of one RHS
+    step (2 n s of state and n (2b+1) s of factor, s = 8)."""
     import torch
-    F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=lrpr.STORE_F64)
+    F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=lrpr.STORE_F64 | lrpr.STORE_SPLIT)
     X = lrpr.colmajor(torch.zeros((P.n, 1), dtype=torch.float64, device="cuda"))
     f = lrpr.colmajor(torch.from_numpy(P.source().reshape(-1, 1)).to("cuda"))
     fsc = torch.from_numpy(P.fscale(1).reshape(1, -1).copy()).to("cuda")
@@ -204,11 +215,15 @@ def plain_per_rhs(ctx, lrpr, P):
     ctx.fine_step_batched([spec], P.m, 0)
     torch.cuda.synchronize()
     ctx.profile(True)
-    ctx.fine_step_batched([spec], P.m, 0)
+    for _ in range(reps):
+        ctx.fine_step_batched([spec], P.m, 0)
     p = ctx.profile_read()
     ctx.profile(False)
     F.close()
-    return P.m / (p["ms"] / 1000.0)
+    rate = reps * P.m / (p["ms"] / 1000.0)
+    gbs = p["bytes"] / (p["ms"] / 1000.0) / 1e9
+    return {"rhs_steps_per_s": rate, "path": "partitioned passes (factor with spikes), FP64",
+            "algorithmic_GBs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS, "ms_per_call": p["ms"] / reps}
 
 
 def fwd_adj_rates(ctx, lrpr, P, prec):
@@ -383,12 +398,111 @@ def per_step_operators(ctx, lrpr, inputs, prec, seed):
             "parareal_iters": int(out["iters"][0]), "eps_max_sigma_k1": float(sig[:, P.k].max())}
 
 
-def traffic_from_profile(prec):
+def c2_problem(seed):
+    from paper_2508_08873_amd import inputs
+    return inputs.dar511t(seed=seed)
+
+
+def c2_bench(ctx, lrpr, args):
+    """The 511^2 workload with time-dependent coefficients: nu_n = 1 + 0.5
+    sin(2 pi t_n) per slice (128 slices x 16 implicit-Euler steps, dt =
+    1/2048), so each slice has its own operator and band LU; k = 64, p = 16.
+    One step:
+      1. assemble and factor the 128 operators (band LU in FP64, tiles stored
+         in FP32: 146 GB), the LU workspaces released afterwards;
+      2. rSVD build of all 128 slices together (128 x 80 = 10240 forward and
+         10240 adjoint right-hand sides x 16 steps in FP32, one sweep launch
+         each way; CholeskyQR2 Gram and Cholesky, Jacobi SVD and rotations in
+         FP64), its workspaces released afterwards;
+      3. Parareal with FP32 fine solves (one right-hand side per slice and
+         factor, the HBM-bound regime) and the FP64 correction to
+         max_n ||u^{k+1}_n - u^k_n|| < 1e-6, with the per-slice a posteriori
+         bound (Thm. 3) from the computed singular values.
+    Inputs (Omega in FP32 from the library's Philox generator, u0, f) are in
+    HBM before the timed region.  Returns the result dict and the profile
+    records."""
+    import torch
+    P = c2_problem(args.seed)
+    ops = [P.op_params(s) for s in range(1, P.N + 1)]
+    torch.cuda.empty_cache()
+    Om = torch.empty((P.N, P.l, P.n), device="cuda", dtype=torch.float32)
+    for s_ in range(P.N):
+        ctx.randn(Om[s_], args.seed, s_)
+    u0 = lrpr.colmajor(torch.from_numpy(P.u0().reshape(-1, 1)).to("cuda"))
+    f = lrpr.colmajor(torch.from_numpy(P.source().reshape(-1, 1)).to("cuda"))
+    fsc = torch.from_numpy(np.concatenate([P.fscale(s) for s in range(1, P.N + 1)])).to("cuda")
+    torch.cuda.synchronize()
+
+    def one_step(recs, times):
+        ta = time.perf_counter()
+        facs = ctx.factor_many(ops, store_mask=lrpr.STORE_F32)
+        ctx.release_workspaces()
+        tb = time.perf_counter()
+        coarse = ctx.rsvd_build([(facs[s], P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, 1)
+        ctx.release_workspaces()
+        tc = time.perf_counter()
+        if recs is not None:
+            recs["range"].append(ctx.profile_read())
+        out = ctx.parareal_solve(coarse, facs, P.m, u0, f, fsc, tol=TOL_F32, fine_prec=1)
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        if recs is not None:
+            recs["parareal"].append(ctx.profile_read())
+        sig = np.array(coarse.sigma).reshape(P.N, P.l)
+        if times is not None:
+            times.append((tb - ta, tc - tb, td - tc))
+        coarse.close()
+        for F in facs:
+            F.close()
+        ctx.release_workspaces()
+        return out, sig
+
+    for _ in range(args.warmup):
+        one_step(None, None)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    recs = {"range": [], "parareal": []}
+    times = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, sig = one_step(recs, times)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile(False)
+    del Om
+    torch.cuda.empty_cache()
+    return P, out, sig, recs, times, t1 - t0
+
+
+def c2_cpu_baseline(P, ncols, nsteps, seed):
+    """Oracle fine propagator on a bounded sample of the 511^2 workload:
+    ncols right-hand sides x nsteps implicit-Euler steps (with the source)
+    of slice 1's operator, timed on the host cores after the oracle's band
+    LU of that operator (timed separately)."""
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    op = oracle.Operator(**P.op_params(1))
+    t1 = time.perf_counter()
+    r = np.random.default_rng([seed, 511])
+    X0 = r.standard_normal((P.n, ncols))
+    fsc = np.tile(P.fscale(1)[:nsteps], (ncols, 1))
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), ncols)
+    t2 = time.perf_counter()
+    op.fine(X0, nsteps, P.source(), None, fsc)
+    t3 = time.perf_counter()
+    return {"value": ncols * nsteps / (t3 - t2), "unit": "RHS*steps/s", "cores": threads, "kind": "oracle",
+            "sample": "%d RHS x %d implicit-Euler steps of slice 1's 511^2 operator with source (FP64 C oracle, "
+                      "OpenMP over RHS columns), %.1f s; the oracle's band LU of that operator took %.1f s "
+                      "(not in the rate)" % (ncols, nsteps, t3 - t2, t1 - t0)}
+
+
+def traffic_from_profile(stem):
     """HBM bytes per range-finder sweep call from the committed rocprofv3
     counter summary of this workload, if it was taken from the current sweep
     sources."""
     from paper_2508_08873_amd import prof_summary
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_sweep_dar255_%s.json" % prec)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", stem + ".json")
     if not os.path.exists(path):
         return None, None
     d = json.load(open(path))
@@ -401,22 +515,15 @@ def traffic_from_profile(prec):
 UL_MASK = [0]
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the hot path runs on a single MI355X "
-              "(multi-GPU sharding is described, not built); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    if args.copy_calib:
-        copy_calib(args.copy_calib)
-        return
+def c1_bench(args, ctx, lrpr, inputs):
+    """The 255^2 workload (one shared operator, 64 slices x 32 steps, k = 40,
+    p = 10): the whole path per step on --pipelines concurrent pipelines, the
+    single-pipeline latency, phase times, the range-finder roofline, the FP64
+    side run and the studies.  Returns the result dict."""
     import torch
-    from paper_2508_08873_amd import inputs, lrpr
-
     UL_MASK[0] = 0 if args.no_ul else lrpr.STORE_UL
     P = inputs.dar255(seed=args.seed)
     prec = args.prec
-    ctx = lrpr.Context(0)
     # inputs, resident in HBM before the timed region
     # Omega_n: the library's on-device Philox4x32-10 Gaussians, stream n
     Om64 = torch.empty((P.N, P.l, P.n), device="cuda", dtype=torch.float64)
@@ -544,13 +651,14 @@ def main():
             c.close()
         return t1 - t0, rhs_steps, iters
 
-    times, recs, wall, out, tol = pipeline(prec, args.steps, args.warmup)
+    times, recs, wall, out, tol = pipeline(prec, K if args.workload == "dar511t" else args.steps,
+                                           args.warmup)
     t0, t1 = 0.0, wall
 
     def tot(key, field):
         return sum(r[field] for r in recs[key])
 
-    K = args.steps
+    K = args.c1_steps if args.workload == "dar511t" else args.steps
     allp = {k: tot("range", k) + tot("parareal", k) for k in ("ms", "rhs_steps")}
     lat_ms_per_step = (t1 - t0) * 1000.0 / K
     rhs_steps = allp["rhs_steps"] / K
@@ -572,7 +680,7 @@ def main():
     achieved_gbs = prof["bytes"] / sweep_s / 1e9 if sweep_s > 0 else 0.0
     peak = PEAK_TFLOPS[prec]
     calls = max(prof["launches"], 1)
-    traffic, tsrc = traffic_from_profile(prec)
+    traffic, tsrc = traffic_from_profile("k_sweep_dar255_" + prec)
     roofline = {"bound": "mfma", "achieved": achieved_tf, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved_tf / peak, "traffic": traffic,
                 "kernel": ("k_sweep + k_sweep_pair (range-finder band sweeps: 3200 RHS x 32 implicit-Euler steps, "
@@ -614,11 +722,14 @@ def main():
     }
     if prec == "f32" and not args.no_fp64_side:
         # the same pipeline with FP64 fine solves and range finder (to 1e-10)
-        t64, r64, w64, o64, tol64 = pipeline("f64", 1, 1)
+        t64, r64, w64, o64, tol64 = pipeline("f64", args.fp64_steps, 1)
         rs64 = sum(r["rhs_steps"] for k in r64 for r in r64[k])
-        res["fp64_side"] = {"ms_per_step": w64 * 1000.0, "value": rs64 / w64, "parareal_tol": tol64,
-                            "parareal_iters": o64["iters"][0], "factor_s": t64[0][0], "rsvd_only_s": t64[0][1],
-                            "parareal_s": t64[0][2],
+        res["fp64_side"] = {"steps": args.fp64_steps, "warmup": 1,
+                            "ms_per_step": w64 * 1000.0 / args.fp64_steps, "value": rs64 / w64,
+                            "parareal_tol": tol64, "parareal_iters": o64["iters"][0],
+                            "factor_s": float(np.mean([t[0] for t in t64])),
+                            "rsvd_only_s": float(np.mean([t[1] for t in t64])),
+                            "parareal_s": float(np.mean([t[2] for t in t64])),
                             "range_finder_sweeps_rhs_steps_per_s":
                                 sum(r["rhs_steps"] for r in r64["range"]) /
                                 (sum(r["ms"] for r in r64["range"]) / 1000.0)}
@@ -629,14 +740,101 @@ def main():
         res["fine_steppers"] = stepper_study(ctx, lrpr, P, prec, Om64 if prec == "f64" else Om64.to(torch.float32))
         res["rsvd_variants"] = rsvd_variants(
             ctx, lrpr, P, prec, Om64 if prec == "f64" else Om64.to(torch.float32))
-        res["plain_per_rhs_fp64_rhs_steps_per_s"] = plain_per_rhs(ctx, lrpr, P)
-        res["batched_vs_plain_per_rhs"] = rr / res["plain_per_rhs_fp64_rhs_steps_per_s"]
+        plain = plain_per_rhs(ctx, lrpr, P)
+        res["plain_per_rhs_fp64"] = plain
+        if "fp64_side" in res:
+            res["batched_vs_plain_per_rhs_fp64_vs_fp64"] = (res["fp64_side"]["range_finder_sweeps_rhs_steps_per_s"] /
+                                                            plain["rhs_steps_per_s"])
+        res["batched_vs_plain_per_rhs_%s_vs_fp64" % prec] = rr / plain["rhs_steps_per_s"]
     if not args.no_serve:
         res["serve"] = serve_bench(ctx, lrpr, inputs, args.seed, args.serve_rate, args.serve_duration)
     if not args.no_cpu:
         cb, err = cpu_baseline_and_parity(ctx, lrpr, P, prec, args.cpu_cols, args.cpu_steps, args.seed)
         res["cpu_baseline"] = cb
         res["fine_err_vs_oracle"] = err
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the hot path runs on a single MI355X "
+              "(multi-GPU sharding is described, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calib:
+        copy_calib(args.copy_calib)
+        return
+    import torch
+    from paper_2508_08873_amd import inputs, lrpr
+
+    if args.workload == "dar255":
+        res = c1_bench(args, lrpr.Context(0), lrpr, inputs)
+        print(json.dumps(res), flush=True)
+        return
+    ctx = lrpr.Context(0)
+    P, out, sig, recs, times, wall = c2_bench(ctx, lrpr, args)
+    K = args.steps
+
+    def tot(key, field):
+        return sum(r[field] for r in recs[key])
+
+    rhs_steps = (tot("range", "rhs_steps") + tot("parareal", "rhs_steps")) / K
+    ms_per_step = wall * 1000.0 / K
+    value = rhs_steps * K / wall
+    # dominant kernel: the range-finder sweeps (one k_sweep launch each way
+    # per step: 10240 RHS x 16 steps over 128 factors), FP32 MFMA-bound
+    rng = {k: tot("range", k) for k in ("ms", "launches", "flops", "bytes", "rhs_steps")}
+    calls = max(rng["launches"], 1)
+    sweep_s = rng["ms"] / 1000.0
+    achieved = rng["flops"] / sweep_s / 1e12
+    traffic, tsrc = traffic_from_profile("k_sweep_dar511t_f32")
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                "frac": achieved / PEAK_TFLOPS["f32"], "traffic": traffic,
+                "kernel": "k_sweep (range-finder band sweeps of the 128 slice factors: 10240 RHS x 16 "
+                          "implicit-Euler steps in one launch, forward or adjoint)",
+                "sweep_calls": rng["launches"], "avg_sweep_ms": rng["ms"] / calls,
+                "algorithmic_flops_per_sweep": rng["flops"] / calls,
+                "algorithmic_bytes_per_sweep": rng["bytes"] / calls,
+                "traffic_unit": "HBM bytes per sweep call",
+                "algorithmic_hbm_GBs": rng["bytes"] / sweep_s / 1e9,
+                "hbm_frac": rng["bytes"] / sweep_s / 1e9 / PEAK_HBM_GBS,
+                "traffic_source": tsrc["name"] if tsrc else None}
+    # the Parareal sweeps: one RHS per factor, the HBM-bound regime
+    par = {k: tot("parareal", k) for k in ("ms", "launches", "flops", "bytes", "rhs_steps")}
+    par_s = par["ms"] / 1000.0
+    apost = np.array(out["apost"][0])
+    res = {
+        "metric": "fine-propagator RHS\u00b7steps/s; rSVD build s; served solve p50/p99 latency",
+        "value": value, "unit": "RHS\u00b7steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "dar511t: 2D diffusion-advection-reaction, 511x511 interior grid (n=261121, b=511), "
+                               "nu_n = 1 + 0.5 sin(2 pi t_n) per slice, beta=(20,10), c=1, T=1, 128 slices x 16 "
+                               "implicit-Euler steps, k=64, p=16; step = 128 band LUs + rSVD build of all slices + "
+                               "Parareal to %g with the per-slice a posteriori bound" % TOL_F32,
+                   "rhs_steps_per_step": rhs_steps, "parareal_iters": out["iters"][0],
+                   "range_finder_and_fine_precision": "f32",
+                   "fp64_steps": "LU, CholeskyQR2 Gram/Cholesky, Jacobi SVD, Parareal correction and residual",
+                   "factor_storage": "FP32 tiles, 146 GB for the 128 factors"},
+        "rsvd_build_s": float(np.mean([t[0] + t[1] for t in times])),
+        "factor_s": float(np.mean([t[0] for t in times])), "rsvd_only_s": float(np.mean([t[1] for t in times])),
+        "parareal_s": float(np.mean([t[2] for t in times])),
+        "range_finder_sweeps_rhs_steps_per_s": rng["rhs_steps"] / sweep_s,
+        "parareal_sweeps": {"rhs_steps_per_s": par["rhs_steps"] / par_s, "calls": par["launches"],
+                            "avg_ms": par["ms"] / max(par["launches"], 1),
+                            "algorithmic_GBs": par["bytes"] / par_s / 1e9,
+                            "hbm_frac": par["bytes"] / par_s / 1e9 / PEAK_HBM_GBS,
+                            "note": "one RHS per slice factor (128 factors), FP32; algorithmic bytes = factor "
+                                    "read once per step per factor plus the state"},
+        "eps_max_sigma_k1": float(sig[:, P.k].max()), "delta_max_sigma_1": float(sig[:, 0].max()),
+        "apost_bound": {"max": float(apost.max()), "slice_1": float(apost[0]), "slice_64": float(apost[63]),
+                        "slice_128": float(apost[-1]), "incr": out["incr"][0][:out["iters"][0]]},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = c2_cpu_baseline(P, args.c2_cpu_cols, P.m, args.seed)
+    if not args.no_side:
+        res["dar255"] = c1_bench(args, ctx, lrpr, inputs)
     print(json.dumps(res), flush=True)
 
 

@@ -101,6 +101,11 @@ lrpr_status lrpr_mass_weights(const lrpr_op_desc *op, double *w_host);
  * must not be used from two threads at once. */
 lrpr_status lrpr_ctx_create(int device, void *hip_stream, lrpr_ctx *out);
 void lrpr_ctx_destroy(lrpr_ctx ctx);
+/* Free every cached workspace of ctx (synchronises its stream).  Later
+ * calls allocate them again; handles are not affected.  For callers that
+ * need the device memory between phases of different shapes.
+ * Errors: LRPR_ERR_ARG, LRPR_ERR_HIP. */
+lrpr_status lrpr_ctx_release_workspaces(lrpr_ctx ctx);
 /* Replace the stream used by later calls. */
 lrpr_status lrpr_ctx_set_stream(lrpr_ctx ctx, void *hip_stream);
 /* Message of the last failing call on ctx (static storage owned by ctx). */
@@ -207,6 +212,15 @@ lrpr_status lrpr_factor_stepper(lrpr_ctx ctx, const lrpr_op_desc *op, int store_
  * owns its step factors (lrpr_factor_destroy frees them).  Errors: as
  * lrpr_factor; LRPR_ERR_ARG for m < 1 or mismatched grids. */
 lrpr_status lrpr_factor_sequence(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, int store_mask, lrpr_fac *out);
+/* Independent factors of count operators on one grid (e.g. one per time
+ * slice when the coefficients change from slice to slice, Sec. 4): outs[j]
+ * receives the factor of ops[j], as lrpr_factor would make it.  The band LUs
+ * of several operators run in one launch, in chunks that bound the FP64
+ * bands held at once (the matrices one launch holds together, at least
+ * about 2 GB of bands).  On error no handle is returned (every outs[j] is
+ * NULL).  Errors: as lrpr_factor; LRPR_ERR_ARG for count < 1 or operators
+ * on different grids. */
+lrpr_status lrpr_factor_many(lrpr_ctx ctx, const lrpr_op_desc *ops, int count, int store_mask, lrpr_fac *outs);
 void lrpr_factor_destroy(lrpr_fac f);
 /* n = unknowns, bw = half-bandwidth, dt = step (of the factor's stepper). */
 lrpr_status lrpr_factor_info(lrpr_fac f, int64_t *n, int *bw, double *dt);

@@ -403,6 +403,46 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
     return factor_batch(ctx, op, 1, store_mask, out);
 }
 
+lrpr_status lrpr_factor_many(lrpr_ctx ctx, const lrpr_op_desc *ops, int count, int store_mask, lrpr_fac *outs) {
+    if (!ctx || !ops || !outs || count < 1) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_many: invalid arguments");
+    for (int j = 1; j < count; ++j)
+        if (ops[j].dim != ops[0].dim || ops[j].nx != ops[0].nx)
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_many: the operators must share dim and nx");
+    for (int j = 0; j < count; ++j) outs[j] = nullptr;
+    // chunks of the matrices one LU launch holds (its workgroups resident
+    // together), or of at least 2 GB of FP64 bands per chunk for small grids
+    const int64_t n = ops[0].dim == 1 ? ops[0].nx : (int64_t)ops[0].nx * ops[0].nx;
+    const int bw = ops[0].dim == 1 ? 1 : ops[0].nx;
+    const int NT = (int)((n + TILE - 1) / TILE), nb = (bw + TILE - 1) / TILE;
+    const int P = std::min(nb + 9, NT);
+    const int per_launch = P > 256 ? 1 : 256 / P;
+    const double band_bytes = 8.0 * (double)n * (2 * bw + 1);
+    int chunk = std::max(per_launch, (int)std::min<double>(64.0, 2e9 / std::max(band_bytes, 1.0)));
+    if (store_mask & LRPR_STORE_UL) chunk = std::max(1, chunk / 2);
+    for (int j0 = 0; j0 < count; j0 += chunk) {
+        const int c = std::min(chunk, count - j0);
+        lrpr_status r = factor_batch(ctx, ops + j0, c, store_mask, outs + j0);
+        if (r != LRPR_OK) {
+            for (int j = 0; j < j0; ++j) {
+                lrpr_factor_destroy(outs[j]);
+                outs[j] = nullptr;
+            }
+            return r;
+        }
+    }
+    return LRPR_OK;
+}
+
+lrpr_status lrpr_ctx_release_workspaces(lrpr_ctx ctx) {
+    if (!ctx) return LRPR_ERR_ARG;
+    HIPCHK(hipSetDevice(ctx->dev), "hipSetDevice");
+    HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+    for (auto &kv : ctx->ws)
+        if (kv.second.first) hipFree(kv.second.first);
+    ctx->ws.clear();
+    return LRPR_OK;
+}
+
 lrpr_status lrpr_factor_info(lrpr_fac f, int64_t *n, int *bw, double *dt) {
     if (!f) return LRPR_ERR_ARG;
     if (n) *n = f->n;
@@ -546,7 +586,7 @@ void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err);
 // solves of all blocks, chain, update; then the U pass the same way.
 static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels,
                              const std::vector<SweepItem> &groups, int nsteps, bool f32, int max_nb, int step0,
-                             bool record) {
+                             bool record, SweepPlan *plan, const std::string &pre) {
     hipStream_t st = ctx->stream;
     const size_t esz = f32 ? 4 : 8;
     // factor of every group (items were built panel by panel)
@@ -564,7 +604,7 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
         bnd_elems += (size_t)F->P * F->nb * TILE_ELEMS;
     }
     hipError_t e = hipSuccess;
-    char *bnd = (char *)ws_get(ctx, "split_bnd", bnd_elems * esz, &e);
+    char *bnd = (char *)ws_get(ctx, (pre + "split_bnd").c_str(), bnd_elems * esz, &e);
     // runs of consecutive groups on one factor (the update reads their spikes once)
     // (at most SPLIT_RUN_GROUPS groups per run, so wide launches still spread
     // the update over many workgroups; a group's arithmetic is the same in any run)
@@ -573,8 +613,10 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
         if (g > 0 && gf[g] == gf[g - 1] && runs.back().y < SPLIT_RUN_GROUPS) ++runs.back().y;
         else runs.push_back(make_int2((int)g, 1));
     }
-    SplitGroup *d_groups = (SplitGroup *)ws_get(ctx, "split_groups", sizeof(SplitGroup) * sg.size(), &e);
-    int2 *d_runs = d_groups ? (int2 *)ws_get(ctx, "split_runs", sizeof(int2) * runs.size(), &e) : nullptr;
+    SplitGroup *d_groups =
+        (SplitGroup *)ws_get(ctx, (pre + "split_groups").c_str(), sizeof(SplitGroup) * sg.size(), &e);
+    int2 *d_runs =
+        d_groups ? (int2 *)ws_get(ctx, (pre + "split_runs").c_str(), sizeof(int2) * runs.size(), &e) : nullptr;
     if (!bnd || !d_groups || !d_runs)
         return hipfail(ctx, e == hipSuccess ? hipErrorOutOfMemory : e, "split workspace");
     size_t off = 0;
@@ -612,9 +654,16 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
         off += (size_t)F->P * F->nb * TILE_ELEMS;
     }
     const int nL = (int)(loc.size() / 2);
-    lrpr_status ls = ensure_items(ctx, loc.size());
-    if (ls != LRPR_OK) return ls;
-    if ((e = hipMemcpyAsync(ctx->d_items, loc.data(), loc.size() * sizeof(SweepItem), hipMemcpyHostToDevice, st)) !=
+    SweepItem *d_items = nullptr;
+    if (plan) {
+        d_items = (SweepItem *)ws_get(ctx, (pre + "items").c_str(), sizeof(SweepItem) * loc.size(), &e);
+        if (!d_items) return hipfail(ctx, e == hipSuccess ? hipErrorOutOfMemory : e, "split items");
+    } else {
+        lrpr_status ls = ensure_items(ctx, loc.size());
+        if (ls != LRPR_OK) return ls;
+        d_items = ctx->d_items;
+    }
+    if ((e = hipMemcpyAsync(d_items, loc.data(), loc.size() * sizeof(SweepItem), hipMemcpyHostToDevice, st)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(d_groups, sg.data(), sg.size() * sizeof(SplitGroup), hipMemcpyHostToDevice, st)) !=
             hipSuccess ||
@@ -622,6 +671,7 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
             hipSuccess)
         return hipfail(ctx, e, "split upload");
     lrpr_ctx_s::ProfRec rec{};
+    record = record && !plan;
     if (record && ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
         return hipfail(ctx, e, "profile event");
     const int ng = (int)sg.size();
@@ -630,13 +680,22 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
     const int nr = uni ? (int)runs.size() : 0;
     const int2 *dr = uni ? d_runs : nullptr;
     for (int step = 0; step < nsteps; ++step) {
-        if ((e = launch_sweep(false, false, f32, nL, ctx->d_items, 1, max_nb, st, step0 + step, true)) != hipSuccess ||
-            (e = launch_split_chain(f32, false, ng, d_groups, max_nb, st, uni)) != hipSuccess ||
-            (e = launch_split_update(f32, false, ng, d_groups, max_P, max_rows, st, max_nb, nr, dr)) != hipSuccess ||
-            (e = launch_sweep(false, false, f32, nL, ctx->d_items + nL, 1, max_nb, st, step0 + step, true)) != hipSuccess ||
-            (e = launch_split_chain(f32, true, ng, d_groups, max_nb, st, uni)) != hipSuccess ||
-            (e = launch_split_update(f32, true, ng, d_groups, max_P, max_rows, st, max_nb, nr, dr)) != hipSuccess)
-            return hipfail(ctx, e, "split sweep");
+        const int sj = step0 + step;
+        auto one = [=](hipStream_t s) -> hipError_t {
+            hipError_t ee;
+            if ((ee = launch_sweep(false, false, f32, nL, d_items, 1, max_nb, s, sj, true)) != hipSuccess ||
+                (ee = launch_split_chain(f32, false, ng, d_groups, max_nb, s, uni)) != hipSuccess ||
+                (ee = launch_split_update(f32, false, ng, d_groups, max_P, max_rows, s, max_nb, nr, dr)) !=
+                    hipSuccess ||
+                (ee = launch_sweep(false, false, f32, nL, d_items + nL, 1, max_nb, s, sj, true)) != hipSuccess ||
+                (ee = launch_split_chain(f32, true, ng, d_groups, max_nb, s, uni)) != hipSuccess ||
+                (ee = launch_split_update(f32, true, ng, d_groups, max_P, max_rows, s, max_nb, nr, dr)) !=
+                    hipSuccess)
+                return ee;
+            return hipSuccess;
+        };
+        if (plan) plan->launches.push_back(one);
+        else if ((e = one(st)) != hipSuccess) return hipfail(ctx, e, "split sweep");
     }
     if (record && ctx->prof) {
         if ((e = hipEventRecord(rec.b, st)) != hipSuccess) return hipfail(ctx, e, "profile event");
@@ -649,7 +708,8 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
 // of nsteps solve steps.  A column's source factors are fscale[c * fstride +
 // step0 + j], j < nsteps.  record: add a profile record for the launch.
 static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
-                                  bool adjoint, int fstride, int step0, bool record, bool split_any_width) {
+                                  bool adjoint, int fstride, int step0, bool record, bool split_any_width,
+                                  SweepPlan *plan = nullptr, const std::string &pre = std::string()) {
     const bool f32 = prec == LRPR_F32;
     std::vector<SweepItem> items;
     int max_nb = 1;
@@ -694,7 +754,7 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
                  max_nb <= (f32 ? 64 : 32);
     for (int p = 0; p < npanels && split; ++p)
         split = panels[p].w == 0 || (panels[p].F->P >= 2 && (f32 ? panels[p].F->s32.S : panels[p].F->s64.S));
-    if (split) return run_split(ctx, npanels, panels, items, nsteps, f32, max_nb, step0, record);
+    if (split) return run_split(ctx, npanels, panels, items, nsteps, f32, max_nb, step0, record, plan, pre);
     // Pass pairs when every factor carries the UL set (and, for the
     // adjoint, its mirrored tiles) and all have the same band-tile count
     // (tile arrays addressed with 32-bit byte offsets)
@@ -720,34 +780,63 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
             r.fscale = nullptr;
         }
     }
-    lrpr_status st = ensure_items(ctx, items.size());
-    if (st != LRPR_OK) return st;
-    e = hipMemcpyAsync(ctx->d_items, items.data(), items.size() * sizeof(SweepItem),
-                       hipMemcpyHostToDevice, ctx->stream);
+    SweepItem *d_items = nullptr;
+    if (plan) {
+        d_items = (SweepItem *)ws_get(ctx, (pre + "items").c_str(), sizeof(SweepItem) * items.size(), &e);
+        if (!d_items) return hipfail(ctx, e == hipSuccess ? hipErrorOutOfMemory : e, "sweep items");
+    } else {
+        lrpr_status st = ensure_items(ctx, items.size());
+        if (st != LRPR_OK) return st;
+        d_items = ctx->d_items;
+    }
+    e = hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(SweepItem), hipMemcpyHostToDevice, ctx->stream);
     if (e != hipSuccess) return hipfail(ctx, e, "sweep item upload");
     lrpr_ctx_s::ProfRec rec{};
+    record = record && !plan;
     if (record && ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
         return hipfail(ctx, e, "profile event");
+    const int nii = (int)ni;
+    std::function<hipError_t(hipStream_t)> go;
     if (!paired) {
-        e = launch_sweep(adjoint, strided, f32, (int)ni, ctx->d_items, nsteps, max_nb, ctx->stream, step0);
-        if (e != hipSuccess) return hipfail(ctx, e, "sweep launch");
+        go = [=](hipStream_t s) {
+            return launch_sweep(adjoint, strided, f32, nii, d_items, nsteps, max_nb, s, step0);
+        };
     } else {
         // even steps (from step0) L U, odd steps U' L'; the second
         // substitution of step s runs with the first of step s+1
-        e = launch_sweep(adjoint, false, f32, (int)ni, ctx->d_items, 1, max_nb, ctx->stream, step0);
-        for (int s = 0; s + 1 < nsteps && e == hipSuccess; ++s)
-            e = launch_sweep_pair(adjoint, (s & 1) != 0, f32, (int)ni, ctx->d_items, max_nb, ctx->stream,
-                                  step0 + s + 1);
-        if (e == hipSuccess)
-            e = launch_sweep(adjoint, false, f32, (int)ni, ctx->d_items + (((nsteps - 1) & 1) ? 2 * ni : ni), 1,
-                             max_nb, ctx->stream, step0 + nsteps - 1);
-        if (e != hipSuccess) return hipfail(ctx, e, "paired sweep launch");
+        go = [=](hipStream_t s) {
+            hipError_t ee = launch_sweep(adjoint, false, f32, nii, d_items, 1, max_nb, s, step0);
+            for (int q = 0; q + 1 < nsteps && ee == hipSuccess; ++q)
+                ee = launch_sweep_pair(adjoint, (q & 1) != 0, f32, nii, d_items, max_nb, s, step0 + q + 1);
+            if (ee == hipSuccess)
+                ee = launch_sweep(adjoint, false, f32, nii, d_items + (((nsteps - 1) & 1) ? 2 * ni : ni), 1, max_nb,
+                                  s, step0 + nsteps - 1);
+            return ee;
+        };
+    }
+    if (plan) {
+        plan->launches.push_back(go);
+    } else if ((e = go(ctx->stream)) != hipSuccess) {
+        return hipfail(ctx, e, paired ? "paired sweep launch" : "sweep launch");
     }
     if (record && ctx->prof) {
         if ((e = hipEventRecord(rec.b, ctx->stream)) != hipSuccess) return hipfail(ctx, e, "profile event");
         ctx->prof_recs.push_back(rec);
     }
     return LRPR_OK;
+}
+
+lrpr_status plan_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
+                       bool adjoint, bool split_any_width, const char *ws_prefix, SweepPlan *plan) {
+    if (!ctx || !plan || !ws_prefix) return LRPR_ERR_ARG;
+    if (npanels < 0 || (npanels > 0 && !panels) || nsteps < 0 || (prec != LRPR_F64 && prec != LRPR_F32))
+        return fail(ctx, LRPR_ERR_ARG, "sweep plan: invalid arguments");
+    for (int p = 0; p < npanels; ++p)
+        if (!panels[p].F || (panels[p].w > 0 && panels[p].F->stepper != LRPR_STEP_EULER))
+            return fail(ctx, LRPR_ERR_ARG, "sweep plan: implicit-Euler factors only");
+    plan->launches.clear();
+    return run_sweep_core(ctx, npanels, panels, nsteps, prec, adjoint, nsteps, 0, false, split_any_width, plan,
+                          ws_prefix);
 }
 
 // Sweeps of nsteps time steps of the panels' common stepper.  Implicit

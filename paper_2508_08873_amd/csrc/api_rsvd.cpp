@@ -242,8 +242,8 @@ static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_d
         const int l = d.k + d.p;
         if (!d.F || !d.Omega || d.k < 0 || d.p < 0 || l < 1 || l > LMAX || l > d.F->n)
             return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: slice needs factor, Omega, 1 <= k+p <= min(96, n)");
-        if (!(d.F->mask & LRPR_STORE_F64) || (f32 && !(d.F->mask & LRPR_STORE_F32)))
-            return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: factor lacks the FP64 (and, for FP32, FP32) copy");
+        if (!(d.F->mask & (f32 ? LRPR_STORE_F32 : LRPR_STORE_F64)))
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: factor lacks the copy in the range finder's precision");
         if (d.F->dev != ctx->dev) return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: factor on another device");
         lmax = std::max(lmax, l);
         kmax = std::max(kmax, d.k);

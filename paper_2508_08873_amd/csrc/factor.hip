@@ -262,6 +262,67 @@ __global__ void k_pack_band32(LuAcc F, int NT, int nb, const double *Linv, const
     });
 }
 
+// Band tiles of one tile row per workgroup (256 threads, one per element of
+// a tile), for every requested set (blockIdx.y): the row's diagonal-tile
+// inverse and each 16x16 factor block are staged in LDS, the products
+// (the same sums in the same order as band_elem) go to the FP64 tiles and to
+// an LDS copy of the tile row's 16 x 16 nb values, from which 16 threads
+// round the FP32 rows with their sums kept (round_row_keep_sum).  Replaces
+// one thread per element or per row reading the band entries directly.
+__global__ __launch_bounds__(256) void k_pack_rows(LuAcc F, int NT, int nb, const double *Linv, const double *Uinv,
+                                                   BandOut o64, BandOut o32) {
+    extern __shared__ double rowv[];   // [16][16 nb]
+    __shared__ double Ds[TILE_ELEMS];
+    __shared__ double Ms[TILE_ELEMS];
+    const int a = blockIdx.y;
+    if (!o64.b[a] && !o32.b[a]) return;
+    const int64_t I = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t base = I * TILE;
+    const double *Di = ((a == 0 || a == 3) ? Linv : Uinv) + I * TILE_ELEMS;
+    Ds[t] = Di[t];
+    const int r = t >> 4, q = t & 15;
+    const int W = 16 * nb;
+    for (int j = 0; j < nb; ++j) {
+        const int64_t jl = (I - nb + j) * TILE, ju = (I + 1 + j) * TILE;
+        // stage M[k][qq] = the factor block's element, read along the
+        // contiguous direction of the band storage
+        {
+            int k, qq;
+            double m;
+            if (a < 2) {
+                k = t >> 4;
+                qq = t & 15;
+                m = a == 0 ? F.lower(base + k, jl + qq) : F.upper(base + k, ju + qq);
+            } else {
+                qq = t >> 4;
+                k = t & 15;
+                m = a == 2 ? F.upper(jl + qq, base + k) : F.lower(ju + qq, base + k);
+            }
+            Ms[k * TILE + qq] = m;
+        }
+        __syncthreads();
+        double v = 0.0;
+        if (a < 2) {
+            for (int k = 0; k < TILE; ++k) v += Ds[r * TILE + k] * Ms[k * TILE + q];
+        } else {
+            for (int k = 0; k < TILE; ++k) v += Ds[k * TILE + r] * Ms[k * TILE + q];
+        }
+        const int64_t tile = (I * nb + j) * TILE_ELEMS;
+        if (o64.b[a]) ((double *)o64.b[a])[tile + aslot(false, r, q)] = v;
+        rowv[r * W + j * TILE + q] = v;
+        __syncthreads();
+    }
+    if (o32.b[a] && t < TILE) {
+        const double *rv = rowv + t * W;
+        round_row_keep_sum((float *)o32.b[a], W, [&](int c, int64_t &dst) {
+            const int j = c / TILE, qq = c % TILE;
+            dst = (I * nb + j) * TILE_ELEMS + aslot(true, t, qq);
+            return rv[c];
+        });
+    }
+}
+
 // Phase 1: FP64 inverses of the diagonal tiles, natural row-major 16x16 per
 // tile row (scratch).  One thread per (tile row, column of the inverse).
 __global__ void k_diag_inv(LuAcc F, int NT, double *Linv, double *Uinv) {
@@ -344,14 +405,20 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
         b64.b[a] = t64 ? t64->a[bidx[a]] : nullptr;
         b32.b[a] = t32 ? t32->a[bidx[a]] : nullptr;
     }
-    if (t64) {
-        hipLaunchKernelGGL(k_pack_band, dim3((unsigned)blocks), dim3(256), 0, s, F, NT, nb, Linv, Uinv, b64);
+    if (nb <= 64) {
+        const size_t lds = sizeof(double) * TILE_ELEMS * (size_t)nb;
+        hipLaunchKernelGGL(k_pack_rows, dim3((unsigned)NT, 4), dim3(256), lds, s, F, NT, nb, Linv, Uinv, b64, b32);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (t32) {
-        hipLaunchKernelGGL(k_pack_band32, dim3((unsigned)((4 * th + 127) / 128)), dim3(128), 0, s, F, NT, nb, Linv,
-                           Uinv, b64, b32);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+        if (t64) {
+            hipLaunchKernelGGL(k_pack_band, dim3((unsigned)blocks), dim3(256), 0, s, F, NT, nb, Linv, Uinv, b64);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        if (t32) {
+            hipLaunchKernelGGL(k_pack_band32, dim3((unsigned)((4 * th + 127) / 128)), dim3(128), 0, s, F, NT, nb,
+                               Linv, Uinv, b64, b32);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     DiagOut o64{}, o32{};
     const int didx[4] = {TS_DL, TS_DU, TS_DLT, TS_DUT};

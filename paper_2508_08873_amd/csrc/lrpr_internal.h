@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <map>
 #include <string>
 #include <utility>
@@ -176,6 +177,25 @@ lrpr_status fail(lrpr_ctx ctx, lrpr_status st, const std::string &msg);
 // Device address of the fixed scratch array of lrpr_coarse_apply_noalloc on
 // device dev (noalloc.hip); dev must be current.  Looked up once per device.
 hipError_t noalloc_scratch_init(int dev, double **out);
+
+// A sweep as the list of its kernel launches over work-item arrays already
+// in device memory (planned and uploaded once): it can run any number of
+// times, on any stream, and be captured in a HIP graph, as long as the
+// panels' buffers and the workspaces it names stay in place.
+struct SweepPlan {
+    std::vector<std::function<hipError_t(hipStream_t)>> launches;
+    hipError_t run(hipStream_t s) const {
+        for (const auto &l : launches)
+            if (hipError_t e = l(s); e != hipSuccess) return e;
+        return hipSuccess;
+    }
+};
+// Plan an implicit-Euler sweep (the factors' stepper must be LRPR_STEP_EULER)
+// with the same path choice as run_sweep; its item arrays go to workspaces
+// named after ws_prefix (so that another sweep of the context does not
+// overwrite them).  The uploads are queued on the context's stream.
+lrpr_status plan_sweep(lrpr_ctx ctx, int npanels, const lrpr_panel *panels, int nsteps, lrpr_prec prec,
+                       bool adjoint, bool split_any_width, const char *ws_prefix, SweepPlan *plan);
 
 // Batched sweeps of nsteps steps of the panels' stepper (api_core.cpp).
 // Forward sweeps on factors that all carry spikes take the partitioned passes

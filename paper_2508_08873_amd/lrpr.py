@@ -18,7 +18,9 @@ LRPR_F64, LRPR_F32 = 0, 1
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_ZERO_PIVOT", 4: "ERR_QR_BREAKDOWN",
           5: "ERR_NOCONV", 6: "ERR_NONFINITE", 7: "ERR_HIP"}
 EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_last_error",
-           "lrpr_factor", "lrpr_factor_stepper", "lrpr_factor_sequence", "lrpr_factor_destroy", "lrpr_factor_info", "lrpr_factor_copy_lu",
+           "lrpr_ctx_release_workspaces",
+           "lrpr_factor", "lrpr_factor_stepper", "lrpr_factor_sequence", "lrpr_factor_many", "lrpr_factor_destroy",
+           "lrpr_factor_info", "lrpr_factor_copy_lu",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build", "lrpr_rsvd_build_q",
            "lrpr_rsvd_build_two_sided", "lrpr_rsvd_build_w", "lrpr_coarse_from_factors", "lrpr_mass_weights",
            "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_coarse_apply_noalloc",
@@ -86,6 +88,8 @@ def load():
     lib.lrpr_factor.argtypes = [vp, P(OpDesc), i32, P(vp)]
     lib.lrpr_factor_stepper.argtypes = [vp, P(OpDesc), i32, i32, P(vp)]
     lib.lrpr_factor_sequence.argtypes = [vp, P(OpDesc), i32, i32, P(vp)]
+    lib.lrpr_factor_many.argtypes = [vp, P(OpDesc), i32, i32, P(vp)]
+    lib.lrpr_ctx_release_workspaces.argtypes = [vp]
     lib.lrpr_factor_destroy.argtypes = [vp]
     lib.lrpr_factor_destroy.restype = None
     lib.lrpr_factor_info.argtypes = [vp, P(i64), P(i32), P(dbl)]
@@ -220,6 +224,21 @@ class Context:
         self.sync_stream()
         self._check(self.lib.lrpr_factor_sequence(self.h, arr, len(ops), int(store_mask), ctypes.byref(h)))
         return Factor(self, h)
+
+    def factor_many(self, ops, store_mask=1):
+        """Independent factors of operators on one grid (lrpr_factor_many):
+        ops is a list of dicts (dim, nx, nu, beta, c, dt); returns Factors."""
+        arr = (OpDesc * len(ops))()
+        for j, o in enumerate(ops):
+            arr[j] = _opdesc(o["dim"], o["nx"], o["nu"], o["beta"], o["c"], o["dt"], o.get("bc", BC_DIRICHLET))
+        hs = (ctypes.c_void_p * len(ops))()
+        self.sync_stream()
+        self._check(self.lib.lrpr_factor_many(self.h, arr, len(ops), int(store_mask), hs))
+        return [Factor(self, ctypes.c_void_p(hs[j])) for j in range(len(ops))]
+
+    def release_workspaces(self):
+        self.sync_stream()
+        self._check(self.lib.lrpr_ctx_release_workspaces(self.h))
 
     # -- sweeps -----------------------------------------------------------
     def _panels(self, specs):

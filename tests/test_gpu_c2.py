@@ -1,0 +1,110 @@
+"""GPU checks of the 511^2 workload with time-dependent coefficients, as the
+benchmark times it: nu_n = 1 + 0.5 sin(2 pi t_n) per slice, 128 slices x 16
+implicit-Euler steps (each slice its own operator and band LU, factored by
+lrpr_factor_many, tiles stored in FP32 only), the FP32 rSVD build of all 128
+slices together (k = 64, p = 16) on the library's Philox Omega, and Parareal
+with FP32 fine solves to 1e-6.
+
+* two sampled slices (the first and the last, with different operators)
+  against the oracle's randomized SVD (Sec. 2.1 steps 1-6) of that slice's
+  own operator on the oracle's draws of the same Omega, rounded to FP32 as
+  the range finder sees them: singular values (max |d sigma_j| / sigma_1)
+  and the coarse product on a Gaussian probe within 1e-5;
+* the Parareal iterate a fixed point of the oracle's FP64 fine propagator on
+  sampled slices, u_n = F_n u_{n-1}, within 1e-5 of the largest state norm;
+* sigma_1 <= 1 on every slice (diagonal dominance), singular values
+  descending, and the per-slice a posteriori bound (Thm. 3) zero on slice 1,
+  finite and non-negative elsewhere.
+"""
+import gc
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2508_08873_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+_OPS = {}
+
+
+def _oracle_op(ora, P, s):
+    if s not in _OPS:
+        print("oracle LU of slice", s, flush=True)
+        _OPS[s] = ora.Operator(**P.op_params(s))
+    return _OPS[s]
+
+
+@pytest.fixture(scope="module")
+def c2():
+    from paper_2508_08873_amd import lrpr
+    gc.collect()
+    torch.cuda.empty_cache()
+    ctx = lrpr.Context(0)
+    P = inputs.dar511t()
+    print("dar511t: factoring", P.N, "operators", flush=True)
+    facs = ctx.factor_many([P.op_params(s) for s in range(1, P.N + 1)], store_mask=lrpr.STORE_F32)
+    ctx.release_workspaces()
+    Om = torch.empty((P.N, P.l, P.n), device="cuda", dtype=torch.float32)
+    for s in range(P.N):
+        ctx.randn(Om[s], 0, s)
+    print("dar511t: rSVD build", flush=True)
+    coarse = ctx.rsvd_build([(facs[s], P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, 1)
+    ctx.release_workspaces()
+    del Om
+    torch.cuda.empty_cache()
+    u0, f = P.u0(), P.source()
+    fsc = torch.from_numpy(np.concatenate([P.fscale(s) for s in range(1, P.N + 1)])).to("cuda")
+    dev = lambda a: lrpr.colmajor(torch.from_numpy(a.reshape(-1, 1)).to("cuda"))
+    print("dar511t: Parareal", flush=True)
+    out = ctx.parareal_solve(coarse, facs, P.m, dev(u0), dev(f), fsc, tol=1e-6, fine_prec=1)
+    torch.cuda.synchronize()
+    yield {"P": P, "coarse": coarse, "out": out, "u0": u0, "f": f}
+    coarse.close()
+    for F in facs:
+        F.close()
+    ctx.release_workspaces()
+    ctx.close()
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("s", [0, 127])
+def test_dar511t_rsvd_sampled_slice(ora, c2, s):
+    from oracle import philox
+    from paper_2508_08873_amd.lrpr import device_view
+    P, coarse = c2["P"], c2["coarse"]
+    Om = philox.randn(P.l * P.n, 0, s).reshape(P.l, P.n).T.astype(np.float32).astype(np.float64)
+    print("dar511t rsvd: oracle slice", s + 1, flush=True)
+    Uo, So, Vo = ora.rsvd(_oracle_op(ora, P, s + 1), P.m, P.k, P.p, Om)
+    Sg = np.array(coarse.sigma[s * P.l:(s + 1) * P.l])
+    k, n, U, S, V = coarse.get(s)
+    Ug, Vg = device_view(U, n, k).cpu().numpy(), device_view(V, n, k).cpu().numpy()
+    X = np.random.default_rng(5).standard_normal((n, 4))
+    Pg, Po = Ug @ (Sg[:k, None] * (Vg.T @ X)), Uo @ (So[:k, None] * (Vo.T @ X))
+    es, ep = np.abs(Sg - So).max() / So[0], np.linalg.norm(Pg - Po) / np.linalg.norm(Po)
+    print("dar511t rsvd slice %d: sigma error %.2e, product error %.2e, sigma_1 %.6f, sigma_k+1 %.3e"
+          % (s + 1, es, ep, So[0], So[k]), flush=True)
+    assert es <= 1e-5 and ep <= 1e-5
+    assert np.abs(Ug.T @ Ug - np.eye(k)).max() <= 1e-5
+
+
+def test_dar511t_parareal_fixed_point_and_bounds(ora, c2):
+    P, coarse, out = c2["P"], c2["coarse"], c2["out"]
+    assert out["status"] == 0 and 1 <= out["iters"][0] <= P.N
+    sig = np.array(coarse.sigma).reshape(P.N, P.l)
+    assert np.all(sig[:, 0] <= 1.0 + 1e-6)
+    assert np.all(np.diff(sig, axis=1) <= 1e-6 * sig[:, :1])
+    apost = np.array(out["apost"][0])
+    assert apost[0] == 0.0 and np.all(np.isfinite(apost)) and np.all(apost >= 0)
+    U = out["U"][0].cpu().numpy()
+    assert np.array_equal(U[0], c2["u0"])
+    scale = np.linalg.norm(U, axis=1).max()
+    for n_ in (1, 128):
+        op = _oracle_op(ora, P, n_)
+        ref = op.fine(U[n_ - 1].reshape(-1, 1), P.m, c2["f"], None, P.fscale(n_).reshape(1, -1))[:, 0]
+        e = np.linalg.norm(U[n_] - ref) / scale
+        print("dar511t parareal: slice %d fixed-point residual %.2e (iterations %d, increments %s)"
+              % (n_, e, out["iters"][0], out["incr"][0][:out["iters"][0]]), flush=True)
+        assert e <= 1e-5, n_
