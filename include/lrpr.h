@@ -106,6 +106,30 @@ void lrpr_ctx_destroy(lrpr_ctx ctx);
  * need the device memory between phases of different shapes.
  * Errors: LRPR_ERR_ARG, LRPR_ERR_HIP. */
 lrpr_status lrpr_ctx_release_workspaces(lrpr_ctx ctx);
+/* Tunable launch shapes of a context (set by hand or by the autotuner).
+ * They change how work is spread over the chip and issued, not the results:
+ *   LRPR_TUNE_LU_WGS         workgroups per matrix of the batched band LU
+ *                            (0 = the library's choice; clipped to nb + 9,
+ *                            nb = ceil(b/16) band tiles);
+ *   LRPR_TUNE_LU_BUDGET      bytes of FP64 bands and LU scratch that
+ *                            lrpr_factor_many holds at once (0 = 96e9);
+ *   LRPR_TUNE_PARAREAL_GRAPH 1 (default): a Parareal iteration is captured
+ *                            once in a HIP graph and replayed; 0: its
+ *                            kernels are launched one by one.
+ * Errors: LRPR_ERR_ARG for an unknown parameter or a value out of range. */
+enum { LRPR_TUNE_LU_WGS = 1, LRPR_TUNE_LU_BUDGET = 2, LRPR_TUNE_PARAREAL_GRAPH = 3 };
+lrpr_status lrpr_tune_set(lrpr_ctx ctx, int param, int64_t value);
+lrpr_status lrpr_tune_get(lrpr_ctx ctx, int param, int64_t *value);
+/* Autotuner of the batched band LU for a later lrpr_factor_many of `count`
+ * operators on op's grid: factors copies of *op, as many as one chunk of
+ * that call holds (store_mask as given), once per candidate number of
+ * workgroups per matrix (nb + 9 and narrower ones that let more matrices
+ * share a launch), after one untimed run, timed with HIP events; keeps the
+ * fastest as the context's LRPR_TUNE_LU_WGS and returns it (best_wgs,
+ * best_ms may be NULL).  The factors do not depend on the choice.
+ * Synchronises.  Errors: as lrpr_factor_many. */
+lrpr_status lrpr_autotune_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int count, int store_mask, int *best_wgs,
+                                 double *best_ms);
 /* Replace the stream used by later calls. */
 lrpr_status lrpr_ctx_set_stream(lrpr_ctx ctx, void *hip_stream);
 /* Message of the last failing call on ctx (static storage owned by ctx). */
@@ -421,6 +445,38 @@ lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, 
                                 const double *fscale, double tol, int max_iter, double *U,
                                 int *iters_host, double *incr_host, double *apost_host);
 
+
+/* Independent Parareal problems solved together (problems of uneven grid
+ * size, slice count, rank and request count): per problem, the arguments of
+ * lrpr_parareal_solve.  Every iteration runs the fine solves of all
+ * problems, slices and requests as one batched sweep launch, then each
+ * problem's sequential coarse correction; with implicit-Euler factors the
+ * iteration is captured once in a HIP graph and replayed
+ * (LRPR_TUNE_PARAREAL_GRAPH).  A problem stops when its own requests have
+ * converged or reached its own cap; its results are the same bit for bit as
+ * when it is solved alone. */
+typedef struct {
+    lrpr_coarse C;            /* coarse propagators of the problem's N slices */
+    const lrpr_fac *F;        /* host array of N factors (slice n uses F[n-1]) */
+    int nreq;                 /* requests sharing the operators */
+    const double *u0;         /* device, n x nreq */
+    const double *f;          /* device, n x nreq sources, or NULL */
+    const double *fscale;     /* device, N*nsteps time factors, or NULL */
+    double tol;
+    int max_iter;
+    double *U;                /* device output, nreq blocks of n x (N+1) */
+    int *iters_host;          /* host int[nreq] */
+    double *incr_host;        /* host double[nreq*max_iter] or NULL */
+    double *apost_host;       /* host double[nreq*N] or NULL */
+} lrpr_parareal_problem;
+
+/* Solve nprob problems together (all with nsteps fine steps per slice of
+ * one stepper and fine precision).  Outputs per problem as in
+ * lrpr_parareal_solve.  Returns LRPR_ERR_NOCONV (all outputs written) if a
+ * problem did not reach its tolerance; LRPR_ERR_NONFINITE on a non-finite
+ * increment.  Synchronises. */
+lrpr_status lrpr_parareal_solve_many(lrpr_ctx ctx, int nprob, const lrpr_parareal_problem *probs, int nsteps,
+                                     lrpr_prec fine_prec);
 
 /* ---- serving: continuous batching of Parareal solves (Sec. 2) ----------- */
 

@@ -321,7 +321,7 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
     if (!d_args) return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: LU argument buffer");
     std::vector<int *> d_info(mm), d_err(mm);
     if ((e = launch_tile_lu_batch(mm, rows.data(), bw, NT, nb, bands.data(), scr.data(), d_info.data(),
-                                  d_err.data(), d_args, st)) != hipSuccess)
+                                  d_err.data(), d_args, st, ctx->tune_lu_wgs)) != hipSuccess)
         return cleanup(LRPR_ERR_HIP, std::string("band LU: ") + hipGetErrorString(e));
     std::vector<int> flags(2 * (size_t)mm, 0);
     for (int j = 0; j < mm; ++j)
@@ -403,22 +403,33 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
     return factor_batch(ctx, op, 1, store_mask, out);
 }
 
+}  // extern "C"
+
+// Matrices lrpr_factor_many factors together: as many as the workspace
+// budget holds (FP64 band and LU scratch per matrix; 96 GB by default), at
+// most 64, in equal chunks; each chunk's band LUs run in as few launches as
+// its size allows.
+static int many_chunk(lrpr_ctx ctx, const lrpr_op_desc &op, int count, int store_mask) {
+    const int64_t n = op.dim == 1 ? op.nx : (int64_t)op.nx * op.nx;
+    const int bw = op.dim == 1 ? 1 : op.nx;
+    const int NT = (int)((n + TILE - 1) / TILE), nb = (bw + TILE - 1) / TILE;
+    const double per_matrix = 8.0 * (double)n * (2 * bw + 1) + (double)tile_lu_scratch_bytes(NT, nb);
+    const double budget = ctx->tune_lu_budget ? (double)ctx->tune_lu_budget : 96e9;
+    int chunk = (int)std::max(1.0, std::min(64.0, budget / std::max(per_matrix, 1.0)));
+    if (store_mask & LRPR_STORE_UL) chunk = std::max(1, chunk / 2);
+    const int nchunk = (count + chunk - 1) / chunk;
+    return (count + nchunk - 1) / nchunk;
+}
+
+extern "C" {
+
 lrpr_status lrpr_factor_many(lrpr_ctx ctx, const lrpr_op_desc *ops, int count, int store_mask, lrpr_fac *outs) {
     if (!ctx || !ops || !outs || count < 1) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_many: invalid arguments");
     for (int j = 1; j < count; ++j)
         if (ops[j].dim != ops[0].dim || ops[j].nx != ops[0].nx)
             return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_many: the operators must share dim and nx");
     for (int j = 0; j < count; ++j) outs[j] = nullptr;
-    // chunks of the matrices one LU launch holds (its workgroups resident
-    // together), or of at least 2 GB of FP64 bands per chunk for small grids
-    const int64_t n = ops[0].dim == 1 ? ops[0].nx : (int64_t)ops[0].nx * ops[0].nx;
-    const int bw = ops[0].dim == 1 ? 1 : ops[0].nx;
-    const int NT = (int)((n + TILE - 1) / TILE), nb = (bw + TILE - 1) / TILE;
-    const int P = std::min(nb + 9, NT);
-    const int per_launch = P > 256 ? 1 : 256 / P;
-    const double band_bytes = 8.0 * (double)n * (2 * bw + 1);
-    int chunk = std::max(per_launch, (int)std::min<double>(64.0, 2e9 / std::max(band_bytes, 1.0)));
-    if (store_mask & LRPR_STORE_UL) chunk = std::max(1, chunk / 2);
+    const int chunk = many_chunk(ctx, ops[0], count, store_mask);
     for (int j0 = 0; j0 < count; j0 += chunk) {
         const int c = std::min(chunk, count - j0);
         lrpr_status r = factor_batch(ctx, ops + j0, c, store_mask, outs + j0);
@@ -430,6 +441,86 @@ lrpr_status lrpr_factor_many(lrpr_ctx ctx, const lrpr_op_desc *ops, int count, i
             return r;
         }
     }
+    return LRPR_OK;
+}
+
+lrpr_status lrpr_tune_set(lrpr_ctx ctx, int param, int64_t value) {
+    if (!ctx) return LRPR_ERR_ARG;
+    switch (param) {
+        case LRPR_TUNE_LU_WGS:
+            if (value < 0 || value > 256) return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_set: LU workgroups in [0, 256]");
+            ctx->tune_lu_wgs = (int)value;
+            return LRPR_OK;
+        case LRPR_TUNE_LU_BUDGET:
+            if (value < 0) return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_set: negative budget");
+            ctx->tune_lu_budget = (size_t)value;
+            return LRPR_OK;
+        case LRPR_TUNE_PARAREAL_GRAPH:
+            if (value != 0 && value != 1) return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_set: graph switch is 0 or 1");
+            ctx->tune_pr_graph = (int)value;
+            return LRPR_OK;
+        default:
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_set: unknown parameter");
+    }
+}
+
+lrpr_status lrpr_tune_get(lrpr_ctx ctx, int param, int64_t *value) {
+    if (!ctx || !value) return LRPR_ERR_ARG;
+    switch (param) {
+        case LRPR_TUNE_LU_WGS: *value = ctx->tune_lu_wgs; return LRPR_OK;
+        case LRPR_TUNE_LU_BUDGET: *value = (int64_t)ctx->tune_lu_budget; return LRPR_OK;
+        case LRPR_TUNE_PARAREAL_GRAPH: *value = ctx->tune_pr_graph; return LRPR_OK;
+        default: return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_get: unknown parameter");
+    }
+}
+
+lrpr_status lrpr_autotune_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int count, int store_mask, int *best_wgs,
+                                 double *best_ms) {
+    if (!ctx || !op || count < 1) return fail(ctx, LRPR_ERR_ARG, "lrpr_autotune_factor: invalid arguments");
+    const int64_t n = op->dim == 1 ? op->nx : (int64_t)op->nx * op->nx;
+    const int bw = op->dim == 1 ? 1 : op->nx;
+    const int NT = (int)((n + TILE - 1) / TILE), nb = (bw + TILE - 1) / TILE;
+    const int full = std::min(nb + 9, NT);
+    // candidates: the full width and narrower ones that fit more matrices
+    // into a launch; each times one factor_many of `count` copies of op
+    std::vector<int> cand;
+    for (int c : {full, 24, 16, 12, 8, 6, 4})
+        if (c <= full && c >= 1 && std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    // one chunk of a factor_many of `count` operators
+    const int cnt = many_chunk(ctx, *op, count, store_mask);
+    std::vector<lrpr_op_desc> ops(cnt, *op);
+    std::vector<lrpr_fac> outs(cnt, nullptr);
+    const int saved = ctx->tune_lu_wgs;
+    int best = 0;
+    double best_t = 1e300;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipSetDevice(ctx->dev), "hipSetDevice");
+    HIPCHK(hipEventCreate(&e0), "event");
+    HIPCHK(hipEventCreate(&e1), "event");
+    lrpr_status r = LRPR_OK;
+    // one untimed run first (first-use allocations), then one timed run per candidate
+    for (int i = -1; i < (int)cand.size() && r == LRPR_OK; ++i) {
+        const int c = cand[i < 0 ? 0 : i];
+        ctx->tune_lu_wgs = c;
+        hipEventRecord(e0, ctx->stream);
+        r = lrpr_factor_many(ctx, ops.data(), cnt, store_mask, outs.data());
+        hipEventRecord(e1, ctx->stream);
+        hipEventSynchronize(e1);
+        for (lrpr_fac f : outs)
+            if (f) lrpr_factor_destroy(f);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (i >= 0 && r == LRPR_OK && ms < best_t) {
+            best_t = ms;
+            best = c;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ctx->tune_lu_wgs = r == LRPR_OK ? best : saved;
+    if (r != LRPR_OK) return r;
+    if (best_wgs) *best_wgs = best;
+    if (best_ms) *best_ms = best_t;
     return LRPR_OK;
 }
 

@@ -565,195 +565,367 @@ lrpr_status lrpr_coarse_apply(lrpr_ctx ctx, lrpr_coarse c, int s, int w, const d
 // ---------------------------------------------------------------------------
 // Parareal
 // ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+// Device and host state of one problem of a Parareal solve.
+struct PrState {
+    lrpr_parareal_problem d;
+    int N = 0, kcap = 0, nreq = 1;
+    int64_t n = 0;
+    size_t blk = 0;                // one slice's n x nreq block
+    double *Ucur = nullptr, *Gold = nullptr, *Bv = nullptr;
+    void *X = nullptr, *fsrc = nullptr;
+    int *fcol = nullptr, *active = nullptr;
+    double *fsc = nullptr, *part = nullptr, *incpart = nullptr, *inc2 = nullptr;
+    int64_t nch = 0;
+    std::vector<int> hact, iters, conv;
+    std::vector<double> incr, last_inc, hinc;
+    int nactive = 0;
+};
+
+}  // namespace
+
+// Parareal (eq. def_Parareal) for several independent problems at once: the
+// fine solves of an iteration (all problems, all slices, all requests) run
+// as one batched sweep launch, then each problem's sequential coarse
+// correction over its slices; problems may differ in grid, slice count,
+// rank and requests.  The iteration (conversion of the iterates, the sweep
+// and every problem's correction) is captured once in a HIP graph and
+// replayed, when all factors use implicit Euler.
+static lrpr_status parareal_impl(lrpr_ctx ctx, int nprob, const lrpr_parareal_problem *probs, int nsteps,
+                                 lrpr_prec fine_prec) {
+    if (!ctx) return LRPR_ERR_ARG;
+    if (nprob < 1 || !probs || nsteps < 1 || (fine_prec != LRPR_F64 && fine_prec != LRPR_F32))
+        return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: invalid arguments");
+    const bool f32 = fine_prec == LRPR_F32;
+    const size_t esz = f32 ? 4 : 8;
+    std::vector<PrState> ps(nprob);
+    int stepper = -1;
+    for (int p = 0; p < nprob; ++p) {
+        const lrpr_parareal_problem &d = probs[p];
+        if (!d.C || !d.F || d.nreq < 1 || !d.u0 || !d.U || !d.iters_host || d.max_iter < 1 || !(d.tol >= 0))
+            return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: invalid problem");
+        const int N = d.C->nslices;
+        const int64_t n = d.C->n[0];
+        int kmax = 0;
+        for (int s = 0; s < N; ++s) {
+            if (!d.F[s] || d.F[s]->n != n || d.C->n[s] != n)
+                return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: a problem's slices must share one size n");
+            if (stepper >= 0 && d.F[s]->stepper != stepper)
+                return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: slices must share one time stepper");
+            stepper = d.F[s]->stepper;
+            if ((f32 && !(d.F[s]->mask & LRPR_STORE_F32)) || (!f32 && !(d.F[s]->mask & LRPR_STORE_F64)))
+                return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: factor lacks the requested precision");
+            if (d.F[s]->dev != ctx->dev) return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: factor on another device");
+            kmax = std::max(kmax, d.C->k[s]);
+        }
+        if ((size_t)kmax * d.nreq > 12288) return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: k * nreq above 12288");
+        PrState &q = ps[p];
+        q.d = d;
+        q.N = N;
+        q.n = n;
+        q.nreq = d.nreq;
+        // iterations are capped at N (Parareal is exact there); max_iter
+        // stays the row stride of incr_host
+        q.kcap = std::min(d.max_iter, N);
+        q.blk = (size_t)n * d.nreq;
+        q.nch = lr_chunks(n);
+        (void)kmax;
+    }
+    CK(hipSetDevice(ctx->dev), "hipSetDevice");
+    hipStream_t st = ctx->stream;
+    const int fs = fac_stages(probs[0].F[0]) * nsteps;   // source time factors per slice and column
+    hipError_t e = hipSuccess;
+    for (int p = 0; p < nprob; ++p) {
+        PrState &q = ps[p];
+        char key[48];
+        auto W = [&](const char *name, size_t bytes) {
+            snprintf(key, sizeof key, "pr%d_%s", p, name);
+            return ws_get(ctx, key, bytes, &e);
+        };
+        int kmax = 0;
+        for (int s = 0; s < q.N; ++s) kmax = std::max(kmax, q.d.C->k[s]);
+        q.Ucur = (double *)W("u", sizeof(double) * q.blk * (q.N + 1));
+        q.Gold = (double *)W("gold", sizeof(double) * q.blk * q.N);
+        q.Bv = (double *)W("b", sizeof(double) * q.blk * q.N);
+        q.X = W("x", esz * q.blk * q.N);
+        q.fsrc = q.d.f ? W("f", esz * q.blk) : nullptr;
+        q.fcol = (int *)W("fcol", sizeof(int) * (size_t)q.N * q.nreq);
+        q.fsc = (double *)W("fsc", sizeof(double) * (size_t)q.N * q.nreq * fs);
+        q.part = (double *)W("part", sizeof(double) * (size_t)lr_part_elems(q.n, kmax, q.nreq));
+        q.incpart = (double *)W("incpart", sizeof(double) * (size_t)q.nch * q.nreq);
+        q.inc2 = (double *)W("inc2", sizeof(double) * (size_t)q.N * q.nreq);
+        q.active = (int *)W("active", sizeof(int) * q.nreq);
+        if (e != hipSuccess || !q.Ucur || !q.Gold || !q.Bv || !q.X || !q.fcol || !q.fsc || !q.part || !q.incpart ||
+            !q.inc2 || !q.active || (q.d.f && !q.fsrc))
+            return herr(ctx, e == hipSuccess ? hipErrorOutOfMemory : e, "parareal workspace");
+    }
+    // per-column source index and time factors: column (slice s, request r)
+    std::vector<lrpr_panel> P;
+    for (int p = 0; p < nprob; ++p) {
+        PrState &q = ps[p];
+        const int N = q.N, nreq = q.nreq;
+        std::vector<int> hfcol((size_t)N * nreq);
+        std::vector<double> hfsc((size_t)N * nreq * fs, 1.0);
+        std::vector<double> hphi;
+        if (q.d.fscale) {
+            hphi.resize((size_t)N * fs);
+            CK(hipMemcpyAsync(hphi.data(), q.d.fscale, sizeof(double) * hphi.size(), hipMemcpyDeviceToHost, st),
+               "fscale");
+            CK(hipStreamSynchronize(st), "sync");
+        }
+        for (int s = 0; s < N; ++s)
+            for (int r = 0; r < nreq; ++r) {
+                hfcol[(size_t)s * nreq + r] = r;
+                if (q.d.fscale)
+                    for (int j = 0; j < fs; ++j) hfsc[((size_t)s * nreq + r) * fs + j] = hphi[(size_t)s * fs + j];
+            }
+        CK(upload(q.fcol, hfcol, st), "fcol");
+        CK(upload(q.fsc, hfsc, st), "fscale");
+        if (q.d.f) CK(launch_convert(0, f32 ? 1 : 0, q.d.f, q.fsrc, (int64_t)q.blk, st), "source copy");
+        q.hact.assign(nreq, 1);
+        CK(upload(q.active, q.hact, st), "active");
+        q.nactive = nreq;
+        q.iters.assign(nreq, 0);
+        q.conv.assign(nreq, 0);
+        q.incr.assign((size_t)nreq * q.d.max_iter, 0.0);
+        q.last_inc.assign((size_t)N * nreq, 0.0);
+        q.hinc.assign((size_t)N * nreq, 0.0);
+        // panels: consecutive slices with the same factor share one panel
+        const size_t first = P.size();
+        for (int s = 0; s < N; ++s) {
+            if (P.size() > first && P.back().F == q.d.F[s]) {
+                P.back().w += nreq;
+                continue;
+            }
+            lrpr_panel pn{};
+            pn.F = q.d.F[s];
+            pn.X = (char *)q.X + (size_t)s * q.blk * esz;
+            pn.ldx = q.n;
+            pn.w = nreq;
+            pn.f = q.fsrc;
+            pn.ldf = q.n;
+            pn.fcol = q.fsrc ? q.fcol + (size_t)s * nreq : nullptr;
+            pn.fscale = q.fsrc ? q.fsc + (size_t)s * nreq * fs : nullptr;
+            P.push_back(pn);
+        }
+    }
+    // b_n = F_n 0 (all problems in one sweep)
+    for (PrState &q : ps) {
+        if (f32) CK(launch_fillf((float *)q.X, (int64_t)q.blk * q.N, 0.0f, st), "zero");
+        else CK(launch_fill((double *)q.X, (int64_t)q.blk * q.N, 0.0, st), "zero");
+    }
+    lrpr_status r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, fine_prec, false, true);
+    if (r != LRPR_OK) return r;
+    // u^0: u^0_0 = u0, u^0_n = G_n' u^0_{n-1} + b_n
+    for (PrState &q : ps) {
+        CK(launch_convert(f32 ? 1 : 0, 0, q.X, q.Bv, (int64_t)q.blk * q.N, st), "b_n");
+        CK(hipMemcpyAsync(q.Ucur, q.d.u0, sizeof(double) * q.blk, hipMemcpyDeviceToDevice, st), "u0");
+        for (int s = 0; s < q.N; ++s) {
+            LrArgs a{};
+            a.U = q.d.C->U[s]; a.S = q.d.C->S[s]; a.V = q.d.C->V[s];
+            a.x = q.Ucur + (size_t)s * q.blk;
+            a.out = q.Ucur + (size_t)(s + 1) * q.blk;
+            a.gold = q.Gold + (size_t)s * q.blk;
+            a.bvec = q.Bv + (size_t)s * q.blk;
+            a.active = q.active;
+            a.n = q.n; a.k = q.d.C->k[s]; a.w = q.nreq; a.mode = 1;
+            CK(lowrank_cols(a, q.part, nullptr, st), "coarse init");
+        }
+    }
+    // one iteration's device work on stream cs: the fine solves of all
+    // problems from u^k_{n-1}, then every problem's correction sweep (slice
+    // by slice, the problems interleaved)
+    int Nmax = 0;
+    for (const PrState &q : ps) Nmax = std::max(Nmax, q.N);
+    SweepPlan plan;
+    const bool graph = stepper == LRPR_STEP_EULER && ctx->tune_pr_graph != 0;
+    if (graph && (r = plan_sweep(ctx, (int)P.size(), P.data(), nsteps, fine_prec, false, true, "pr_it_", &plan)) !=
+                     LRPR_OK)
+        return r;
+    auto iteration = [&](hipStream_t cs) -> lrpr_status {
+        for (PrState &q : ps)
+            CK(launch_convert(0, f32 ? 1 : 0, q.Ucur, q.X, (int64_t)q.blk * q.N, cs), "u -> X");
+        if (graph) {
+            CK(plan.run(cs), "fine sweep");
+        } else {
+            lrpr_status rr = run_sweep(ctx, (int)P.size(), P.data(), nsteps, fine_prec, false, true);
+            if (rr != LRPR_OK) return rr;
+        }
+        for (int s = 0; s < Nmax; ++s)
+            for (PrState &q : ps) {
+                if (s >= q.N) continue;
+                LrArgs a{};
+                a.U = q.d.C->U[s]; a.S = q.d.C->S[s]; a.V = q.d.C->V[s];
+                a.x = q.Ucur + (size_t)s * q.blk;
+                a.out = q.Ucur + (size_t)(s + 1) * q.blk;
+                a.gold = q.Gold + (size_t)s * q.blk;
+                if (f32) a.fu32 = (const float *)q.X + (size_t)s * q.blk;
+                else a.fu64 = (const double *)q.X + (size_t)s * q.blk;
+                a.active = q.active;
+                a.n = q.n; a.k = q.d.C->k[s]; a.w = q.nreq; a.mode = 2;
+                CK(lowrank_cols(a, q.part, q.incpart, cs), "correction");
+                CK(launch_inc_reduce(q.incpart, q.nch, q.nreq, q.inc2 + (size_t)s * q.nreq, cs), "increment");
+            }
+        return LRPR_OK;
+    };
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t g = nullptr;
+    hipStream_t cs = nullptr;
+    auto release = [&]() {
+        if (gexec) hipGraphExecDestroy(gexec);
+        if (g) hipGraphDestroy(g);
+        if (cs) hipStreamDestroy(cs);
+        gexec = nullptr;
+        g = nullptr;
+        cs = nullptr;
+    };
+    if (graph) {
+        // captured on a stream of its own (no work runs while capturing);
+        // replayed on the context's stream
+        if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed)) != hipSuccess) {
+            release();
+            return herr(ctx, e, "graph capture");
+        }
+        lrpr_status rr = iteration(cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (rr != LRPR_OK) {
+            release();
+            return rr;
+        }
+        if (e2 != hipSuccess || (e2 = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            release();
+            return herr(ctx, e2, "graph instantiate");
+        }
+    }
+    int kmax_all = 0;
+    for (const PrState &q : ps) kmax_all = std::max(kmax_all, q.kcap);
+    lrpr_status result = LRPR_OK;
+    for (int k = 0; k < kmax_all; ++k) {
+        bool any = false;
+        for (const PrState &q : ps) any = any || q.nactive > 0;
+        if (!any) break;
+        if (graph) {
+            if ((e = hipGraphLaunch(gexec, st)) != hipSuccess) {
+                release();
+                return herr(ctx, e, "graph launch");
+            }
+        } else if ((r = iteration(st)) != LRPR_OK) {
+            return r;
+        }
+        for (PrState &q : ps)
+            if ((e = hipMemcpyAsync(q.hinc.data(), q.inc2, sizeof(double) * q.hinc.size(), hipMemcpyDeviceToHost,
+                                    st)) != hipSuccess)
+                break;
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            release();
+            return herr(ctx, e, "increments");
+        }
+        for (PrState &q : ps) {
+            bool changed = false;
+            for (int rq = 0; rq < q.nreq; ++rq) {
+                if (!q.hact[rq]) continue;
+                double mx = 0.0;
+                bool finite = true;
+                for (int s = 0; s < q.N; ++s) {
+                    const double v = q.hinc[(size_t)s * q.nreq + rq];
+                    q.last_inc[(size_t)s * q.nreq + rq] = std::sqrt(v);
+                    finite = finite && std::isfinite(v);   // std::max would drop a NaN
+                    mx = std::max(mx, v);
+                }
+                const double inc = std::sqrt(mx);
+                if (!finite || !std::isfinite(inc)) {
+                    release();
+                    return fail(ctx, LRPR_ERR_NONFINITE, "non-finite Parareal increment");
+                }
+                q.incr[(size_t)rq * q.d.max_iter + k] = inc;
+                q.iters[rq] = k + 1;
+                if (inc < q.d.tol || k + 1 >= q.N) {
+                    q.conv[rq] = 1;
+                    q.hact[rq] = 0;
+                    --q.nactive;
+                    changed = true;
+                } else if (k + 1 >= q.kcap) {
+                    q.hact[rq] = 0;   // max_iter reached: stops without converging
+                    --q.nactive;
+                    changed = true;
+                }
+            }
+            if (changed && q.nactive > 0 && (e = upload(q.active, q.hact, st)) != hipSuccess) {
+                release();
+                return herr(ctx, e, "active");
+            }
+        }
+    }
+    release();
+    for (PrState &q : ps) {
+        const int N = q.N;
+        const int64_t n = q.n;
+        // output layout: request r -> n x (N+1) block
+        for (int rq = 0; rq < q.nreq; ++rq)
+            CK(hipMemcpy2DAsync(q.d.U + (size_t)rq * n * (N + 1), sizeof(double) * n, q.Ucur + (size_t)rq * n,
+                                sizeof(double) * q.blk, sizeof(double) * n, N + 1, hipMemcpyDeviceToDevice, st),
+               "output");
+        // a posteriori bound (eq. apost_bound) with delta = max sigma_1, eps = max sigma_{k+1}
+        double delta = 0.0, eps = 0.0;
+        bool have_eps = true;
+        size_t pos = 0;
+        for (int s = 0; s < N; ++s) {
+            delta = std::max(delta, q.d.C->sigma[pos]);
+            if (q.d.C->l[s] > q.d.C->k[s]) eps = std::max(eps, q.d.C->sigma[pos + q.d.C->k[s]]);
+            else have_eps = false;
+            pos += q.d.C->l[s];
+        }
+        for (int rq = 0; rq < q.nreq; ++rq) {
+            q.d.iters_host[rq] = q.iters[rq];
+            if (q.d.incr_host)
+                for (int k = 0; k < q.d.max_iter; ++k)
+                    q.d.incr_host[(size_t)rq * q.d.max_iter + k] = q.incr[(size_t)rq * q.d.max_iter + k];
+            if (q.d.apost_host) {
+                for (int nn = 1; nn <= N; ++nn) {
+                    double sum = 0.0;
+                    for (int m = 1; m < nn; ++m)
+                        sum += std::pow(delta, nn - m - 1) * q.last_inc[(size_t)(m - 1) * q.nreq + rq];
+                    q.d.apost_host[(size_t)rq * N + nn - 1] = have_eps ? eps * sum : NAN;
+                }
+            }
+            if (!q.conv[rq]) result = LRPR_ERR_NOCONV;
+        }
+    }
+    CK(hipStreamSynchronize(st), "sync");
+    if (result != LRPR_OK) return fail(ctx, result, "Parareal did not reach tol within max_iter");
+    return LRPR_OK;
+}
+
+extern "C" {
+
 lrpr_status lrpr_parareal_solve(lrpr_ctx ctx, lrpr_coarse c, const lrpr_fac *F, int nsteps, lrpr_prec fine_prec,
                                 int nreq, const double *u0, const double *f, const double *fscale, double tol,
                                 int max_iter, double *U, int *iters_host, double *incr_host, double *apost_host) {
     if (!ctx) return LRPR_ERR_ARG;
-    if (!c || !F || nsteps < 1 || nreq < 1 || !u0 || !U || !iters_host || max_iter < 1 ||
-        (fine_prec != LRPR_F64 && fine_prec != LRPR_F32) || !(tol >= 0))
-        return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: invalid arguments");
-    const int N = c->nslices;
-    const int64_t n = c->n[0];
-    const bool f32 = fine_prec == LRPR_F32;
-    int kmax = 0;
-    for (int s = 0; s < N; ++s) {
-        if (!F[s] || F[s]->n != n || c->n[s] != n)
-            return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: slices must share one size n");
-        if (F[s]->stepper != F[0]->stepper)
-            return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: slices must share one time stepper");
-        if ((f32 && !(F[s]->mask & LRPR_STORE_F32)) || (!f32 && !(F[s]->mask & LRPR_STORE_F64)))
-            return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: factor lacks the requested precision");
-        kmax = std::max(kmax, c->k[s]);
-    }
-    // iterations are capped at N (Parareal is exact there); max_iter stays the
-    // row stride of incr_host
-    const int kcap = std::min(max_iter, N);
-    CK(hipSetDevice(ctx->dev), "hipSetDevice");
-    hipStream_t st = ctx->stream;
-    const size_t blk = (size_t)n * nreq;           // one slice's n x nreq block
-    const size_t esz = f32 ? 4 : 8;
-    hipError_t e = hipSuccess;
-    auto W = [&](const char *key, size_t bytes) { return ws_get(ctx, key, bytes, &e); };
-    double *Ucur = (double *)W("pr_u", sizeof(double) * blk * (N + 1));
-    double *Gold = (double *)W("pr_gold", sizeof(double) * blk * N);
-    double *Bv = (double *)W("pr_b", sizeof(double) * blk * N);
-    void *X = W("pr_x", esz * blk * N);
-    void *fsrc = f ? W("pr_f", esz * blk) : nullptr;
-    int *fcol = (int *)W("pr_fcol", sizeof(int) * (size_t)N * nreq);
-    const int fs = fac_stages(F[0]) * nsteps;      // source time factors per slice and column
-    double *fsc = (double *)W("pr_fsc", sizeof(double) * (size_t)N * nreq * fs);
-    const int64_t nch = lr_chunks(n);
-    double *part = (double *)W("pr_part", sizeof(double) * (size_t)lr_part_elems(n, kmax, nreq));
-    double *incpart = (double *)W("pr_incpart", sizeof(double) * (size_t)nch * nreq);
-    double *inc2 = (double *)W("pr_inc2", sizeof(double) * (size_t)N * nreq);
-    int *active = (int *)W("pr_active", sizeof(int) * nreq);
-    if (e != hipSuccess || !Ucur || !Gold || !Bv || !X || !fcol || !fsc || !part || !incpart || !inc2 || !active)
-        return herr(ctx, e == hipSuccess ? hipErrorOutOfMemory : e, "parareal workspace");
-    if ((size_t)kmax * nreq > 12288) return fail(ctx, LRPR_ERR_ARG, "lrpr_parareal_solve: k * nreq above 12288");
+    lrpr_parareal_problem p{};
+    p.C = c;
+    p.F = F;
+    p.nreq = nreq;
+    p.u0 = u0;
+    p.f = f;
+    p.fscale = fscale;
+    p.tol = tol;
+    p.max_iter = max_iter;
+    p.U = U;
+    p.iters_host = iters_host;
+    p.incr_host = incr_host;
+    p.apost_host = apost_host;
+    return parareal_impl(ctx, 1, &p, nsteps, fine_prec);
+}
 
-    // per-column source index and time factors: column (slice s, request r)
-    std::vector<int> hfcol((size_t)N * nreq);
-    std::vector<double> hfsc((size_t)N * nreq * fs, 1.0);
-    std::vector<double> hphi;
-    if (fscale) {
-        hphi.resize((size_t)N * fs);
-        CK(hipMemcpyAsync(hphi.data(), fscale, sizeof(double) * hphi.size(), hipMemcpyDeviceToHost, st), "fscale");
-        CK(hipStreamSynchronize(st), "sync");
-    }
-    for (int s = 0; s < N; ++s)
-        for (int q = 0; q < nreq; ++q) {
-            hfcol[(size_t)s * nreq + q] = q;
-            if (fscale)
-                for (int j = 0; j < fs; ++j) hfsc[((size_t)s * nreq + q) * fs + j] = hphi[(size_t)s * fs + j];
-        }
-    CK(upload(fcol, hfcol, st), "fcol");
-    CK(upload(fsc, hfsc, st), "fscale");
-    if (f) CK(launch_convert(0, f32 ? 1 : 0, f, fsrc, (int64_t)blk, st), "source copy");
-    std::vector<int> hact(nreq, 1);
-    CK(upload(active, hact, st), "active");
-    // panels: consecutive slices with the same factor share one panel
-    std::vector<lrpr_panel> P;
-    for (int s = 0; s < N; ++s) {
-        if (!P.empty() && P.back().F == F[s]) {
-            P.back().w += nreq;
-            continue;
-        }
-        lrpr_panel p{};
-        p.F = F[s];
-        p.X = (char *)X + (size_t)s * blk * esz;
-        p.ldx = n;
-        p.w = nreq;
-        p.f = fsrc;
-        p.ldf = n;
-        p.fcol = fsrc ? fcol + (size_t)s * nreq : nullptr;
-        p.fscale = fsrc ? fsc + (size_t)s * nreq * fs : nullptr;
-        P.push_back(p);
-    }
-    // b_n = F_n 0
-    if (f32) CK(launch_fillf((float *)X, (int64_t)blk * N, 0.0f, st), "zero");
-    else CK(launch_fill((double *)X, (int64_t)blk * N, 0.0, st), "zero");
-    lrpr_status r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, fine_prec, false, true);
-    if (r != LRPR_OK) return r;
-    CK(launch_convert(f32 ? 1 : 0, 0, X, Bv, (int64_t)blk * N, st), "b_n");
-    // u^0: u^0_0 = u0, u^0_n = G_n' u^0_{n-1} + b_n
-    CK(hipMemcpyAsync(Ucur, u0, sizeof(double) * blk, hipMemcpyDeviceToDevice, st), "u0");
-    for (int s = 0; s < N; ++s) {
-        LrArgs a{};
-        a.U = c->U[s]; a.S = c->S[s]; a.V = c->V[s];
-        a.x = Ucur + (size_t)s * blk;
-        a.out = Ucur + (size_t)(s + 1) * blk;
-        a.gold = Gold + (size_t)s * blk;
-        a.bvec = Bv + (size_t)s * blk;
-        a.active = active;
-        a.n = n; a.k = c->k[s]; a.w = nreq; a.mode = 1;
-        CK(lowrank_cols(a, part, nullptr, st), "coarse init");
-    }
-    std::vector<int> iters(nreq, 0);
-    std::vector<double> incr((size_t)nreq * max_iter, 0.0);
-    std::vector<double> last_inc((size_t)N * nreq, 0.0), hinc((size_t)N * nreq);
-    std::vector<int> conv(nreq, 0);
-    int nactive = nreq;
-    for (int k = 0; k < kcap && nactive > 0; ++k) {
-        // fine solves of all slices from u^k_{n-1}, one batched launch
-        CK(launch_convert(0, f32 ? 1 : 0, Ucur, X, (int64_t)blk * N, st), "u -> X");
-        r = run_sweep(ctx, (int)P.size(), P.data(), nsteps, fine_prec, false, true);
-        if (r != LRPR_OK) return r;
-        // sequential correction sweep
-        for (int s = 0; s < N; ++s) {
-            LrArgs a{};
-            a.U = c->U[s]; a.S = c->S[s]; a.V = c->V[s];
-            a.x = Ucur + (size_t)s * blk;
-            a.out = Ucur + (size_t)(s + 1) * blk;
-            a.gold = Gold + (size_t)s * blk;
-            if (f32) a.fu32 = (const float *)X + (size_t)s * blk;
-            else a.fu64 = (const double *)X + (size_t)s * blk;
-            a.active = active;
-            a.n = n; a.k = c->k[s]; a.w = nreq; a.mode = 2;
-            CK(lowrank_cols(a, part, incpart, st), "correction");
-            CK(launch_inc_reduce(incpart, nch, nreq, inc2 + (size_t)s * nreq, st), "increment");
-        }
-        CK(hipMemcpyAsync(hinc.data(), inc2, sizeof(double) * hinc.size(), hipMemcpyDeviceToHost, st), "inc");
-        CK(hipStreamSynchronize(st), "sync");
-        bool changed = false;
-        for (int q = 0; q < nreq; ++q) {
-            if (!hact[q]) continue;
-            double mx = 0.0;
-            bool finite = true;
-            for (int s = 0; s < N; ++s) {
-                const double v = hinc[(size_t)s * nreq + q];
-                last_inc[(size_t)s * nreq + q] = std::sqrt(v);
-                finite = finite && std::isfinite(v);   // std::max would drop a NaN
-                mx = std::max(mx, v);
-            }
-            const double inc = std::sqrt(mx);
-            if (!finite || !std::isfinite(inc))
-                return fail(ctx, LRPR_ERR_NONFINITE, "non-finite Parareal increment");
-            incr[(size_t)q * max_iter + k] = inc;
-            iters[q] = k + 1;
-            if (inc < tol || k + 1 >= N) {
-                conv[q] = 1;
-                hact[q] = 0;
-                --nactive;
-                changed = true;
-            }
-        }
-        if (changed && nactive > 0) {
-            CK(upload(active, hact, st), "active");
-        }
-    }
-    // output layout: request q -> n x (N+1) block
-    for (int q = 0; q < nreq; ++q)
-        CK(hipMemcpy2DAsync(U + (size_t)q * n * (N + 1), sizeof(double) * n, Ucur + (size_t)q * n,
-                            sizeof(double) * blk, sizeof(double) * n, N + 1, hipMemcpyDeviceToDevice, st),
-           "output");
-    // a posteriori bound (eq. apost_bound) with delta = max sigma_1, eps = max sigma_{k+1}
-    double delta = 0.0, eps = 0.0;
-    bool have_eps = true;
-    {
-        size_t pos = 0;
-        for (int s = 0; s < N; ++s) {
-            delta = std::max(delta, c->sigma[pos]);
-            if (c->l[s] > c->k[s]) eps = std::max(eps, c->sigma[pos + c->k[s]]);
-            else have_eps = false;
-            pos += c->l[s];
-        }
-    }
-    for (int q = 0; q < nreq; ++q) {
-        iters_host[q] = iters[q];
-        if (incr_host)
-            for (int k = 0; k < max_iter; ++k) incr_host[(size_t)q * max_iter + k] = incr[(size_t)q * max_iter + k];
-        if (apost_host) {
-            for (int nn = 1; nn <= N; ++nn) {
-                double sum = 0.0;
-                for (int m = 1; m < nn; ++m) sum += std::pow(delta, nn - m - 1) * last_inc[(size_t)(m - 1) * nreq + q];
-                apost_host[(size_t)q * N + nn - 1] = have_eps ? eps * sum : NAN;
-            }
-        }
-    }
-    CK(hipStreamSynchronize(st), "sync");
-    for (int q = 0; q < nreq; ++q)
-        if (!conv[q]) return fail(ctx, LRPR_ERR_NOCONV, "Parareal did not reach tol within max_iter");
-    return LRPR_OK;
+lrpr_status lrpr_parareal_solve_many(lrpr_ctx ctx, int nprob, const lrpr_parareal_problem *probs, int nsteps,
+                                     lrpr_prec fine_prec) {
+    return parareal_impl(ctx, nprob, probs, nsteps, fine_prec);
 }
 
 }  // extern "C"

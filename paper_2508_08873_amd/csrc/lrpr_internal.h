@@ -163,6 +163,10 @@ struct lrpr_ctx_s {
     std::vector<ProfRec> prof_recs;
     // device workspaces cached by purpose (grown on demand, freed on destroy)
     std::map<std::string, std::pair<void *, size_t>> ws;
+    // tuned launch shapes (lrpr_tune_set / lrpr_autotune_factor), 0 = default
+    int tune_lu_wgs = 0;
+    size_t tune_lu_budget = 0;   // bytes of FP64 bands and LU scratch per factor_many chunk
+    int tune_pr_graph = 1;       // Parareal iterations replayed from a captured HIP graph
 };
 
 namespace lrpr {
@@ -213,8 +217,13 @@ hipError_t launch_assemble(const lrpr_op_desc &op, int64_t n, int64_t rows, int 
 size_t tile_lu_scratch_bytes(int NT, int nb);
 // count independent factorisations of one tile shape (rows ns[i], band and
 // scratch per matrix)
+// wgs: workgroups per matrix, 0 = tile_lu_wgs's choice
 hipError_t launch_tile_lu_batch(int count, const int64_t *ns, int bw, int NT, int nb, double *const *bands,
-                                void *const *scratch, int **info_dev, int **err_dev, void *d_args, hipStream_t s);
+                                void *const *scratch, int **info_dev, int **err_dev, void *d_args, hipStream_t s,
+                                int wgs = 0);
+// workgroups per matrix of a batched LU of count matrices (wgs > 0: that
+// request, clipped to nb + 9 and NT)
+int tile_lu_wgs(int count, int NT, int nb, int wgs);
 size_t tile_lu_args_bytes(int count);
 // rev: lu is the LU of the reversed matrix (16 NT rows); the sets then hold
 // the UL factors (Lb / DL: the lower factor, Ub / DU: the upper one)

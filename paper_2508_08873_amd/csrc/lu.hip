@@ -21,6 +21,7 @@
 // is bounded: on time-out it raises *err and the kernel runs to its end.
 // All P workgroups are resident together (P is a few dozen), and every wait
 // is for a lower column, so the pipeline always drains.
+#include <algorithm>
 #include <vector>
 
 #include "lrpr_internal.h"
@@ -307,15 +308,32 @@ size_t tile_lu_scratch_bytes(int NT, int nb) {
     return sizeof(double) * ((size_t)NT * nb + NT) * TILE_ELEMS + sizeof(int) * ((size_t)NT + 2);
 }
 
-// Several independent factorisations of one shape in one launch: P = nb + 9
-// workgroups per matrix, at most 256 workgroups per launch so that every
+int tile_lu_wgs(int count, int NT, int nb, int wgs) {
+    const int full = std::min(nb + 9, NT);
+    if (wgs > 0) return std::max(1, std::min(wgs, full));
+    // one matrix's P workgroups own every P-th tile column; a column's owner
+    // applies its nb panels as they are published, about nb*(nb+1) tile
+    // products, and must be done before the chain reaches its next column
+    // P columns later.  nb + 9 leaves wide slack; when a batch would need
+    // more launches at that width, fewer workgroups per matrix let more
+    // matrices share a launch (at least 6 each)
+    if ((int64_t)count * full <= 256) return full;
+    const int lo = std::min(full, 6);
+    return std::max(lo, std::min(full, 256 / count));
+}
+
+// Several independent factorisations of one shape in one launch: P workgroups
+// per matrix (tile_lu_wgs), at most 256 workgroups per launch so that every
 // matrix's workgroups are resident together (their waits only involve each
 // other).  Each matrix i has its band, scratch (tile_lu_scratch_bytes) and
 // on return info_dev[i] / err_dev[i] point into its scratch (pivot info:
 // 0x7f7f7f7f if all pivots are fine, else the first bad row + 1; err:
 // nonzero on a wait time-out).  d_args: device space for count LuArgs.
+// The factors do not depend on P: every column applies its panels in the
+// same order whichever workgroup owns it.
 hipError_t launch_tile_lu_batch(int count, const int64_t *ns, int bw, int NT, int nb, double *const *bands,
-                                void *const *scratch, int **info_dev, int **err_dev, void *d_args, hipStream_t s) {
+                                void *const *scratch, int **info_dev, int **err_dev, void *d_args, hipStream_t s,
+                                int wgs) {
     std::vector<LuArgs> hv(count);
     for (int i = 0; i < count; ++i) {
         LuArgs &a = hv[i];
@@ -337,8 +355,7 @@ hipError_t launch_tile_lu_batch(int count, const int64_t *ns, int bw, int NT, in
         if ((e = hipMemsetAsync(a.info, 0x7f, sizeof(int), s)) != hipSuccess) return e;
         if ((e = hipMemsetAsync(a.err, 0, sizeof(int), s)) != hipSuccess) return e;
     }
-    int P = nb + 9;
-    if (P > NT) P = NT;
+    const int P = tile_lu_wgs(count, NT, nb, wgs);
     const int per = P > 256 ? 1 : 256 / P;   // matrices per launch
     LuArgs *dA = (LuArgs *)d_args;
     hipError_t e = hipMemcpyAsync(dA, hv.data(), sizeof(LuArgs) * (size_t)count, hipMemcpyHostToDevice, s);

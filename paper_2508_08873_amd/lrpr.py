@@ -18,18 +18,20 @@ LRPR_F64, LRPR_F32 = 0, 1
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_ZERO_PIVOT", 4: "ERR_QR_BREAKDOWN",
           5: "ERR_NOCONV", 6: "ERR_NONFINITE", 7: "ERR_HIP"}
 EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_last_error",
-           "lrpr_ctx_release_workspaces",
+           "lrpr_ctx_release_workspaces", "lrpr_tune_set", "lrpr_tune_get", "lrpr_autotune_factor",
            "lrpr_factor", "lrpr_factor_stepper", "lrpr_factor_sequence", "lrpr_factor_many", "lrpr_factor_destroy",
            "lrpr_factor_info", "lrpr_factor_copy_lu",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build", "lrpr_rsvd_build_q",
            "lrpr_rsvd_build_two_sided", "lrpr_rsvd_build_w", "lrpr_coarse_from_factors", "lrpr_mass_weights",
            "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_coarse_apply_noalloc",
-           "lrpr_parareal_solve",
+           "lrpr_parareal_solve", "lrpr_parareal_solve_many",
            "lrpr_profile_enable", "lrpr_profile_read", "lrpr_randn",
            "lrpr_server_create", "lrpr_server_destroy", "lrpr_server_submit", "lrpr_server_progress",
            "lrpr_server_stats", "lrpr_server_last_error"]
 
 
+# lrpr_tune_set parameters
+TUNE_LU_WGS, TUNE_LU_BUDGET, TUNE_PARAREAL_GRAPH = 1, 2, 3
 # lrpr_factor store_mask bits (include/lrpr.h)
 STORE_F64, STORE_F32, STORE_MIRROR, STORE_SPLIT, STORE_UL = 1, 2, 4, 8, 16
 # lrpr_factor_stepper steppers
@@ -61,6 +63,13 @@ class ServeOp(ctypes.Structure):
                 ("fscale", ctypes.c_void_p)]
 
 
+class PararealProblem(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_void_p), ("F", ctypes.c_void_p), ("nreq", ctypes.c_int),
+                ("u0", ctypes.c_void_p), ("f", ctypes.c_void_p), ("fscale", ctypes.c_void_p),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("U", ctypes.c_void_p),
+                ("iters_host", ctypes.c_void_p), ("incr_host", ctypes.c_void_p), ("apost_host", ctypes.c_void_p)]
+
+
 class SliceDesc(ctypes.Structure):
     _fields_ = [("F", ctypes.c_void_p), ("k", ctypes.c_int), ("p", ctypes.c_int),
                 ("Omega", ctypes.c_void_p)]
@@ -90,6 +99,9 @@ def load():
     lib.lrpr_factor_sequence.argtypes = [vp, P(OpDesc), i32, i32, P(vp)]
     lib.lrpr_factor_many.argtypes = [vp, P(OpDesc), i32, i32, P(vp)]
     lib.lrpr_ctx_release_workspaces.argtypes = [vp]
+    lib.lrpr_tune_set.argtypes = [vp, i32, i64]
+    lib.lrpr_tune_get.argtypes = [vp, i32, P(i64)]
+    lib.lrpr_autotune_factor.argtypes = [vp, P(OpDesc), i32, i32, P(i32), P(dbl)]
     lib.lrpr_factor_destroy.argtypes = [vp]
     lib.lrpr_factor_destroy.restype = None
     lib.lrpr_factor_info.argtypes = [vp, P(i64), P(i32), P(dbl)]
@@ -106,6 +118,7 @@ def load():
     lib.lrpr_coarse_apply.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.lrpr_coarse_apply_noalloc.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.lrpr_parareal_solve.argtypes = [vp, vp, P(vp), i32, i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
+    lib.lrpr_parareal_solve_many.argtypes = [vp, i32, P(PararealProblem), i32, i32]
     lib.lrpr_profile_enable.argtypes = [vp, i32]
     lib.lrpr_profile_read.argtypes = [vp, P(dbl), P(i64), P(dbl), P(dbl), P(dbl)]
     lib.lrpr_randn.argtypes = [vp, vp, i64, i32, ctypes.c_uint64, ctypes.c_uint64]
@@ -236,6 +249,26 @@ class Context:
         self._check(self.lib.lrpr_factor_many(self.h, arr, len(ops), int(store_mask), hs))
         return [Factor(self, ctypes.c_void_p(hs[j])) for j in range(len(ops))]
 
+    def tune_set(self, param, value):
+        self._check(self.lib.lrpr_tune_set(self.h, int(param), int(value)))
+
+    def tune_get(self, param):
+        v = ctypes.c_int64()
+        self._check(self.lib.lrpr_tune_get(self.h, int(param), ctypes.byref(v)))
+        return v.value
+
+    def autotune_factor(self, dim, nx, nu, beta, c, dt, count, store_mask=1):
+        """lrpr_autotune_factor: returns (workgroups per matrix, ms)."""
+        d = _opdesc(dim, nx, nu, beta, c, dt)
+        wg, ms = ctypes.c_int(), ctypes.c_double()
+        self.sync_stream()
+        self._check(self.lib.lrpr_autotune_factor(self.h, ctypes.byref(d), int(count), int(store_mask),
+                                                  ctypes.byref(wg), ctypes.byref(ms)))
+        return wg.value, ms.value
+
+    def parareal_solve_many(self, problems, nsteps, fine_prec=LRPR_F64):
+        return _parareal_many(self, problems, nsteps, fine_prec)
+
     def release_workspaces(self):
         self.sync_stream()
         self._check(self.lib.lrpr_ctx_release_workspaces(self.h))
@@ -335,6 +368,40 @@ class Context:
             self._check(st)
         return {"U": U, "iters": list(iters), "incr": [list(incr[r * max_iter:(r + 1) * max_iter]) for r in range(nreq)],
                 "apost": [list(apost[r * N:(r + 1) * N]) for r in range(nreq)], "status": st}
+
+
+def _parareal_many(ctx, problems, nsteps, fine_prec):
+    """lrpr_parareal_solve_many; problems: list of dicts {coarse, factors,
+    u0 (n x nreq), f or None, fscale or None, tol, max_iter or None}."""
+    arr = (PararealProblem * len(problems))()
+    keep, outs = [], []
+    for i, pr in enumerate(problems):
+        facs = pr["factors"]
+        N = len(facs)
+        mi = pr.get("max_iter") or N
+        u0 = pr["u0"]
+        n, nreq = u0.shape
+        U = torch.zeros((nreq, N + 1, n), dtype=torch.float64, device=u0.device)
+        fa = (ctypes.c_void_p * N)(*[F.h.value for F in facs])
+        iters = (ctypes.c_int * nreq)()
+        incr = (ctypes.c_double * (nreq * mi))()
+        apost = (ctypes.c_double * (nreq * N))()
+        keep += [fa, iters, incr, apost, U]
+        addr = lambda t: t.data_ptr() if t is not None else None
+        arr[i] = PararealProblem(pr["coarse"].h, ctypes.cast(fa, ctypes.c_void_p), nreq, addr(u0), addr(pr.get("f")),
+                                 addr(pr.get("fscale")), float(pr["tol"]), int(mi), addr(U),
+                                 ctypes.cast(iters, ctypes.c_void_p), ctypes.cast(incr, ctypes.c_void_p),
+                                 ctypes.cast(apost, ctypes.c_void_p))
+        outs.append((U, iters, incr, apost, nreq, mi, N))
+    ctx.sync_stream()
+    st = ctx.lib.lrpr_parareal_solve_many(ctx.h, len(problems), arr, int(nsteps), int(fine_prec))
+    if st not in (0, 5):
+        ctx._check(st)
+    res = []
+    for U, iters, incr, apost, nreq, mi, N in outs:
+        res.append({"U": U, "iters": list(iters), "incr": [list(incr[r * mi:(r + 1) * mi]) for r in range(nreq)],
+                    "apost": [list(apost[r * N:(r + 1) * N]) for r in range(nreq)], "status": st})
+    return res
 
 
 class Factor:

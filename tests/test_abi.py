@@ -59,6 +59,9 @@ def test_struct_layouts():
     assert ctypes.sizeof(lrpr.Panel) == 8 * 8
     # lrpr_slice_desc: F, k, p, Omega
     assert ctypes.sizeof(lrpr.SliceDesc) == 8 + 4 + 4 + 8
+    # lrpr_parareal_problem: C, F, nreq(+pad), u0, f, fscale, tol, max_iter(+pad), U, iters, incr, apost
+    assert ctypes.sizeof(lrpr.PararealProblem) == 12 * 8
+    assert lrpr.PararealProblem.tol.offset == 48 and lrpr.PararealProblem.U.offset == 64
 
 
 def test_mass_weights_host_entry_point(ora):
@@ -75,6 +78,9 @@ def test_null_context_is_an_argument_error(lib):
     assert lib.lrpr_factor(None, None, 1, None) == 1
     assert lib.lrpr_fine_step_batched(None, 0, None, 1, 0) == 1
     assert lib.lrpr_adjoint_step_batched(None, 0, None, 1, 0) == 1
+    assert lib.lrpr_parareal_solve_many(None, 1, None, 1, 0) == 1
+    assert lib.lrpr_tune_set(None, 1, 0) == 1
+    assert lib.lrpr_factor_many(None, None, 1, 1, None) == 1
     assert lib.lrpr_last_error(None) == b"null context"
 
 
