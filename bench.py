@@ -409,11 +409,11 @@ def c2_bench(ctx, lrpr, args):
     1/2048), so each slice has its own operator and band LU; k = 64, p = 16.
     One step:
       1. assemble and factor the 128 operators (band LU in FP64, tiles stored
-         in FP32: 146 GB), the LU workspaces released afterwards;
+         in FP32: 146 GB);
       2. rSVD build of all 128 slices together (128 x 80 = 10240 forward and
          10240 adjoint right-hand sides x 16 steps in FP32, one sweep launch
          each way; CholeskyQR2 Gram and Cholesky, Jacobi SVD and rotations in
-         FP64), its workspaces released afterwards;
+         FP64), its panels in the workspace the LU bands used;
       3. Parareal with FP32 fine solves (one right-hand side per slice and
          factor, the HBM-bound regime) and the FP64 correction to
          max_n ||u^{k+1}_n - u^k_n|| < 1e-6, with the per-slice a posteriori
@@ -442,10 +442,8 @@ def c2_bench(ctx, lrpr, args):
     def one_step(recs, times):
         ta = time.perf_counter()
         facs = ctx.factor_many(ops, store_mask=lrpr.STORE_F32)
-        ctx.release_workspaces()
         tb = time.perf_counter()
         coarse = ctx.rsvd_build([(facs[s], P.k, P.p, Om[s].t()) for s in range(P.N)], P.m, 1)
-        ctx.release_workspaces()
         tc = time.perf_counter()
         if recs is not None:
             recs["range"].append(ctx.profile_read())
@@ -460,7 +458,6 @@ def c2_bench(ctx, lrpr, args):
         coarse.close()
         for F in facs:
             F.close()
-        ctx.release_workspaces()
         return out, sig
 
     for _ in range(args.warmup):
@@ -477,6 +474,7 @@ def c2_bench(ctx, lrpr, args):
     ctx.profile(False)
     del Om
     torch.cuda.empty_cache()
+    ctx.device_trim()   # the pool's free blocks back to the device for what follows
     return P, out, sig, recs, times, t1 - t0, tune
 
 

@@ -130,6 +130,13 @@ lrpr_status lrpr_tune_get(lrpr_ctx ctx, int param, int64_t *value);
  * Synchronises.  Errors: as lrpr_factor_many. */
 lrpr_status lrpr_autotune_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int count, int store_mask, int *best_wgs,
                                  double *best_ms);
+/* Device memory that destroy calls free (factor tiles and bands, spikes,
+ * coarse factors) is kept by the library, per device and block size, for
+ * the next handle of the same shape.  lrpr_device_trim synchronises the
+ * device and frees the kept blocks (lrpr_ctx_destroy does so too, and an
+ * allocation that fails retries after it), for callers that need the memory
+ * otherwise.  Errors: LRPR_ERR_HIP. */
+lrpr_status lrpr_device_trim(int device);
 /* Replace the stream used by later calls. */
 lrpr_status lrpr_ctx_set_stream(lrpr_ctx ctx, void *hip_stream);
 /* Message of the last failing call on ctx (static storage owned by ctx). */

@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <type_traits>
 
@@ -33,6 +35,59 @@ static lrpr_status hipfail(lrpr_ctx ctx, hipError_t e, const char *what) {
         if (e_ != hipSuccess) return lrpr::hipfail(ctx, e_, what); \
     } while (0)
 
+namespace lrpr {
+
+// Blocks of handle memory freed by destroy calls, kept per device and size
+// for the next allocation of the same size (handles of one shape are
+// destroyed and made again step after step), until lrpr_device_trim.
+namespace {
+std::mutex g_mem_mu;
+std::multimap<std::pair<int, size_t>, void *> g_free;   // (device, bytes) -> block
+std::map<void *, std::pair<int, size_t>> g_live;        // block -> (device, bytes)
+}  // namespace
+
+hipError_t dmalloc(void **p, size_t bytes, hipStream_t) {
+    if (!bytes) bytes = 16;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    {
+        std::lock_guard<std::mutex> lock(g_mem_mu);
+        auto it = g_free.find({dev, bytes});
+        if (it != g_free.end()) {
+            *p = it->second;
+            g_free.erase(it);
+            g_live[*p] = {dev, bytes};
+            return hipSuccess;
+        }
+    }
+    e = hipMalloc(p, bytes);
+    if (e == hipErrorOutOfMemory) {   // give the kept blocks back and try once more
+        lrpr_device_trim(dev);
+        hipSetDevice(dev);
+        e = hipMalloc(p, bytes);
+    }
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    g_live[*p] = {dev, bytes};
+    return hipSuccess;
+}
+
+// p must not be in use by queued work (callers synchronise first)
+void dfree(void *p, hipStream_t) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) {
+        hipFree(p);
+        return;
+    }
+    g_free.insert({it->second, p});
+    g_live.erase(it);
+}
+
+}  // namespace lrpr
+
 extern "C" {
 
 lrpr_status lrpr_ctx_create(int device, void *hip_stream, lrpr_ctx *out) {
@@ -58,7 +113,26 @@ void lrpr_ctx_destroy(lrpr_ctx ctx) {
     if (ctx->d_items) hipFree(ctx->d_items);
     for (auto &kv : ctx->ws)
         if (kv.second.first) hipFree(kv.second.first);
+    lrpr_device_trim(ctx->dev);
     delete ctx;
+}
+
+lrpr_status lrpr_device_trim(int device) {
+    if (hipSetDevice(device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return LRPR_ERR_HIP;
+    std::vector<void *> blocks;
+    {
+        std::lock_guard<std::mutex> lock(lrpr::g_mem_mu);
+        for (auto it = lrpr::g_free.begin(); it != lrpr::g_free.end();) {
+            if (it->first.first == device) {
+                blocks.push_back(it->second);
+                it = lrpr::g_free.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    for (void *p : blocks) hipFree(p);
+    return LRPR_OK;
 }
 
 lrpr_status lrpr_ctx_set_stream(lrpr_ctx ctx, void *hip_stream) {
@@ -71,31 +145,39 @@ const char *lrpr_last_error(lrpr_ctx ctx) { return ctx ? ctx->err.c_str() : "nul
 
 // ---------------------------------------------------------------------------
 static void free_tiles(TileSet &t) {
-    for (void *p : t.alloc)
-        if (p) hipFree(p);
-    if (t.zt) hipFree(t.zt);
-    if (t.sink) hipFree(t.sink);
+    dfree(t.block, nullptr);
     t = TileSet();
 }
 
 // Tile arrays with guard_rows(nb) zero tile rows on both sides; the TileSet
 // pointers address tile row 0.  The mirrored band arrays only with `mirror`.
+// One allocation (and one clearing fill) holds every array of the set, the
+// zero tile and the sink tile.
 static hipError_t alloc_tiles(TileSet &t, int NT, int nb, size_t esz, bool mirror, hipStream_t s) {
     const size_t G = (size_t)guard_rows(nb);
     const size_t rows = (size_t)NT + 2 * G;
-    hipError_t e;
+    const size_t tile = TILE_ELEMS * esz;
+    size_t off[TS_COUNT] = {}, total = 0;
     for (int a = 0; a < TS_COUNT; ++a) {
         const bool band = a == TS_LB || a == TS_UB || a == TS_UTB || a == TS_LTB;
         if (!mirror && (a == TS_UTB || a == TS_LTB)) continue;
-        const size_t per_row = band ? (size_t)nb : 1;
-        const size_t bytes = rows * per_row * TILE_ELEMS * esz;
-        if ((e = hipMalloc(&t.alloc[a], bytes)) != hipSuccess) return e;
-        if ((e = hipMemsetAsync(t.alloc[a], 0, bytes, s)) != hipSuccess) return e;
-        t.a[a] = (char *)t.alloc[a] + G * per_row * TILE_ELEMS * esz;
+        off[a] = total;
+        total += rows * (band ? (size_t)nb : 1) * tile;
     }
-    if ((e = hipMalloc(&t.zt, TILE_ELEMS * esz)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(t.zt, 0, TILE_ELEMS * esz, s)) != hipSuccess) return e;
-    if ((e = hipMalloc(&t.sink, TILE_ELEMS * esz)) != hipSuccess) return e;
+    const size_t zoff = total, soff = total + tile;
+    total += 2 * tile;
+    hipError_t e;
+    if ((e = dmalloc(&t.block, total, s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(t.block, 0, total, s)) != hipSuccess) return e;
+    char *b = (char *)t.block;
+    for (int a = 0; a < TS_COUNT; ++a) {
+        const bool band = a == TS_LB || a == TS_UB || a == TS_UTB || a == TS_LTB;
+        if (!mirror && (a == TS_UTB || a == TS_LTB)) continue;
+        t.alloc[a] = b + off[a];
+        t.a[a] = b + off[a] + G * (band ? (size_t)nb : 1) * tile;
+    }
+    t.zt = b + zoff;
+    t.sink = b + soff;
     return hipSuccess;
 }
 
@@ -105,13 +187,13 @@ void lrpr_factor_destroy(lrpr_fac f) {
     f->seq.clear();
     hipSetDevice(f->dev);
     hipDeviceSynchronize();
-    if (f->lu) hipFree(f->lu);
+    dfree(f->lu, nullptr);
     free_tiles(f->t64);
     free_tiles(f->t32);
     free_tiles(f->t64r);
     free_tiles(f->t32r);
-    for (void *p : {f->s64.S, f->s64.T, f->s32.S, f->s32.T, (void *)f->d_blk})
-        if (p) hipFree(p);
+    for (void *p : {f->s64.S, f->s64.T, f->s32.S, f->s32.T}) dfree(p, nullptr);
+    if (f->d_blk) hipFree(f->d_blk);
     delete f;
 }
 
@@ -219,7 +301,7 @@ static lrpr_status build_split(lrpr_ctx ctx, lrpr_fac f, const double *band) {
         if (!(f->mask & (f32 ? LRPR_STORE_F32 : LRPR_STORE_F64))) continue;
         SplitSet &ss = f32 ? f->s32 : f->s64;
         const size_t tiles = (size_t)NT * nb * TILE_ELEMS * (f32 ? 4 : 8);
-        if ((e = hipMalloc(&ss.S, tiles)) != hipSuccess || (e = hipMalloc(&ss.T, tiles)) != hipSuccess)
+        if ((e = dmalloc(&ss.S, tiles, ctx->stream)) != hipSuccess || (e = dmalloc(&ss.T, tiles, ctx->stream)) != hipSuccess)
             return bail(e, "spike tiles");
         if ((e = launch_spike_pack(f32, NT, nb, f32 ? (void *)RL32 : (void *)RL, ld, ss.S, st)) != hipSuccess ||
             (e = launch_spike_pack(f32, NT, nb, f32 ? (void *)RU32 : (void *)RU, ld, ss.T, st)) != hipSuccess)
@@ -276,7 +358,7 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
     auto cleanup = [&](lrpr_status stt, const std::string &msg) {
         hipStreamSynchronize(st);
         for (int j = 0; j < mm; ++j) {
-            if (bands[j] && owned[j] && (!fs[j] || bands[j] != fs[j]->lu)) hipFree(bands[j]);
+            if (bands[j] && owned[j] && (!fs[j] || bands[j] != fs[j]->lu)) dfree(bands[j], st);
             if (j < m && fs[j]) lrpr_factor_destroy(fs[j]);
         }
         return fail(ctx, stt, msg);
@@ -299,21 +381,29 @@ static lrpr_status factor_batch(lrpr_ctx ctx, const lrpr_op_desc *ops, int m, in
         f->mask = store_mask;
         f->dt_step = ops[j].dt;
     }
+    // temporaries (bands not kept, LU scratch) carved from the context's
+    // arena, the workspace that the rSVD build's panels reuse afterwards
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t arena_bytes = 0;
+    for (int j = 0; j < mm; ++j) {
+        if (!(j < m && keep_lu)) arena_bytes += al(sizeof(double) * (size_t)rows[j] * (2 * bw + 1));
+        arena_bytes += al(sbytes);
+    }
+    char *arena = (char *)ws_get(ctx, "arena", arena_bytes, &e);
+    if (!arena) return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: band and scratch workspace");
+    size_t at = 0;
     for (int j = 0; j < mm; ++j) {
         const size_t bbytes = sizeof(double) * (size_t)rows[j] * (2 * bw + 1);
-        char key[32];
         if (j < m && keep_lu) {
-            if ((e = hipMalloc(&bands[j], bbytes)) != hipSuccess)
+            if ((e = dmalloc((void **)&bands[j], bbytes, st)) != hipSuccess)
                 return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: band allocation");
             owned[j] = 1;
         } else {
-            snprintf(key, sizeof key, "fac_band%d", j);
-            if (!(bands[j] = (double *)ws_get(ctx, key, bbytes, &e)))
-                return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: band allocation");
+            bands[j] = (double *)(arena + at);
+            at += al(bbytes);
         }
-        snprintf(key, sizeof key, "fac_scr%d", j);
-        if (!(scr[j] = ws_get(ctx, key, sbytes, &e)))
-            return cleanup(LRPR_ERR_NOMEM, "lrpr_factor: scratch allocation");
+        scr[j] = arena + at;
+        at += al(sbytes);
         if ((e = launch_assemble(ops[j % m], n, rows[j], bw, j >= m, bands[j], st)) != hipSuccess)
             return cleanup(LRPR_ERR_HIP, std::string("assemble: ") + hipGetErrorString(e));
     }
@@ -795,6 +885,52 @@ static lrpr_status run_split(lrpr_ctx ctx, int npanels, const lrpr_panel *panels
     return LRPR_OK;
 }
 
+// XCD-aware order of a launch's work items.  Workgroups are dispatched to
+// the chip's 8 XCDs round-robin (workgroup i on XCD i % 8), and each XCD has
+// its own L2.  Runs of consecutive items on one factor (the column groups of
+// one panel) are dealt whole to the XCD queue with the fewest items (split
+// only to keep the queues equal), and item l of queue x goes to position
+// 8 l + x: the groups that read the same factor tiles start together on one
+// XCD and share its L2 instead of each fetching the factor from HBM.  The
+// items are independent, so the order changes no result.
+static void xcd_order(std::vector<SweepItem> &items) {
+    constexpr int NX = 8;
+    const size_t ni = items.size();
+    if (ni < 2 * NX) return;
+    std::vector<std::pair<size_t, size_t>> runs;   // first item, count
+    for (size_t i = 0; i < ni; ++i) {
+        if (i > 0 && items[i].fac.a[TS_LB] == items[i - 1].fac.a[TS_LB] &&
+            items[i].fac.a[TS_UB] == items[i - 1].fac.a[TS_UB])
+            ++runs.back().second;
+        else
+            runs.push_back({i, 1});
+    }
+    if (runs.size() < 2) return;
+    const size_t target = (ni + NX - 1) / NX;
+    std::vector<std::vector<size_t>> q(NX);
+    for (auto r : runs) {
+        size_t at = r.first, left = r.second;
+        while (left > 0) {
+            int x = 0;
+            for (int y = 1; y < NX; ++y)
+                if (q[y].size() < q[x].size()) x = y;
+            const size_t room = target > q[x].size() ? target - q[x].size() : 1;
+            const size_t take = std::min(left, room);
+            for (size_t k = 0; k < take; ++k) q[x].push_back(at + k);
+            at += take;
+            left -= take;
+        }
+    }
+    std::vector<SweepItem> out;
+    out.reserve(ni);
+    size_t maxlen = 0;
+    for (auto &v : q) maxlen = std::max(maxlen, v.size());
+    for (size_t l = 0; l < maxlen; ++l)
+        for (int x = 0; x < NX; ++x)
+            if (l < q[x].size()) out.push_back(items[q[x][l]]);
+    items.swap(out);
+}
+
 // Validate panels and turn them into 16-column work items; launch one sweep
 // of nsteps solve steps.  A column's source factors are fscale[c * fstride +
 // step0 + j], j < nsteps.  record: add a profile record for the launch.
@@ -853,6 +989,7 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
     for (const SweepItem &it : items)
         paired = paired && it.fac.nb == max_nb && it.fac.ar[TS_LB] && (!adjoint || it.fac.ar[TS_UTB]) &&
                  (double)(it.fac.NT + 2 * guard_rows(max_nb)) * max_nb * TILE_ELEMS * (f32 ? 4 : 8) < 4.0e9;
+    xcd_order(items);
     const size_t ni = items.size();
     if (paired) {
         // [0, ni): first substitution of the first step; [ni, 2ni): second

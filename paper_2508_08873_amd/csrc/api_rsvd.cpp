@@ -100,7 +100,7 @@ void lrpr_coarse_destroy(lrpr_coarse c) {
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
     if (c->block) {
-        hipFree(c->block);
+        dfree(c->block, nullptr);
     } else {
         for (size_t s = 0; s < c->U.size(); ++s) {
             if (c->U[s]) hipFree(c->U[s]);
@@ -260,13 +260,21 @@ static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_d
         off[s + 1] = off[s] + slices[s].F->n * ls[s];
     }
     const int64_t tot = off[nslices];
+    // the five panel arenas, carved from the context's arena (the workspace
+    // that the factorisation's bands and scratch used before)
     char *Y = nullptr, *Z = nullptr;
     double *Q = nullptr, *QZ = nullptr, *T2 = nullptr;
-    CK(mem.alloc(&Y, tot * esz), "rsvd Y");
-    CK(mem.alloc(&Z, tot * esz), "rsvd Z");
-    CK(mem.alloc(&Q, tot), "rsvd Q");
-    CK(mem.alloc(&QZ, tot), "rsvd Qz");
-    CK(mem.alloc(&T2, tot), "rsvd tmp");
+    {
+        const size_t a1 = ((size_t)tot * esz + 255) / 256 * 256, a2 = ((size_t)tot * 8 + 255) / 256 * 256;
+        hipError_t ea = hipSuccess;
+        char *base = (char *)ws_get(ctx, "arena", 2 * a1 + 3 * a2, &ea);
+        if (!base) return herr(ctx, ea == hipSuccess ? hipErrorOutOfMemory : ea, "rsvd panels");
+        Y = base;
+        Z = base + a1;
+        Q = (double *)(base + 2 * a1);
+        QZ = (double *)(base + 2 * a1 + a2);
+        T2 = (double *)(base + 2 * a1 + 2 * a2);
+    }
     const size_t SM = (size_t)LMAX * LMAX;
     double *G, *R1, *I1, *R2, *I2, *RY, *RZ, *Mm, *Uh, *Vh, *Sd, *part;
     int *d_ls, *stat1, *stat2, *sweeps;
@@ -483,7 +491,8 @@ static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_d
     size_t elems = 0;
     for (int s = 0; s < nslices; ++s)
         elems += 2 * pad((size_t)slices[s].F->n * std::max(slices[s].k, 1)) + pad(LMAX);
-    if (hipMalloc(&c->block, elems * sizeof(double)) != hipSuccess) return bail(LRPR_ERR_NOMEM, "coarse factors");
+    if (dmalloc((void **)&c->block, elems * sizeof(double), st) != hipSuccess)
+        return bail(LRPR_ERR_NOMEM, "coarse factors");
     size_t at = 0;
     for (int s = 0; s < nslices; ++s) {
         c->n[s] = slices[s].F->n;
@@ -942,6 +951,11 @@ void *ws_get(lrpr_ctx ctx, const char *key, size_t bytes, hipError_t *err) {
     }
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+    if (e == hipErrorOutOfMemory) {   // give the kept handle blocks back and try once more
+        lrpr_device_trim(ctx->dev);
+        hipSetDevice(ctx->dev);
+        e = hipMalloc(&p, bytes ? bytes : 16);
+    }
     if (e != hipSuccess) {
         if (err) *err = e;
         return nullptr;

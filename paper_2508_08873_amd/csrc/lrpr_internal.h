@@ -54,7 +54,8 @@ struct TileSet {            // device arrays of one precision (pointers to tile 
     void *a[TS_COUNT] = {};      // indexed by TS_*; UTb/LTb null without the mirrored set
     void *zt = nullptr;          // one all-zero tile: target of loads outside the band
     void *sink = nullptr;        // one scratch tile: target of masked-off stores
-    void *alloc[TS_COUNT] = {};  // allocations behind a[] (they start guard rows earlier)
+    void *alloc[TS_COUNT] = {};  // starts of the arrays behind a[] (guard rows earlier)
+    void *block = nullptr;       // one allocation holding every array, zt and sink
 };
 
 // Device-side view of one factor, passed by value to the sweep kernels.
@@ -177,6 +178,16 @@ inline int fac_stages(const lrpr_factor_s *f) { return (f->stepper == 1 || f->st
 
 // error helper: record message in ctx and return status
 lrpr_status fail(lrpr_ctx ctx, lrpr_status st, const std::string &msg);
+
+// Device memory of handles (factor tiles and bands, spikes, coarse
+// factors): blocks freed by destroy calls are kept per device and size and
+// handed to the next allocation of the same size (a batch of factors
+// destroyed and made again with the same shapes maps no new memory), until
+// lrpr_device_trim; an allocation that fails first gives them back.  The
+// current device must be the handle's.  dfree: the block must not be in use
+// by queued work.
+hipError_t dmalloc(void **p, size_t bytes, hipStream_t s);
+void dfree(void *p, hipStream_t s);
 
 // Device address of the fixed scratch array of lrpr_coarse_apply_noalloc on
 // device dev (noalloc.hip); dev must be current.  Looked up once per device.

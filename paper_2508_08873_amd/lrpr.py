@@ -19,6 +19,7 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_NOMEM", 3: "ERR_ZERO_PIVOT", 4: "ERR_QR
           5: "ERR_NOCONV", 6: "ERR_NONFINITE", 7: "ERR_HIP"}
 EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_last_error",
            "lrpr_ctx_release_workspaces", "lrpr_tune_set", "lrpr_tune_get", "lrpr_autotune_factor",
+           "lrpr_device_trim",
            "lrpr_factor", "lrpr_factor_stepper", "lrpr_factor_sequence", "lrpr_factor_many", "lrpr_factor_destroy",
            "lrpr_factor_info", "lrpr_factor_copy_lu",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build", "lrpr_rsvd_build_q",
@@ -99,6 +100,7 @@ def load():
     lib.lrpr_factor_sequence.argtypes = [vp, P(OpDesc), i32, i32, P(vp)]
     lib.lrpr_factor_many.argtypes = [vp, P(OpDesc), i32, i32, P(vp)]
     lib.lrpr_ctx_release_workspaces.argtypes = [vp]
+    lib.lrpr_device_trim.argtypes = [i32]
     lib.lrpr_tune_set.argtypes = [vp, i32, i64]
     lib.lrpr_tune_get.argtypes = [vp, i32, P(i64)]
     lib.lrpr_autotune_factor.argtypes = [vp, P(OpDesc), i32, i32, P(i32), P(dbl)]
@@ -268,6 +270,9 @@ class Context:
 
     def parareal_solve_many(self, problems, nsteps, fine_prec=LRPR_F64):
         return _parareal_many(self, problems, nsteps, fine_prec)
+
+    def device_trim(self):
+        self._check(self.lib.lrpr_device_trim(self.device))
 
     def release_workspaces(self):
         self.sync_stream()

@@ -65,7 +65,7 @@ def c2():
     for F in facs:
         F.close()
     ctx.release_workspaces()
-    ctx.close()
+    ctx.close()   # also returns the pool's free blocks to the device
     gc.collect()
     torch.cuda.empty_cache()
 
