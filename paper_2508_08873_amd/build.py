@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "liblrpr.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["factor.hip", "lu.hip", "sweep.hip", "split.hip", "dense.hip", "rng.hip", "noalloc.hip", "api_core.cpp", "api_rsvd.cpp",
+SOURCES = ["factor.hip", "lu.hip", "sweep.hip", "narrow.hip", "split.hip", "dense.hip", "rng.hip", "noalloc.hip", "api_core.cpp", "api_rsvd.cpp",
            "api_serve.cpp"]
 ARCH = os.environ.get("LRPR_ARCH", "gfx950")
 

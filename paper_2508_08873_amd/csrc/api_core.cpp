@@ -989,6 +989,32 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
     for (const SweepItem &it : items)
         paired = paired && it.fac.nb == max_nb && it.fac.ar[TS_LB] && (!adjoint || it.fac.ar[TS_UTB]) &&
                  (double)(it.fac.NT + 2 * guard_rows(max_nb)) * max_nb * TILE_ELEMS * (f32 ? 4 : 8) < 4.0e9;
+    // Narrow panels (at most sweep_narrow_cols columns per factor; with
+    // split_any_width every width, cut into such items) run on the vector
+    // ALUs: a single column then does not pay for a 16-column group.  The
+    // alternating L U / U' L' pairs measured about half the FP32 error of
+    // L U steps alone (32 steps on 255^2 grids), so factors that carry the
+    // UL set keep the matrix-core pass pairs.
+    const int ncmax = sweep_narrow_cols(f32);
+    bool narrow = !adjoint && !paired && max_nb >= 2 && max_nb <= 64;
+    if (narrow && !split_any_width)
+        for (const SweepItem &it : items) narrow = narrow && it.ncols <= ncmax;
+    int narrow_cols = 0;
+    if (narrow) {
+        const size_t esz = f32 ? 4 : 8;
+        std::vector<SweepItem> nit;
+        for (const SweepItem &it : items)
+            for (int c0 = 0; c0 < it.ncols; c0 += ncmax) {
+                SweepItem q = it;
+                q.X = (char *)it.X + (size_t)c0 * it.ldx * esz;
+                q.ncols = std::min(ncmax, it.ncols - c0);
+                if (q.fcol) q.fcol = it.fcol + c0;
+                if (q.fscale) q.fscale = it.fscale + (size_t)c0 * it.fsteps;
+                narrow_cols = std::max(narrow_cols, q.ncols);
+                nit.push_back(q);
+            }
+        items.swap(nit);
+    }
     xcd_order(items);
     const size_t ni = items.size();
     if (paired) {
@@ -1025,7 +1051,11 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
         return hipfail(ctx, e, "profile event");
     const int nii = (int)ni;
     std::function<hipError_t(hipStream_t)> go;
-    if (!paired) {
+    if (narrow) {
+        go = [=](hipStream_t s) {
+            return launch_sweep_narrow(f32, nii, d_items, nsteps, max_nb, narrow_cols, s, step0);
+        };
+    } else if (!paired) {
         go = [=](hipStream_t s) {
             return launch_sweep(adjoint, strided, f32, nii, d_items, nsteps, max_nb, s, step0);
         };

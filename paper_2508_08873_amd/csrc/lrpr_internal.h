@@ -253,6 +253,12 @@ hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const 
 hipError_t launch_sweep_pair(bool adjoint, bool asc, bool f32, int nitems, const SweepItem *d_items, int nb,
                              hipStream_t s, int stepB);
 bool sweep_pairable(int nb);
+// narrow forward sweeps on the vector ALUs (narrow.hip): items of at most
+// sweep_narrow_cols(f32) columns, 2..64 band tiles per row
+int sweep_narrow_cols(bool f32);
+bool sweep_narrow_ok(bool f32, int max_nb, int ncols);
+hipError_t launch_sweep_narrow(bool f32, int nitems, const SweepItem *d_items, int nsteps, int max_nb,
+                               int ncols_max, hipStream_t s, int step0);
 // out = ca a + cb b + cc c on an n x w block (column-major, own leading
 // dimensions; c may be null), element type of the precision (dense.hip)
 hipError_t launch_combine3(bool f32, void *out, int64_t ldo, const void *a, int64_t lda, double ca, const void *b,

@@ -320,16 +320,41 @@ def test_fp32_smooth_mode_accuracy(ctx, ora):
     V = np.stack([(np.sin(np.pi * Xg) * np.sin(np.pi * Yg)).reshape(-1),
                   (np.sin(2 * np.pi * Xg) * np.sin(np.pi * Yg)).reshape(-1)], axis=1)
     V = V.astype(np.float32).astype(np.float64)
+    # padded to 16 columns so that the forward sweep runs on the matrix cores
+    # (two columns alone take the vector-ALU sweep: test_fp32_smooth_mode_narrow)
+    Vp = np.concatenate([V, np.random.default_rng(2).standard_normal((P.n, 14)).astype(np.float32)], axis=1)
     op = _oracle_op(ora, P)
     for adjoint in (False, True):
         print("smooth modes, adjoint", adjoint, flush=True)
-        Xd = _dev(V, torch.float32)
+        Xd = _dev(Vp, torch.float32)
         (ctx.adjoint_step_batched if adjoint else ctx.fine_step_batched)([{"F": F, "X": Xd}], P.m, 1)
-        g = Xd.double().cpu().numpy()
+        g = Xd.double().cpu().numpy()[:, :2]
         ref = op.adjoint(V, P.m) if adjoint else op.fine(V, P.m)
         err = np.linalg.norm(g - ref, axis=0) / np.linalg.norm(ref, axis=0)
         print("smooth-mode error", err, flush=True)
         assert err.max() <= (1e-6 if not adjoint else 3e-6), err
+    F.close()
+
+
+def test_fp32_smooth_mode_narrow(ctx, ora):
+    """The same smooth modes through the vector-ALU sweep of narrow panels
+    (two columns, FP32 products and sums): 32 steps of the 255^2 operator
+    forward, against the oracle, within the FP32 target."""
+    from paper_2508_08873_amd import lrpr
+    P = inputs.dar255()
+    F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=lrpr.STORE_F64 | lrpr.STORE_F32)
+    x = np.arange(1, P.nx + 1) / (P.nx + 1)
+    Xg, Yg = np.meshgrid(x, x, indexing="xy")
+    V = np.stack([(np.sin(np.pi * Xg) * np.sin(np.pi * Yg)).reshape(-1),
+                  (np.sin(2 * np.pi * Xg) * np.sin(np.pi * Yg)).reshape(-1)], axis=1)
+    V = V.astype(np.float32).astype(np.float64)
+    Xd = _dev(V, torch.float32)
+    ctx.fine_step_batched([{"F": F, "X": Xd}], P.m, 1)
+    g = Xd.double().cpu().numpy()
+    ref = _oracle_op(ora, P).fine(V, P.m)
+    err = np.linalg.norm(g - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    print("narrow smooth-mode error", err, flush=True)
+    assert err.max() <= 5e-6, err
     F.close()
 
 

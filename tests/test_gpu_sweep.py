@@ -197,3 +197,42 @@ def test_partitioned_equals_plain(ctx):
     ctx.fine_step_batched([{"F": Fs, "X": Xs}], P.m, 0)
     torch.cuda.synchronize()
     assert _colerr(Xs.cpu().numpy(), Xp.cpu().numpy()) <= 1e-13
+
+
+NARROW = [
+    ("2d_nx31_w1", lambda: inputs.tiny2d(nx=31, m=4), 1),
+    ("2d_nx47_w2", lambda: inputs.tiny2d(nx=47, m=3), 2),
+    ("2d_nx100_w3", lambda: inputs.tiny2d(nx=100, m=2, beta=(-12.0, 25.0)), 3),
+    ("2d_nx255_w4", lambda: inputs.tiny2d(nx=255, m=2, T=1.0 / 64), 4),
+    ("2d_nx130_w1", lambda: inputs.tiny2d(nx=130, m=3, beta=(7.0, -9.0)), 1),
+]
+
+
+@pytest.mark.parametrize("name,mk,w", NARROW, ids=[c[0] for c in NARROW])
+@pytest.mark.parametrize("prec", [0, 1], ids=["f64", "f32"])
+def test_narrow_fine_sweep_parity(ctx, ora, name, mk, w, prec):
+    """Panels of 1 to 4 columns (at most 2 per item in FP64) take the
+    vector-ALU sweep: 2 to 9 band tiles per row, ragged last tile rows, the
+    source with a time factor per column and step."""
+    P = mk()
+    print("narrow case", name, "prec", prec, flush=True)
+    err = _run(ctx, ora, P, w, prec, adjoint=False, with_src=True)
+    assert err <= TOL[prec], err
+
+
+def test_narrow_equals_wide_columns(ctx):
+    """A column's narrow-sweep result does not depend on the other columns
+    of its launch (1 vs 2 vs 4 columns), and agrees with the matrix-core
+    sweep of the same column inside a 16-column panel to 1e-13 (FP64)."""
+    from paper_2508_08873_amd.lrpr import STORE_F64
+    P = inputs.tiny2d(nx=63, m=3)
+    F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=STORE_F64)
+    X0 = np.random.default_rng(8).standard_normal((P.n, 16))
+    outs = {}
+    for w in (1, 2, 16):
+        X = _to_dev(X0[:, :w], 0)
+        ctx.fine_step_batched([{"F": F, "X": X}], P.m, 0)
+        outs[w] = X.cpu().numpy()
+    assert np.array_equal(outs[1][:, 0], outs[2][:, 0])
+    assert np.abs(outs[16][:, 0] - outs[1][:, 0]).max() <= 1e-13 * np.abs(outs[16][:, 0]).max()
+    F.close()
