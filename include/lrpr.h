@@ -115,9 +115,15 @@ lrpr_status lrpr_ctx_release_workspaces(lrpr_ctx ctx);
  *                            lrpr_factor_many holds at once (0 = 96e9);
  *   LRPR_TUNE_PARAREAL_GRAPH 1 (default): a Parareal iteration is captured
  *                            once in a HIP graph and replayed; 0: its
- *                            kernels are launched one by one.
+ *                            kernels are launched one by one;
+ *   LRPR_TUNE_SWEEP_GROUPS   sixteen-column groups that one workgroup of an
+ *                            FP32 sweep (4 < nb <= 32) carries, reading
+ *                            each band tile once for all of them: 0 = the
+ *                            library's choice (the most, up to 3, that
+ *                            still gives every compute unit a workgroup),
+ *                            1..3 = that many.
  * Errors: LRPR_ERR_ARG for an unknown parameter or a value out of range. */
-enum { LRPR_TUNE_LU_WGS = 1, LRPR_TUNE_LU_BUDGET = 2, LRPR_TUNE_PARAREAL_GRAPH = 3 };
+enum { LRPR_TUNE_LU_WGS = 1, LRPR_TUNE_LU_BUDGET = 2, LRPR_TUNE_PARAREAL_GRAPH = 3, LRPR_TUNE_SWEEP_GROUPS = 4 };
 lrpr_status lrpr_tune_set(lrpr_ctx ctx, int param, int64_t value);
 lrpr_status lrpr_tune_get(lrpr_ctx ctx, int param, int64_t *value);
 /* Autotuner of the batched band LU for a later lrpr_factor_many of `count`

@@ -98,7 +98,8 @@ lrpr_status lrpr_ctx_create(int device, void *hip_stream, lrpr_ctx *out) {
     if (!ctx) return LRPR_ERR_NOMEM;
     ctx->dev = device;
     ctx->stream = (hipStream_t)hip_stream;
-    if (hipSetDevice(device) != hipSuccess || lrpr::noalloc_scratch_init(device, nullptr) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess || lrpr::noalloc_scratch_init(device, nullptr) != hipSuccess ||
+        hipDeviceGetAttribute(&ctx->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
         delete ctx;
         return LRPR_ERR_HIP;
     }
@@ -549,6 +550,10 @@ lrpr_status lrpr_tune_set(lrpr_ctx ctx, int param, int64_t value) {
             if (value != 0 && value != 1) return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_set: graph switch is 0 or 1");
             ctx->tune_pr_graph = (int)value;
             return LRPR_OK;
+        case LRPR_TUNE_SWEEP_GROUPS:
+            if (value < 0 || value > 3) return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_set: sweep groups in [0, 3]");
+            ctx->tune_sweep_groups = (int)value;
+            return LRPR_OK;
         default:
             return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_set: unknown parameter");
     }
@@ -560,6 +565,7 @@ lrpr_status lrpr_tune_get(lrpr_ctx ctx, int param, int64_t *value) {
         case LRPR_TUNE_LU_WGS: *value = ctx->tune_lu_wgs; return LRPR_OK;
         case LRPR_TUNE_LU_BUDGET: *value = (int64_t)ctx->tune_lu_budget; return LRPR_OK;
         case LRPR_TUNE_PARAREAL_GRAPH: *value = ctx->tune_pr_graph; return LRPR_OK;
+        case LRPR_TUNE_SWEEP_GROUPS: *value = ctx->tune_sweep_groups; return LRPR_OK;
         default: return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_get: unknown parameter");
     }
 }
@@ -931,6 +937,36 @@ static void xcd_order(std::vector<SweepItem> &items) {
     items.swap(out);
 }
 
+// Merge runs of consecutive 16-column items of one panel (same factor and
+// sources, columns 16 apart, all but the last full) into items of up to ng
+// groups.
+static std::vector<SweepItem> group_items(const std::vector<SweepItem> &items, int ng, size_t esz) {
+    std::vector<SweepItem> out;
+    for (size_t i = 0; i < items.size();) {
+        SweepItem m = items[i];
+        size_t j = i + 1;
+        int groups = 1;
+        while (j < items.size() && groups < ng) {
+            const SweepItem &b = items[j];
+            const bool next = b.fac.a[TS_LB] == m.fac.a[TS_LB] && b.fac.a[TS_UB] == m.fac.a[TS_UB] &&
+                              b.ldx == m.ldx && m.ncols == 16 * groups &&
+                              (const char *)b.X == (const char *)m.X + (size_t)16 * groups * m.ldx * esz &&
+                              b.f == m.f && b.ldf == m.ldf && b.passes == m.passes && b.r0 == m.r0 && b.r1 == m.r1 &&
+                              b.fsteps == m.fsteps && (b.fcol == nullptr) == (m.fcol == nullptr) &&
+                              (!m.fcol || b.fcol == m.fcol + 16 * groups) &&
+                              (b.fscale == nullptr) == (m.fscale == nullptr) &&
+                              (!m.fscale || b.fscale == m.fscale + (size_t)16 * groups * m.fsteps);
+            if (!next) break;
+            m.ncols += b.ncols;
+            ++groups;
+            ++j;
+        }
+        out.push_back(m);
+        i = j;
+    }
+    return out;
+}
+
 // Validate panels and turn them into 16-column work items; launch one sweep
 // of nsteps solve steps.  A column's source factors are fscale[c * fstride +
 // step0 + j], j < nsteps.  record: add a profile record for the launch.
@@ -995,10 +1031,13 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
     // alternating L U / U' L' pairs measured about half the FP32 error of
     // L U steps alone (32 steps on 255^2 grids), so factors that carry the
     // UL set keep the matrix-core pass pairs.
+    // With split_any_width (Parareal) the choice depends on nothing but the
+    // band, so a problem rounds the same whatever else shares the launch.
     const int ncmax = sweep_narrow_cols(f32);
-    bool narrow = !adjoint && !paired && max_nb >= 2 && max_nb <= 64;
+    bool narrow = !adjoint && max_nb >= 2 && max_nb <= 64 && (split_any_width || !paired);
     if (narrow && !split_any_width)
         for (const SweepItem &it : items) narrow = narrow && it.ncols <= ncmax;
+    paired = paired && !narrow;
     int narrow_cols = 0;
     if (narrow) {
         const size_t esz = f32 ? 4 : 8;
@@ -1014,6 +1053,16 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
                 nit.push_back(q);
             }
         items.swap(nit);
+    }
+    // Several 16-column groups of one panel per workgroup: every band tile
+    // read then feeds all of them (the groups' arithmetic is unchanged).
+    int ng = 1;
+    if (!narrow && !paired) {
+        ng = ctx->tune_sweep_groups ? std::min(ctx->tune_sweep_groups, sweep_max_groups(f32, max_nb))
+                                    : sweep_max_groups(f32, max_nb);
+        // by default the most groups that still leave no compute unit idle
+        while (!ctx->tune_sweep_groups && ng > 1 && (int)group_items(items, ng, f32 ? 4 : 8).size() < ctx->ncu) --ng;
+        if (ng > 1) items = group_items(items, ng, f32 ? 4 : 8);
     }
     xcd_order(items);
     const size_t ni = items.size();
@@ -1057,7 +1106,7 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
         };
     } else if (!paired) {
         go = [=](hipStream_t s) {
-            return launch_sweep(adjoint, strided, f32, nii, d_items, nsteps, max_nb, s, step0);
+            return launch_sweep(adjoint, strided, f32, nii, d_items, nsteps, max_nb, s, step0, false, ng);
         };
     } else {
         // even steps (from step0) L U, odd steps U' L'; the second

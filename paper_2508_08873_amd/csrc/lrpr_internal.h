@@ -75,7 +75,7 @@ struct SweepItem {
     FacView fac;
     void *X;               // first column of the group
     int64_t ldx;
-    int ncols;             // 1..16
+    int ncols;             // 1..16 (1..16 ng in a sweep of ng-group items)
     int passes;            // bit 0: first pass (L, or U^T), bit 1: second pass (U, or L^T)
     int r0, r1;            // tile rows [r0, r1) solved; rows outside are not coupled in
     int fsteps;            // length of a column's fscale row
@@ -168,6 +168,8 @@ struct lrpr_ctx_s {
     int tune_lu_wgs = 0;
     size_t tune_lu_budget = 0;   // bytes of FP64 bands and LU scratch per factor_many chunk
     int tune_pr_graph = 1;       // Parareal iterations replayed from a captured HIP graph
+    int tune_sweep_groups = 0;   // 16-column groups per sweep workgroup (0 = by occupancy)
+    int ncu = 256;               // compute units of the device
 };
 
 namespace lrpr {
@@ -242,9 +244,11 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
                              const TileSet *t32, double *scratch, hipStream_t s);
 // adjoint sweeps read the mirrored set unless `strided` (then the forward
 // tiles are read transposed); `local`: forward block solves of a partitioned
-// pass (same code, launched as k_sweep_local)
+// pass (same code, launched as k_sweep_local); ng: 16-column groups per item
+// (1 .. sweep_max_groups; items then hold up to 16 ng columns)
 hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const SweepItem *d_items, int nsteps,
-                        int max_nb, hipStream_t s, int step0 = 0, bool local = false);
+                        int max_nb, hipStream_t s, int step0 = 0, bool local = false, int ng = 1);
+int sweep_max_groups(bool f32, int max_nb);
 // One pass pair over full-range items whose factors all carry the UL set
 // (mirrored too for the adjoint) and have nb band tiles per row, with
 // sweep_pairable(nb).  Descending (asc false): the second substitution of an

@@ -51,6 +51,12 @@ template <int C1, int C2, int C3, int C4, int C5>
 struct Split {
     static constexpr int c1 = C1, c2 = C2, c3 = C3, c4 = C4, c5 = C5;
     static constexpr int cmax = max5(C1, C2, C3, C4, C5);
+    __host__ __device__ static constexpr int cn(int wb) {
+        return wb == 0 ? C1 : wb == 1 ? C2 : wb == 2 ? C3 : wb == 3 ? C4 : C5;
+    }
+    __host__ __device__ static constexpr int st(int wb) {
+        return (wb > 0 ? C1 : 0) + (wb > 1 ? C2 : 0) + (wb > 2 ? C3 : 0) + (wb > 3 ? C4 : 0);
+    }
 };
 
 // One pass (ascending or descending tile rows) over one 16-column group.
@@ -160,16 +166,22 @@ struct Pass {
             if (t < cn) {
                 int j, J;
                 bulk(q, st + t, j, J);
-                const T *rj = ring + slot_of(sI, j) * TILE_ELEMS;
+                T bv[4];
+                ring_ld(ring + slot_of(sI, j) * TILE_ELEMS, bv);
 #pragma unroll
-                for (int kc = 0; kc < 4; ++kc)
-                    acc[t % NA] = Mf<T>::mma(ab[t][kc], rj[64 * kc + lane], acc[t % NA]);
+                for (int kc = 0; kc < 4; ++kc) acc[t % NA] = Mf<T>::mma(ab[t][kc], bv[kc], acc[t % NA]);
             }
         }
 #pragma unroll
         for (int a = 1; a < NA; ++a) acc[0] += acc[a];
         return acc[0];
     }
+    // ring tiles keep a lane's four values together (one wide LDS access)
+    __device__ __forceinline__ void ring_ld(const T *tile, T (&v)[4]) const {
+        const v4 x = *(const v4 *)(tile + 4 * lane);
+        v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+    }
+    __device__ __forceinline__ void ring_st(T *tile, const v4 &v) const { *(v4 *)(tile + 4 * lane) = v; }
     __device__ __forceinline__ int next_slot(int sI) const {
         return ASC ? (sI + 1 == RS ? 0 : sI + 1) : (sI == 0 ? RS - 1 : sI - 1);
     }
@@ -196,47 +208,140 @@ struct Pass {
     }
 };
 
-template <typename T, int KW, typename SP, int PD, bool ASC, bool STRIDED>
+// Bulk wave WB of a sweep: tiles [ST, ST+CN) of row q between barriers q
+// and q+1, operands prefetched PD-1 rows ahead.  Products accumulate in two
+// chains per group (even and odd tiles), as in Pass::bulk_mma.
+template <typename T, typename PS, typename SP, int PD, int NG, int WB>
+__device__ __forceinline__ void sweep_bulk(const PS &P, int NTp, T *red, int grs) {
+    typedef typename Mf<T>::v4 v4;
+    constexpr int CN = SP::cn(WB), ST = SP::st(WB), NBW = PS::NBW;
+    constexpr int NA = SP::cmax < 2 ? SP::cmax : 2;
+    const int lane = P.lane;
+    if constexpr (CN == 0) {
+        lds_barrier();
+        for (int q = 0; q < NTp; ++q) {
+            T *rd = red + ((q & 1) * NBW + WB) * NG * TILE_ELEMS;
+#pragma unroll
+            for (int k = 0; k < NG; ++k)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) rd[k * TILE_ELEMS + i * 64 + lane] = (T)0;
+            lds_barrier();
+        }
+        __syncthreads();
+        return;
+    } else {
+        T abuf[PD][CN][4];
+#pragma unroll
+        for (int u = 0; u < PD - 1; ++u) P.template load_bulk<CN>(u, ST, CN, abuf[u]);
+        lds_barrier();
+        int sI = P.row_of(0) % P.RS;
+        for (int q0 = 0; q0 < NTp; q0 += PD) {
+#pragma unroll
+            for (int u = 0; u < PD; ++u) {
+                const int q = q0 + u;
+                const int un = (u + PD - 1) % PD;
+                P.template load_bulk<CN>(q + PD - 1, ST, CN, abuf[un]);
+                __builtin_amdgcn_sched_barrier(0);
+                // ring operands of tile t+1 are read while tile t's products run
+                auto ring_read = [&](int t, T (&bv)[NG][4]) {
+                    int j, J;
+                    P.bulk(q, ST + t, j, J);
+                    const T *rj = P.ring + P.slot_of(sI, j) * TILE_ELEMS;
+#pragma unroll
+                    for (int k = 0; k < NG; ++k) P.ring_ld(rj + k * grs, bv[k]);
+                };
+                v4 acc[NA][NG];
+#pragma unroll
+                for (int a = 0; a < NA; ++a)
+#pragma unroll
+                    for (int k = 0; k < NG; ++k) acc[a][k] = v4{0, 0, 0, 0};
+                T bv[2][NG][4];
+                ring_read(0, bv[0]);
+#pragma unroll
+                for (int t = 0; t < CN; ++t) {
+                    if (t + 1 < CN) ring_read(t + 1, bv[(t + 1) & 1]);
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+                        for (int k = 0; k < NG; ++k)
+                            acc[t % NA][k] = Mf<T>::mma(abuf[u][t][kc], bv[t & 1][k][kc], acc[t % NA][k]);
+                }
+                T *rd = red + ((q & 1) * NBW + WB) * NG * TILE_ELEMS;
+#pragma unroll
+                for (int k = 0; k < NG; ++k) {
+                    v4 r = acc[0][k];
+#pragma unroll
+                    for (int a = 1; a < NA; ++a) r += acc[a][k];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) rd[k * TILE_ELEMS + i * 64 + lane] = r[i];
+                }
+                sI = P.next_slot(sI);
+                lds_barrier();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One pass over NG 16-column groups of one item (columns 16 i .. 16 i + 15
+// of the item in group i).  Every band tile loaded by a bulk wave multiplies
+// the solved tiles of all NG groups, so the factor streams from HBM once per
+// NG groups; the finisher runs NG independent chains.  LDS: ring [NG][nb+2],
+// partial sums [2][bulk waves][NG], hand-off [2][1 + NG] (E, then r of each
+// group), all in tiles.
+template <typename T, int KW, typename SP, int PD, bool ASC, bool STRIDED, int NG>
 __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restrict__ band,
                                            const T *__restrict__ dtile, T *ring, T *red, T *hand, bool with_src,
                                            int step, int nsteps) {
+    static_assert(KW > 1 || NG == 1, "the single-wave sweep handles one column group");
     typedef typename Mf<T>::v4 v4;
     typedef Pass<T, KW, PD, ASC, STRIDED> PS;
     constexpr int TPW = SP::cmax;
     constexpr bool LEFT = !STRIDED;   // left form: r = D (x + dt phi f); right form: y = D v
+    constexpr int HS = (1 + NG) * TILE_ELEMS;   // one hand-off buffer
     PS P(it, band, dtile, ring);
     const int NT = P.NT, lane = P.lane, g = P.g, c = P.c, n = P.n;
     const int NTp = (NT + PD - 1) / PD * PD;   // rows beyond NT are zero work
+    const int grs = (P.nb + 2) * TILE_ELEMS;    // ring stride between groups
     T *X = (T *)it.X;
     const int64_t ldx = it.ldx;
-    const bool colok = c < it.ncols;
-    const int col = colok ? c : 0;
-    // source of this lane's column: f(x) * dt * phi(t_step), or the zero tile
-    const T *fsrc = P.zt;
-    int64_t fstride = 0;
-    T fs = 0;
-    if (with_src && colok) {
-        const int fc = it.fcol ? gld(it.fcol + c) : 0;
-        if (fc >= 0) {
-            fsrc = (const T *)it.f + (int64_t)fc * it.ldf;
-            fstride = 1;
-            const double sc = it.fscale ? gld(it.fscale + (int64_t)c * it.fsteps + step) : 1.0;
-            fs = (T)(it.fac.dt * sc);
+    bool colok[NG];
+    int col[NG];
+    // source of this lane's columns: f(x) * dt * phi(t_step), or the zero tile
+    const T *fsrc[NG];
+    int64_t fstride[NG];
+    T fs[NG];
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+        const int cc = 16 * i + c;
+        colok[i] = cc < it.ncols;
+        col[i] = colok[i] ? cc : 0;
+        fsrc[i] = P.zt;
+        fstride[i] = 0;
+        fs[i] = 0;
+        if (with_src && colok[i]) {
+            const int fc = it.fcol ? gld(it.fcol + cc) : 0;
+            if (fc >= 0) {
+                fsrc[i] = (const T *)it.f + (int64_t)fc * it.ldf;
+                fstride[i] = 1;
+                const double sc = it.fscale ? gld(it.fscale + (int64_t)cc * it.fsteps + step) : 1.0;
+                fs[i] = (T)(it.fac.dt * sc);
+            }
         }
     }
     T *sink = (T *)it.fac.sink;
     const int w = P.w;
-    // pass output of tile row q (accumulator order) to X
-    auto store_out = [&](const v4 &y, int q) {
+    // pass output of tile row q (accumulator order) of group i to X
+    auto store_out = [&](const v4 &y, int q, int i) {
         const int Irow = P.row_of(q);
-        const bool ok = q < NT;
+        const bool ok = q < NT && colok[i];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = Irow * TILE + Mf<T>::row(g, i);
-            gst((ok && colok && row < n) ? X + row + (int64_t)c * ldx : sink + lane, y[i]);
+        for (int e = 0; e < 4; ++e) {
+            const int row = Irow * TILE + Mf<T>::row(g, e);
+            gst((ok && row < n) ? X + row + (int64_t)col[i] * ldx : sink + lane, y[e]);
         }
     };
-    if (KW == 1) {
+    if constexpr (KW == 1) {
         // ---- single wave: everything, prefetching PD-1 rows ahead
         T abuf[PD][TPW][4];
         T ebuf[PD][4], dbuf[PD][4], xbuf[PD][4], fbuf[PD][4];
@@ -245,7 +350,7 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
             P.template load_bulk<TPW>(u, 0, TPW, abuf[u]);
             P.load_newest(u + 1, ebuf[u]);
             P.load_d(u, dbuf[u]);
-            P.load_state(u, X, ldx, col, fsrc, fstride, xbuf[u], fbuf[u]);
+            P.load_state(u, X, ldx, col[0], fsrc[0], fstride[0], xbuf[u], fbuf[u]);
         }
         v4 t = {0, 0, 0, 0};
         int sI = P.row_of(0) % P.RS;
@@ -257,77 +362,63 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
                 P.template load_bulk<TPW>(q + PD - 1, 0, TPW, abuf[un]);
                 P.load_newest(q + PD, ebuf[un]);
                 P.load_d(q + PD - 1, dbuf[un]);
-                P.load_state(q + PD - 1, X, ldx, col, fsrc, fstride, xbuf[un], fbuf[un]);
+                P.load_state(q + PD - 1, X, ldx, col[0], fsrc[0], fstride[0], xbuf[un], fbuf[un]);
                 __builtin_amdgcn_sched_barrier(0);
                 const v4 a = P.template bulk_mma<TPW>(q, sI, 0, TPW, abuf[u]);
                 v4 r;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) r[i] = xbuf[u][i] + fs * fbuf[u][i];
+                for (int i = 0; i < 4; ++i) r[i] = xbuf[u][i] + fs[0] * fbuf[u][i];
                 if (LEFT) r = P.dmul(dbuf[u], r);
                 v4 v;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) v[i] = r[i] - (a[i] + t[i]);
-                T *ri = ring + (q < NT ? sI : P.RS) * TILE_ELEMS;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) ri[i * 64 + lane] = v[i];
+                P.ring_st(ring + (q < NT ? sI : P.RS) * TILE_ELEMS, v);
                 t = P.dmul(ebuf[u], v);
-                store_out(LEFT ? v : P.dmul(dbuf[u], v), q);
+                store_out(LEFT ? v : P.dmul(dbuf[u], v), q, 0);
                 sI = P.next_slot(sI);
                 lds_barrier();
             }
         }
     } else if (w == 0) {
         // ---- finisher: row q after barrier q+1
-        v4 t = {0, 0, 0, 0};
+        v4 t[NG];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) t[k] = v4{0, 0, 0, 0};
         int sI = P.row_of(0) % P.RS;
         lds_barrier();
         for (int q = 0; q < NTp; ++q) {
             lds_barrier();
-            const T *h = hand + (q & 1) * 2 * TILE_ELEMS;
+            const T *h = hand + (q & 1) * HS;
             T ecur[4];
-            v4 v;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                T a = t[i];
+            for (int i = 0; i < 4; ++i) ecur[i] = h[i * 64 + lane];
+            const int so = (q < NT ? sI : P.RS) * TILE_ELEMS;
 #pragma unroll
-                for (int ww = 0; ww < PS::NBW; ++ww) a += red[((q & 1) * PS::NBW + ww) * TILE_ELEMS + i * 64 + lane];
-                v[i] = h[TILE_ELEMS + i * 64 + lane] - a;
-                ecur[i] = h[i * 64 + lane];
+            for (int k = 0; k < NG; ++k) {
+                v4 v;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    T a = t[k][i];
+#pragma unroll
+                    for (int ww = 0; ww < PS::NBW; ++ww)
+                        a += red[(((q & 1) * PS::NBW + ww) * NG + k) * TILE_ELEMS + i * 64 + lane];
+                    v[i] = h[(1 + k) * TILE_ELEMS + i * 64 + lane] - a;
+                }
+                P.ring_st(ring + k * grs + so, v);
+                t[k] = P.dmul(ecur, v);
             }
-            T *ri = ring + (q < NT ? sI : P.RS) * TILE_ELEMS;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ri[i * 64 + lane] = v[i];
-            t = P.dmul(ecur, v);
             sI = P.next_slot(sI);
         }
         __syncthreads();
     } else if (w <= PS::NBW) {
-        // ---- bulk waves: tiles [st, st+cn) of row q between barriers q and
-        //      q+1, operands prefetched PD-1 rows ahead
-        const int wb = w - 1;
-        const int cn = wb == 0 ? SP::c1 : wb == 1 ? SP::c2 : wb == 2 ? SP::c3 : wb == 3 ? SP::c4 : SP::c5;
-        const int st = wb == 0 ? 0 : wb == 1 ? SP::c1 : wb == 2 ? SP::c1 + SP::c2
-                     : wb == 3 ? SP::c1 + SP::c2 + SP::c3 : SP::c1 + SP::c2 + SP::c3 + SP::c4;
-        T abuf[PD][TPW][4];
-#pragma unroll
-        for (int u = 0; u < PD - 1; ++u) P.template load_bulk<TPW>(u, st, cn, abuf[u]);
-        lds_barrier();
-        int sI = P.row_of(0) % P.RS;
-        for (int q0 = 0; q0 < NTp; q0 += PD) {
-#pragma unroll
-            for (int u = 0; u < PD; ++u) {
-                const int q = q0 + u;
-                const int un = (u + PD - 1) % PD;
-                P.template load_bulk<TPW>(q + PD - 1, st, cn, abuf[un]);
-                __builtin_amdgcn_sched_barrier(0);
-                const v4 acc = P.template bulk_mma<TPW>(q, sI, st, cn, abuf[u]);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) red[((q & 1) * PS::NBW + wb) * TILE_ELEMS + i * 64 + lane] = acc[i];
-                sI = P.next_slot(sI);
-                lds_barrier();
-            }
+        // ---- bulk waves (compile-time share of each wave)
+        switch (w) {
+            case 1: sweep_bulk<T, PS, SP, PD, NG, 0>(P, NTp, red, grs); break;
+            case 2: sweep_bulk<T, PS, SP, PD, NG, 1>(P, NTp, red, grs); break;
+            case 3: sweep_bulk<T, PS, SP, PD, NG, 2>(P, NTp, red, grs); break;
+            case 4: sweep_bulk<T, PS, SP, PD, NG, 3>(P, NTp, red, grs); break;
+            default: sweep_bulk<T, PS, SP, PD, NG, 4>(P, NTp, red, grs); break;
         }
-        __syncthreads();
     } else {
         // ---- helpers: between barriers q and q+1 they hand over row q's r and
         //      row q+1's newest tile; the factor helper also writes the output
@@ -337,6 +428,17 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
 #endif
         constexpr int PDH = LRPR_PDH;   // helpers' prefetch depth
         const int NTh = (NTp + PDH - 1) / PDH * PDH;
+        // output of ring slot so (tile row qo) of every group; D of the row
+        // in the right form
+        auto write_rows = [&](int so, int qo, const T (&d)[4]) {
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+                T x[4];
+                P.ring_ld(ring + k * grs + so * TILE_ELEMS, x);
+                const v4 v = {x[0], x[1], x[2], x[3]};
+                store_out(LEFT ? v : P.dmul(d, v), qo, k);
+            }
+        };
         if (w == PS::NBW + 1) {
             // b0: newest tile of row q+1, b1: D of row q-2 (right form)
             T b0[PDH][4], b1[PDH][4];
@@ -356,15 +458,11 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
                     if (!LEFT) P.load_d(q + PDH - 3, b1[un]);
                     __builtin_amdgcn_sched_barrier(0);
                     if (q < NTp) {
-                        T *h = hand + (q & 1) * 2 * TILE_ELEMS;
+                        T *h = hand + (q & 1) * HS;
 #pragma unroll
                         for (int i = 0; i < 4; ++i) h[i * 64 + lane] = b0[u][i];
                         if (q >= 2) {
-                            const T *ro = ring + so * TILE_ELEMS;
-                            v4 v;
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) v[i] = ro[i * 64 + lane];
-                            store_out(LEFT ? v : P.dmul(b1[u], v), q - 2);
+                            write_rows(so, q - 2, b1[u]);
                             so = P.next_slot(so);
                         }
                         lds_barrier();
@@ -376,29 +474,23 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
             {
                 T d2[4];
                 if (!LEFT) P.load_d(NTp - 2, d2);
-                const T *ro = ring + so * TILE_ELEMS;
-                v4 v;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = ro[i * 64 + lane];
-                store_out(LEFT ? v : P.dmul(d2, v), NTp - 2);
+                write_rows(so, NTp - 2, d2);
                 so = P.next_slot(so);
             }
             __syncthreads();
             {
                 T d1[4];
                 if (!LEFT) P.load_d(NTp - 1, d1);
-                const T *ro = ring + so * TILE_ELEMS;
-                v4 v;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = ro[i * 64 + lane];
-                store_out(LEFT ? v : P.dmul(d1, v), NTp - 1);
+                write_rows(so, NTp - 1, d1);
             }
         } else {
-            // state helper: b0 x, b1 f, b2 D of row q
-            T b0[PDH][4], b1[PDH][4], b2[PDH][4];
+            // state helper: b0 x, b1 f (per group), b2 D of row q
+            T b0[PDH][NG][4], b1[PDH][NG][4], b2[PDH][4];
 #pragma unroll
             for (int u = 0; u < PDH - 1; ++u) {
-                P.load_state(u, X, ldx, col, fsrc, fstride, b0[u], b1[u]);
+#pragma unroll
+                for (int k = 0; k < NG; ++k)
+                    P.load_state(u, X, ldx, col[k], fsrc[k], fstride[k], b0[u][k], b1[u][k]);
                 if (LEFT) P.load_d(u, b2[u]);
             }
             lds_barrier();
@@ -407,17 +499,22 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
                 for (int u = 0; u < PDH; ++u) {
                     const int q = q0 + u;
                     const int un = (u + PDH - 1) % PDH;
-                    P.load_state(q + PDH - 1, X, ldx, col, fsrc, fstride, b0[un], b1[un]);
+#pragma unroll
+                    for (int k = 0; k < NG; ++k)
+                        P.load_state(q + PDH - 1, X, ldx, col[k], fsrc[k], fstride[k], b0[un][k], b1[un][k]);
                     if (LEFT) P.load_d(q + PDH - 1, b2[un]);
                     __builtin_amdgcn_sched_barrier(0);
                     if (q < NTp) {
-                        v4 r;
+                        T *h = hand + (q & 1) * HS + TILE_ELEMS;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) r[i] = b0[u][i] + fs * b1[u][i];
-                        if (LEFT) r = P.dmul(b2[u], r);
-                        T *h = hand + (q & 1) * 2 * TILE_ELEMS + TILE_ELEMS;
+                        for (int k = 0; k < NG; ++k) {
+                            v4 r;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) h[i * 64 + lane] = r[i];
+                            for (int i = 0; i < 4; ++i) r[i] = b0[u][k][i] + fs[k] * b1[u][k][i];
+                            if (LEFT) r = P.dmul(b2[u], r);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) h[k * TILE_ELEMS + i * 64 + lane] = r[i];
+                        }
                         lds_barrier();
                     }
                 }
@@ -429,53 +526,61 @@ __device__ __forceinline__ void sweep_pass(const SweepItem &it, const T *__restr
     __syncthreads();
 }
 
-// Zero the LDS ring before a pass: it must hold finite values only (zero
+// Zero the LDS rings before a pass: they must hold finite values only (zero
 // tiles multiply stale slots), and rows before the item's range must read as
 // zero (they are not coupled in).
 template <typename T>
-__device__ __forceinline__ void clear_ring(T *ring, int nb) {
-    for (int e = threadIdx.x; e < (nb + 2) * TILE_ELEMS; e += blockDim.x) ring[e] = (T)0;
+__device__ __forceinline__ void clear_ring(T *ring, int tiles) {
+    for (int e = threadIdx.x; e < tiles * TILE_ELEMS; e += blockDim.x) ring[e] = (T)0;
     __syncthreads();
+}
+
+// LDS tiles of a sweep workgroup: NG rings of nb+1 solved tiles (+1 dummy
+// slot), double-buffered partial sums of the bulk waves, double-buffered
+// hand-offs (E and one r per group)
+__host__ __device__ constexpr int sweep_lds_tiles(int nb, int kw, int ng) {
+    return ng * (nb + 2) + 2 * (kw > 1 ? kw - 3 : 1) * ng + 2 * (1 + ng);
 }
 
 // ADJ: adjoint sweep, on the mirrored set or (STRIDED) the transposed
 // forward tiles.  Steps step0 .. step0+nsteps-1 (the step picks the source's
 // time factor); each item runs the passes its mask selects.
-template <typename T, int KW, typename SP, int PD, bool ADJ, bool STRIDED>
+template <typename T, int KW, typename SP, int PD, bool ADJ, bool STRIDED, int NG>
 __device__ __forceinline__ void sweep_items(const SweepItem *__restrict__ items, int nitems, int nsteps,
                                             int step0) {
     extern __shared__ __align__(16) unsigned char smem[];
     for (int idx = blockIdx.x; idx < nitems; idx += gridDim.x) {
         const SweepItem it = items[idx];
+        const int nrt = NG * (it.fac.nb + 2);
         T *ring = (T *)smem;
-        T *red = ring + (it.fac.nb + 2) * TILE_ELEMS;              // [2][KW-3][256]
-        T *hand = red + 2 * (KW > 1 ? KW - 3 : 1) * TILE_ELEMS;     // [2][2][256]: E, r
+        T *red = ring + nrt * TILE_ELEMS;                                // [2][KW-3][NG][256]
+        T *hand = red + 2 * (KW > 1 ? KW - 3 : 1) * NG * TILE_ELEMS;     // [2][1+NG][256]: E, r
         const void *const *a = it.fac.a;
         for (int s = 0; s < nsteps; ++s) {
             const int step = step0 + s;
             if (it.passes & 1) {
-                clear_ring(ring, it.fac.nb);
+                clear_ring(ring, nrt);
                 if (!ADJ)
-                    sweep_pass<T, KW, SP, PD, true, false>(it, (const T *)a[TS_LB], (const T *)a[TS_DL], ring, red,
-                                                           hand, it.f != nullptr, step, nsteps);
+                    sweep_pass<T, KW, SP, PD, true, false, NG>(it, (const T *)a[TS_LB], (const T *)a[TS_DL], ring,
+                                                               red, hand, it.f != nullptr, step, nsteps);
                 else if (!STRIDED)
-                    sweep_pass<T, KW, SP, PD, true, false>(it, (const T *)a[TS_UTB], (const T *)a[TS_DUT], ring, red,
-                                                           hand, false, step, nsteps);
+                    sweep_pass<T, KW, SP, PD, true, false, NG>(it, (const T *)a[TS_UTB], (const T *)a[TS_DUT], ring,
+                                                               red, hand, false, step, nsteps);
                 else
-                    sweep_pass<T, KW, SP, PD, true, true>(it, (const T *)a[TS_UB], (const T *)a[TS_DUT], ring, red,
-                                                          hand, false, step, nsteps);
+                    sweep_pass<T, KW, SP, PD, true, true, NG>(it, (const T *)a[TS_UB], (const T *)a[TS_DUT], ring,
+                                                              red, hand, false, step, nsteps);
             }
             if (it.passes & 2) {
-                clear_ring(ring, it.fac.nb);
+                clear_ring(ring, nrt);
                 if (!ADJ)
-                    sweep_pass<T, KW, SP, PD, false, false>(it, (const T *)a[TS_UB], (const T *)a[TS_DU], ring, red,
-                                                            hand, false, step, nsteps);
+                    sweep_pass<T, KW, SP, PD, false, false, NG>(it, (const T *)a[TS_UB], (const T *)a[TS_DU], ring,
+                                                                red, hand, false, step, nsteps);
                 else if (!STRIDED)
-                    sweep_pass<T, KW, SP, PD, false, false>(it, (const T *)a[TS_LTB], (const T *)a[TS_DLT], ring, red,
-                                                            hand, false, step, nsteps);
+                    sweep_pass<T, KW, SP, PD, false, false, NG>(it, (const T *)a[TS_LTB], (const T *)a[TS_DLT], ring,
+                                                                red, hand, false, step, nsteps);
                 else
-                    sweep_pass<T, KW, SP, PD, false, true>(it, (const T *)a[TS_LB], (const T *)a[TS_DLT], ring, red,
-                                                           hand, false, step, nsteps);
+                    sweep_pass<T, KW, SP, PD, false, true, NG>(it, (const T *)a[TS_LB], (const T *)a[TS_DLT], ring,
+                                                               red, hand, false, step, nsteps);
             }
         }
     }
@@ -940,15 +1045,15 @@ __global__ __launch_bounds__(512, sizeof(T) == 4 ? LRPR_PAIR_WG32 : 1) void k_sw
             bB = ASC ? a[TS_UTB] : ar[TS_LTB];
             dB = ASC ? a[TS_DUT] : ar[TS_DLT];
         }
-        clear_ring(ringA, 2 * NB + 2);   // both rings
+        clear_ring(ringA, 2 * NB + 4);   // both rings
         sweep_pair<T, NB, SP, PD, ASC>(it, bA, dA, bB, dB, ringA, ringB, red, hand, !ADJ && it.f != nullptr, stepB);
     }
 }
 
-template <typename T, int KW, typename SP, int PD, bool ADJ, bool STRIDED>
+template <typename T, int KW, typename SP, int PD, bool ADJ, bool STRIDED, int NG>
 __global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__ items, int nitems, int nsteps,
                                                    int step0) {
-    sweep_items<T, KW, SP, PD, ADJ, STRIDED>(items, nitems, nsteps, step0);
+    sweep_items<T, KW, SP, PD, ADJ, STRIDED, NG>(items, nitems, nsteps, step0);
 }
 
 // The local block solves of partitioned passes (forward items on row ranges):
@@ -957,27 +1062,27 @@ __global__ __launch_bounds__(64 * KW) void k_sweep(const SweepItem *__restrict__
 template <typename T, int KW, typename SP, int PD>
 __global__ __launch_bounds__(64 * KW) void k_sweep_local(const SweepItem *__restrict__ items, int nitems,
                                                          int nsteps, int step0) {
-    sweep_items<T, KW, SP, PD, false, false>(items, nitems, nsteps, step0);
+    sweep_items<T, KW, SP, PD, false, false, 1>(items, nitems, nsteps, step0);
 }
 
-template <typename T, int KW, typename SP, int PD>
+template <typename T, int KW, typename SP, int PD, int NG = 1>
 static hipError_t launch_t(bool adjoint, bool strided, int nitems, const SweepItem *d_items, int nsteps,
                            int max_nb, hipStream_t s, int step0, bool local) {
-    // LDS: ring of nb+1 solved tiles (+1 dummy slot), double-buffered partial
-    // sums of the bulk waves, double-buffered hand-off (E, r)
-    const size_t lds = (size_t)(max_nb + 2 + 2 * (KW > 1 ? KW - 3 : 1) + 4) * TILE_ELEMS * sizeof(T);
+    const size_t lds = (size_t)sweep_lds_tiles(max_nb, KW, NG) * TILE_ELEMS * sizeof(T);
     const int grid = nitems < 65536 ? nitems : 65536;
-    if (local)
+    if (local && NG == 1)
         hipLaunchKernelGGL((k_sweep_local<T, KW, SP, PD>), dim3(grid), dim3(64 * KW), lds, s, d_items, nitems,
                            nsteps, step0);
+    else if (local)
+        return hipErrorInvalidValue;
     else if (!adjoint)
-        hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, false, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
+        hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, false, false, NG>), dim3(grid), dim3(64 * KW), lds, s, d_items,
                            nitems, nsteps, step0);
     else if (!strided)
-        hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, true, false>), dim3(grid), dim3(64 * KW), lds, s, d_items,
+        hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, true, false, NG>), dim3(grid), dim3(64 * KW), lds, s, d_items,
                            nitems, nsteps, step0);
     else
-        hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, true, true>), dim3(grid), dim3(64 * KW), lds, s, d_items,
+        hipLaunchKernelGGL((k_sweep<T, KW, SP, PD, true, true, NG>), dim3(grid), dim3(64 * KW), lds, s, d_items,
                            nitems, nsteps, step0);
     return hipGetLastError();
 }
@@ -1058,17 +1163,57 @@ static hipError_t launch_prec(bool adjoint, bool strided, int nitems, const Swee
             return launch_t<T, 8, Split<LRPR_SPLIT16_F32>, LRPR_PD16_F32>(adjoint, strided, nitems, d_items, nsteps,
                                                                           max_nb, s, step0, local);
     }
-    if (max_nb <= 32)
-        return launch_t<T, 8, Split<6, 7, 6, 6, 6>, F64 ? 2 : 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, local);
+    if (max_nb <= 32) {
+        // FP32: the shares of the multi-group sweeps (the same arithmetic
+        // for every group count)
+        if constexpr (F64)
+            return launch_t<T, 8, Split<6, 7, 6, 6, 6>, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb, s,
+                                                           step0, local);
+        else
+            return launch_t<T, 8, Split<4, 8, 8, 7, 4>, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s,
+                                                           step0, local);
+    }
     if (max_nb <= 64)
         return launch_t<T, 8, Split<13, 13, 13, 13, 11>, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, local);
     return hipErrorInvalidValue;
 }
 
+// Column groups per item (FP32, 4 < nb <= 32): one band tile feeds the
+// matrix-core products of NG groups, with the bulk shares of the one-group
+// sweep of the same band class (so the same arithmetic per column).  For
+// nb <= 32 those shares favour the SIMDs that run no finisher or helper
+// wave besides their bulk waves (waves 1 and 5 share SIMD 1).
+int sweep_max_groups(bool f32, int max_nb) { return (f32 && max_nb > 4 && max_nb <= 32) ? 3 : 1; }
+
+static hipError_t launch_groups_f32(bool adjoint, bool strided, int nitems, const SweepItem *d_items, int nsteps,
+                                   int max_nb, hipStream_t s, int step0, int ng) {
+    if (max_nb <= 8) {
+        if (ng == 2)
+            return launch_t<float, 8, Split<1, 2, 2, 1, 1>, 4, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb,
+                                                                  s, step0, false);
+        return launch_t<float, 8, Split<1, 2, 2, 1, 1>, 4, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s,
+                                                              step0, false);
+    }
+    if (max_nb <= 16) {
+        if (ng == 2)
+            return launch_t<float, 8, Split<LRPR_SPLIT16_F32>, 3, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb,
+                                                                  s, step0, false);
+        return launch_t<float, 8, Split<LRPR_SPLIT16_F32>, 3, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s,
+                                                              step0, false);
+    }
+    if (ng == 2)
+        return launch_t<float, 8, Split<4, 8, 8, 7, 4>, 3, 2>(adjoint, strided, nitems, d_items, nsteps, max_nb, s,
+                                                              step0, false);
+    return launch_t<float, 8, Split<4, 8, 8, 7, 4>, 3, 3>(adjoint, strided, nitems, d_items, nsteps, max_nb, s,
+                                                          step0, false);
+}
+
 hipError_t launch_sweep(bool adjoint, bool strided, bool f32, int nitems, const SweepItem *d_items, int nsteps,
-                        int max_nb, hipStream_t s, int step0, bool local) {
+                        int max_nb, hipStream_t s, int step0, bool local, int ng) {
     if (nitems <= 0 || nsteps <= 0) return hipSuccess;
     if (local && adjoint) return hipErrorInvalidValue;
+    if (ng < 1 || ng > sweep_max_groups(f32, max_nb) || (local && ng > 1)) return hipErrorInvalidValue;
+    if (ng > 1) return launch_groups_f32(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, ng);
     if (f32) return launch_prec<float>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, local);
     return launch_prec<double>(adjoint, strided, nitems, d_items, nsteps, max_nb, s, step0, local);
 }

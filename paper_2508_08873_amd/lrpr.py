@@ -32,7 +32,7 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
 
 
 # lrpr_tune_set parameters
-TUNE_LU_WGS, TUNE_LU_BUDGET, TUNE_PARAREAL_GRAPH = 1, 2, 3
+TUNE_LU_WGS, TUNE_LU_BUDGET, TUNE_PARAREAL_GRAPH, TUNE_SWEEP_GROUPS = 1, 2, 3, 4
 # lrpr_factor store_mask bits (include/lrpr.h)
 STORE_F64, STORE_F32, STORE_MIRROR, STORE_SPLIT, STORE_UL = 1, 2, 4, 8, 16
 # lrpr_factor_stepper steppers
