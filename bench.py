@@ -802,7 +802,8 @@ def main():
                 "traffic_unit": "HBM bytes per sweep call",
                 "algorithmic_hbm_GBs": rng["bytes"] / sweep_s / 1e9,
                 "hbm_frac": rng["bytes"] / sweep_s / 1e9 / PEAK_HBM_GBS,
-                "traffic_source": tsrc["name"] if tsrc else None}
+                "traffic_source": tsrc["name"] if tsrc else None,
+                "mfma_busy_frac_counters": tsrc.get("mfma_busy_frac") if tsrc else None}
     # the Parareal sweeps: one RHS per factor, the HBM-bound regime
     par = {k: tot("parareal", k) for k in ("ms", "launches", "flops", "bytes", "rhs_steps")}
     par_s = par["ms"] / 1000.0

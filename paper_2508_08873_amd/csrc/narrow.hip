@@ -42,7 +42,7 @@ __device__ __forceinline__ T group_sum(T v) {
 template <typename T, int NC, int TMAX, int PD, bool ASC>
 __device__ __forceinline__ void narrow_pass(const SweepItem &it, const T *__restrict__ band,
                                             const T *__restrict__ dtile, T *ring, T *red, bool with_src, int step) {
-    static_assert(PD % 2 == 0 && PD >= 2, "state slots alternate with the row's parity");
+    static_assert(PD % 2 == 0 && PD >= 2, "even prefetch depth");
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, m = lane & 15;
@@ -151,10 +151,12 @@ __device__ __forceinline__ void narrow_pass(const SweepItem &it, const T *__rest
                 }
             }
         }
-        // tiles PD rows ahead; the state (x, f) and D of wave 1 one row ahead
-        // (PD is even: state slot q % 2)
+        // tiles PD-1 rows ahead; the state (x, f) and D of wave 1 SD-1 rows
+        // ahead (SD divides PD: state slot q % SD)
+        constexpr int SD = PD / 2 < 2 ? 2 : PD / 2;
+        static_assert(PD % SD == 0, "state slots must repeat within the unrolled period");
         T ab[PD][TMAX][4];
-        T db[2][4], xb[2][NC][4], fb[2][NC][4];
+        T db[SD][4], xb[SD][NC][4], fb[SD][NC][4];
         auto ld_tiles = [&](int q, T (&abu)[TMAX][4]) {
             const int I = row_of(q < NT ? q : NT - 1);
 #pragma unroll
@@ -185,13 +187,14 @@ __device__ __forceinline__ void narrow_pass(const SweepItem &it, const T *__rest
         };
 #pragma unroll
         for (int u = 0; u < PD - 1; ++u) ld_tiles(u, ab[u]);
-        ld_state(0, db[0], xb[0], fb[0]);
+#pragma unroll
+        for (int u = 0; u < SD - 1; ++u) ld_state(u, db[u], xb[u], fb[u]);
         for (int q0 = 0; q0 < NT; q0 += PD) {
 #pragma unroll
             for (int u = 0; u < PD; ++u) {
                 const int q = q0 + u;   // row computed in period q
                 ld_tiles(q + PD - 1, ab[(u + PD - 1) % PD]);
-                ld_state(q + 1, db[(u + 1) % 2], xb[(u + 1) % 2], fb[(u + 1) % 2]);
+                ld_state(q + SD - 1, db[(u + SD - 1) % SD], xb[(u + SD - 1) % SD], fb[(u + SD - 1) % SD]);
                 if (q < NT) {
                     T p[NC];
 #pragma unroll
@@ -222,7 +225,7 @@ __device__ __forceinline__ void narrow_pass(const SweepItem &it, const T *__rest
                             T d = 0;
 #pragma unroll
                             for (int kc = 0; kc < 4; ++kc)
-                                d += db[u % 2][kc] * (xb[u % 2][c][kc] + fs[c] * fb[u % 2][c][kc]);
+                                d += db[u % SD][kc] * (xb[u % SD][c][kc] + fs[c] * fb[u % SD][c][kc]);
                             d = group_sum(d);
                             if (lane < 16) rd[(NBULK * 16 + m) * NC + c] = d;
                         }

@@ -1,9 +1,11 @@
-"""Summaries of rocprofv3 output for the range-finder sweeps, written to profiles/.
+"""Summaries of rocprofv3 output for one kernel family (the range-finder sweeps
+by default), written to profiles/.
 
     python -m paper_2508_08873_amd.prof_summary --name NAME --command CMD \\
         --stats DIR/kt_kernel_stats.csv --calls N \\
         [--fetch DIR/..._counter_collection.csv --write DIR/..._counter_collection.csv \\
-         --fetch-calls M --calib-fetch DIR/... --calib-write DIR/... --calib-bytes B] [--bench bench.json]
+         --fetch-calls M --calib-fetch DIR/... --calib-write DIR/... --calib-bytes B]
+        [--mfma DIR/..._counter_collection.csv --mfma-calls M] [--kernel PATTERNS --label TEXT] [--bench bench.json]
 
 A range-finder sweep (one library call: 32 implicit-Euler steps of 3200
 right-hand sides) is one k_sweep launch, or, on factors with the UL set, two
@@ -67,6 +69,10 @@ def main():
                          "k_sweep_local, the partitioned block solves)")
     ap.add_argument("--calls", type=int, required=True, help="sweep calls in the traced command")
     ap.add_argument("--fetch-calls", type=int, default=0, help="sweep calls in each counter command")
+    ap.add_argument("--mfma", help="counter collection of SQ_INSTS_VALU_MFMA_MOPS_F32/_F64, "
+                                   "SQ_VALU_MFMA_BUSY_CYCLES and SQ_BUSY_CU_CYCLES")
+    ap.add_argument("--mfma-calls", type=int, default=0, help="sweep calls in the MFMA counter command")
+    ap.add_argument("--label", default="Range-finder sweeps", help="what the matched kernels are")
     ap.add_argument("--bench")
     args = ap.parse_args()
 
@@ -90,8 +96,9 @@ def main():
     per_call_ms = sum(float(r["TotalDurationNs"]) for r in sweep) / args.calls / 1e6
     out = {"name": args.name, "command": args.command, "kernel": args.kernel, "source_sha1": sweep_source_hash(),
            "sweep_calls": args.calls, "sweep_launches": launches, "sweep_ms_per_call": per_call_ms}
-    lines += ["", "Range-finder sweeps (kernels matching %s, all instantiations): %d launches in %d sweep calls, "
-              "%.3f ms per call." % (", ".join("`%s`" % k for k in pats), launches, args.calls, per_call_ms)]
+    lines += ["", "%s (kernels matching %s, all instantiations): %d launches in %d calls, "
+              "%.3f ms per call." % (args.label, ", ".join("`%s`" % k for k in pats), launches, args.calls,
+                                     per_call_ms)]
     if args.fetch and args.write and args.calib_fetch and args.calib_write and args.calib_bytes > 0:
         cf = _counter(args.calib_fetch, args.calib_kernel)
         cw = _counter(args.calib_write, args.calib_kernel)
@@ -112,6 +119,24 @@ def main():
                   "- factors: fetch x %.3f, write x %.3f" % (kf, kw),
                   "- per sweep call (%d dispatches over %d calls): fetch %.2f GB, write %.2f GB, total %.2f GB" %
                   (len(f), nc, fb / 1e9, wb / 1e9, (fb + wb) / 1e9)]
+    if args.mfma:
+        sums = {}
+        for r in csv.DictReader(open(args.mfma)):
+            if any(m in r["Kernel_Name"] for m in pats):
+                sums[r["Counter_Name"]] = sums.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        nc = args.mfma_calls or args.calls
+        f32 = sums.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512.0 / nc
+        f64 = sums.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512.0 / nc
+        busy, cu = sums.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0), sums.get("SQ_BUSY_CU_CYCLES", 0.0)
+        util = busy / (4.0 * cu) if cu > 0 else None
+        out.update({"mfma_flops_f32_per_call": f32, "mfma_flops_f64_per_call": f64, "mfma_busy_frac": util})
+        lines += ["", "Matrix cores (`--pmc SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_INSTS_VALU_MFMA_MOPS_F64 "
+                  "SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CU_CYCLES`, a run of its own):", "",
+                  "- MFMA flops per call (MOPS x 512): FP32 %.4g, FP64 %.4g" % (f32, f64),
+                  "- MFMA busy cycles / (4 SIMDs x busy CU cycles): %s" % ("%.3f" % util if util is not None else "n/a")]
+        if per_call_ms > 0:
+            lines.append("- MFMA rate over the traced kernel time: FP32 %.1f TFLOP/s, FP64 %.1f TFLOP/s"
+                         % (f32 / per_call_ms / 1e9, f64 / per_call_ms / 1e9))
     if args.bench:
         b = json.loads(open(args.bench).read().strip().splitlines()[-1])
         lines += ["", "Bench line of the same build:", "", "    " + json.dumps(b)]
