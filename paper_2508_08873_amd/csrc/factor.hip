@@ -1,6 +1,7 @@
 // Operator assembly and packing of the LU factors into the tiled layout read
 // by the sweep kernels (the LU itself is in lu.hip).
 #include "lrpr_internal.h"
+#include "tile_ops.h"
 
 namespace lrpr {
 
@@ -283,36 +284,42 @@ __global__ __launch_bounds__(256) void k_pack_rows(LuAcc F, int NT, int nb, cons
     Ds[t] = Di[t];
     const int r = t >> 4, q = t & 15;
     const int W = 16 * nb;
-    for (int j = 0; j < nb; ++j) {
+    // this thread's element of block j, read along the contiguous direction
+    // of the band storage, staged at Ms[sk][sq]
+    const int sk = a < 2 ? (t >> 4) : (t & 15), sq = a < 2 ? (t & 15) : (t >> 4);
+    auto fetch = [&](int j) -> double {
         const int64_t jl = (I - nb + j) * TILE, ju = (I + 1 + j) * TILE;
-        // stage M[k][qq] = the factor block's element, read along the
-        // contiguous direction of the band storage
-        {
-            int k, qq;
-            double m;
-            if (a < 2) {
-                k = t >> 4;
-                qq = t & 15;
-                m = a == 0 ? F.lower(base + k, jl + qq) : F.upper(base + k, ju + qq);
-            } else {
-                qq = t >> 4;
-                k = t & 15;
-                m = a == 2 ? F.upper(jl + qq, base + k) : F.lower(ju + qq, base + k);
+        if (a < 2) return a == 0 ? F.lower(base + sk, jl + sq) : F.upper(base + sk, ju + sq);
+        return a == 2 ? F.upper(jl + sq, base + sk) : F.lower(ju + sq, base + sk);
+    };
+    // blocks prefetched PF ahead; the barriers order LDS only, so the loads
+    // stay in flight across them
+    constexpr int PF = 8;
+    double mbuf[PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) mbuf[u] = u < nb ? fetch(u) : 0.0;
+    for (int j0 = 0; j0 < nb; j0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int j = j0 + u;
+            if (j < nb) {
+                Ms[sk * TILE + sq] = mbuf[u];
+                if (j + PF < nb) mbuf[u] = fetch(j + PF);
+                lds_barrier();
+                double v = 0.0;
+                if (a < 2) {
+                    for (int k = 0; k < TILE; ++k) v += Ds[r * TILE + k] * Ms[k * TILE + q];
+                } else {
+                    for (int k = 0; k < TILE; ++k) v += Ds[k * TILE + r] * Ms[k * TILE + q];
+                }
+                const int64_t tile = (I * nb + j) * TILE_ELEMS;
+                if (o64.b[a]) ((double *)o64.b[a])[tile + aslot(false, r, q)] = v;
+                rowv[r * W + j * TILE + q] = v;
+                lds_barrier();
             }
-            Ms[k * TILE + qq] = m;
         }
-        __syncthreads();
-        double v = 0.0;
-        if (a < 2) {
-            for (int k = 0; k < TILE; ++k) v += Ds[r * TILE + k] * Ms[k * TILE + q];
-        } else {
-            for (int k = 0; k < TILE; ++k) v += Ds[k * TILE + r] * Ms[k * TILE + q];
-        }
-        const int64_t tile = (I * nb + j) * TILE_ELEMS;
-        if (o64.b[a]) ((double *)o64.b[a])[tile + aslot(false, r, q)] = v;
-        rowv[r * W + j * TILE + q] = v;
-        __syncthreads();
     }
+    __syncthreads();
     if (o32.b[a] && t < TILE) {
         const double *rv = rowv + t * W;
         round_row_keep_sum((float *)o32.b[a], W, [&](int c, int64_t &dst) {

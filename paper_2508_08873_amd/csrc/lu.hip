@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "lrpr_internal.h"
+#include "tile_ops.h"
 
 namespace lrpr {
 
@@ -55,8 +56,10 @@ struct LuArgs {
     int spin_limit;
 };
 
-// wait until column K is published (thread 0 polls, the workgroup follows)
-__device__ __forceinline__ void wait_col(const LuArgs &a, int K) {
+// wait until column K is published, then take every later column up to
+// Kmax that is published too with the same acquire; returns the last of them
+// (workgroup-uniform).  One cache invalidation then covers several panels.
+__device__ __forceinline__ int wait_upto(const LuArgs &a, int K, int Kmax, int *shared_last) {
     if (threadIdx.x == 0) {
         int spins = 0;
         while (__hip_atomic_load(a.flag + K, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
@@ -67,19 +70,33 @@ __device__ __forceinline__ void wait_col(const LuArgs &a, int K) {
             }
             __builtin_amdgcn_s_sleep(2);
         }
+        int last = K;
+        while (last < Kmax && __hip_atomic_load(a.flag + last + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            ++last;
+        *shared_last = last;
     }
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return *shared_last;
 }
+
+// Panels staged through LDS (two buffers of nb tiles) for nb <= 32 with one
+// wave per SIMD; wider bands read the L tiles from memory as they are applied.
+constexpr int PANEL_NB = 32;
+constexpr int PANEL_VECS = PANEL_NB * (TILE_ELEMS / 2) / 256;   // 16-byte vectors per thread (256 threads)
+size_t tile_lu_lds_bytes(int NW, int nb) { return (NW == 4 && nb <= PANEL_NB) ? 2 * (size_t)nb * TILE_ELEMS * 8 : 0; }
 
 template <int NW, int TPW>
 __global__ __launch_bounds__(64 * NW) void k_tile_lu(const LuArgs *args, int P) {
+    constexpr bool LDSP = NW == 4;
+    extern __shared__ __align__(16) double panel_lds[];   // [2][nb][256] when LDSP
     __shared__ double ubuf[2][256];   // U(K,J), accumulator order
     __shared__ double sd[256];        // diagonal tile, row-major
     __shared__ double sd2[256];       // second buffer of the diagonal elimination
     __shared__ double sli[256];       // L(J,J)^{-1}, row-major
     __shared__ double sui[256];       // U(J,J)^{-1}, row-major
     __shared__ double st[NW][256];    // per-wave transposition buffer
+    __shared__ int s_last;            // last published column seen by wait_upto
     // workgroups [P*i, P*i + P) factor matrix i of the launch
     const int wg = blockIdx.x % P;
     const LuArgs a = args[blockIdx.x / P];
@@ -112,23 +129,11 @@ __global__ __launch_bounds__(64 * NW) void k_tile_lu(const LuArgs *args, int P) 
         }
         // ---- apply panels K = J-nb .. J-1
         const int K0 = J - nb > 0 ? J - nb : 0;
-        for (int K = K0; K < J; ++K) {
-            wait_col(a, K);
+        int avail = K0 - 1;   // columns up to avail are published and acquired
+        // U(K,J) = L(K,K)^{-1} A(K,J) by the wave holding tile K, to LDS
+        auto form_u = [&](int K) {
             const int tK = K - J + nb;
             double *ub = ubuf[K & 1];
-            // the panel's L tiles of this wave's rows load while U(K,J) is formed
-            // (while registers allow: PRE tiles per wave)
-            constexpr bool PRE = TPW <= 9;
-            double lt[PRE ? TPW : 1][4];
-            if constexpr (PRE) {
-#pragma unroll
-                for (int s = 0; s < TPW; ++s) {
-                    const int t = w + NW * s;
-                    const int I = J - nb + t;
-                    if (t <= 2 * nb && I > K && I <= K + nb && I < NT)
-                        ld_a(a.Lt + ((int64_t)K * nb + (I - K - 1)) * TILE_ELEMS, lane, lt[s]);
-                }
-            }
             if (w == tK % NW) {
                 double li[4];
                 ld_a(a.Li + (int64_t)K * TILE_ELEMS, lane, li);
@@ -144,7 +149,10 @@ __global__ __launch_bounds__(64 * NW) void k_tile_lu(const LuArgs *args, int P) 
                     }
                 }
             }
-            __syncthreads();
+        };
+        // A(I,J) -= L(I,K) U(K,J) for the wave's tiles in rows K+1..K+nb
+        auto apply = [&](int K, auto &&ltile) {
+            const double *ub = ubuf[K & 1];
             double ubv[4];
 #pragma unroll
             for (int kc = 0; kc < 4; ++kc) ubv[kc] = ub[kc * 64 + lane];
@@ -154,15 +162,63 @@ __global__ __launch_bounds__(64 * NW) void k_tile_lu(const LuArgs *args, int P) 
                 const int I = J - nb + t;
                 if (t <= 2 * nb && I > K && I <= K + nb && I < NT) {
                     double l[4];
-                    if constexpr (PRE) {
-#pragma unroll
-                        for (int kc = 0; kc < 4; ++kc) l[kc] = lt[s][kc];
-                    } else {
-                        ld_a(a.Lt + ((int64_t)K * nb + (I - K - 1)) * TILE_ELEMS, lane, l);
-                    }
+                    ltile(I - K - 1, l);
 #pragma unroll
                     for (int kc = 0; kc < 4; ++kc) acc[s] = mfma64(-l[kc], ubv[kc], acc[s]);
                 }
+            }
+        };
+        if constexpr (LDSP) {
+            // the nb L tiles of a panel are contiguous in Lt: staged through
+            // LDS, panel K+1's loads in flight while panel K is applied (when
+            // K+1 is known to be published); the barriers order LDS only
+            double *pb = panel_lds;
+            const int nv = nb * (TILE_ELEMS / 2);   // 16-byte vectors per panel
+            d2v pr[PANEL_VECS];
+            auto issue = [&](int K) {
+                const double *src = a.Lt + (int64_t)K * nb * TILE_ELEMS;
+#pragma unroll
+                for (int i = 0; i < PANEL_VECS; ++i) {
+                    const int e = tid + 64 * NW * i;
+                    if (e < nv) pr[i] = *(gd2p)(src + 2 * e);
+                }
+            };
+            auto stage = [&](int K) {
+                double *dst = pb + (K & 1) * nb * TILE_ELEMS;
+#pragma unroll
+                for (int i = 0; i < PANEL_VECS; ++i) {
+                    const int e = tid + 64 * NW * i;
+                    if (e < nv) *(d2v *)(dst + 2 * e) = pr[i];
+                }
+            };
+            bool have = false;   // LDS buffer K&1 holds panel K
+            for (int K = K0; K < J; ++K) {
+                if (K > avail) avail = wait_upto(a, K, J - 1, &s_last);
+                if (!have) {
+                    issue(K);
+                    stage(K);
+                }
+                const bool pre = K + 1 < J && K + 1 <= avail;
+                if (pre) issue(K + 1);
+                form_u(K);
+                lds_barrier();
+                const double *cur = pb + (K & 1) * nb * TILE_ELEMS;
+                apply(K, [&](int d, double (&l)[4]) {
+                    const d2v x = *(const d2v *)(cur + d * TILE_ELEMS + 2 * lane);
+                    const d2v y = *(const d2v *)(cur + d * TILE_ELEMS + 128 + 2 * lane);
+                    l[0] = x[0]; l[1] = x[1]; l[2] = y[0]; l[3] = y[1];
+                });
+                if (pre) stage(K + 1);
+                have = pre;
+            }
+        } else {
+            for (int K = K0; K < J; ++K) {
+                if (K > avail) avail = wait_upto(a, K, J - 1, &s_last);
+                form_u(K);
+                lds_barrier();
+                apply(K, [&](int d, double (&l)[4]) {
+                    ld_a(a.Lt + ((int64_t)K * nb + d) * TILE_ELEMS, lane, l);
+                });
             }
         }
         // ---- diagonal tile: unblocked LU in LDS
@@ -364,11 +420,11 @@ hipError_t launch_tile_lu_batch(int count, const int64_t *ns, int bw, int NT, in
         const int c = count - i0 < per ? count - i0 : per;
         const dim3 grid((unsigned)(c * P));
         if (nb <= 4)
-            hipLaunchKernelGGL((k_tile_lu<4, 3>), grid, dim3(256), 0, s, dA + i0, P);
+            hipLaunchKernelGGL((k_tile_lu<4, 3>), grid, dim3(256), tile_lu_lds_bytes(4, nb), s, dA + i0, P);
         else if (nb <= 16)
-            hipLaunchKernelGGL((k_tile_lu<4, 9>), grid, dim3(256), 0, s, dA + i0, P);
+            hipLaunchKernelGGL((k_tile_lu<4, 9>), grid, dim3(256), tile_lu_lds_bytes(4, nb), s, dA + i0, P);
         else if (nb <= 32)
-            hipLaunchKernelGGL((k_tile_lu<4, 17>), grid, dim3(256), 0, s, dA + i0, P);
+            hipLaunchKernelGGL((k_tile_lu<4, 17>), grid, dim3(256), tile_lu_lds_bytes(4, nb), s, dA + i0, P);
         else if (nb <= 64)
             hipLaunchKernelGGL((k_tile_lu<8, 17>), grid, dim3(512), 0, s, dA + i0, P);
         else
