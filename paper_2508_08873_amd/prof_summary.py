@@ -34,7 +34,9 @@ import statistics
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SWEEP_SOURCES = ["csrc/sweep.hip", "csrc/lrpr_internal.h", "csrc/factor.hip", "csrc/tile_ops.h", "csrc/api_core.cpp"]
+# the sweep kernels, their launch logic and the structures they read (the
+# tile contents that csrc/factor.hip writes do not change what a sweep moves)
+SWEEP_SOURCES = ["csrc/sweep.hip", "csrc/lrpr_internal.h", "csrc/tile_ops.h", "csrc/api_core.cpp"]
 
 
 def sweep_source_hash() -> str:
