@@ -54,9 +54,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["dar511t", "dar255"], default="dar511t",
+    ap.add_argument("--workload", choices=["dar511t", "dar255", "uneven48"], default="dar511t",
                     help="timed workload: the 511^2 time-dependent one (default; the 255^2 results ride along "
-                         "as a side field) or the 255^2 one alone")
+                         "as a side field), the 255^2 one alone, or the 48 uneven problems")
     ap.add_argument("--no-side", action="store_true", help="dar511t: skip the 255^2 side run")
     ap.add_argument("--c1-steps", type=int, default=6, help="timed steps of the 255^2 side run")
     ap.add_argument("--fp64-steps", type=int, default=5, help="timed steps of the 255^2 FP64 side run")
@@ -501,6 +501,110 @@ def c2_cpu_baseline(P, ncols, nsteps, seed):
                       "(not in the rate)" % (ncols, nsteps, t3 - t2, t1 - t0)}
 
 
+def c3_bench(ctx, lrpr, inputs, args):
+    """48 independent problems of uneven grid (63^2..511^2), operator, rank
+    (k = 8..64, p = k/4) and slice count (N = 16, 32, 64), 32 implicit-Euler
+    steps per slice, T = 1.  One pass:
+      1. the band LUs, batched per grid (FP64 LU; FP32 and FP64 tiles);
+      2. ONE rSVD build over all 1856 slices of the 48 problems (FP32 range
+         finder: every slice's forward and adjoint right-hand sides in one
+         sweep launch each way);
+      3. ONE batched Parareal over the 48 problems (FP64 fine solves, tol
+         1e-8 per problem; each problem stops on its own), each on a view of
+         its slices' coarse propagators.
+    Error per problem: the converged iterate against the sequential FP64
+    fine solution u_n = F_n(u_{n-1}) computed afterwards on the GPU.
+    Returns the result dict."""
+    import torch
+    probs = inputs.uneven48(seed=args.seed)
+    tol = 1e-8
+    # inputs in HBM: Omega per slice (library Philox, FP32), u0, f, time factors
+    Oms, u0s, fs, fscs = [], [], [], []
+    for i, P in enumerate(probs):
+        Om = torch.empty((P.N, P.l, P.n), device="cuda", dtype=torch.float32)
+        for s_ in range(P.N):
+            ctx.randn(Om[s_], args.seed, 1000 * (i + 1) + s_)
+        Oms.append(Om)
+        u0s.append(lrpr.colmajor(torch.from_numpy(P.u0().reshape(-1, 1)).to("cuda")))
+        fs.append(lrpr.colmajor(torch.from_numpy(P.source().reshape(-1, 1)).to("cuda")))
+        fscs.append(torch.from_numpy(np.concatenate([P.fscale(n) for n in range(1, P.N + 1)])).to("cuda"))
+    torch.cuda.synchronize()
+    grids = sorted(set(P.nx for P in probs))
+    t0 = time.perf_counter()
+    facs = [None] * len(probs)
+    for nx in grids:
+        idx = [i for i, P in enumerate(probs) if P.nx == nx]
+        got = ctx.factor_many([probs[i].op_params(1) for i in idx], store_mask=lrpr.STORE_F64 | lrpr.STORE_F32)
+        for i, F in zip(idx, got):
+            facs[i] = F
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print("uneven48: %d factors in %.2f s" % (len(facs), t1 - t0), file=sys.stderr, flush=True)
+    slices, first = [], []
+    for i, P in enumerate(probs):
+        first.append(len(slices))
+        slices += [(facs[i], P.k, P.p, Oms[i][s_].t()) for s_ in range(P.N)]
+    ctx.profile(True)
+    coarse = ctx.rsvd_build(slices, 32, 1)
+    rng = ctx.profile_read()
+    t2 = time.perf_counter()
+    print("uneven48: rSVD build of %d slices in %.2f s" % (len(slices), t2 - t1), file=sys.stderr, flush=True)
+    probs_in = [{"coarse": coarse.view(first[i], P.N), "factors": [facs[i]] * P.N, "u0": u0s[i], "f": fs[i],
+                 "fscale": fscs[i], "tol": tol} for i, P in enumerate(probs)]
+    outs = ctx.parareal_solve_many(probs_in, 32, fine_prec=0)
+    torch.cuda.synchronize()
+    par = ctx.profile_read()
+    ctx.profile(False)
+    t3 = time.perf_counter()
+    print("uneven48: Parareal of %d problems in %.2f s" % (len(probs), t3 - t2), file=sys.stderr, flush=True)
+    # sequential FP64 fine solution, slice index by slice index over all problems
+    seq = [torch.zeros((P.N + 1, P.n), dtype=torch.float64, device="cuda") for P in probs]
+    for i in range(len(probs)):
+        seq[i][0] = u0s[i][:, 0]
+    for s_ in range(max(P.N for P in probs)):
+        specs = []
+        for i, P in enumerate(probs):
+            if s_ < P.N:
+                X = lrpr.colmajor(seq[i][s_].clone().reshape(-1, 1))
+                specs.append((i, {"F": facs[i], "X": X, "f": fs[i],
+                                  "fscale": fscs[i][s_ * P.m:(s_ + 1) * P.m].reshape(1, -1).contiguous()}))
+        ctx.fine_step_batched([sp for _, sp in specs], 32, 0)
+        for i, sp in specs:
+            seq[i][s_ + 1] = sp["X"][:, 0]
+    torch.cuda.synchronize()
+    errs, iters, per_grid = [], [], {}
+    for i, P in enumerate(probs):
+        U = outs[i]["U"][0]
+        e = float((U - seq[i]).norm(dim=1).max() / seq[i].norm(dim=1).max())
+        errs.append(e)
+        iters.append(outs[i]["iters"][0])
+        g = per_grid.setdefault("%d^2" % P.nx, {"problems": 0, "max_err": 0.0, "iters": []})
+        g["problems"] += 1
+        g["max_err"] = max(g["max_err"], e)
+        g["iters"].append(outs[i]["iters"][0])
+    for pr in probs_in:
+        pr["coarse"].close()
+    coarse.close()
+    for F in facs:
+        F.close()
+    rhs_steps = rng["rhs_steps"] + par["rhs_steps"]
+    wall = t3 - t0
+    return {"workload": "uneven48: 48 problems, nx in {63,127,255,511} (%s), nu~U[0.5,2], |beta|~U[0,30], "
+                        "c~U[0,5], k~U{8..64}, p=k/4, N in {16,32,64}, 32 implicit-Euler steps per slice, T=1; "
+                        "FP32 range finder, FP64 Parareal to %g" % (
+                            ", ".join("%d x %d^2" % (sum(1 for P in probs if P.nx == g), g) for g in grids), tol),
+            "slices": len(slices), "factor_s": t1 - t0, "rsvd_s": t2 - t1, "parareal_s": t3 - t2, "wall_s": wall,
+            "rhs_steps_per_s": rhs_steps / wall,
+            "range_finder": {"ms": rng["ms"], "launches": rng["launches"], "tflop": rng["flops"] / 1e12,
+                             "tflops_per_s": rng["flops"] / rng["ms"] / 1e9},
+            "parareal_fine": {"ms": par["ms"], "launches": par["launches"],
+                              "algorithmic_GBs": par["bytes"] / max(par["ms"], 1e-9) / 1e6},
+            "iters": {"min": int(min(iters)), "max": int(max(iters)), "mean": float(np.mean(iters))},
+            "max_err_vs_sequential_fine": float(max(errs)),
+            "per_grid": {k: {"problems": v["problems"], "max_err": v["max_err"],
+                             "mean_iters": float(np.mean(v["iters"]))} for k, v in per_grid.items()}}
+
+
 def traffic_from_profile(stem):
     """HBM bytes per range-finder sweep call from the committed rocprofv3
     counter summary of this workload, if it was taken from the current sweep
@@ -774,6 +878,15 @@ def main():
     if args.workload == "dar255":
         res = c1_bench(args, lrpr.Context(0), lrpr, inputs)
         print(json.dumps(res), flush=True)
+        return
+    if args.workload == "uneven48":
+        ctx = lrpr.Context(0)
+        res = c3_bench(ctx, lrpr, inputs, args)
+        print(json.dumps({"metric": "fine-propagator RHS\u00b7steps/s; rSVD build s; served solve p50/p99 latency",
+                          "value": res["rhs_steps_per_s"], "unit": "RHS\u00b7steps/s", "n_gpus": 1, "steps": 1,
+                          "warmup": 0, "ms_per_step": res["wall_s"] * 1000.0, "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+                          "config": {"workload": res["workload"]}, "uneven48": res}), flush=True)
         return
     ctx = lrpr.Context(0)
     P, out, sig, recs, times, wall, tune = c2_bench(ctx, lrpr, args)

@@ -121,9 +121,20 @@ lrpr_status lrpr_ctx_release_workspaces(lrpr_ctx ctx);
  *                            each band tile once for all of them: 0 = the
  *                            library's choice (the most, up to 3, that
  *                            still gives every compute unit a workgroup),
- *                            1..3 = that many.
+ *                            1..3 = that many;
+ *   LRPR_TUNE_RSVD_BUDGET    bytes of panels (n (k+p) per slice, two in the
+ *                            range finder's precision and three in FP64)
+ *                            that one rSVD build holds at once (0 = 96e9):
+ *                            larger builds run in chunks of consecutive
+ *                            slices, with the same results per slice.
  * Errors: LRPR_ERR_ARG for an unknown parameter or a value out of range. */
-enum { LRPR_TUNE_LU_WGS = 1, LRPR_TUNE_LU_BUDGET = 2, LRPR_TUNE_PARAREAL_GRAPH = 3, LRPR_TUNE_SWEEP_GROUPS = 4 };
+enum {
+    LRPR_TUNE_LU_WGS = 1,
+    LRPR_TUNE_LU_BUDGET = 2,
+    LRPR_TUNE_PARAREAL_GRAPH = 3,
+    LRPR_TUNE_SWEEP_GROUPS = 4,
+    LRPR_TUNE_RSVD_BUDGET = 5
+};
 lrpr_status lrpr_tune_set(lrpr_ctx ctx, int param, int64_t value);
 lrpr_status lrpr_tune_get(lrpr_ctx ctx, int param, int64_t *value);
 /* Autotuner of the batched band LU for a later lrpr_factor_many of `count`
@@ -393,6 +404,13 @@ lrpr_status lrpr_coarse_from_factors(lrpr_ctx ctx, int nslices, const lrpr_fac *
                                      const double *const *U, const double *const *S, const double *const *V,
                                      lrpr_coarse *out);
 void lrpr_coarse_destroy(lrpr_coarse c);
+/* A handle on slices [first, first+count) of c (their U, S, V and singular
+ * values, in order), for solving problems built together in one
+ * lrpr_rsvd_build call one by one (Sec. 2.2: the coarse propagators of
+ * different intervals are independent).  The view owns no device memory:
+ * lrpr_coarse_destroy on it frees only the view, and c must outlive it.
+ * Errors: LRPR_ERR_ARG (range outside c), LRPR_ERR_NOMEM. */
+lrpr_status lrpr_coarse_view(lrpr_coarse c, int first, int count, lrpr_coarse *out);
 /* Device pointers (owned by the handle) of slice s: U (n x k), S (k+p
  * values), V (n x k); k and n of that slice. */
 lrpr_status lrpr_coarse_get(lrpr_coarse c, int s, const double **U, const double **S,

@@ -554,6 +554,10 @@ lrpr_status lrpr_tune_set(lrpr_ctx ctx, int param, int64_t value) {
             if (value < 0 || value > 3) return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_set: sweep groups in [0, 3]");
             ctx->tune_sweep_groups = (int)value;
             return LRPR_OK;
+        case LRPR_TUNE_RSVD_BUDGET:
+            if (value < 0) return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_set: negative budget");
+            ctx->tune_rsvd_budget = (size_t)value;
+            return LRPR_OK;
         default:
             return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_set: unknown parameter");
     }
@@ -566,6 +570,7 @@ lrpr_status lrpr_tune_get(lrpr_ctx ctx, int param, int64_t *value) {
         case LRPR_TUNE_LU_BUDGET: *value = (int64_t)ctx->tune_lu_budget; return LRPR_OK;
         case LRPR_TUNE_PARAREAL_GRAPH: *value = ctx->tune_pr_graph; return LRPR_OK;
         case LRPR_TUNE_SWEEP_GROUPS: *value = ctx->tune_sweep_groups; return LRPR_OK;
+        case LRPR_TUNE_RSVD_BUDGET: *value = (int64_t)ctx->tune_rsvd_budget; return LRPR_OK;
         default: return fail(ctx, LRPR_ERR_ARG, "lrpr_tune_get: unknown parameter");
     }
 }
@@ -975,6 +980,7 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
                                   SweepPlan *plan = nullptr, const std::string &pre = std::string()) {
     const bool f32 = prec == LRPR_F32;
     std::vector<SweepItem> items;
+    std::vector<int> item_w;   // width of the item's panel
     int max_nb = 1;
     bool strided = false;   // adjoint: some factor has no mirrored set
     for (int p = 0; p < npanels; ++p) {
@@ -1004,6 +1010,7 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
             it.fcol = (!adjoint && P.f && P.fcol) ? P.fcol + c0 : nullptr;
             it.fscale = (!adjoint && P.f && P.fscale) ? P.fscale + (size_t)c0 * fstride : nullptr;
             items.push_back(it);
+            item_w.push_back(P.w);
         }
     }
     if (items.empty() || nsteps == 0) return LRPR_OK;
@@ -1020,29 +1027,42 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
     if (split) return run_split(ctx, npanels, panels, items, nsteps, f32, max_nb, step0, record, plan, pre);
     // Pass pairs when every factor carries the UL set (and, for the
     // adjoint, its mirrored tiles) and all have the same band-tile count
-    // (tile arrays addressed with 32-bit byte offsets)
-    bool paired = nsteps >= 2 && sweep_pairable(max_nb) && !(adjoint && strided);
+    // (tile arrays addressed with 32-bit byte offsets).  Not with
+    // split_any_width: there a problem's path must not depend on the others.
+    bool paired = !split_any_width && nsteps >= 2 && sweep_pairable(max_nb) && !(adjoint && strided);
     for (const SweepItem &it : items)
         paired = paired && it.fac.nb == max_nb && it.fac.ar[TS_LB] && (!adjoint || it.fac.ar[TS_UTB]) &&
                  (double)(it.fac.NT + 2 * guard_rows(max_nb)) * max_nb * TILE_ELEMS * (f32 ? 4 : 8) < 4.0e9;
-    // Narrow panels (at most sweep_narrow_cols columns per factor; with
-    // split_any_width every width, cut into such items) run on the vector
-    // ALUs: a single column then does not pay for a 16-column group.  The
-    // alternating L U / U' L' pairs measured about half the FP32 error of
-    // L U steps alone (32 steps on 255^2 grids), so factors that carry the
-    // UL set keep the matrix-core pass pairs.
-    // With split_any_width (Parareal) the choice depends on nothing but the
-    // band, so a problem rounds the same whatever else shares the launch.
+    // Narrow panels (at most sweep_narrow_cols columns per factor) run on the
+    // vector ALUs: a single column then does not pay for a 16-column group.
+    // Without split_any_width the whole launch goes narrow when every item
+    // is; the alternating L U / U' L' pairs measured about half the FP32
+    // error of L U steps alone (32 steps on 255^2 grids), so factors that
+    // carry the UL set keep the matrix-core pass pairs.  With split_any_width
+    // (Parareal) each panel's own width decides, so a problem rounds the same
+    // whatever else shares the launch.
     const int ncmax = sweep_narrow_cols(f32);
-    bool narrow = !adjoint && max_nb >= 2 && max_nb <= 64 && (split_any_width || !paired);
-    if (narrow && !split_any_width)
-        for (const SweepItem &it : items) narrow = narrow && it.ncols <= ncmax;
-    paired = paired && !narrow;
-    int narrow_cols = 0;
-    if (narrow) {
-        const size_t esz = f32 ? 4 : 8;
-        std::vector<SweepItem> nit;
-        for (const SweepItem &it : items)
+    std::vector<char> is_narrow(items.size(), 0);
+    if (!adjoint && !paired) {
+        bool all = true;
+        for (size_t i = 0; i < items.size(); ++i) {
+            const int nb = items[i].fac.nb;
+            is_narrow[i] = nb >= 2 && nb <= 64 && (split_any_width ? item_w[i] <= ncmax : items[i].ncols <= ncmax);
+            all = all && is_narrow[i];
+        }
+        if (!split_any_width && !all) std::fill(is_narrow.begin(), is_narrow.end(), 0);
+    }
+    // narrow items (cut into <= ncmax columns) first, then the matrix-core
+    // items by band class: each class runs its own kernel, so an item's
+    // arithmetic depends only on its own factor's band
+    const size_t esz = f32 ? 4 : 8;
+    std::vector<SweepItem> nit;
+    int narrow_cols = 0, narrow_nb = 1;
+    std::vector<std::vector<SweepItem>> cls(7);
+    auto class_of = [](int nb) { return nb <= 1 ? 0 : nb <= 4 ? 1 : nb <= 8 ? 2 : nb <= 16 ? 3 : nb <= 32 ? 4 : 5; };
+    for (size_t i = 0; i < items.size(); ++i) {
+        const SweepItem &it = items[i];
+        if (is_narrow[i]) {
             for (int c0 = 0; c0 < it.ncols; c0 += ncmax) {
                 SweepItem q = it;
                 q.X = (char *)it.X + (size_t)c0 * it.ldx * esz;
@@ -1050,26 +1070,47 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
                 if (q.fcol) q.fcol = it.fcol + c0;
                 if (q.fscale) q.fscale = it.fscale + (size_t)c0 * it.fsteps;
                 narrow_cols = std::max(narrow_cols, q.ncols);
+                narrow_nb = std::max(narrow_nb, it.fac.nb);
                 nit.push_back(q);
             }
-        items.swap(nit);
+        } else {
+            cls[paired ? 6 : class_of(it.fac.nb)].push_back(it);
+        }
     }
-    // Several 16-column groups of one panel per workgroup: every band tile
-    // read then feeds all of them (the groups' arithmetic is unchanged).
-    int ng = 1;
-    if (!narrow && !paired) {
-        ng = ctx->tune_sweep_groups ? std::min(ctx->tune_sweep_groups, sweep_max_groups(f32, max_nb))
-                                    : sweep_max_groups(f32, max_nb);
-        // by default the most groups that still leave no compute unit idle
-        while (!ctx->tune_sweep_groups && ng > 1 && (int)group_items(items, ng, f32 ? 4 : 8).size() < ctx->ncu) --ng;
-        if (ng > 1) items = group_items(items, ng, f32 ? 4 : 8);
+    struct Launch {
+        size_t at, count;
+        int nb, ng;
+    };
+    std::vector<Launch> wide;
+    xcd_order(nit);
+    std::vector<SweepItem> all_items = nit;
+    for (int c = 0; c < 7; ++c) {
+        std::vector<SweepItem> &v = cls[c];
+        if (v.empty()) continue;
+        int cnb = 1;
+        for (const SweepItem &it : v) cnb = std::max(cnb, it.fac.nb);
+        // Several 16-column groups of one panel per workgroup: every band
+        // tile read then feeds all of them (the groups' arithmetic is
+        // unchanged); by default the most that still leave no compute unit
+        // idle
+        int ng = 1;
+        if (!paired) {
+            ng = ctx->tune_sweep_groups ? std::min(ctx->tune_sweep_groups, sweep_max_groups(f32, cnb))
+                                        : sweep_max_groups(f32, cnb);
+            while (!ctx->tune_sweep_groups && ng > 1 && (int)group_items(v, ng, esz).size() < ctx->ncu) --ng;
+            if (ng > 1) v = group_items(v, ng, esz);
+        }
+        xcd_order(v);
+        wide.push_back({all_items.size(), v.size(), cnb, ng});
+        all_items.insert(all_items.end(), v.begin(), v.end());
     }
-    xcd_order(items);
-    const size_t ni = items.size();
+    items.swap(all_items);
+    const size_t nn = nit.size();
     if (paired) {
         // [0, ni): first substitution of the first step; [ni, 2ni): second
         // substitution of an L U step; [2ni, 3ni): second substitution of a
         // U' L' step (the UL set's first-pass tiles, no source)
+        const size_t ni = items.size();
         items.resize(3 * ni);
         for (size_t i = 0; i < ni; ++i) {
             items[i].passes = 1;
@@ -1098,19 +1139,22 @@ static lrpr_status run_sweep_core(lrpr_ctx ctx, int npanels, const lrpr_panel *p
     record = record && !plan;
     if (record && ctx->prof && (e = prof_begin(ctx, npanels, panels, nsteps, f32, rec)) != hipSuccess)
         return hipfail(ctx, e, "profile event");
-    const int nii = (int)ni;
     std::function<hipError_t(hipStream_t)> go;
-    if (narrow) {
+    if (!paired) {
         go = [=](hipStream_t s) {
-            return launch_sweep_narrow(f32, nii, d_items, nsteps, max_nb, narrow_cols, s, step0);
-        };
-    } else if (!paired) {
-        go = [=](hipStream_t s) {
-            return launch_sweep(adjoint, strided, f32, nii, d_items, nsteps, max_nb, s, step0, false, ng);
+            hipError_t ee = hipSuccess;
+            if (nn > 0) ee = launch_sweep_narrow(f32, (int)nn, d_items, nsteps, narrow_nb, narrow_cols, s, step0);
+            for (const Launch &L : wide)
+                if (ee == hipSuccess)
+                    ee = launch_sweep(adjoint, strided, f32, (int)L.count, d_items + L.at, nsteps, L.nb, s, step0,
+                                      false, L.ng);
+            return ee;
         };
     } else {
         // even steps (from step0) L U, odd steps U' L'; the second
         // substitution of step s runs with the first of step s+1
+        const size_t ni = items.size() / 3;
+        const int nii = (int)ni;
         go = [=](hipStream_t s) {
             hipError_t ee = launch_sweep(adjoint, false, f32, nii, d_items, 1, max_nb, s, step0);
             for (int q = 0; q + 1 < nsteps && ee == hipSuccess; ++q)

@@ -95,12 +95,41 @@ hipError_t lowrank_cols(LrArgs a, double *part, double *incpart, hipStream_t s) 
 // ---------------------------------------------------------------------------
 extern "C" {
 
+lrpr_status lrpr_coarse_view(lrpr_coarse c, int first, int count, lrpr_coarse *out) {
+    if (!c || !out || first < 0 || count < 1 || first + count > c->nslices) return LRPR_ERR_ARG;
+    lrpr_coarse v = new (std::nothrow) lrpr_coarse_s();
+    if (!v) return LRPR_ERR_NOMEM;
+    size_t pos = 0;
+    for (int s = 0; s < first; ++s) pos += (size_t)c->l[s];
+    v->dev = c->dev;
+    v->nslices = count;
+    v->view = true;
+    for (int s = first; s < first + count; ++s) {
+        v->n.push_back(c->n[s]);
+        v->k.push_back(c->k[s]);
+        v->l.push_back(c->l[s]);
+        v->U.push_back(c->U[s]);
+        v->S.push_back(c->S[s]);
+        v->V.push_back(c->V[s]);
+        if ((size_t)s < c->F.size()) v->F.push_back(c->F[s]);
+        v->sigma.insert(v->sigma.end(), c->sigma.begin() + pos, c->sigma.begin() + pos + c->l[s]);
+        pos += (size_t)c->l[s];
+    }
+    *out = v;
+    return LRPR_OK;
+}
+
 void lrpr_coarse_destroy(lrpr_coarse c) {
     if (!c) return;
+    if (c->view) {
+        delete c;
+        return;
+    }
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
     if (c->block) {
         dfree(c->block, nullptr);
+        for (double *b : c->more) dfree(b, nullptr);
     } else {
         for (size_t s = 0; s < c->U.size(); ++s) {
             if (c->U[s]) hipFree(c->U[s]);
@@ -225,10 +254,80 @@ lrpr_status lrpr_rsvd_build_two_sided(lrpr_ctx ctx, int nslices, const lrpr_slic
 // W^{-1/2} and its output by W^{1/2}, every adjoint sweep's input by W^{1/2}
 // and its output by W^{-1/2}, and the factors are mapped back at the end
 // (U_k by W^{-1/2}, V_k by W^{1/2}) before the signs are fixed.
+static lrpr_status rsvd_build_one(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
+                                  const void *const *psi, int nsteps, int q, lrpr_prec range_prec,
+                                  lrpr_coarse *out, double *sigma_host, int *fallback_host,
+                                  const double *const *weights);
+
+// The build in chunks of consecutive slices whose panels fit the budget
+// (each chunk is one build; every slice's result is the same as in a build
+// of all slices at once, as no step couples slices), merged into one handle.
 static lrpr_status rsvd_build_impl(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
                                    const void *const *psi, int nsteps, int q, lrpr_prec range_prec,
                                    lrpr_coarse *out, double *sigma_host, int *fallback_host,
                                    const double *const *weights) {
+    if (!ctx) return LRPR_ERR_ARG;
+    if (nslices <= 0 || !slices || !out) return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: invalid arguments");
+    for (int s = 0; s < nslices; ++s)
+        if (!slices[s].F) return fail(ctx, LRPR_ERR_ARG, "lrpr_rsvd_build: slice needs factor");
+    const size_t esz = range_prec == LRPR_F32 ? sizeof(float) : sizeof(double);
+    const double budget = ctx->tune_rsvd_budget ? (double)ctx->tune_rsvd_budget : 96e9;
+    // panel bytes of a chunk: two arenas in the range finder's precision and
+    // three in FP64, each n x (k+p) per slice
+    std::vector<int> cut{0};
+    double bytes = 0.0;
+    for (int s = 0; s < nslices; ++s) {
+        const double b = (double)slices[s].F->n * (slices[s].k + slices[s].p) * (2.0 * esz + 3.0 * 8.0);
+        if (s > cut.back() && bytes + b > budget) {
+            cut.push_back(s);
+            bytes = 0.0;
+        }
+        bytes += b;
+    }
+    cut.push_back(nslices);
+    if (cut.size() == 2)
+        return rsvd_build_one(ctx, nslices, slices, psi, nsteps, q, range_prec, out, sigma_host, fallback_host,
+                              weights);
+    lrpr_coarse all = new (std::nothrow) lrpr_coarse_s();
+    if (!all) return fail(ctx, LRPR_ERR_NOMEM, "coarse handle");
+    all->dev = ctx->dev;
+    size_t sig_at = 0;
+    for (size_t ci = 0; ci + 1 < cut.size(); ++ci) {
+        const int a = cut[ci], cnt = cut[ci + 1] - cut[ci];
+        lrpr_coarse part = nullptr;
+        lrpr_status st = rsvd_build_one(ctx, cnt, slices + a, psi ? psi + a : nullptr, nsteps, q, range_prec, &part,
+                                        sigma_host ? sigma_host + sig_at : nullptr,
+                                        fallback_host ? fallback_host + a : nullptr, weights ? weights + a : nullptr);
+        if (st != LRPR_OK) {
+            lrpr_coarse_destroy(all);
+            return st;
+        }
+        all->nslices += part->nslices;
+        all->n.insert(all->n.end(), part->n.begin(), part->n.end());
+        all->k.insert(all->k.end(), part->k.begin(), part->k.end());
+        all->l.insert(all->l.end(), part->l.begin(), part->l.end());
+        all->U.insert(all->U.end(), part->U.begin(), part->U.end());
+        all->S.insert(all->S.end(), part->S.begin(), part->S.end());
+        all->V.insert(all->V.end(), part->V.begin(), part->V.end());
+        all->sigma.insert(all->sigma.end(), part->sigma.begin(), part->sigma.end());
+        all->F.insert(all->F.end(), part->F.begin(), part->F.end());
+        sig_at += part->sigma.size();
+        if (!all->block) all->block = part->block;
+        else all->more.push_back(part->block);
+        part->block = nullptr;
+        part->U.clear();
+        part->S.clear();
+        part->V.clear();
+        delete part;
+    }
+    *out = all;
+    return LRPR_OK;
+}
+
+static lrpr_status rsvd_build_one(lrpr_ctx ctx, int nslices, const lrpr_slice_desc *slices,
+                                  const void *const *psi, int nsteps, int q, lrpr_prec range_prec,
+                                  lrpr_coarse *out, double *sigma_host, int *fallback_host,
+                                  const double *const *weights) {
     if (!ctx) return LRPR_ERR_ARG;
     if (nslices <= 0 || !slices || !out || nsteps < 0 || q < 0 ||
         (range_prec != LRPR_F64 && range_prec != LRPR_F32))

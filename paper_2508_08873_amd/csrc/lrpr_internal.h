@@ -144,8 +144,10 @@ struct lrpr_coarse_s {
     std::vector<int> k, l;
     std::vector<double *> U, S, V;  // device, per slice (inside `block` when that is set)
     double *block = nullptr;        // one allocation holding every slice's U, S, V
+    std::vector<double *> more;     // further such allocations (a build done in chunks)
     std::vector<double> sigma;      // host copy of all singular values, per slice
     std::vector<lrpr_fac> F;     // factors the slices were built from (not owned)
+    bool view = false;              // slices of another handle: owns no device memory
 };
 
 struct lrpr_ctx_s {
@@ -169,6 +171,7 @@ struct lrpr_ctx_s {
     size_t tune_lu_budget = 0;   // bytes of FP64 bands and LU scratch per factor_many chunk
     int tune_pr_graph = 1;       // Parareal iterations replayed from a captured HIP graph
     int tune_sweep_groups = 0;   // 16-column groups per sweep workgroup (0 = by occupancy)
+    size_t tune_rsvd_budget = 0; // bytes of rSVD panels per build chunk (0 = 96e9)
     int ncu = 256;               // compute units of the device
 };
 

@@ -109,12 +109,16 @@ struct Pass {
     }
     // bulk tile idx (0..nb-2) of row q.  Tile rows outside [0, NT) are zero
     // guard rows of the tile arrays, so every address within the prefetch
-    // window is valid; surplus slots (idx >= nb-1) read the zero tile.
+    // window is valid; surplus slots (idx >= nb-1, on factors with fewer band
+    // tiles than the launch's widest) read the zero tile and take the first
+    // bulk tile's index, so that their ring slot stays inside the ring.
     __device__ __forceinline__ bool bulk(int q, int idx, int &j, int &J) const {
         const int I = row_of(q);
-        j = ASC ? idx : idx + 1;
+        const bool ok = idx < nbulk;
+        const int id = ok ? idx : 0;
+        j = ASC ? id : id + 1;
         J = ASC ? I - nb + j : I + 1 + j;
-        return idx < nbulk;
+        return ok;
     }
     __device__ __forceinline__ void ld_tile(const T *tp, T (&v)[4]) const {
         if (STRIDED) {

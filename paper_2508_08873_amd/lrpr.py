@@ -24,7 +24,8 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
            "lrpr_factor_info", "lrpr_factor_copy_lu",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build", "lrpr_rsvd_build_q",
            "lrpr_rsvd_build_two_sided", "lrpr_rsvd_build_w", "lrpr_coarse_from_factors", "lrpr_mass_weights",
-           "lrpr_coarse_destroy", "lrpr_coarse_get", "lrpr_coarse_apply", "lrpr_coarse_apply_noalloc",
+           "lrpr_coarse_destroy", "lrpr_coarse_view", "lrpr_coarse_get", "lrpr_coarse_apply",
+           "lrpr_coarse_apply_noalloc",
            "lrpr_parareal_solve", "lrpr_parareal_solve_many",
            "lrpr_profile_enable", "lrpr_profile_read", "lrpr_randn",
            "lrpr_server_create", "lrpr_server_destroy", "lrpr_server_submit", "lrpr_server_progress",
@@ -32,7 +33,7 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
 
 
 # lrpr_tune_set parameters
-TUNE_LU_WGS, TUNE_LU_BUDGET, TUNE_PARAREAL_GRAPH, TUNE_SWEEP_GROUPS = 1, 2, 3, 4
+TUNE_LU_WGS, TUNE_LU_BUDGET, TUNE_PARAREAL_GRAPH, TUNE_SWEEP_GROUPS, TUNE_RSVD_BUDGET = 1, 2, 3, 4, 5
 # lrpr_factor store_mask bits (include/lrpr.h)
 STORE_F64, STORE_F32, STORE_MIRROR, STORE_SPLIT, STORE_UL = 1, 2, 4, 8, 16
 # lrpr_factor_stepper steppers
@@ -116,6 +117,7 @@ def load():
     lib.lrpr_mass_weights.argtypes = [P(OpDesc), vp]
     lib.lrpr_coarse_destroy.argtypes = [vp]
     lib.lrpr_coarse_destroy.restype = None
+    lib.lrpr_coarse_view.argtypes = [vp, i32, i32, P(vp)]
     lib.lrpr_coarse_get.argtypes = [vp, i32, P(vp), P(vp), P(vp), P(i32), P(i64)]
     lib.lrpr_coarse_apply.argtypes = [vp, vp, i32, i32, vp, vp]
     lib.lrpr_coarse_apply_noalloc.argtypes = [vp, vp, i32, i32, vp, vp]
@@ -333,7 +335,8 @@ class Context:
         else:
             self._check(self.lib.lrpr_rsvd_build(self.h, len(slices), arr, int(nsteps), int(range_prec),
                                                  ctypes.byref(h), sig, fb))
-        return Coarse(self, h, [F for (F, _, _, _) in slices], list(sig)[:tot], list(fb)[:len(slices)])
+        return Coarse(self, h, [F for (F, _, _, _) in slices], list(sig)[:tot], list(fb)[:len(slices)],
+                      ls=[k + p for (_, k, p, _) in slices])
 
     def coarse_from_factors(self, factors, U, S, V):
         """A priori coarse solvers (lrpr_coarse_from_factors): per slice float64
@@ -435,8 +438,10 @@ class Factor:
 
 
 class Coarse:
-    def __init__(self, ctx, h, factors, sigma, fallback):
+    def __init__(self, ctx, h, factors, sigma, fallback, parent=None, ls=None):
         self.ctx, self.h, self.factors, self.sigma, self.fallback = ctx, h, factors, sigma, fallback
+        self.parent = parent   # a view keeps the handle it shares memory with alive
+        self.ls = ls           # singular values per slice (sigma is their concatenation)
 
     def get(self, s):
         """(U, S, V) of slice s copied into new torch tensors (n x k, k+p, n x k)."""
@@ -445,6 +450,17 @@ class Coarse:
         self.ctx._check(self.ctx.lib.lrpr_coarse_get(self.h, s, ctypes.byref(U), ctypes.byref(S), ctypes.byref(V),
                                                      ctypes.byref(k), ctypes.byref(n)))
         return k.value, n.value, U.value, S.value, V.value
+
+    def view(self, first, count):
+        """lrpr_coarse_view: slices [first, first+count) as a handle of their
+        own (no device memory of its own; this handle must outlive it)."""
+        h = ctypes.c_void_p()
+        self.ctx._check(self.ctx.lib.lrpr_coarse_view(self.h, int(first), int(count), ctypes.byref(h)))
+        ls = self.ls[first:first + count] if self.ls else None
+        pos = sum(self.ls[:first]) if self.ls else 0
+        sig = self.sigma[pos:pos + sum(ls)] if ls else []
+        return Coarse(self.ctx, h, self.factors[first:first + count] if self.factors else self.factors,
+                      sig, self.fallback[first:first + count] if self.fallback else self.fallback, parent=self, ls=ls)
 
     def apply(self, s, Vin):
         out = torch.empty_like(Vin)

@@ -139,3 +139,34 @@ def test_groups_tune_range(ctx):
     with pytest.raises(lrpr.LrprError):
         ctx.tune_set(lrpr.TUNE_SWEEP_GROUPS, 4)
     ctx.tune_set(lrpr.TUNE_SWEEP_GROUPS, 0)
+
+
+@pytest.mark.parametrize("prec,groups", [(0, 1), (1, 1), (1, 3)], ids=["f64", "f32", "f32_groups3"])
+def test_mixed_band_classes_parity(ctx, ora, prec, groups):
+    """One launch over factors of 2, 4, 16 and 17 band tiles per row (the
+    launch runs the widest class's kernel; the narrower factors' surplus
+    bulk tiles must read zero tiles against ring slots of their own)."""
+    from paper_2508_08873_amd import lrpr
+    probs = [inputs.tiny2d(nx=31, m=2), inputs.tiny2d(nx=63, m=2, beta=(-4.0, 9.0)),
+             inputs.tiny2d(nx=255, m=2), inputs.tiny2d(nx=260, m=2, beta=(12.0, 3.0))]
+    widths = [19, 35, 16, 33]
+    dt = torch.float64 if prec == 0 else torch.float32
+    specs, refs, facs = [], [], []
+    for i, (P, w) in enumerate(zip(probs, widths)):
+        F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt, store_mask=lrpr.STORE_F64 | lrpr.STORE_F32)
+        facs.append(F)
+        X0 = np.random.default_rng(40 + i).standard_normal((P.n, w))
+        refs.append(ora.Operator(**P.op_params()).fine(X0, 2))
+        specs.append({"F": F, "X": _dev(X0, dt)})
+    ctx.tune_set(lrpr.TUNE_SWEEP_GROUPS, groups)
+    ctx.fine_step_batched(specs, 2, prec)
+    torch.cuda.synchronize()
+    ctx.tune_set(lrpr.TUNE_SWEEP_GROUPS, 0)
+    tol = 1e-11 if prec == 0 else 1e-5
+    for sp, ref, P in zip(specs, refs, probs):
+        got = sp["X"].double().cpu().numpy()
+        err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        print("nx", P.nx, "max column error", err.max(), flush=True)
+        assert np.isfinite(err).all() and err.max() <= tol, (P.nx, err.max())
+    for F in facs:
+        F.close()
