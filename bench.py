@@ -54,9 +54,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["dar511t", "dar255", "uneven48"], default="dar511t",
+    ap.add_argument("--workload", choices=["dar511t", "dar255", "uneven48", "serve3"], default="dar511t",
                     help="timed workload: the 511^2 time-dependent one (default; the 255^2 results ride along "
-                         "as a side field), the 255^2 one alone, or the 48 uneven problems")
+                         "as a side field), the 255^2 one alone, the 48 uneven problems, or serving at load")
     ap.add_argument("--no-side", action="store_true", help="dar511t: skip the 255^2 side run")
     ap.add_argument("--c1-steps", type=int, default=6, help="timed steps of the 255^2 side run")
     ap.add_argument("--fp64-steps", type=int, default=5, help="timed steps of the 255^2 FP64 side run")
@@ -75,8 +75,11 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-RHS FP64 run")
     ap.add_argument("--no-ul", action="store_true",
                     help="factor without the UL set (every step L U, unpaired substitution passes)")
-    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrival rate (requests/s)")
-    ap.add_argument("--serve-duration", type=float, default=15.0, help="arrival window (s)")
+    ap.add_argument("--serve-rate", type=float, default=None,
+                    help="Poisson arrival rate (requests/s; default 4 in the 255^2 run's serving study, 200 for "
+                         "--workload serve3)")
+    ap.add_argument("--serve-duration", type=float, default=None,
+                    help="arrival window (s; default 15 in the serving study, 60 for --workload serve3)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -197,6 +200,128 @@ def serve_bench(ctx, lrpr, inputs, seed, rate, duration):
             "requests": int(len(L)), "p50_s": float(np.percentile(L, 50)), "p99_s": float(np.percentile(L, 99)),
             "solves_per_s": float(len(L) / t_end), "wall_s": t_end, "setup_s": t_setup,
             "failed": int(sum(1 for v in iters.values() if v < 0)), "per_operator": per_op}
+
+
+def c4_bench(ctx, lrpr, inputs, args):
+    """Serving at the specified load: three operators (127^2, 255^2, 511^2;
+    nu=1, beta=(10,5), c=1, 64 slices x 32 steps, k=48, p=12) with
+    device-resident coarse propagators (FP64 rSVD, Philox Omega), Poisson
+    arrivals at --serve-rate (default here 200/s) for --serve-duration
+    (60 s), operator uniform, FP64 fine steps, tolerance 1e-8.  Requests wait
+    in the client's FIFO and are handed to lrpr_server while its queue holds
+    fewer than 64; latency = completion - arrival (queueing included).  After
+    the arrivals stop, the run drains for at most 60 s; requests still open
+    then are reported as unfinished (their latency exceeds the run).  The
+    measured capacity (completions per second while the server was never
+    idle) sets a second run at 0.7 x capacity, drained to the end.  Each
+    request's u0 and f are drawn per request index modulo 32 (per operator)
+    from the serving distribution (8x8 sine modes, 1-6 bumps).  The plain
+    per-request FP64 path for comparison: the sequential fine solution of one
+    request (64 x 32 implicit-Euler steps, one right-hand side, FP64
+    partitioned passes), per operator."""
+    import collections
+    import torch
+    probs = inputs.serve3(seed=args.seed)
+    ops, pools = [], []
+    t_setup = time.perf_counter()
+    for oi, P in enumerate(probs):
+        F = ctx.factor(P.dim, P.nx, P.nu, P.beta, P.c, P.dt,
+                       store_mask=lrpr.STORE_F64 | lrpr.STORE_MIRROR | lrpr.STORE_SPLIT)
+        Om = torch.empty((P.N, P.l, P.n), device="cuda", dtype=torch.float64)
+        for s_ in range(P.N):
+            ctx.randn(Om[s_], args.seed, 50000 + 1000 * oi + s_)
+        coarse = ctx.rsvd_build([(F, P.k, P.p, Om[s_].t()) for s_ in range(P.N)], P.m, 0)
+        del Om
+        fsc = torch.from_numpy(np.concatenate([P.fscale(s_) for s_ in range(1, P.N + 1)])).to("cuda")
+        ops.append((coarse, [F] * P.N, P.m, fsc))
+        pools.append([(lrpr.colmajor(torch.from_numpy(P.u0(req=j + 1)).to("cuda").reshape(-1, 1)),
+                       lrpr.colmajor(torch.from_numpy(P.source(req=j + 1)).to("cuda").reshape(-1, 1)))
+                      for j in range(32)])
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    print("serve3: setup %.1f s" % t_setup, file=sys.stderr, flush=True)
+
+    def run(rate, duration, drain, tag):
+        arr = inputs.arrivals(seed=args.seed, rate=rate, duration=duration)
+        which = inputs.rng(args.seed, "request", 0).integers(0, len(probs), size=len(arr))
+        srv = lrpr.Server(ctx, ops, tol=probs[0].tol, budget_bytes=64 << 30)
+        waiting = collections.deque()
+        arrival, opof, lat, iters = {}, {}, {}, {}
+        nxt, busy_t, last_report = 0, 0.0, 0.0
+        t0 = time.perf_counter()
+        while True:
+            now = time.perf_counter() - t0
+            while nxt < len(arr) and arr[nxt] <= now:
+                waiting.append(nxt)
+                nxt += 1
+            st = srv.stats()
+            while waiting and st["queued"] < 64:
+                i = waiting.popleft()
+                op = int(which[i])
+                u0, f = pools[op][i % 32]
+                rid, _ = srv.submit(op, u0, f, sync=False)
+                arrival[rid], opof[rid] = arr[i], op
+                st["queued"] += 1
+            fin = srv.progress(wait=False)
+            tnow = time.perf_counter() - t0
+            for rid, it in fin:
+                lat[rid] = tnow - arrival[rid]
+                iters[rid] = it
+            if st["active"] > 0 or st["queued"] > 0:
+                busy_t = tnow
+            if tnow - last_report > 10.0:
+                print("serve3 %s: t=%.0f s, arrived %d, done %d, client queue %d" % (tag, tnow, nxt, len(lat),
+                                                                                    len(waiting)),
+                      file=sys.stderr, flush=True)
+                last_report = tnow
+            if nxt == len(arr) and not waiting and len(lat) == len(arrival):
+                break
+            if tnow > duration + drain:
+                break
+            if not fin:
+                time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+        srv.close()
+        done = np.array([lat[k] for k in sorted(lat)]) if lat else np.zeros(1)
+        per_op = {}
+        for o, P in enumerate(probs):
+            lo = np.array([lat[k] for k in lat if opof[k] == o])
+            if len(lo):
+                per_op[P.name] = {"done": int(len(lo)), "p50_s": float(np.percentile(lo, 50)),
+                                  "p99_s": float(np.percentile(lo, 99))}
+        return {"rate_per_s": rate, "arrival_s": duration, "arrived": int(len(arr)), "done": int(len(lat)),
+                "unfinished": int(len(arr) - len(lat)), "wall_s": wall,
+                "solves_per_s": float(len(lat) / max(busy_t, 1e-9)),
+                "p50_s": float(np.percentile(done, 50)), "p99_s": float(np.percentile(done, 99)),
+                "failed": int(sum(1 for v in iters.values() if v < 0)), "per_operator": per_op}
+
+    rate = args.serve_rate if args.serve_rate is not None else 200.0
+    duration = args.serve_duration if args.serve_duration is not None else 60.0
+    sat = run(rate, duration, 60.0, "saturation")
+    cap = sat["solves_per_s"]
+    sus = run(0.7 * cap, duration, 120.0, "0.7 x capacity")
+    # plain per-request FP64: the sequential fine solution of one request
+    plain = {}
+    for oi, P in enumerate(probs):
+        coarse, facs, m, fsc = ops[oi]
+        u0, f = pools[oi][0]
+        X = lrpr.colmajor(u0.clone())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in range(P.N):
+            ctx.fine_step_batched([{"F": facs[0], "X": X, "f": f,
+                                    "fscale": fsc[s_ * m:(s_ + 1) * m].reshape(1, -1).contiguous()}], m, 0)
+        torch.cuda.synchronize()
+        plain[P.name] = time.perf_counter() - t0
+    plain_rate = 1.0 / float(np.mean(list(plain.values())))
+    for c in ops:
+        c[0].close()
+        c[1][0].close()
+    return {"workload": "serve3: operators 127^2, 255^2, 511^2 (nu=1, beta=(10,5), c=1, 64 slices x 32 steps, "
+                        "k=48, p=12), Poisson arrivals, operator uniform, FP64 fine steps, tol 1e-8",
+            "setup_s": t_setup, "saturation": sat, "capacity_solves_per_s": cap, "sustained": sus,
+            "plain_per_request_fp64_s": plain, "plain_per_request_solves_per_s": plain_rate,
+            "served_vs_plain_solves": cap / plain_rate}
 
 
 def plain_per_rhs(ctx, lrpr, P, reps=8):
@@ -855,7 +980,8 @@ def c1_bench(args, ctx, lrpr, inputs):
                                                             plain["rhs_steps_per_s"])
         res["batched_vs_plain_per_rhs_%s_vs_fp64" % prec] = rr / plain["rhs_steps_per_s"]
     if not args.no_serve:
-        res["serve"] = serve_bench(ctx, lrpr, inputs, args.seed, args.serve_rate, args.serve_duration)
+        res["serve"] = serve_bench(ctx, lrpr, inputs, args.seed, args.serve_rate if args.serve_rate is not None else 4.0,
+                                   args.serve_duration if args.serve_duration is not None else 15.0)
     if not args.no_cpu:
         cb, err = cpu_baseline_and_parity(ctx, lrpr, P, prec, args.cpu_cols, args.cpu_steps, args.seed)
         res["cpu_baseline"] = cb
@@ -878,6 +1004,16 @@ def main():
     if args.workload == "dar255":
         res = c1_bench(args, lrpr.Context(0), lrpr, inputs)
         print(json.dumps(res), flush=True)
+        return
+    if args.workload == "serve3":
+        ctx = lrpr.Context(0)
+        res = c4_bench(ctx, lrpr, inputs, args)
+        sus = res["sustained"]
+        print(json.dumps({"metric": "fine-propagator RHS\u00b7steps/s; rSVD build s; served solve p50/p99 latency",
+                          "value": res["capacity_solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1,
+                          "warmup": 0, "ms_per_step": sus["wall_s"] * 1000.0, "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": res["workload"]}, "serve3": res}), flush=True)
         return
     if args.workload == "uneven48":
         ctx = lrpr.Context(0)
