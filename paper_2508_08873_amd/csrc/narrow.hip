@@ -31,12 +31,30 @@ namespace {
 constexpr int NW = 8;          // waves per workgroup
 constexpr int NBULK = NW - 1;  // bulk waves
 
-// reduce over the four lane groups (lanes m, m+16, m+32, m+48)
-template <typename T>
-__device__ __forceinline__ T group_sum(T v) {
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
+// reduce over the four lane groups (lanes m, m+16, m+32, m+48) with the
+// row-swapping permutes of the vector ALU (no LDS round trip): after the
+// 16-lane swap every lane holds x_r + x_(r^1) of its row pair, after the
+// 32-lane swap (x_0 + x_1) + (x_2 + x_3), the order of a butterfly over
+// lane distances 16 and 32
+__device__ __forceinline__ float group_sum(float v) {
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    const float s = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+__device__ __forceinline__ double group_sum(double v) {
+    auto swap_add = [](double x, bool wide) {
+        const unsigned lo = (unsigned)(__double_as_longlong(x) & 0xffffffffull);
+        const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(x) >> 32);
+        const auto a = wide ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                            : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto b = wide ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                            : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        const double x0 = __longlong_as_double((long long)(((unsigned long long)b[0] << 32) | a[0]));
+        const double x1 = __longlong_as_double((long long)(((unsigned long long)b[1] << 32) | a[1]));
+        return x0 + x1;
+    };
+    return swap_add(swap_add(v, false), true);
 }
 
 template <typename T, int NC, int TMAX, int PD, bool ASC>
@@ -95,8 +113,8 @@ __device__ __forceinline__ void narrow_pass(const SweepItem &it, const T *__rest
                         t = group_sum(t);
                         T a = 0;
 #pragma unroll
-                        for (int b = 0; b < NBULK; ++b) a += rd[(b * 16 + m) * NC + c];
-                        v[c] = rd[(NBULK * 16 + m) * NC + c] - (a + t);   // D r - (partials + newest)
+                        for (int b = 0; b < NBULK; ++b) a += rd[(m * (NBULK + 1) + b) * NC + c];
+                        v[c] = rd[(m * (NBULK + 1) + NBULK) * NC + c] - (a + t);   // D r - (partials + newest)
                     }
                     const int sq = slot(q);
                     if (lane < 16) {
@@ -217,7 +235,7 @@ __device__ __forceinline__ void narrow_pass(const SweepItem &it, const T *__rest
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
                         const T s = group_sum(p[c]);
-                        if (lane < 16) rd[(wb * 16 + m) * NC + c] = s;
+                        if (lane < 16) rd[(m * (NBULK + 1) + wb) * NC + c] = s;
                     }
                     if (dr) {
 #pragma unroll
@@ -227,7 +245,7 @@ __device__ __forceinline__ void narrow_pass(const SweepItem &it, const T *__rest
                             for (int kc = 0; kc < 4; ++kc)
                                 d += db[u % SD][kc] * (xb[u % SD][c][kc] + fs[c] * fb[u % SD][c][kc]);
                             d = group_sum(d);
-                            if (lane < 16) rd[(NBULK * 16 + m) * NC + c] = d;
+                            if (lane < 16) rd[(m * (NBULK + 1) + NBULK) * NC + c] = d;
                         }
                     }
                     lds_barrier();
