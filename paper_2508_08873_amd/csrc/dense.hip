@@ -473,62 +473,80 @@ __global__ __launch_bounds__(256) void k_signfix(const SignJob *jobs) {
 //   combine: g = U coef;  then either out = g, or the correction
 //            u_new = Fu + g - gold, gold = g, with per-chunk partial sums of
 //            ||u_new - u_old||^2 for the increment.
-// x, out, Fu, gold, u: n x w column-major (ld n).  Chunks are 256 rows (one
-// per thread), so that a 65025-row slice spreads over 255 workgroups; every
-// reduction runs in a fixed order, independent of w and of the other columns.
+// x, out, Fu, gold, u: n x w column-major (ld n).  Chunks are 256 rows, so
+// that a 65025-row slice spreads over 255 workgroups; every reduction runs in
+// a fixed order, independent of w and of the other columns.
 // ---------------------------------------------------------------------------
 constexpr int LR_CHUNK = 256;
 constexpr int LR_THREADS = 256;
-constexpr int LR_RB = 8;    // rank block of the dots tile
-constexpr int LR_CB = 8;    // column block
-constexpr int LR_UB = 16;   // U rows in flight per batch (combine)
 constexpr int LR_RED = 16;  // waves of the chunk reductions
 
-// part[chunk][r*w + c] = sum over the chunk's rows of V[i][r] x[i][c]
+typedef double lr_v4d __attribute__((ext_vector_type(4)));
+constexpr int LR_SUB = 32;   // chunk rows staged in LDS per pass (dots)
+constexpr int LR_WC = 64;    // columns per pass (dots)
+
+// part[chunk][r*w + c] = sum over the chunk's rows of V[i][r] x[i][c], on the
+// matrix cores: output tiles of 16 ranks x 16 columns, each accumulating
+// V^T (16 x 4) times x (4 x 16) over the chunk's rows in order (4 rows per
+// product).  The chunk's rows pass through LDS 32 at a time (loads along the
+// columns, consecutive threads on consecutive rows).  An output element sums
+// only its own rank's and column's products, in an order fixed by the row
+// index, so it does not depend on w or on the other columns.
 __global__ __launch_bounds__(LR_THREADS) void k_lr_dots(LrArgs a) {
-    __shared__ double red[LR_THREADS / 64][LR_RB * LR_CB];
-    const int64_t i = (int64_t)blockIdx.x * LR_CHUNK + threadIdx.x;
-    const bool in = i < a.n;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nk = a.k * a.w;
-    for (int cb = 0; cb < a.w; cb += LR_CB) {
-        double xx[LR_CB];
+    __shared__ double Vs[LR_SUB][LMAX + 1];
+    __shared__ double Xs[LR_SUB][LR_WC + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int g = lane >> 4, m = lane & 15;
+    const int64_t i0 = (int64_t)blockIdx.x * LR_CHUNK;
+    const int K = a.k, W = a.w, nk = K * W;
+    const int RT = (K + 15) / 16;
+    constexpr int TPW = (LMAX / 16) * (LR_WC / 16) / (LR_THREADS / 64);   // output tiles per wave
+    for (int cb = 0; cb < W; cb += LR_WC) {
+        const int wc = W - cb < LR_WC ? W - cb : LR_WC;
+        const int CT = (wc + 15) / 16, ntile = RT * CT;
+        lr_v4d acc[TPW];
 #pragma unroll
-        for (int q = 0; q < LR_CB; ++q)
-            xx[q] = (!in || cb + q >= a.w) ? 0.0 : a.cu ? a.cu[cb + q][a.coff + i] : a.x[i + (int64_t)(cb + q) * a.n];
-        double vv[LR_RB];
-#pragma unroll
-        for (int p = 0; p < LR_RB; ++p) vv[p] = (in && p < a.k) ? a.V[i + (int64_t)p * a.n] : 0.0;
-        for (int rb = 0; rb < a.k; rb += LR_RB) {
-            // next rank block in flight while this one reduces
-            double vn[LR_RB];
-#pragma unroll
-            for (int p = 0; p < LR_RB; ++p) {
-                const int r = rb + LR_RB + p;
-                vn[p] = (in && r < a.k) ? a.V[i + (int64_t)r * a.n] : 0.0;
+        for (int t = 0; t < TPW; ++t) acc[t] = lr_v4d{0, 0, 0, 0};
+        for (int sub = 0; sub < LR_CHUNK; sub += LR_SUB) {
+            for (int e = tid; e < LR_SUB * K; e += LR_THREADS) {
+                const int r = e / LR_SUB, ii = e % LR_SUB;
+                const int64_t i = i0 + sub + ii;
+                Vs[ii][r] = i < a.n ? a.V[i + (int64_t)r * a.n] : 0.0;
             }
-#pragma unroll
-            for (int p = 0; p < LR_RB; ++p)
-#pragma unroll
-                for (int q = 0; q < LR_CB; ++q)
-                    if (rb + p < a.k && cb + q < a.w) {   // uniform
-                        double v = vv[p] * xx[q];
-                        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-                        if (lane == 0) red[wv][p * LR_CB + q] = v;
-                    }
+            for (int e = tid; e < LR_SUB * wc; e += LR_THREADS) {
+                const int c = e / LR_SUB, ii = e % LR_SUB;
+                const int64_t i = i0 + sub + ii;
+                Xs[ii][c] = i >= a.n ? 0.0 : a.cu ? a.cu[cb + c][a.coff + i] : a.x[i + (int64_t)(cb + c) * a.n];
+            }
             __syncthreads();
-            if (threadIdx.x < LR_RB * LR_CB) {
-                const int p = threadIdx.x / LR_CB, q = threadIdx.x % LR_CB;
-                if (rb + p < a.k && cb + q < a.w) {
-                    double sum = 0.0;
 #pragma unroll
-                    for (int t = 0; t < LR_THREADS / 64; ++t) sum += red[t][threadIdx.x];
-                    a.part[(int64_t)blockIdx.x * nk + (rb + p) * a.w + cb + q] = sum;
+            for (int t = 0; t < TPW; ++t) {
+                const int tt = wv + (LR_THREADS / 64) * t;
+                if (tt < ntile) {
+                    const int r = (tt / CT) * 16 + m, c = (tt % CT) * 16 + m;
+                    // A[m][kk] = V[row kk][rank m] in lane m + 16 kk; B[kk][n] = x[row kk][column n]
+#pragma unroll
+                    for (int ks = 0; ks < LR_SUB / 4; ++ks) {
+                        const int row = 4 * ks + g;
+                        const double av = r < K ? Vs[row][r] : 0.0;
+                        const double bv = c < wc ? Xs[row][c] : 0.0;
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+                    }
                 }
             }
             __syncthreads();
+        }
+        // D[mm][n] in lane n + 16 (mm % 4), register mm / 4
 #pragma unroll
-            for (int p = 0; p < LR_RB; ++p) vv[p] = vn[p];
+        for (int t = 0; t < TPW; ++t) {
+            const int tt = wv + (LR_THREADS / 64) * t;
+            if (tt < ntile) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = (tt / CT) * 16 + 4 * q + g, c = (tt % CT) * 16 + m;
+                    if (r < K && c < wc) a.part[(int64_t)blockIdx.x * nk + r * W + cb + c] = acc[t][q];
+                }
+            }
         }
     }
 }
@@ -560,89 +578,89 @@ __global__ __launch_bounds__(64 * LR_RED) void k_lr_coef(const double *part, int
 // Columns with active[c] == 0 are left untouched (modes 1, 2).  With column
 // tables the mode is per column (and 0 means untouched); increments are
 // written for every column (zero unless mode 2).
+// On the matrix cores: each wave takes 64 of the chunk's rows (4 tiles of 16)
+// and forms g^T tile by tile, coef^T (16 columns x 4 ranks, from LDS) times
+// U^T (4 ranks x 16 rows, read along the rows), so that a lane ends with one
+// row of four columns and the epilogue reads and writes along the rows.
+// Every element's sum and every increment's order are fixed by the rank and
+// row indices alone.
 __global__ __launch_bounds__(LR_THREADS) void k_lr_combine(LrArgs a) {
     extern __shared__ double coef[];   // [k*w]
-    __shared__ double red[LR_THREADS / 64][LR_CB];
-    const int nk = a.k * a.w;
+    __shared__ double red[LR_THREADS / 64][16];
+    const int K = a.k, W = a.w, nk = K * W;
     for (int e = threadIdx.x; e < nk; e += LR_THREADS) coef[e] = a.coef[e];
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * LR_CHUNK + threadIdx.x;
-    const bool in = i < a.n;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int g = lane >> 4, nr = lane & 15;
+    const int64_t i0 = (int64_t)blockIdx.x * LR_CHUNK;
     const bool incs = a.mode == 2 || a.cu;
-    for (int cb = 0; cb < a.w; cb += LR_CB) {
-        double inc[LR_CB];
-        // per-column operands: u (x) and out, gold, bvec / Fu, mode
-        double *outp[LR_CB], *goldp[LR_CB];
-        const double *bp[LR_CB];
-        const float *fp32[LR_CB];
-        int md[LR_CB];
-#pragma unroll
-        for (int q = 0; q < LR_CB; ++q) {
-            inc[q] = 0.0;
-            const int cc = cb + q < a.w ? cb + q : a.w - 1;
-            if (a.cu) {
-                outp[q] = a.cu[cc] + a.coff + a.n;
-                goldp[q] = a.cgold[cc] + a.coff;
-                bp[q] = a.cfu[cc] + a.coff;
-                fp32[q] = nullptr;
-                md[q] = cb + q < a.w ? a.cmode[cc] : 0;
-            } else {
-                const int64_t o = (int64_t)cc * a.n;
-                outp[q] = a.out + o;
-                goldp[q] = a.gold ? a.gold + o : nullptr;
-                bp[q] = a.mode == 1 ? (a.bvec ? a.bvec + o : nullptr) : (a.fu64 ? a.fu64 + o : nullptr);
-                fp32[q] = a.fu32 ? a.fu32 + o : nullptr;
-                md[q] = cb + q >= a.w ? -1 : (a.mode != 0 && a.active && !a.active[cc]) ? -1 : a.mode;
-                if (a.mode == 0 && cb + q < a.w) md[q] = 0;
+    for (int c0 = 0; c0 < W; c0 += 16) {
+        double incv[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < LR_CHUNK / 64; ++q) {
+            const int64_t rbase = i0 + (int64_t)(wv * (LR_CHUNK / 64) + q) * 16;
+            lr_v4d acc = {0, 0, 0, 0};
+            for (int r0 = 0; r0 < K; r0 += 4) {
+                const int r = r0 + g;
+                const int64_t iu = rbase + nr;
+                const double av = (r < K && c0 + nr < W) ? coef[r * W + c0 + nr] : 0.0;
+                const double bv = (r < K && iu < a.n) ? a.U[iu + (int64_t)r * a.n] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
             }
-        }
-        if (in) {
-            double gs[LR_CB];
+            // element (column c0 + 4 reg + g, row rbase + nr) in register reg
+            const int64_t i = rbase + nr;
+            if (i >= a.n) continue;
 #pragma unroll
-            for (int q = 0; q < LR_CB; ++q) gs[q] = 0.0;
-            for (int r0 = 0; r0 < a.k; r0 += LR_UB) {
-                double u[LR_UB];
-#pragma unroll
-                for (int p = 0; p < LR_UB; ++p) u[p] = r0 + p < a.k ? a.U[i + (int64_t)(r0 + p) * a.n] : 0.0;
-#pragma unroll
-                for (int p = 0; p < LR_UB; ++p)
-                    if (r0 + p < a.k)
-#pragma unroll
-                        for (int q = 0; q < LR_CB; ++q)
-                            if (cb + q < a.w) gs[q] += u[p] * coef[(r0 + p) * a.w + cb + q];
-            }
-#pragma unroll
-            for (int q = 0; q < LR_CB; ++q) {
-                const int m = md[q];
-                if (a.cu ? m == 0 : m < 0) continue;
-                if (!a.cu && m == 0) {
-                    outp[q][i] = gs[q];
-                } else if (m == 1) {
-                    goldp[q][i] = gs[q];
-                    outp[q][i] = gs[q] + (bp[q] ? bp[q][i] : 0.0);
+            for (int reg = 0; reg < 4; ++reg) {
+                const int c = c0 + 4 * reg + g;
+                if (c >= W) continue;
+                const double gs = acc[reg];
+                double *outp, *goldp;
+                const double *bp;
+                const float *fp32 = nullptr;
+                int md;
+                if (a.cu) {
+                    outp = a.cu[c] + a.coff + a.n;
+                    goldp = a.cgold[c] + a.coff;
+                    bp = a.cfu[c] + a.coff;
+                    md = a.cmode[c];
+                    if (md == 0) continue;
                 } else {
-                    const double fu = fp32[q] ? (double)fp32[q][i] : bp[q][i];
-                    const double un = fu + gs[q] - goldp[q][i];
-                    const double d = un - outp[q][i];
-                    inc[q] += d * d;
-                    outp[q][i] = un;
-                    goldp[q][i] = gs[q];
+                    const int64_t o = (int64_t)c * a.n;
+                    outp = a.out + o;
+                    goldp = a.gold ? a.gold + o : nullptr;
+                    bp = a.mode == 1 ? (a.bvec ? a.bvec + o : nullptr) : (a.fu64 ? a.fu64 + o : nullptr);
+                    fp32 = a.fu32 ? a.fu32 + o : nullptr;
+                    md = (a.mode != 0 && a.active && !a.active[c]) ? -1 : a.mode;
+                    if (md < 0) continue;
+                }
+                if (!a.cu && md == 0) {
+                    outp[i] = gs;
+                } else if (md == 1) {
+                    goldp[i] = gs;
+                    outp[i] = gs + (bp ? bp[i] : 0.0);
+                } else {
+                    const double fu = fp32 ? (double)fp32[i] : bp[i];
+                    const double un = fu + gs - goldp[i];
+                    const double d = un - outp[i];
+                    incv[reg] += d * d;
+                    outp[i] = un;
+                    goldp[i] = gs;
                 }
             }
         }
         if (incs) {
+            // sum over the 16 rows of a lane group, then over the waves
 #pragma unroll
-            for (int q = 0; q < LR_CB; ++q) {
-                double v = inc[q];
-                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-                if (lane == 0) red[wv][q] = v;
+            for (int reg = 0; reg < 4; ++reg) {
+                double v = incv[reg];
+                for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
+                if (nr == 0) red[wv][4 * reg + g] = v;
             }
             __syncthreads();
-            if (threadIdx.x < LR_CB && cb + threadIdx.x < a.w) {
+            if (tid < 16 && c0 + tid < W) {
                 double sum = 0.0;
-                for (int t = 0; t < LR_THREADS / 64; ++t) sum += red[t][threadIdx.x];
-                a.incpart[(int64_t)blockIdx.x * a.w + cb + threadIdx.x] = sum;
+                for (int t = 0; t < LR_THREADS / 64; ++t) sum += red[t][tid];
+                a.incpart[(int64_t)blockIdx.x * W + c0 + tid] = sum;
             }
             __syncthreads();
         }
