@@ -177,7 +177,14 @@ __global__ __launch_bounds__(256) void k_chol(const int *ls, const double *G, do
 // row; outputs in chunks of 32 columns.  With upper != 0, B is upper
 // triangular (only k <= j terms are summed).
 // ---------------------------------------------------------------------------
-constexpr int RM_CB = 32;   // output columns per pass over a row of A
+// C = A B on the matrix cores, as C^T tiles: B^T (16 columns x 4 of l, from
+// LDS) times A^T (4 of l x 16 rows, read along the rows of A), so a lane ends
+// with one row of four output columns and the stores run along the rows.
+// Each wave takes 64 of a workgroup's 256 rows (four tiles of 16) and every
+// column tile of the output; with `upper` (B upper triangular) the products
+// past a column tile's last column are skipped (they are zero).
+constexpr int RM_ROWS = 256;   // rows per workgroup pass
+constexpr int RM_CT = LMAX / 16;   // most column tiles
 
 template <typename TA, typename TC>
 __global__ __launch_bounds__(256) void k_rowmat(const RowMatJob *jobs) {
@@ -202,22 +209,43 @@ __global__ __launch_bounds__(256) void k_rowmat(const RowMatJob *jobs) {
     __syncthreads();
     const TA *A = (const TA *)jb.A;
     TC *C = (TC *)jb.C;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < jb.n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        for (int j0 = 0; j0 < jb.nc; j0 += RM_CB) {
-            double acc[RM_CB];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, nr = lane & 15;
+    const int l = jb.l, nc = jb.nc, nct = (nc + 15) / 16;
+    for (int64_t base = (int64_t)blockIdx.x * RM_ROWS; base < jb.n; base += (int64_t)gridDim.x * RM_ROWS) {
+        for (int q = 0; q < RM_ROWS / 64; ++q) {
+            const int64_t row = base + (int64_t)(wv * (RM_ROWS / 64) + q) * 16 + nr;
+            typedef double v4 __attribute__((ext_vector_type(4)));
+            v4 acc[RM_CT];
 #pragma unroll
-            for (int jj = 0; jj < RM_CB; ++jj) acc[jj] = 0.0;
-            const int kend = jb.upper ? ((j0 + RM_CB < jb.l) ? j0 + RM_CB : jb.l) : jb.l;
-#pragma unroll 4
-            for (int k = 0; k < kend; ++k) {
-                const double av = ld_as_double(A, i + (int64_t)k * jb.lda);
+            for (int t = 0; t < RM_CT; ++t) acc[t] = v4{0, 0, 0, 0};
+            // the k range that any column tile reads
+            const int kend = jb.upper ? (nct * 16 < l ? nct * 16 : l) : l;
+            for (int k0 = 0; k0 < kend; k0 += 4) {
+                const int k = k0 + g;
+                const double bv = (k < l && row < jb.n) ? ld_as_double(A, row + (int64_t)k * jb.lda) : 0.0;
 #pragma unroll
-                for (int jj = 0; jj < RM_CB; ++jj) acc[jj] += av * Bs[k * LMAX + j0 + jj];
+                for (int t = 0; t < RM_CT; ++t) {
+                    if (t < nct && !(jb.upper && k0 > 16 * t + 15)) {
+                        const int col = 16 * t + nr;
+                        const double av = (k < l && col < nc) ? Bs[k * LMAX + col] : 0.0;
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+                    }
+                }
             }
+            // element (column 16 t + 4 reg + g, row) in register reg of tile t
+            if (row < jb.n) {
 #pragma unroll
-            for (int jj = 0; jj < RM_CB; ++jj)
-                if (j0 + jj < jb.nc) C[i + (int64_t)(j0 + jj) * jb.ldc] = (TC)acc[jj];
+                for (int t = 0; t < RM_CT; ++t) {
+                    if (t < nct) {
+#pragma unroll
+                        for (int reg = 0; reg < 4; ++reg) {
+                            const int col = 16 * t + 4 * reg + g;
+                            if (col < nc) C[row + (int64_t)col * jb.ldc] = (TC)acc[t][reg];
+                        }
+                    }
+                }
+            }
         }
     }
 }
@@ -859,7 +887,7 @@ hipError_t launch_chol(const int *d_ls, int nslices, const double *G, double *R,
 }
 
 hipError_t launch_rowmat(int ta, int tc, const RowMatJob *d_jobs, int njobs, int64_t nmax, hipStream_t s) {
-    dim3 grid(blocks_for(nmax, 256) > 2048 ? 2048 : blocks_for(nmax, 256), njobs);
+    dim3 grid(blocks_for(nmax, RM_ROWS) > 2048 ? 2048 : blocks_for(nmax, RM_ROWS), njobs);
     if (ta == 0 && tc == 0) hipLaunchKernelGGL((k_rowmat<double, double>), grid, dim3(256), 0, s, d_jobs);
     else if (ta == 1 && tc == 0) hipLaunchKernelGGL((k_rowmat<float, double>), grid, dim3(256), 0, s, d_jobs);
     else if (ta == 0 && tc == 1) hipLaunchKernelGGL((k_rowmat<double, float>), grid, dim3(256), 0, s, d_jobs);
