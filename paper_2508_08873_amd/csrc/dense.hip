@@ -185,10 +185,11 @@ __global__ __launch_bounds__(256) void k_chol(const int *ls, const double *G, do
 // past a column tile's last column are skipped (they are zero).
 constexpr int RM_ROWS = 256;   // rows per workgroup pass
 constexpr int RM_CT = LMAX / 16;   // most column tiles
+constexpr int RM_LD = LMAX + 2;    // LDS row stride of B (rows k and k+1 on different banks)
 
 template <typename TA, typename TC>
-__global__ __launch_bounds__(256) void k_rowmat(const RowMatJob *jobs) {
-    __shared__ double Bs[LMAX * LMAX];
+__global__ __launch_bounds__(256, 2) void k_rowmat(const RowMatJob *jobs) {
+    __shared__ double Bs[LMAX * RM_LD];
     const RowMatJob jb = jobs[blockIdx.y];
     {   // rows k < l of B (the only ones read), four loads in flight per thread
         const int tot = jb.l * LMAX;
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(256) void k_rowmat(const RowMatJob *jobs) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x;
-                if (e < tot) Bs[e] = v[u];
+                if (e < tot) Bs[(e / LMAX) * RM_LD + e % LMAX] = v[u];
             }
         }
     }
@@ -219,17 +220,33 @@ __global__ __launch_bounds__(256) void k_rowmat(const RowMatJob *jobs) {
             v4 acc[RM_CT];
 #pragma unroll
             for (int t = 0; t < RM_CT; ++t) acc[t] = v4{0, 0, 0, 0};
-            // the k range that any column tile reads
+            // the k range that any column tile reads; this lane's values of A
+            // for every k step are loaded first, all in flight together
             const int kend = jb.upper ? (nct * 16 < l ? nct * 16 : l) : l;
-            for (int k0 = 0; k0 < kend; k0 += 4) {
-                const int k = k0 + g;
-                const double bv = (k < l && row < jb.n) ? ld_as_double(A, row + (int64_t)k * jb.lda) : 0.0;
+            // (unconditional loads of clamped, valid addresses: a load under
+            // a lane condition would be waited for before the next one)
+            typedef __attribute__((address_space(1))) const TA *gA;
+            const int64_t rc = row < jb.n ? row : jb.n - 1;
+            TA raw[LMAX / 4];
 #pragma unroll
-                for (int t = 0; t < RM_CT; ++t) {
-                    if (t < nct && !(jb.upper && k0 > 16 * t + 15)) {
-                        const int col = 16 * t + nr;
-                        const double av = (k < l && col < nc) ? Bs[k * LMAX + col] : 0.0;
-                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+            for (int ks = 0; ks < LMAX / 4; ++ks) {
+                const int k = 4 * ks + g < l ? 4 * ks + g : l - 1;
+                if (4 * ks < kend) raw[ks] = *(gA)(A + rc + (int64_t)k * jb.lda);
+            }
+            // (rows past n read row n-1 and k past l read column l-1: finite
+            // values that meet only zero entries of B or land in rows that
+            // are not stored)
+#pragma unroll
+            for (int ks = 0; ks < LMAX / 4; ++ks) {
+                if (4 * ks < kend) {
+                    const int k = 4 * ks + g;
+#pragma unroll
+                    for (int t = 0; t < RM_CT; ++t) {
+                        if (t < nct && !(jb.upper && 4 * ks > 16 * t + 15)) {
+                            const int col = 16 * t + nr;
+                            const double av = (k < l && col < nc) ? Bs[k * RM_LD + col] : 0.0;
+                            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, (double)raw[ks], acc[t], 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -627,12 +644,25 @@ __global__ __launch_bounds__(LR_THREADS) void k_lr_combine(LrArgs a) {
         for (int q = 0; q < LR_CHUNK / 64; ++q) {
             const int64_t rbase = i0 + (int64_t)(wv * (LR_CHUNK / 64) + q) * 16;
             lr_v4d acc = {0, 0, 0, 0};
-            for (int r0 = 0; r0 < K; r0 += 4) {
-                const int r = r0 + g;
-                const int64_t iu = rbase + nr;
-                const double av = (r < K && c0 + nr < W) ? coef[r * W + c0 + nr] : 0.0;
-                const double bv = (r < K && iu < a.n) ? a.U[iu + (int64_t)r * a.n] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            // this lane's U values for every rank step, all loads in flight
+            const int64_t iu = rbase + nr;
+            const int64_t iuc = iu < a.n ? iu : a.n - 1;
+            typedef __attribute__((address_space(1))) const double *gD;
+            double raw[LMAX / 4];
+#pragma unroll
+            for (int ks = 0; ks < LMAX / 4; ++ks) {
+                const int r = 4 * ks + g < K ? 4 * ks + g : K - 1;
+                if (4 * ks < K) raw[ks] = *(gD)(a.U + iuc + (int64_t)r * a.n);
+            }
+            // (rows past n read row n-1 and ranks past k rank k-1: finite
+            // values that meet zero coefficients or land in rows not written)
+#pragma unroll
+            for (int ks = 0; ks < LMAX / 4; ++ks) {
+                if (4 * ks < K) {
+                    const int r = 4 * ks + g;
+                    const double av = (r < K && c0 + nr < W) ? coef[r * W + c0 + nr] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, raw[ks], acc, 0, 0, 0);
+                }
             }
             // element (column c0 + 4 reg + g, row rbase + nr) in register reg
             const int64_t i = rbase + nr;
