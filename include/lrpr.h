@@ -112,7 +112,7 @@ lrpr_status lrpr_ctx_release_workspaces(lrpr_ctx ctx);
  *                            (0 = the library's choice; clipped to nb + 9,
  *                            nb = ceil(b/16) band tiles);
  *   LRPR_TUNE_LU_BUDGET      bytes of FP64 bands and LU scratch that
- *                            lrpr_factor_many holds at once (0 = 96e9);
+ *                            lrpr_factor_many holds at once (0 = 110e9);
  *   LRPR_TUNE_PARAREAL_GRAPH 1 (default): a Parareal iteration is captured
  *                            once in a HIP graph and replayed; 0: its
  *                            kernels are launched one by one;
@@ -140,8 +140,9 @@ lrpr_status lrpr_tune_get(lrpr_ctx ctx, int param, int64_t *value);
 /* Autotuner of the batched band LU for a later lrpr_factor_many of `count`
  * operators on op's grid: factors copies of *op, as many as one chunk of
  * that call holds (store_mask as given), once per candidate number of
- * workgroups per matrix (nb + 9 and narrower ones that let more matrices
- * share a launch), after one untimed run, timed with HIP events; keeps the
+ * workgroups per matrix (the default choice, nb + 9 and narrower ones that
+ * let more matrices share a launch), after one untimed run, timed with HIP
+ * events; keeps the
  * fastest as the context's LRPR_TUNE_LU_WGS and returns it (best_wgs,
  * best_ms may be NULL).  The factors do not depend on the choice.
  * Synchronises.  Errors: as lrpr_factor_many. */
@@ -277,6 +278,22 @@ lrpr_status lrpr_factor_info(lrpr_fac f, int64_t *n, int *bw, double *dt);
  * entry (i, j) of L (j < i, unit diagonal not stored) or U (j >= i) at
  * lu_host[i*(2*bw+1) + j - i + bw].  Synchronises. */
 lrpr_status lrpr_factor_copy_lu(lrpr_ctx ctx, lrpr_fac f, double *lu_host);
+/* Copy the packed band tiles that the sweeps read (Sec. 4.4: the factors
+ * reused by every solve), kept with LRPR_STORE_F64 or LRPR_STORE_F32:
+ * set 0 = the lower factor's tiles L(I,I)^{-1} L(I, I-nb+j), set 1 = the
+ * upper factor's U(I,I)^{-1} U(I, I+1+j), for tile rows I = 0..NT-1 and
+ * j = 0..nb-1 (16x16 tiles, NT = ceil(n/16), nb = ceil(bw/16)).  Tile
+ * (I, j) starts at element (I*nb + j)*256 of host; entry (r, k) of a tile
+ * sits at 128*(k/8) + 2*(16*(k%4) + r) + (k/4)%2 (FP64) or
+ * 4*(16*(k/4) + r) + k%4 (FP32), the matrix cores' A-operand order.  The
+ * FP32 tiles are the FP64 products rounded row by row (a row = the 16 nb
+ * entries of one matrix row) with the row sum kept: every entry rounded,
+ * the FP64 sum of the rounding errors added to the largest entry, and what
+ * that entry's rounding leaves added to the smallest entry of at least
+ * 2^-12 of the largest (ties: the first entry in j, k order).
+ * host: NT*nb*256 elements of the precision.  Synchronises.
+ * Errors: LRPR_ERR_ARG (null argument, set not 0 or 1, precision not kept). */
+lrpr_status lrpr_factor_copy_tiles(lrpr_ctx ctx, lrpr_fac f, int set, lrpr_prec prec, void *host);
 
 /* ---- batched fine propagator and its adjoint (Sec. 2, Sec. 2.1) --------- */
 

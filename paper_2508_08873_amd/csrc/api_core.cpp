@@ -497,15 +497,16 @@ lrpr_status lrpr_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int store_mask, lr
 }  // extern "C"
 
 // Matrices lrpr_factor_many factors together: as many as the workspace
-// budget holds (FP64 band and LU scratch per matrix; 96 GB by default), at
-// most 64, in equal chunks; each chunk's band LUs run in as few launches as
-// its size allows.
+// budget holds (FP64 band and LU scratch per matrix; 110 GB by default,
+// which takes 32 matrices of 511^2 at once: one launch of 8 workgroups
+// each), at most 64, in equal chunks; each chunk's band LUs run in as few
+// launches as its size allows.
 static int many_chunk(lrpr_ctx ctx, const lrpr_op_desc &op, int count, int store_mask) {
     const int64_t n = op.dim == 1 ? op.nx : (int64_t)op.nx * op.nx;
     const int bw = op.dim == 1 ? 1 : op.nx;
     const int NT = (int)((n + TILE - 1) / TILE), nb = (bw + TILE - 1) / TILE;
     const double per_matrix = 8.0 * (double)n * (2 * bw + 1) + (double)tile_lu_scratch_bytes(NT, nb);
-    const double budget = ctx->tune_lu_budget ? (double)ctx->tune_lu_budget : 96e9;
+    const double budget = ctx->tune_lu_budget ? (double)ctx->tune_lu_budget : 110e9;
     int chunk = (int)std::max(1.0, std::min(64.0, budget / std::max(per_matrix, 1.0)));
     if (store_mask & LRPR_STORE_UL) chunk = std::max(1, chunk / 2);
     const int nchunk = (count + chunk - 1) / chunk;
@@ -582,20 +583,21 @@ lrpr_status lrpr_autotune_factor(lrpr_ctx ctx, const lrpr_op_desc *op, int count
     const int bw = op->dim == 1 ? 1 : op->nx;
     const int NT = (int)((n + TILE - 1) / TILE), nb = (bw + TILE - 1) / TILE;
     const int full = std::min(nb + 9, NT);
-    // candidates: the full width and narrower ones that fit more matrices
-    // into a launch; each times one factor_many of `count` copies of op
-    std::vector<int> cand;
-    for (int c : {full, 24, 16, 12, 8, 6, 4})
-        if (c <= full && c >= 1 && std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    HIPCHK(hipSetDevice(ctx->dev), "hipSetDevice");
     // one chunk of a factor_many of `count` operators
     const int cnt = many_chunk(ctx, *op, count, store_mask);
+    // candidates: the default choice for the chunk, the full width and
+    // narrower ones that fit more matrices into a launch; each times one
+    // factor_many of the chunk's `cnt` copies of op
+    std::vector<int> cand;
+    for (int c : {tile_lu_wgs(cnt, NT, nb, 0, tile_lu_resident(nb)), full, 24, 16, 12, 8, 6, 4})
+        if (c <= full && c >= 1 && std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
     std::vector<lrpr_op_desc> ops(cnt, *op);
     std::vector<lrpr_fac> outs(cnt, nullptr);
     const int saved = ctx->tune_lu_wgs;
     int best = 0;
     double best_t = 1e300;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIPCHK(hipSetDevice(ctx->dev), "hipSetDevice");
     HIPCHK(hipEventCreate(&e0), "event");
     HIPCHK(hipEventCreate(&e1), "event");
     lrpr_status r = LRPR_OK;
@@ -698,6 +700,19 @@ lrpr_status lrpr_factor_copy_lu(lrpr_ctx ctx, lrpr_fac f, double *lu_host) {
     HIPCHK(hipMemcpyAsync(lu_host, f->lu, sizeof(double) * (size_t)f->n * (2 * f->bw + 1),
                           hipMemcpyDeviceToHost, ctx->stream),
            "copy LU");
+    HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+    return LRPR_OK;
+}
+
+lrpr_status lrpr_factor_copy_tiles(lrpr_ctx ctx, lrpr_fac f, int set, lrpr_prec prec, void *host) {
+    if (!ctx || !f || !host || (set != 0 && set != 1) || (prec != LRPR_F64 && prec != LRPR_F32))
+        return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_copy_tiles: invalid arguments");
+    const bool f32 = prec == LRPR_F32;
+    const void *src = (f32 ? f->t32 : f->t64).a[set == 0 ? TS_LB : TS_UB];
+    if (!src) return fail(ctx, LRPR_ERR_ARG, "lrpr_factor_copy_tiles: factor kept without tiles of that precision");
+    const size_t bytes = (f32 ? 4 : 8) * (size_t)f->NT * f->nb * TILE_ELEMS;
+    HIPCHK(hipSetDevice(ctx->dev), "hipSetDevice");
+    HIPCHK(hipMemcpyAsync(host, src, bytes, hipMemcpyDeviceToHost, ctx->stream), "copy tiles");
     HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
     return LRPR_OK;
 }

@@ -1,5 +1,7 @@
 // Operator assembly and packing of the LU factors into the tiled layout read
 // by the sweep kernels (the LU itself is in lu.hip).
+#include <climits>
+
 #include "lrpr_internal.h"
 #include "tile_ops.h"
 
@@ -264,69 +266,129 @@ __global__ void k_pack_band32(LuAcc F, int NT, int nb, const double *Linv, const
 }
 
 // Band tiles of one tile row per workgroup (256 threads, one per element of
-// a tile), for every requested set (blockIdx.y): the row's diagonal-tile
-// inverse and each 16x16 factor block are staged in LDS, the products
-// (the same sums in the same order as band_elem) go to the FP64 tiles and to
-// an LDS copy of the tile row's 16 x 16 nb values, from which 16 threads
-// round the FP32 rows with their sums kept (round_row_keep_sum).  Replaces
-// one thread per element or per row reading the band entries directly.
+// a tile), for every requested set (blockIdx.y).  The nb 16x16 factor
+// blocks of the row are loaded at once (every load in flight together) and
+// staged in LDS; thread (r, q) forms entry (r, q) of every block's product
+// with the row's diagonal-tile inverse (the same sums in the same order as
+// band_elem: one independent chain per block), for the FP64 tiles and an
+// LDS copy of the tile row's 16 x 16 nb values.  The FP32 rows are rounded
+// by round_row_keep_sum's rule with 16 threads per row (entries l, l + 16,
+// ... for thread l; the rounding errors summed over the 16 threads, ties of
+// the largest and smallest entries going to the lower entry index), and the
+// FP32 tiles are written in their memory order.
+template <int NBMAX>
 __global__ __launch_bounds__(256) void k_pack_rows(LuAcc F, int NT, int nb, const double *Linv, const double *Uinv,
                                                    BandOut o64, BandOut o32) {
-    extern __shared__ double rowv[];   // [16][16 nb]
-    __shared__ double Ds[TILE_ELEMS];
-    __shared__ double Ms[TILE_ELEMS];
+    // dynamic LDS: the factor blocks [nb][16][16] (element (k, q) of block j at
+    // j*256 + 16 k + q), then over them the row values [16][16 nb + 1]
+    extern __shared__ double lds[];
+    __shared__ int s_at[TILE], s_at2[TILE];
+    __shared__ float s_fat[TILE], s_f2[TILE];
     const int a = blockIdx.y;
     if (!o64.b[a] && !o32.b[a]) return;
     const int64_t I = blockIdx.x;
     const int t = threadIdx.x;
     const int64_t base = I * TILE;
-    const double *Di = ((a == 0 || a == 3) ? Linv : Uinv) + I * TILE_ELEMS;
-    Ds[t] = Di[t];
     const int r = t >> 4, q = t & 15;
-    const int W = 16 * nb;
+    const int W = 16 * nb, WS = W + 1;
     // this thread's element of block j, read along the contiguous direction
-    // of the band storage, staged at Ms[sk][sq]
+    // of the band storage, staged at (sk, sq)
     const int sk = a < 2 ? (t >> 4) : (t & 15), sq = a < 2 ? (t & 15) : (t >> 4);
     auto fetch = [&](int j) -> double {
         const int64_t jl = (I - nb + j) * TILE, ju = (I + 1 + j) * TILE;
         if (a < 2) return a == 0 ? F.lower(base + sk, jl + sq) : F.upper(base + sk, ju + sq);
         return a == 2 ? F.upper(jl + sq, base + sk) : F.lower(ju + sq, base + sk);
     };
-    // blocks prefetched PF ahead; the barriers order LDS only, so the loads
-    // stay in flight across them
-    constexpr int PF = 8;
-    double mbuf[PF];
+    {
+        double m[NBMAX];
 #pragma unroll
-    for (int u = 0; u < PF; ++u) mbuf[u] = u < nb ? fetch(u) : 0.0;
-    for (int j0 = 0; j0 < nb; j0 += PF) {
+        for (int j = 0; j < NBMAX; ++j) m[j] = j < nb ? fetch(j) : 0.0;
 #pragma unroll
-        for (int u = 0; u < PF; ++u) {
-            const int j = j0 + u;
-            if (j < nb) {
-                Ms[sk * TILE + sq] = mbuf[u];
-                if (j + PF < nb) mbuf[u] = fetch(j + PF);
-                lds_barrier();
-                double v = 0.0;
-                if (a < 2) {
-                    for (int k = 0; k < TILE; ++k) v += Ds[r * TILE + k] * Ms[k * TILE + q];
-                } else {
-                    for (int k = 0; k < TILE; ++k) v += Ds[k * TILE + r] * Ms[k * TILE + q];
+        for (int j = 0; j < NBMAX; ++j)
+            if (j < nb) lds[j * TILE_ELEMS + sk * TILE + sq] = m[j];
+    }
+    // row r of the diagonal-tile inverse (column r for the transposed sets)
+    const double *Di = ((a == 0 || a == 3) ? Linv : Uinv) + I * TILE_ELEMS;
+    double d[TILE];
+#pragma unroll
+    for (int k = 0; k < TILE; ++k) d[k] = a < 2 ? Di[r * TILE + k] : Di[k * TILE + r];
+    __syncthreads();
+    double v[NBMAX];
+#pragma unroll
+    for (int j = 0; j < NBMAX; ++j) {
+        double x = 0.0;
+        if (j < nb) {
+#pragma unroll
+            for (int k = 0; k < TILE; ++k) x += d[k] * lds[j * TILE_ELEMS + k * TILE + q];
+        }
+        v[j] = x;
+    }
+    __syncthreads();   // every block read: the row values overwrite them
+    double *const rowv = lds;
+#pragma unroll
+    for (int j = 0; j < NBMAX; ++j)
+        if (j < nb) {
+            rowv[r * WS + j * TILE + q] = v[j];
+            if (o64.b[a]) ((double *)o64.b[a])[(I * nb + j) * TILE_ELEMS + aslot(false, r, q)] = v[j];
+        }
+    if (!o32.b[a]) return;
+    __syncthreads();
+    {
+        const int l = q;   // thread l of row r
+        const double *rv = rowv + r * WS;
+        double err = 0.0, amax = 0.0;
+        int imax = INT_MAX;   // none: every entry is zero (or NaN)
+        for (int c = l; c < W; c += TILE) {
+            const double x = rv[c];
+            err += x - (double)(float)x;
+            if (fabs(x) > amax) { amax = fabs(x); imax = c; }
+        }
+#pragma unroll
+        for (int m = 8; m >= 1; m >>= 1) {
+            err += __shfl_xor(err, m, TILE);
+            const double oa = __shfl_xor(amax, m, TILE);
+            const int oi = __shfl_xor(imax, m, TILE);
+            if (oa > amax || (oa == amax && oi < imax)) { amax = oa; imax = oi; }
+        }
+        int at2 = INT_MAX;
+        float fat = 0.f, f2 = 0.f;
+        if (imax != INT_MAX) {
+            const double want = (double)(float)rv[imax] + err;
+            fat = (float)want;
+            const double res = want - (double)fat;
+            if (res != 0.0) {   // row-uniform
+                const double lo = amax * (1.0 / 4096.0);
+                double best = amax;
+                for (int c = l; c < W; c += TILE) {
+                    const double ax = fabs(rv[c]);
+                    if (c != imax && ax >= lo && ax < best) { best = ax; at2 = c; }
                 }
-                const int64_t tile = (I * nb + j) * TILE_ELEMS;
-                if (o64.b[a]) ((double *)o64.b[a])[tile + aslot(false, r, q)] = v;
-                rowv[r * W + j * TILE + q] = v;
-                lds_barrier();
+#pragma unroll
+                for (int m = 8; m >= 1; m >>= 1) {
+                    const double ob = __shfl_xor(best, m, TILE);
+                    const int oi = __shfl_xor(at2, m, TILE);
+                    if (ob < best || (ob == best && oi < at2)) { best = ob; at2 = oi; }
+                }
+                if (at2 != INT_MAX) f2 = (float)((double)(float)rv[at2] + res);
             }
+        }
+        if (l == 0) {
+            s_at[r] = imax;
+            s_at2[r] = at2;
+            s_fat[r] = fat;
+            s_f2[r] = f2;
         }
     }
     __syncthreads();
-    if (o32.b[a] && t < TILE) {
-        const double *rv = rowv + t * W;
-        round_row_keep_sum((float *)o32.b[a], W, [&](int c, int64_t &dst) {
-            const int j = c / TILE, qq = c % TILE;
-            dst = (I * nb + j) * TILE_ELEMS + aslot(true, t, qq);
-            return rv[c];
-        });
+    // the tile row's FP32 tiles are nb * 256 consecutive floats: position p
+    // holds element (r, q) of tile p / 256 (p % 256 = aslot(true, r, q))
+    float *const out = (float *)o32.b[a] + I * nb * TILE_ELEMS;
+    for (int p = t; p < nb * TILE_ELEMS; p += 256) {
+        const int j = p >> 8, sl = p & 255;
+        const int rr = (sl >> 2) & 15, qq = ((sl >> 6) << 2) | (sl & 3);
+        const int c = j * TILE + qq;
+        const float f = c == s_at[rr] ? s_fat[rr] : c == s_at2[rr] ? s_f2[rr] : (float)rowv[rr * WS + c];
+        out[p] = f;
     }
 }
 
@@ -413,8 +475,13 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
         b32.b[a] = t32 ? t32->a[bidx[a]] : nullptr;
     }
     if (nb <= 64) {
-        const size_t lds = sizeof(double) * TILE_ELEMS * (size_t)nb;
-        hipLaunchKernelGGL(k_pack_rows, dim3((unsigned)NT, 4), dim3(256), lds, s, F, NT, nb, Linv, Uinv, b64, b32);
+        const size_t lds = sizeof(double) * (TILE_ELEMS * (size_t)nb + TILE);
+        if (nb <= 32)
+            hipLaunchKernelGGL(k_pack_rows<32>, dim3((unsigned)NT, 4), dim3(256), lds, s, F, NT, nb, Linv, Uinv, b64,
+                               b32);
+        else
+            hipLaunchKernelGGL(k_pack_rows<64>, dim3((unsigned)NT, 4), dim3(256), lds, s, F, NT, nb, Linv, Uinv, b64,
+                               b32);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
         if (t64) {

@@ -238,8 +238,11 @@ hipError_t launch_tile_lu_batch(int count, const int64_t *ns, int bw, int NT, in
                                 void *const *scratch, int **info_dev, int **err_dev, void *d_args, hipStream_t s,
                                 int wgs = 0);
 // workgroups per matrix of a batched LU of count matrices (wgs > 0: that
-// request, clipped to nb + 9 and NT)
-int tile_lu_wgs(int count, int NT, int nb, int wgs);
+// request, clipped to nb + 9 and NT); resident: tile_lu_resident(nb)
+int tile_lu_wgs(int count, int NT, int nb, int wgs, int resident);
+// LU workgroups the current device keeps resident at once (compute units x
+// workgroups per compute unit of the kernel variant for nb)
+int tile_lu_resident(int nb);
 size_t tile_lu_args_bytes(int count);
 // rev: lu is the LU of the reversed matrix (16 NT rows); the sets then hold
 // the UL factors (Lb / DL: the lower factor, Ub / DU: the upper one)

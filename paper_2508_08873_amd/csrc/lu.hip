@@ -19,8 +19,9 @@
 // and the L(I,J) tiles (MFMA A-operand layout) and raises flag[J]; the owner
 // of a later column waits for flag[K] before applying panel K.  Every wait
 // is bounded: on time-out it raises *err and the kernel runs to its end.
-// All P workgroups are resident together (P is a few dozen), and every wait
-// is for a lower column, so the pipeline always drains.
+// All P workgroups are resident together (a launch holds no more workgroups
+// than the device keeps resident at once), and every wait is for a lower
+// column, so the pipeline always drains.
 #include <algorithm>
 #include <vector>
 
@@ -86,6 +87,15 @@ constexpr int PANEL_NB = 32;
 constexpr int PANEL_VECS = PANEL_NB * (TILE_ELEMS / 2) / 256;   // 16-byte vectors per thread (256 threads)
 size_t tile_lu_lds_bytes(int NW, int nb) { return (NW == 4 && nb <= PANEL_NB) ? 2 * (size_t)nb * TILE_ELEMS * 8 : 0; }
 
+// Linear workgroup order in which each XCD holds a contiguous range: the
+// chip deals workgroup b to XCD b % 8, and each XCD has its own L2, so a
+// matrix's workgroups (consecutive in this order) read its panels through
+// one L2.  A bijection on [0, G).
+__device__ __forceinline__ int lu_xcd_linear(int b, int G) {
+    const int q = G >> 3, r = G & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 template <int NW, int TPW>
 __global__ __launch_bounds__(64 * NW) void k_tile_lu(const LuArgs *args, int P) {
     constexpr bool LDSP = NW == 4;
@@ -97,9 +107,10 @@ __global__ __launch_bounds__(64 * NW) void k_tile_lu(const LuArgs *args, int P) 
     __shared__ double sui[256];       // U(J,J)^{-1}, row-major
     __shared__ double st[NW][256];    // per-wave transposition buffer
     __shared__ int s_last;            // last published column seen by wait_upto
-    // workgroups [P*i, P*i + P) factor matrix i of the launch
-    const int wg = blockIdx.x % P;
-    const LuArgs a = args[blockIdx.x / P];
+    // workgroups [P*i, P*i + P) of the XCD-contiguous order factor matrix i
+    const int lin = lu_xcd_linear(blockIdx.x, gridDim.x);
+    const int wg = lin % P;
+    const LuArgs a = args[lin / P];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -364,7 +375,30 @@ size_t tile_lu_scratch_bytes(int NT, int nb) {
     return sizeof(double) * ((size_t)NT * nb + NT) * TILE_ELEMS + sizeof(int) * ((size_t)NT + 2);
 }
 
-int tile_lu_wgs(int count, int NT, int nb, int wgs) {
+// the kernel variant for nb band tiles per row (f gets the kernel and its
+// waves per workgroup)
+template <typename F>
+static hipError_t with_lu_kernel(int nb, F &&f) {
+    if (nb <= 4) return f(k_tile_lu<4, 3>, 4);
+    if (nb <= 16) return f(k_tile_lu<4, 9>, 4);
+    if (nb <= 32) return f(k_tile_lu<4, 17>, 4);
+    if (nb <= 64) return f(k_tile_lu<8, 17>, 8);
+    return hipErrorInvalidValue;
+}
+
+int tile_lu_resident(int nb) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        return 256;
+    const hipError_t e = with_lu_kernel(nb, [&](auto kern, int NW) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * NW, tile_lu_lds_bytes(NW, nb));
+    });
+    if (e != hipSuccess || per_cu < 1) return ncu;
+    return ncu * per_cu;
+}
+
+int tile_lu_wgs(int count, int NT, int nb, int wgs, int resident) {
     const int full = std::min(nb + 9, NT);
     if (wgs > 0) return std::max(1, std::min(wgs, full));
     // one matrix's P workgroups own every P-th tile column; a column's owner
@@ -373,15 +407,15 @@ int tile_lu_wgs(int count, int NT, int nb, int wgs) {
     // P columns later.  nb + 9 leaves wide slack; when a batch would need
     // more launches at that width, fewer workgroups per matrix let more
     // matrices share a launch (at least 6 each)
-    if ((int64_t)count * full <= 256) return full;
+    if ((int64_t)count * full <= resident) return full;
     const int lo = std::min(full, 6);
-    return std::max(lo, std::min(full, 256 / count));
+    return std::max(lo, std::min(full, resident / count));
 }
 
 // Several independent factorisations of one shape in one launch: P workgroups
-// per matrix (tile_lu_wgs), at most 256 workgroups per launch so that every
-// matrix's workgroups are resident together (their waits only involve each
-// other).  Each matrix i has its band, scratch (tile_lu_scratch_bytes) and
+// per matrix (tile_lu_wgs), no more workgroups per launch than the device
+// keeps resident at once (tile_lu_resident), so that every matrix's
+// workgroups are resident together (their waits only involve each other).  Each matrix i has its band, scratch (tile_lu_scratch_bytes) and
 // on return info_dev[i] / err_dev[i] point into its scratch (pivot info:
 // 0x7f7f7f7f if all pivots are fine, else the first bad row + 1; err:
 // nonzero on a wait time-out).  d_args: device space for count LuArgs.
@@ -411,25 +445,21 @@ hipError_t launch_tile_lu_batch(int count, const int64_t *ns, int bw, int NT, in
         if ((e = hipMemsetAsync(a.info, 0x7f, sizeof(int), s)) != hipSuccess) return e;
         if ((e = hipMemsetAsync(a.err, 0, sizeof(int), s)) != hipSuccess) return e;
     }
-    const int P = tile_lu_wgs(count, NT, nb, wgs);
-    const int per = P > 256 ? 1 : 256 / P;   // matrices per launch
+    if (nb > 64) return hipErrorInvalidValue;
+    const int resident = tile_lu_resident(nb);
+    const int P = tile_lu_wgs(count, NT, nb, wgs, resident);
+    const int per = P > resident ? 1 : resident / P;   // matrices per launch
     LuArgs *dA = (LuArgs *)d_args;
     hipError_t e = hipMemcpyAsync(dA, hv.data(), sizeof(LuArgs) * (size_t)count, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
     for (int i0 = 0; i0 < count; i0 += per) {
         const int c = count - i0 < per ? count - i0 : per;
         const dim3 grid((unsigned)(c * P));
-        if (nb <= 4)
-            hipLaunchKernelGGL((k_tile_lu<4, 3>), grid, dim3(256), tile_lu_lds_bytes(4, nb), s, dA + i0, P);
-        else if (nb <= 16)
-            hipLaunchKernelGGL((k_tile_lu<4, 9>), grid, dim3(256), tile_lu_lds_bytes(4, nb), s, dA + i0, P);
-        else if (nb <= 32)
-            hipLaunchKernelGGL((k_tile_lu<4, 17>), grid, dim3(256), tile_lu_lds_bytes(4, nb), s, dA + i0, P);
-        else if (nb <= 64)
-            hipLaunchKernelGGL((k_tile_lu<8, 17>), grid, dim3(512), 0, s, dA + i0, P);
-        else
-            return hipErrorInvalidValue;
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        e = with_lu_kernel(nb, [&](auto kern, int NW) {
+            hipLaunchKernelGGL(kern, grid, dim3(64 * NW), tile_lu_lds_bytes(NW, nb), s, dA + i0, P);
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }

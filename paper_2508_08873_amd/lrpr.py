@@ -21,7 +21,7 @@ EXPORTS = ["lrpr_ctx_create", "lrpr_ctx_destroy", "lrpr_ctx_set_stream", "lrpr_l
            "lrpr_ctx_release_workspaces", "lrpr_tune_set", "lrpr_tune_get", "lrpr_autotune_factor",
            "lrpr_device_trim",
            "lrpr_factor", "lrpr_factor_stepper", "lrpr_factor_sequence", "lrpr_factor_many", "lrpr_factor_destroy",
-           "lrpr_factor_info", "lrpr_factor_copy_lu",
+           "lrpr_factor_info", "lrpr_factor_copy_lu", "lrpr_factor_copy_tiles",
            "lrpr_fine_step_batched", "lrpr_adjoint_step_batched", "lrpr_rsvd_build", "lrpr_rsvd_build_q",
            "lrpr_rsvd_build_two_sided", "lrpr_rsvd_build_w", "lrpr_coarse_from_factors", "lrpr_mass_weights",
            "lrpr_coarse_destroy", "lrpr_coarse_view", "lrpr_coarse_get", "lrpr_coarse_apply",
@@ -109,6 +109,7 @@ def load():
     lib.lrpr_factor_destroy.restype = None
     lib.lrpr_factor_info.argtypes = [vp, P(i64), P(i32), P(dbl)]
     lib.lrpr_factor_copy_lu.argtypes = [vp, vp, vp]
+    lib.lrpr_factor_copy_tiles.argtypes = [vp, vp, i32, i32, vp]
     lib.lrpr_fine_step_batched.argtypes = [vp, i32, P(Panel), i32, i32]
     lib.lrpr_adjoint_step_batched.argtypes = [vp, i32, P(Panel), i32, i32]
     lib.lrpr_rsvd_build.argtypes = [vp, i32, P(SliceDesc), i32, i32, P(vp), vp, vp]
@@ -423,6 +424,16 @@ class Factor:
         import numpy as np
         out = np.zeros((self.n, 2 * self.bw + 1), dtype=np.float64)
         self.ctx._check(self.ctx.lib.lrpr_factor_copy_lu(self.ctx.h, self.h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def tiles_host(self, which, prec):
+        """Packed band tiles (which: 0 lower, 1 upper; prec LRPR_F64 or
+        LRPR_F32) as an array [NT, nb, 256] in the tiles' own element order."""
+        import numpy as np
+        NT, nb = (self.n + 15) // 16, (self.bw + 15) // 16
+        out = np.zeros((NT, nb, 256), dtype=np.float32 if prec == LRPR_F32 else np.float64)
+        self.ctx._check(self.ctx.lib.lrpr_factor_copy_tiles(self.ctx.h, self.h, which, prec,
+                                                            out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
     def close(self):
