@@ -240,8 +240,8 @@ hipError_t launch_tile_lu_batch(int count, const int64_t *ns, int bw, int NT, in
 // workgroups per matrix of a batched LU of count matrices (wgs > 0: that
 // request, clipped to nb + 9 and NT); resident: tile_lu_resident(nb)
 int tile_lu_wgs(int count, int NT, int nb, int wgs, int resident);
-// LU workgroups the current device keeps resident at once (compute units x
-// workgroups per compute unit of the kernel variant for nb)
+// LU workgroups per launch on the current device, all resident at once: one
+// per compute unit (0 if the kernel variant for nb cannot be resident)
 int tile_lu_resident(int nb);
 size_t tile_lu_args_bytes(int count);
 // rev: lu is the LU of the reversed matrix (16 NT rows); the sets then hold

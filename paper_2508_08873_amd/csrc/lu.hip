@@ -81,11 +81,19 @@ __device__ __forceinline__ int wait_upto(const LuArgs &a, int K, int Kmax, int *
     return *shared_last;
 }
 
-// Panels staged through LDS (two buffers of nb tiles) for nb <= 32 with one
-// wave per SIMD; wider bands read the L tiles from memory as they are applied.
+// Panels staged through LDS (one buffer of nb tiles, filled by direct
+// global-to-LDS loads) for nb <= 32 with one wave per SIMD; wider bands read
+// the L tiles from memory as they are applied.  The diagonal tile's buffers
+// share the dynamic LDS with the panel (they are used after a column's panel
+// loop).  No register buffer holds a panel, which leaves the registers to the
+// column's tiles.
 constexpr int PANEL_NB = 32;
 constexpr int PANEL_VECS = PANEL_NB * (TILE_ELEMS / 2) / 256;   // 16-byte vectors per thread (256 threads)
-size_t tile_lu_lds_bytes(int NW, int nb) { return (NW == 4 && nb <= PANEL_NB) ? 2 * (size_t)nb * TILE_ELEMS * 8 : 0; }
+static bool lu_ldsp(int NW, int nb) { return NW == 4 && nb <= PANEL_NB; }
+size_t tile_lu_lds_bytes(int NW, int nb) {
+    const size_t panel = lu_ldsp(NW, nb) ? (size_t)nb * TILE_ELEMS : 0, diag = (size_t)(4 + NW) * TILE_ELEMS;
+    return 8 * std::max(panel, diag);
+}
 
 // Linear workgroup order in which each XCD holds a contiguous range: the
 // chip deals workgroup b to XCD b % 8, and each XCD has its own L2, so a
@@ -97,15 +105,15 @@ __device__ __forceinline__ int lu_xcd_linear(int b, int G) {
 }
 
 template <int NW, int TPW>
-__global__ __launch_bounds__(64 * NW) void k_tile_lu(const LuArgs *args, int P) {
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void k_tile_lu(const LuArgs *args, int P) {
     constexpr bool LDSP = NW == 4;
-    extern __shared__ __align__(16) double panel_lds[];   // [2][nb][256] when LDSP
+    // dynamic LDS: the panel [nb][256] while the panels are applied (LDSP),
+    // then the diagonal tile's buffers, all row-major 16x16: sd, sd2 (the two
+    // buffers of the diagonal elimination), sli = L(J,J)^{-1},
+    // sui = U(J,J)^{-1}, st[w] (wave w's transposition buffer)
+    extern __shared__ __align__(16) double lu_lds[];
+    double *const sd = lu_lds, *const sd2 = lu_lds + 256, *const sli = lu_lds + 512, *const sui = lu_lds + 768;
     __shared__ double ubuf[2][256];   // U(K,J), accumulator order
-    __shared__ double sd[256];        // diagonal tile, row-major
-    __shared__ double sd2[256];       // second buffer of the diagonal elimination
-    __shared__ double sli[256];       // L(J,J)^{-1}, row-major
-    __shared__ double sui[256];       // U(J,J)^{-1}, row-major
-    __shared__ double st[NW][256];    // per-wave transposition buffer
     __shared__ int s_last;            // last published column seen by wait_upto
     // workgroups [P*i, P*i + P) of the XCD-contiguous order factor matrix i
     const int lin = lu_xcd_linear(blockIdx.x, gridDim.x);
@@ -180,48 +188,35 @@ __global__ __launch_bounds__(64 * NW) void k_tile_lu(const LuArgs *args, int P) 
             }
         };
         if constexpr (LDSP) {
-            // the nb L tiles of a panel are contiguous in Lt: staged through
-            // LDS, panel K+1's loads in flight while panel K is applied (when
-            // K+1 is known to be published); the barriers order LDS only
-            double *pb = panel_lds;
-            const int nv = nb * (TILE_ELEMS / 2);   // 16-byte vectors per panel
-            d2v pr[PANEL_VECS];
-            auto issue = [&](int K) {
+            // the nb L tiles of a panel are contiguous in Lt: copied to LDS by
+            // direct global-to-LDS loads (16 bytes a lane, one contiguous KB
+            // a wave instruction), in flight while U(K,J) is formed; the
+            // first barrier orders the previous panel's LDS reads before the
+            // copy, the second waits for every wave's copy
+            double *const pb = lu_lds;
+            const int nv = nb * (TILE_ELEMS / 2);   // 16-byte vectors per panel (a multiple of 128)
+            typedef __attribute__((address_space(3))) void *lds_ptr;
+            for (int K = K0; K < J; ++K) {
+                if (K > avail) avail = wait_upto(a, K, J - 1, &s_last);
+                lds_barrier();
                 const double *src = a.Lt + (int64_t)K * nb * TILE_ELEMS;
 #pragma unroll
                 for (int i = 0; i < PANEL_VECS; ++i) {
-                    const int e = tid + 64 * NW * i;
-                    if (e < nv) pr[i] = *(gd2p)(src + 2 * e);
+                    const int e0 = 256 * i + 64 * w;   // wave-uniform; e0 < nv implies e0 + 64 <= nv
+                    if (e0 < nv)
+                        __builtin_amdgcn_global_load_lds((const void *)(src + 2 * (e0 + lane)), (lds_ptr)(pb + 2 * e0),
+                                                         16, 0, 0);
                 }
-            };
-            auto stage = [&](int K) {
-                double *dst = pb + (K & 1) * nb * TILE_ELEMS;
-#pragma unroll
-                for (int i = 0; i < PANEL_VECS; ++i) {
-                    const int e = tid + 64 * NW * i;
-                    if (e < nv) *(d2v *)(dst + 2 * e) = pr[i];
-                }
-            };
-            bool have = false;   // LDS buffer K&1 holds panel K
-            for (int K = K0; K < J; ++K) {
-                if (K > avail) avail = wait_upto(a, K, J - 1, &s_last);
-                if (!have) {
-                    issue(K);
-                    stage(K);
-                }
-                const bool pre = K + 1 < J && K + 1 <= avail;
-                if (pre) issue(K + 1);
                 form_u(K);
-                lds_barrier();
-                const double *cur = pb + (K & 1) * nb * TILE_ELEMS;
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
                 apply(K, [&](int d, double (&l)[4]) {
-                    const d2v x = *(const d2v *)(cur + d * TILE_ELEMS + 2 * lane);
-                    const d2v y = *(const d2v *)(cur + d * TILE_ELEMS + 128 + 2 * lane);
+                    const d2v x = *(const d2v *)(pb + d * TILE_ELEMS + 2 * lane);
+                    const d2v y = *(const d2v *)(pb + d * TILE_ELEMS + 128 + 2 * lane);
                     l[0] = x[0]; l[1] = x[1]; l[2] = y[0]; l[3] = y[1];
                 });
-                if (pre) stage(K + 1);
-                have = pre;
             }
+            lds_barrier();   // the diagonal tile's buffers overwrite the panel
         } else {
             for (int K = K0; K < J; ++K) {
                 if (K > avail) avail = wait_upto(a, K, J - 1, &s_last);
@@ -270,7 +265,7 @@ __global__ __launch_bounds__(64 * NW) void k_tile_lu(const LuArgs *args, int P) 
         //      U^{-1} = (I - N')(I + N'^2)(I + N'^4)(I + N'^8) D^{-1}.
         if (w < 2) {
             const bool up = w == 1;
-            double *buf = st[w];
+            double *buf = lu_lds + (4 + w) * 256;   // st[w]
             // N (or N') in accumulator layout
             v4d N;
 #pragma unroll
@@ -322,7 +317,7 @@ __global__ __launch_bounds__(64 * NW) void k_tile_lu(const LuArgs *args, int P) 
         double uiv[4];
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc) uiv[kc] = sui[(4 * kc + g) * TILE + c];
-        double *stw = st[w];
+        double *stw = lu_lds + (4 + w) * 256;   // st[w]
 #pragma unroll
         for (int s = 0; s < TPW; ++s) {
             const int t = w + NW * s;
@@ -386,6 +381,10 @@ static hipError_t with_lu_kernel(int nb, F &&f) {
     return hipErrorInvalidValue;
 }
 
+// One workgroup per compute unit: every variant keeps at least one resident
+// per compute unit (an occupancy query confirms it), and two per compute unit
+// (P = 16 for 32 matrices of 511^2: 2.14 s) were slower than one (P = 8:
+// 1.84 s): the compute unit's throughput, not load latency, bounds a column.
 int tile_lu_resident(int nb) {
     int dev = 0, ncu = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -394,8 +393,8 @@ int tile_lu_resident(int nb) {
     const hipError_t e = with_lu_kernel(nb, [&](auto kern, int NW) {
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * NW, tile_lu_lds_bytes(NW, nb));
     });
-    if (e != hipSuccess || per_cu < 1) return ncu;
-    return ncu * per_cu;
+    if (e != hipSuccess || per_cu < 1) return 0;   // the launch reports the error
+    return ncu;
 }
 
 int tile_lu_wgs(int count, int NT, int nb, int wgs, int resident) {
@@ -447,6 +446,7 @@ hipError_t launch_tile_lu_batch(int count, const int64_t *ns, int bw, int NT, in
     }
     if (nb > 64) return hipErrorInvalidValue;
     const int resident = tile_lu_resident(nb);
+    if (resident < 1) return hipErrorInvalidConfiguration;
     const int P = tile_lu_wgs(count, NT, nb, wgs, resident);
     const int per = P > resident ? 1 : resident / P;   // matrices per launch
     LuArgs *dA = (LuArgs *)d_args;
