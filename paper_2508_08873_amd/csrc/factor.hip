@@ -266,31 +266,28 @@ __global__ void k_pack_band32(LuAcc F, int NT, int nb, const double *Linv, const
 }
 
 // Band tiles of one tile row per workgroup (256 threads, one per element of
-// a tile), for every requested set (blockIdx.y).  The nb 16x16 factor
-// blocks of the row are loaded at once (every load in flight together) and
-// staged in LDS; thread (r, q) forms entry (r, q) of every block's product
-// with the row's diagonal-tile inverse (the same sums in the same order as
-// band_elem: one independent chain per block), for the FP64 tiles and an
-// LDS copy of the tile row's 16 x 16 nb values.  The FP32 rows are rounded
-// by round_row_keep_sum's rule with 16 threads per row (entries l, l + 16,
-// ... for thread l; the rounding errors summed over the 16 threads, ties of
-// the largest and smallest entries going to the lower entry index), and the
-// FP32 tiles are written in their memory order.
+// a tile), for every requested set (blockIdx.y).  The nb 16x16 factor blocks
+// of the row are loaded 16 at a time (every load of a chunk in flight
+// together, the next chunk's while the current one is used) and staged in
+// LDS; thread (r, q) forms entry (r, q) of every block's product with the
+// row's diagonal-tile inverse (the same sums in the same order as band_elem:
+// one independent chain per block) and keeps them in registers.  Row r's
+// 16 nb values then sit in the 16 threads (r, 0..15), thread q holding
+// entries q, q + 16, ...: the FP32 row is rounded by round_row_keep_sum's
+// rule with the rounding errors summed over those threads and the largest
+// and smallest entries reduced across them (ties going to the lower entry
+// index), and every thread writes its own entries.
 template <int NBMAX>
 __global__ __launch_bounds__(256) void k_pack_rows(LuAcc F, int NT, int nb, const double *Linv, const double *Uinv,
                                                    BandOut o64, BandOut o32) {
-    // dynamic LDS: the factor blocks [nb][16][16] (element (k, q) of block j at
-    // j*256 + 16 k + q), then over them the row values [16][16 nb + 1]
-    extern __shared__ double lds[];
-    __shared__ int s_at[TILE], s_at2[TILE];
-    __shared__ float s_fat[TILE], s_f2[TILE];
+    constexpr int CH = 16;               // blocks staged at once
+    extern __shared__ double lds[];      // [CH][16][16]: element (k, q) of block u at u*256 + 16 k + q
     const int a = blockIdx.y;
     if (!o64.b[a] && !o32.b[a]) return;
     const int64_t I = blockIdx.x;
     const int t = threadIdx.x;
     const int64_t base = I * TILE;
     const int r = t >> 4, q = t & 15;
-    const int W = 16 * nb, WS = W + 1;
     // this thread's element of block j, read along the contiguous direction
     // of the band storage, staged at (sk, sq)
     const int sk = a < 2 ? (t >> 4) : (t & 15), sq = a < 2 ? (t & 15) : (t >> 4);
@@ -299,97 +296,93 @@ __global__ __launch_bounds__(256) void k_pack_rows(LuAcc F, int NT, int nb, cons
         if (a < 2) return a == 0 ? F.lower(base + sk, jl + sq) : F.upper(base + sk, ju + sq);
         return a == 2 ? F.upper(jl + sq, base + sk) : F.lower(ju + sq, base + sk);
     };
-    {
-        double m[NBMAX];
+    double m[CH];
 #pragma unroll
-        for (int j = 0; j < NBMAX; ++j) m[j] = j < nb ? fetch(j) : 0.0;
-#pragma unroll
-        for (int j = 0; j < NBMAX; ++j)
-            if (j < nb) lds[j * TILE_ELEMS + sk * TILE + sq] = m[j];
-    }
+    for (int u = 0; u < CH; ++u) m[u] = u < nb ? fetch(u) : 0.0;
     // row r of the diagonal-tile inverse (column r for the transposed sets)
     const double *Di = ((a == 0 || a == 3) ? Linv : Uinv) + I * TILE_ELEMS;
     double d[TILE];
 #pragma unroll
     for (int k = 0; k < TILE; ++k) d[k] = a < 2 ? Di[r * TILE + k] : Di[k * TILE + r];
-    __syncthreads();
     double v[NBMAX];
 #pragma unroll
-    for (int j = 0; j < NBMAX; ++j) {
-        double x = 0.0;
-        if (j < nb) {
+    for (int c0 = 0; c0 < NBMAX; c0 += CH) {
+        if (c0 < nb) {   // workgroup-uniform
+            if (c0 > 0) lds_barrier();   // the previous chunk's reads are done
 #pragma unroll
-            for (int k = 0; k < TILE; ++k) x += d[k] * lds[j * TILE_ELEMS + k * TILE + q];
+            for (int u = 0; u < CH; ++u)
+                if (c0 + u < nb) lds[u * TILE_ELEMS + sk * TILE + sq] = m[u];
+            if (c0 + CH < nb) {
+#pragma unroll
+                for (int u = 0; u < CH; ++u) m[u] = c0 + CH + u < nb ? fetch(c0 + CH + u) : 0.0;
+            }
+            lds_barrier();   // LDS only: the next chunk's loads stay in flight
         }
-        v[j] = x;
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int j = c0 + u;
+            double x = 0.0;
+            if (j < nb) {
+#pragma unroll
+                for (int k = 0; k < TILE; ++k) x += d[k] * lds[u * TILE_ELEMS + k * TILE + q];
+            }
+            v[j] = x;
+        }
     }
-    __syncthreads();   // every block read: the row values overwrite them
-    double *const rowv = lds;
+    if (o64.b[a]) {
+#pragma unroll
+        for (int j = 0; j < NBMAX; ++j)
+            if (j < nb) ((double *)o64.b[a])[(I * nb + j) * TILE_ELEMS + aslot(false, r, q)] = v[j];
+    }
+    if (!o32.b[a]) return;
+    // rounding of row r by its 16 threads (entry c = 16 j + q in thread q)
+    double err = 0.0, amax = 0.0, xmax = 0.0;
+    int imax = INT_MAX;   // none: every entry is zero (or NaN)
 #pragma unroll
     for (int j = 0; j < NBMAX; ++j)
         if (j < nb) {
-            rowv[r * WS + j * TILE + q] = v[j];
-            if (o64.b[a]) ((double *)o64.b[a])[(I * nb + j) * TILE_ELEMS + aslot(false, r, q)] = v[j];
-        }
-    if (!o32.b[a]) return;
-    __syncthreads();
-    {
-        const int l = q;   // thread l of row r
-        const double *rv = rowv + r * WS;
-        double err = 0.0, amax = 0.0;
-        int imax = INT_MAX;   // none: every entry is zero (or NaN)
-        for (int c = l; c < W; c += TILE) {
-            const double x = rv[c];
+            const double x = v[j];
             err += x - (double)(float)x;
-            if (fabs(x) > amax) { amax = fabs(x); imax = c; }
+            if (fabs(x) > amax) { amax = fabs(x); xmax = x; imax = TILE * j + q; }
         }
 #pragma unroll
-        for (int m = 8; m >= 1; m >>= 1) {
-            err += __shfl_xor(err, m, TILE);
-            const double oa = __shfl_xor(amax, m, TILE);
-            const int oi = __shfl_xor(imax, m, TILE);
-            if (oa > amax || (oa == amax && oi < imax)) { amax = oa; imax = oi; }
-        }
-        int at2 = INT_MAX;
-        float fat = 0.f, f2 = 0.f;
-        if (imax != INT_MAX) {
-            const double want = (double)(float)rv[imax] + err;
-            fat = (float)want;
-            const double res = want - (double)fat;
-            if (res != 0.0) {   // row-uniform
-                const double lo = amax * (1.0 / 4096.0);
-                double best = amax;
-                for (int c = l; c < W; c += TILE) {
-                    const double ax = fabs(rv[c]);
-                    if (c != imax && ax >= lo && ax < best) { best = ax; at2 = c; }
+    for (int s = 8; s >= 1; s >>= 1) {
+        err += __shfl_xor(err, s, TILE);
+        const double oa = __shfl_xor(amax, s, TILE), ox = __shfl_xor(xmax, s, TILE);
+        const int oi = __shfl_xor(imax, s, TILE);
+        if (oa > amax || (oa == amax && oi < imax)) { amax = oa; xmax = ox; imax = oi; }
+    }
+    int at2 = INT_MAX;
+    float fat = 0.f, f2 = 0.f;
+    if (imax != INT_MAX) {
+        const double want = (double)(float)xmax + err;
+        fat = (float)want;
+        const double res = want - (double)fat;
+        if (res != 0.0) {   // row-uniform
+            const double lo = amax * (1.0 / 4096.0);
+            double best = amax, x2 = 0.0;
+#pragma unroll
+            for (int j = 0; j < NBMAX; ++j)
+                if (j < nb) {
+                    const double ax = fabs(v[j]);
+                    if (TILE * j + q != imax && ax >= lo && ax < best) { best = ax; x2 = v[j]; at2 = TILE * j + q; }
                 }
 #pragma unroll
-                for (int m = 8; m >= 1; m >>= 1) {
-                    const double ob = __shfl_xor(best, m, TILE);
-                    const int oi = __shfl_xor(at2, m, TILE);
-                    if (ob < best || (ob == best && oi < at2)) { best = ob; at2 = oi; }
-                }
-                if (at2 != INT_MAX) f2 = (float)((double)(float)rv[at2] + res);
+            for (int s = 8; s >= 1; s >>= 1) {
+                const double ob = __shfl_xor(best, s, TILE), ox = __shfl_xor(x2, s, TILE);
+                const int oi = __shfl_xor(at2, s, TILE);
+                if (ob < best || (ob == best && oi < at2)) { best = ob; x2 = ox; at2 = oi; }
             }
-        }
-        if (l == 0) {
-            s_at[r] = imax;
-            s_at2[r] = at2;
-            s_fat[r] = fat;
-            s_f2[r] = f2;
+            if (at2 != INT_MAX) f2 = (float)((double)(float)x2 + res);
         }
     }
-    __syncthreads();
-    // the tile row's FP32 tiles are nb * 256 consecutive floats: position p
-    // holds element (r, q) of tile p / 256 (p % 256 = aslot(true, r, q))
     float *const out = (float *)o32.b[a] + I * nb * TILE_ELEMS;
-    for (int p = t; p < nb * TILE_ELEMS; p += 256) {
-        const int j = p >> 8, sl = p & 255;
-        const int rr = (sl >> 2) & 15, qq = ((sl >> 6) << 2) | (sl & 3);
-        const int c = j * TILE + qq;
-        const float f = c == s_at[rr] ? s_fat[rr] : c == s_at2[rr] ? s_f2[rr] : (float)rowv[rr * WS + c];
-        out[p] = f;
-    }
+#pragma unroll
+    for (int j = 0; j < NBMAX; ++j)
+        if (j < nb) {
+            const int c = TILE * j + q;
+            out[j * TILE_ELEMS + aslot(true, r, q)] = c == imax ? fat : c == at2 ? f2 : (float)v[j];
+        }
 }
 
 // Phase 1: FP64 inverses of the diagonal tiles, natural row-major 16x16 per
@@ -475,7 +468,7 @@ hipError_t launch_pack_tiles(int64_t n, int bw, int NT, int nb, const double *lu
         b32.b[a] = t32 ? t32->a[bidx[a]] : nullptr;
     }
     if (nb <= 64) {
-        const size_t lds = sizeof(double) * (TILE_ELEMS * (size_t)nb + TILE);
+        const size_t lds = sizeof(double) * TILE_ELEMS * 16;
         if (nb <= 32)
             hipLaunchKernelGGL(k_pack_rows<32>, dim3((unsigned)NT, 4), dim3(256), lds, s, F, NT, nb, Linv, Uinv, b64,
                                b32);
